@@ -1,0 +1,168 @@
+/*
+ * comm.h -- C ABI of the MI355X (gfx950) library for contraction-only
+ * majorization-minimization updates of nonnegative CP and Tucker models under
+ * beta-divergences (Leplat, "Joint Majorization-Minimization for Nonnegative CP
+ * and Tucker Decompositions under beta-Divergences: Unfolding-Free Updates").
+ *
+ * Problem (Sec. 3): a nonnegative data tensor X (I_1 x ... x I_N), a CP model
+ * (factors A^(n), I_n x R) or a Tucker model (core G, J_1 x ... x J_N, and
+ * factors A^(n), I_n x J_n), all parameters >= eps (Assumption "positivity
+ * safeguard"), and beta in [0, 2).
+ *
+ * Conventions shared by every entry point
+ *   - Tensors, factors and cores are caller-owned DEVICE buffers of float32,
+ *     contiguous row-major (last index fastest).  Factor n is I_n x R (CP) or
+ *     I_n x J_n (Tucker), row stride R (or J_n).
+ *   - Model parameters are updated IN PLACE.
+ *   - Every call is asynchronous on the given HIP stream (NULL = default
+ *     stream).  Results are visible after the caller synchronises the stream.
+ *   - Arguments are validated on the host before anything is launched; on an
+ *     error nothing is modified and the call returns a nonzero code, with a
+ *     message available from comm_last_error() (thread-local).
+ *   - Outputs are clipped to >= eps.  Inputs with entries < eps violate the
+ *     precondition of the paper's updates; the library does not check them.
+ *   - No C++ exception crosses this interface.
+ *   - Calls sharing one context must not overlap in time (the context owns
+ *     the scratch workspace); use one context per concurrent stream.
+ *   - Reductions are deterministic: the same inputs give bitwise identical
+ *     outputs on the same device.
+ *
+ * Supported in this version: dense 3-way tensors; CP rank R <= 32; Tucker core
+ * sizes J_n <= 32.  Other shapes return COMM_EUNSUPPORTED.
+ */
+#ifndef COMM_H_
+#define COMM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define COMM_OK 0
+#define COMM_EINVAL 1        /* bad argument: NULL pointer, dims, rank, beta outside [0,2), eps <= 0, L < 1 */
+#define COMM_EUNSUPPORTED 2  /* valid problem outside what this build implements */
+#define COMM_ENOMEM 3        /* workspace would exceed the context's limit, or allocation failed */
+#define COMM_EHIP 4          /* HIP runtime error; message carries hipGetErrorString */
+
+/* Model kinds. */
+#define COMM_CP 0
+#define COMM_TUCKER 1
+
+/* Arithmetic of the contraction tiles.  Power step and updates are float32 in
+ * both; the objective is accumulated in float64 in both. */
+#define COMM_FP32 0
+
+typedef struct comm_ctx comm_ctx;
+
+/* Dense data tensor X >= 0 (Sec. 3.1).  X points to prod(dims) floats. */
+typedef struct {
+  int ndim;
+  int64_t dims[4];
+  const float* X;
+} comm_dense;
+
+/* Model parameters Theta (Sec. 3.3).
+ *   kind == COMM_CP:     rank R, factors[n] -> I_n x R; core unused.
+ *   kind == COMM_TUCKER: core_dims J_n, core -> J_1 x ... x J_N,
+ *                        factors[n] -> I_n x J_n; rank unused. */
+typedef struct {
+  int kind;
+  int rank;
+  int64_t core_dims[4];
+  float* factors[4];
+  float* core;
+} comm_model;
+
+/* Options.
+ *   beta          in [0, 2).
+ *   eps           lower bound on every parameter (> 0); the reconstruction
+ *                 also enters powers, logs and divisions as max(Xhat, eps).
+ *   eps_x         at beta = 0 the data enter as max(X, eps_x) (> 0).
+ *   inner_sweeps  L >= 1, inner sweeps per J-CoMM outer iteration.
+ *   precision     COMM_FP32.
+ *   cache_pq      J-CoMM at beta != 1: 1 = store P~ and Q~ once per outer
+ *                 iteration in the workspace and stream them in the inner
+ *                 passes; 0 = recompute them from X and the reference. */
+typedef struct {
+  double beta;
+  double eps;
+  double eps_x;
+  int inner_sweeps;
+  int precision;
+  int cache_pq;
+} comm_opts;
+
+/* Sparse COO data (CP, beta = 1 only).  idx[n][t] is the mode-n coordinate of
+ * nonzero t (int32, 0 <= idx < dims[n]); val[t] > 0.  Device buffers. */
+typedef struct {
+  int ndim;
+  int64_t dims[4];
+  int64_t nnz;
+  const int32_t* idx[4];
+  const float* val;
+} comm_coo;
+
+/* Create a context on HIP device `device`.  The context owns a scratch
+ * workspace that grows on demand up to `workspace_limit_bytes` (0 = no limit).
+ * Returns COMM_OK and sets *out, or an error code. */
+int comm_create(int device, size_t workspace_limit_bytes, comm_ctx** out);
+
+/* Synchronise the context's last stream and free its workspace. */
+int comm_destroy(comm_ctx* ctx);
+
+/* Message of the last error raised on this thread (never NULL). */
+const char* comm_last_error(void);
+
+/* Workspace bytes a call with these arguments would need (0 on invalid
+ * arguments).  `op` is 0 = cp_update / tucker_update, 1 = jcomm_outer,
+ * 2 = beta_objective. */
+size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op);
+
+/* Block-MM (B-CoMM) update of a CP model (Theorem "CP block multiplicative
+ * update"; Algorithm B-CoMM).  block in 0..N-1 updates that factor; block = -1
+ * runs one full sweep over modes 1..N, rebuilding Xhat and P, Q before every
+ * block.  Each block: A^(n) <- max(A^(n) * (Num^(n)/Den^(n))^gamma(beta), eps)
+ * with Num/Den = CPContr^(n)(P or Q; other factors). */
+int comm_cp_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int block,
+                   const comm_opts* opts, void* stream);
+
+/* Block-MM update of a Tucker model (Sec. 4.3; Theorem "Tucker block
+ * multiplicative updates"; App. C.2).  block = -1 updates the core, 0..N-1 a
+ * factor, -2 runs a full sweep (core, then modes 1..N). */
+int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int block,
+                       const comm_opts* opts, void* stream);
+
+/* One outer iteration of J-CoMM (Algorithm J-CoMM; Sec. 5.3; App. C.3) for a
+ * CP or Tucker model: reference Theta~ = current parameters, reference tensors
+ * P~ = X * X~^(beta-2), Q~ = X~^(beta-1), then L = opts->inner_sweeps inner
+ * sweeps of anchored updates Theta_b <- max(Theta~_b * (Num_J/Den_J)^gamma, eps).
+ * Block order: CP modes 1..N; Tucker core, then modes 1..N.
+ * If obj_ref_dev is not NULL, the objective at the reference,
+ * F(Theta~) = D_beta(X, X~) (sum over all entries, float64), is written to
+ * that device address. */
+int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
+                     double* obj_ref_dev, void* stream);
+
+/* D_beta(X, Xhat(model)) summed over all entries (Sec. 3.2, Definition of the
+ * beta-divergence), accumulated in float64, written to the device address
+ * out_dev.  Safeguards as in comm_opts. */
+int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
+                        const comm_opts* opts, double* out_dev, void* stream);
+
+/* One J-CoMM outer iteration for a CP model on sparse COO counts at beta = 1
+ * (Sec. 6.4, paragraph on sparse tensors): numerators accumulated over the
+ * nonzeros only; the beta = 1 denominator is the product of the other
+ * factors' column sums.  opts->beta must be 1.  If obj_ref_dev is not NULL the
+ * objective at the reference is written there (zero cells contribute the
+ * model value, summed in closed form). */
+int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
+                            double* obj_ref_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COMM_H_ */

@@ -1,0 +1,272 @@
+"""Python binding of ``libcomm.so``: contraction-only block-MM (B-CoMM) and
+joint-MM (J-CoMM) updates for nonnegative CP and Tucker models under
+beta-divergences, on MI355X (gfx950).
+
+This module only marshals arguments: torch tensors on the GPU supply device
+pointers and the current HIP stream; every step of the computation runs in the
+library's HIP kernels.  The library must have been built
+(``python -m paper_2602_14683_amd.build``); importing this module without it
+raises an error rather than falling back to anything else.
+
+Entry points (same names as the C ABI in ``include/comm.h``):
+``cp_update``, ``tucker_update``, ``jcomm_outer``, ``beta_objective``,
+``cp_jcomm_outer_coo``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcomm.so")
+
+COMM_OK, COMM_EINVAL, COMM_EUNSUPPORTED, COMM_ENOMEM, COMM_EHIP = 0, 1, 2, 3, 4
+COMM_CP, COMM_TUCKER = 0, 1
+COMM_FP32 = 0
+
+EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_cp_update",
+            "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo"]
+
+
+class CommError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Dense(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * 4), ("X", ctypes.c_void_p)]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("rank", ctypes.c_int), ("core_dims", ctypes.c_int64 * 4),
+                ("factors", ctypes.c_void_p * 4), ("core", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("eps_x", ctypes.c_double),
+                ("inner_sweeps", ctypes.c_int), ("precision", ctypes.c_int), ("cache_pq", ctypes.c_int)]
+
+
+class Coo(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * 4), ("nnz", ctypes.c_int64),
+                ("idx", ctypes.c_void_p * 4), ("val", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``libcomm.so`` (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2602_14683_amd.build`")
+    # torch ships its own HIP runtime; load it first so that the library binds to
+    # the same runtime instance (same soname) instead of a second copy.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.comm_create.argtypes = [ctypes.c_int, ctypes.c_size_t, P(ctypes.c_void_p)]
+    lib.comm_destroy.argtypes = [ctypes.c_void_p]
+    lib.comm_last_error.restype = ctypes.c_char_p
+    lib.comm_workspace_bytes.argtypes = [P(Dense), P(Model), P(Opts), ctypes.c_int]
+    lib.comm_workspace_bytes.restype = ctypes.c_size_t
+    lib.comm_cp_update.argtypes = [ctypes.c_void_p, P(Dense), P(Model), ctypes.c_int, P(Opts), ctypes.c_void_p]
+    lib.comm_tucker_update.argtypes = [ctypes.c_void_p, P(Dense), P(Model), ctypes.c_int, P(Opts), ctypes.c_void_p]
+    lib.comm_jcomm_outer.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), ctypes.c_void_p, ctypes.c_void_p]
+    lib.comm_beta_objective.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), ctypes.c_void_p,
+                                        ctypes.c_void_p]
+    lib.comm_cp_jcomm_outer_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
+                                            ctypes.c_void_p]
+    for name in ["comm_create", "comm_destroy", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
+                 "comm_beta_objective", "comm_cp_jcomm_outer_coo"]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != COMM_OK:
+        raise CommError(rc, load_library().comm_last_error().decode())
+
+
+def _ptr(t, what: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t.data_ptr()
+
+
+def _f32(t, what: str) -> int:
+    import torch
+    if t.dtype != torch.float32:
+        raise TypeError(f"{what} must be float32")
+    return _ptr(t, what)
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dense(X) -> Dense:
+    d = Dense()
+    d.ndim = X.dim()
+    for n in range(min(4, X.dim())):
+        d.dims[n] = X.shape[n]
+    d.X = _f32(X, "X")
+    return d
+
+
+def _model(factors: Sequence, core=None) -> Model:
+    m = Model()
+    if core is None:
+        m.kind = COMM_CP
+        m.rank = int(factors[0].shape[1])
+    else:
+        m.kind = COMM_TUCKER
+        m.rank = 0
+        for n in range(core.dim()):
+            m.core_dims[n] = core.shape[n]
+        m.core = _f32(core, "core")
+    for n, A in enumerate(factors):
+        if A.dim() != 2:
+            raise ValueError("factors must be matrices")
+        m.factors[n] = _f32(A, f"factors[{n}]")
+    return m
+
+
+def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq: bool = False) -> Opts:
+    o = Opts()
+    o.beta = float(beta)
+    o.eps = float(eps)
+    o.eps_x = float(eps if eps_x is None else eps_x)
+    o.inner_sweeps = int(L)
+    o.precision = COMM_FP32
+    o.cache_pq = 1 if cache_pq else 0
+    return o
+
+
+class Context:
+    """A library context on one device; owns the scratch workspace."""
+
+    def __init__(self, device: int = 0, workspace_limit: int = 0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self._lib.comm_create(int(device), int(workspace_limit), ctypes.byref(h)))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(self._lib.comm_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- entry points
+
+    def cp_update(self, X, factors, block: int = -1, beta: float = 1.0, eps: float = 1e-12,
+                  eps_x: Optional[float] = None, stream=None) -> None:
+        """B-CoMM block update(s) of a CP model in place (block -1: full sweep)."""
+        d, m, o = _dense(X), _model(factors), _opts(beta, eps, eps_x)
+        _check(self._lib.comm_cp_update(self._h, ctypes.byref(d), ctypes.byref(m), int(block), ctypes.byref(o),
+                                        _stream(stream)))
+
+    def tucker_update(self, X, core, factors, block: int = -2, beta: float = 1.0, eps: float = 1e-12,
+                      eps_x: Optional[float] = None, stream=None) -> None:
+        """B-CoMM block update(s) of a Tucker model in place (-1 core, n factor, -2 sweep)."""
+        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x)
+        _check(self._lib.comm_tucker_update(self._h, ctypes.byref(d), ctypes.byref(m), int(block),
+                                            ctypes.byref(o), _stream(stream)))
+
+    def jcomm_outer(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
+                    eps_x: Optional[float] = None, cache_pq: bool = False, obj_out=None, stream=None) -> None:
+        """One J-CoMM outer iteration in place; F(reference) into obj_out[0] (float64) if given."""
+        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, L, cache_pq)
+        optr = None
+        if obj_out is not None:
+            import torch
+            if obj_out.dtype != torch.float64:
+                raise TypeError("obj_out must be float64")
+            optr = _ptr(obj_out, "obj_out")
+        _check(self._lib.comm_jcomm_outer(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), optr,
+                                          _stream(stream)))
+
+    def beta_objective(self, X, factors, core=None, beta: float = 1.0, eps: float = 1e-12,
+                       eps_x: Optional[float] = None, out=None, stream=None):
+        """D_beta(X, Xhat) in float64, written to out[0] (allocated if None)."""
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=X.device)
+        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x)
+        _check(self._lib.comm_beta_objective(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o),
+                                             _ptr(out, "out"), _stream(stream)))
+        return out
+
+    def cp_jcomm_outer_coo(self, idx: Sequence, val, dims: Sequence[int], factors, L: int = 1,
+                           eps: float = 1e-12, obj_out=None, stream=None) -> None:
+        """One beta = 1 J-CoMM outer iteration on COO data (idx: per-mode int32 tensors)."""
+        import torch
+        c = Coo()
+        c.ndim = len(dims)
+        for n, dn in enumerate(dims):
+            c.dims[n] = int(dn)
+        c.nnz = int(val.numel())
+        for n, ix in enumerate(idx):
+            if ix.dtype != torch.int32:
+                raise TypeError("idx must be int32")
+            c.idx[n] = _ptr(ix, f"idx[{n}]")
+        c.val = _f32(val, "val")
+        m, o = _model(factors), _opts(1.0, eps, None, L)
+        optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
+        _check(self._lib.comm_cp_jcomm_outer_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o), optr,
+                                                 _stream(stream)))
+
+
+_default_ctx = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def cp_update(X, factors, block=-1, beta=1.0, eps=1e-12, eps_x=None, stream=None):
+    default_context().cp_update(X, factors, block, beta, eps, eps_x, stream)
+
+
+def tucker_update(X, core, factors, block=-2, beta=1.0, eps=1e-12, eps_x=None, stream=None):
+    default_context().tucker_update(X, core, factors, block, beta, eps, eps_x, stream)
+
+
+def jcomm_outer(X, factors, core=None, beta=1.0, L=1, eps=1e-12, eps_x=None, cache_pq=False, obj_out=None,
+                stream=None):
+    default_context().jcomm_outer(X, factors, core, beta, L, eps, eps_x, cache_pq, obj_out, stream)
+
+
+def beta_objective(X, factors, core=None, beta=1.0, eps=1e-12, eps_x=None, out=None, stream=None):
+    return default_context().beta_objective(X, factors, core, beta, eps, eps_x, out, stream)
+
+
+def cp_jcomm_outer_coo(idx, val, dims, factors, L=1, eps=1e-12, obj_out=None, stream=None):
+    default_context().cp_jcomm_outer_coo(idx, val, dims, factors, L, eps, obj_out, stream)

@@ -1,0 +1,583 @@
+// C ABI entry points: argument validation, workspace management and the
+// orchestration of B-CoMM and J-CoMM out of the kernels in cp3.hip,
+// tucker3.hip, sparse.hip and kernels_small.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/comm.h"
+#include "kernels.h"
+#include "tucker3.h"
+#include "sparse.h"
+
+using namespace comm;
+
+struct comm_ctx {
+  int device = 0;
+  size_t limit = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(COMM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// Bump allocator over the context workspace (256-byte aligned pieces).
+struct Carve {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int ensure_ws(comm_ctx* ctx, size_t bytes, hipStream_t stream) {
+  if (bytes <= ctx->ws_bytes) return COMM_OK;
+  if (ctx->limit && bytes > ctx->limit)
+    return fail(COMM_ENOMEM, "workspace of %zu bytes exceeds the context limit of %zu", bytes, ctx->limit);
+  if (ctx->ws) {
+    HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  if (ctx->limit && want > ctx->limit) want = ctx->limit;
+  hipError_t e = hipMalloc(&ctx->ws, want);
+  if (e != hipSuccess) return fail(COMM_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+  ctx->ws_bytes = want;
+  return COMM_OK;
+}
+
+int beta_class_of(double beta) {
+  if (beta == 0.0) return kIS;
+  if (beta == 0.5) return kHalf;
+  if (beta == 1.0) return kKL;
+  if (beta == 1.5) return kThreeHalf;
+  return kGeneral;
+}
+
+BetaConst make_beta_const(double beta) {
+  BetaConst bc = {};
+  bc.beta = (float)beta;
+  bc.inv_bb1 = (beta != 0.0 && beta != 1.0) ? (float)(1.0 / (beta * (beta - 1.0))) : 0.0f;
+  bc.inv_beta = beta > 0.0 ? (float)(1.0 / beta) : 0.0f;
+  // c_k = (beta^(k-1) - (beta-1)^(k-1)) / k!, k = 2..17
+  double fact = 1.0;
+  for (int k = 1; k <= 17; ++k) {
+    fact *= k;
+    if (k >= 2) bc.series[k - 2] = (float)((std::pow(beta, k - 1) - std::pow(beta - 1.0, k - 1)) / fact);
+  }
+  return bc;
+}
+
+float gamma_of(double beta) { return beta < 1.0 ? (float)(1.0 / (2.0 - beta)) : 1.0f; }
+
+int check_opts(const comm_opts* o, bool need_L) {
+  if (!o) return fail(COMM_EINVAL, "opts is NULL");
+  if (!(o->beta >= 0.0 && o->beta < 2.0)) return fail(COMM_EINVAL, "beta = %g outside [0, 2)", o->beta);
+  if (!(o->eps > 0.0)) return fail(COMM_EINVAL, "eps must be > 0");
+  if (o->beta == 0.0 && !(o->eps_x > 0.0)) return fail(COMM_EINVAL, "eps_x must be > 0 at beta = 0");
+  if (need_L && o->inner_sweeps < 1) return fail(COMM_EINVAL, "inner_sweeps must be >= 1");
+  if (o->precision != COMM_FP32) return fail(COMM_EUNSUPPORTED, "precision %d not supported", o->precision);
+  return COMM_OK;
+}
+
+int check_dense(const comm_dense* x) {
+  if (!x) return fail(COMM_EINVAL, "x is NULL");
+  if (!x->X) return fail(COMM_EINVAL, "x->X is NULL");
+  if (x->ndim < 1 || x->ndim > 4) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
+  for (int n = 0; n < x->ndim; ++n)
+    if (x->dims[n] < 1 || x->dims[n] > (1 << 24)) return fail(COMM_EINVAL, "dims[%d] = %lld", n, (long long)x->dims[n]);
+  if (x->ndim != 3) return fail(COMM_EUNSUPPORTED, "dense tensors of order %d are not supported (3 only)", x->ndim);
+  return COMM_OK;
+}
+
+int check_cp_model(const comm_model* m, int ndim) {
+  if (!m) return fail(COMM_EINVAL, "model is NULL");
+  if (m->kind != COMM_CP) return fail(COMM_EINVAL, "model kind is not CP");
+  if (m->rank < 1) return fail(COMM_EINVAL, "rank = %d", m->rank);
+  if (m->rank > kRP) return fail(COMM_EUNSUPPORTED, "rank %d > %d not supported", m->rank, kRP);
+  for (int n = 0; n < ndim; ++n)
+    if (!m->factors[n]) return fail(COMM_EINVAL, "factors[%d] is NULL", n);
+  return COMM_OK;
+}
+
+// ---------------------------------------------------------------------------------------- CP dense
+
+struct FactorSet {
+  float* pad[3];   // [rows_p][32]
+  float* padT[3];  // [32][rows_p]
+};
+
+struct CpWs {
+  CpGrid g;
+  int dims[3], rows_p[3];
+  FactorSet ref, cur, num, den;
+  float *m3n, *m1n, *m2n, *m3d, *m1d, *m2d;
+  double* obj_part;
+  float* c[3];
+  float* dprod;
+  float *Pc, *Qc;
+  size_t bytes;
+};
+
+void carve_set(Carve& cv, FactorSet& s, const int* rows_p) {
+  for (int n = 0; n < 3; ++n) {
+    s.pad[n] = cv.take<float>((size_t)rows_p[n] * kRP);
+    s.padT[n] = cv.take<float>((size_t)rows_p[n] * kRP);
+  }
+}
+
+CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
+  CpWs w = {};
+  for (int n = 0; n < 3; ++n) w.dims[n] = (int)x->dims[n];
+  w.g = cp_grid(w.dims[0], w.dims[1], w.dims[2]);
+  w.rows_p[0] = w.g.Ip;
+  w.rows_p[1] = w.g.Jp;
+  w.rows_p[2] = w.g.Kp;
+  Carve cv;
+  cv.base = base;
+  carve_set(cv, w.ref, w.rows_p);
+  carve_set(cv, w.cur, w.rows_p);
+  carve_set(cv, w.num, w.rows_p);
+  carve_set(cv, w.den, w.rows_p);
+  const CpGrid& g = w.g;
+  w.m3n = cv.take<float>((size_t)g.m3_slots() * g.Kp * kRP);
+  w.m1n = cv.take<float>((size_t)g.m1_slots() * g.Ip * kRP);
+  w.m2n = cv.take<float>((size_t)g.m2_slots() * g.Jp * kRP);
+  w.m3d = cv.take<float>((size_t)g.m3_slots() * g.Kp * kRP);
+  w.m1d = cv.take<float>((size_t)g.m1_slots() * g.Ip * kRP);
+  w.m2d = cv.take<float>((size_t)g.m2_slots() * g.Jp * kRP);
+  w.obj_part = cv.take<double>((size_t)g.wgs());
+  for (int n = 0; n < 3; ++n) w.c[n] = cv.take<float>((size_t)w.rows_p[n] * kRP);
+  w.dprod = cv.take<float>(kRP);
+  if (cache) {
+    const size_t total = (size_t)w.dims[0] * w.dims[1] * w.dims[2];
+    w.Pc = cv.take<float>(total);
+    w.Qc = cv.take<float>(total);
+  }
+  w.bytes = cv.off + 256;
+  return w;
+}
+
+CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
+  CpPassArgs a = {};
+  a.X = x->X;
+  a.I = w.dims[0];
+  a.J = w.dims[1];
+  a.K = w.dims[2];
+  a.Ip = w.g.Ip;
+  a.Jp = w.g.Jp;
+  a.Kp = w.g.Kp;
+  a.eps = (float)o->eps;
+  a.eps_x = (float)o->eps_x;
+  a.bc = make_beta_const(o->beta);
+  a.m3n = w.m3n; a.m1n = w.m1n; a.m2n = w.m2n;
+  a.m3d = w.m3d; a.m1d = w.m1d; a.m2d = w.m2d;
+  a.obj_part = w.obj_part;
+  return a;
+}
+
+void set_rebuild(CpPassArgs& a, const FactorSet& s) {
+  a.Ar = s.pad[0]; a.Br = s.pad[1]; a.Cr = s.pad[2];
+}
+void set_num(CpPassArgs& a, const FactorSet& s) {
+  a.An = s.pad[0]; a.Bn = s.pad[1]; a.Ctn = s.padT[2];
+}
+void set_den(CpPassArgs& a, const FactorSet& s) {
+  a.Ad = s.pad[0]; a.Bd = s.pad[1]; a.Ctd = s.padT[2];
+}
+
+int pad_user(const comm_model* m, const CpWs& w, const FactorSet& s, hipStream_t st) {
+  for (int n = 0; n < 3; ++n)
+    HIP_TRY(launch_pad_factor(m->factors[n], w.dims[n], m->rank, m->rank, w.rows_p[n], s.pad[n], s.padT[n], st));
+  return COMM_OK;
+}
+
+// Partial-slot view of mode n.
+void slots_of(const CpWs& w, int n, bool den, const float** part, int* slots, int* rows_total) {
+  const CpGrid& g = w.g;
+  if (n == 0) { *part = den ? w.m1d : w.m1n; *slots = g.m1_slots(); *rows_total = g.Ip; }
+  else if (n == 1) { *part = den ? w.m2d : w.m2n; *slots = g.m2_slots(); *rows_total = g.Jp; }
+  else { *part = den ? w.m3d : w.m3n; *slots = g.m3_slots(); *rows_total = g.Kp; }
+}
+
+// One block update of mode n from the partial slots just written by a pass.
+int cp_apply_update(const comm_model* m, const CpWs& w, int n, const float* anchor, bool closed_den,
+                    const FactorSet& cur, float gamma, float eps, hipStream_t st) {
+  UpdateArgs u = {};
+  slots_of(w, n, false, &u.num_part, &u.num_slots, &u.rows_total);
+  if (closed_den) {
+    const float* F[2];
+    int rows[2], k = 0;
+    for (int q = 0; q < 3; ++q)
+      if (q != n) { F[k] = cur.pad[q]; rows[k] = w.dims[q]; ++k; }
+    HIP_TRY(launch_colsum_prod(F, rows, 2, w.dprod, st));
+    u.den_closed = w.dprod;
+  } else {
+    int rt;
+    slots_of(w, n, true, &u.den_part, &u.den_slots, &rt);
+  }
+  u.rows = w.dims[n];
+  u.cols = m->rank;
+  u.anchor = anchor;
+  u.gamma = gamma;
+  u.eps = eps;
+  u.out_pad = cur.pad[n];
+  u.out_padT = cur.padT[n];
+  u.rows_p = w.rows_p[n];
+  u.out_user = m->factors[n];
+  u.ld_user = m->rank;
+  HIP_TRY(launch_update(u, st));
+  return COMM_OK;
+}
+
+int cp_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
+  CpWs w = cp_layout(x, nullptr, false);
+  int rc = ensure_ws(ctx, w.bytes, st);
+  if (rc) return rc;
+  w = cp_layout(x, ctx->ws, false);
+  rc = pad_user(m, w, w.cur, st);
+  if (rc) return rc;
+  const bool kl = o->beta == 1.0;
+  const int bc = beta_class_of(o->beta);
+  const int first = block < 0 ? 0 : block, last = block < 0 ? 2 : block;
+  for (int n = first; n <= last; ++n) {
+    CpPassArgs a = base_pass(x, w, o);
+    set_rebuild(a, w.cur);
+    set_num(a, w.cur);
+    set_den(a, w.cur);
+    a.want_v = n < 2;
+    a.want_m3 = n == 2;
+    HIP_TRY(launch_cp_pass(a, w.g, bc, !kl, st));
+    rc = cp_apply_update(m, w, n, w.cur.pad[n], kl, w.cur, gamma_of(o->beta), (float)o->eps, st);
+    if (rc) return rc;
+  }
+  return COMM_OK;
+}
+
+int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+  const bool kl = o->beta == 1.0;
+  const bool cache = !kl && o->cache_pq;
+  CpWs w = cp_layout(x, nullptr, cache);
+  int rc = ensure_ws(ctx, w.bytes, st);
+  if (rc) return rc;
+  w = cp_layout(x, ctx->ws, cache);
+  rc = pad_user(m, w, w.ref, st);
+  if (rc) return rc;
+  const int bc = beta_class_of(o->beta);
+  const float eps = (float)o->eps;
+
+  if (kl) {
+    // Reference pass: Xhat~, P~ = X / Xhat~, all three numerators against
+    // chi_1 = A~, the objective at the reference.
+    CpPassArgs a = base_pass(x, w, o);
+    set_rebuild(a, w.ref);
+    set_num(a, w.ref);
+    a.want_v = 1;
+    a.want_m3 = 1;
+    a.want_obj = obj != nullptr;
+    HIP_TRY(launch_cp_pass(a, w.g, bc, false, st));
+    if (obj) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+    KlLoopArgs k = {};
+    k.N = 3;
+    k.R = m->rank;
+    k.L = o->inner_sweeps;
+    k.eps = eps;
+    for (int n = 0; n < 3; ++n) {
+      const float* part;
+      int slots, rows_total;
+      slots_of(w, n, false, &part, &slots, &rows_total);
+      HIP_TRY(launch_scale_reduce(part, slots, rows_total, w.dims[n], m->rank, w.ref.pad[n], w.rows_p[n], w.c[n], st));
+      k.c[n] = w.c[n];
+      k.ref[n] = w.ref.pad[n];
+      k.rows[n] = w.dims[n];
+      k.rows_p[n] = w.rows_p[n];
+      k.cur_pad[n] = w.cur.pad[n];
+      k.cur_padT[n] = nullptr;
+      k.user[n] = m->factors[n];
+    }
+    HIP_TRY(launch_kl_loop(k, st));
+    return COMM_OK;
+  }
+
+  // beta != 1: current inner iterate starts at the reference.
+  for (int n = 0; n < 3; ++n) {
+    HIP_TRY(hipMemcpyAsync(w.cur.pad[n], w.ref.pad[n], (size_t)w.rows_p[n] * kRP * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.cur.padT[n], w.ref.padT[n], (size_t)w.rows_p[n] * kRP * 4, hipMemcpyDeviceToDevice, st));
+  }
+  bool obj_pending = obj != nullptr;
+  if (cache) {
+    CpPassArgs a = base_pass(x, w, o);
+    set_rebuild(a, w.ref);
+    set_num(a, w.ref);
+    a.cache_mode = 1;
+    a.Pw = w.Pc;
+    a.Qw = w.Qc;
+    a.want_obj = obj_pending;
+    HIP_TRY(launch_cp_pass(a, w.g, bc, false, st));
+    if (obj_pending) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+    obj_pending = false;
+  }
+  for (int l = 0; l < o->inner_sweeps; ++l) {
+    for (int n = 0; n < 3; ++n) {
+      for (int q = 0; q < 3; ++q) {
+        if (q == n) continue;
+        HIP_TRY(launch_chi(w.cur.pad[q], w.ref.pad[q], w.rows_p[q], (float)o->beta, w.num.pad[q], w.den.pad[q],
+                           q == 2 ? w.num.padT[q] : nullptr, q == 2 ? w.den.padT[q] : nullptr, st));
+      }
+      CpPassArgs a = base_pass(x, w, o);
+      set_rebuild(a, w.ref);
+      set_num(a, w.num);
+      set_den(a, w.den);
+      if (n == 2) {  // mode 3 contracts with modes 1 and 2 only; the C operand is unused
+        a.Ctn = w.ref.padT[2];
+        a.Ctd = w.ref.padT[2];
+      } else if (n == 0) {
+        a.An = w.ref.pad[0];  // A rows are read but do not enter the mode-1 result
+        a.Ad = w.ref.pad[0];
+      } else {
+        a.Bn = w.ref.pad[1];
+        a.Bd = w.ref.pad[1];
+      }
+      a.want_v = n < 2;
+      a.want_m3 = n == 2;
+      if (cache) {
+        a.cache_mode = 2;
+        a.Pc = w.Pc;
+        a.Qc = w.Qc;
+      } else {
+        a.want_obj = obj_pending;
+      }
+      HIP_TRY(launch_cp_pass(a, w.g, bc, true, st));
+      if (obj_pending) {
+        HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+        obj_pending = false;
+      }
+      rc = cp_apply_update(m, w, n, w.ref.pad[n], false, w.cur, gamma_of(o->beta), eps, st);
+      if (rc) return rc;
+    }
+  }
+  return COMM_OK;
+}
+
+int cp_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
+                 hipStream_t st) {
+  CpWs w = cp_layout(x, nullptr, false);
+  int rc = ensure_ws(ctx, w.bytes, st);
+  if (rc) return rc;
+  w = cp_layout(x, ctx->ws, false);
+  rc = pad_user(m, w, w.cur, st);
+  if (rc) return rc;
+  CpPassArgs a = base_pass(x, w, o);
+  set_rebuild(a, w.cur);
+  set_num(a, w.cur);
+  a.want_obj = 1;
+  HIP_TRY(launch_cp_pass(a, w.g, beta_class_of(o->beta), false, st));
+  HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, out, st));
+  return COMM_OK;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::exception& e) {
+    return fail(COMM_EHIP, "internal error: %s", e.what());
+  } catch (...) {
+    return fail(COMM_EHIP, "internal error");
+  }
+}
+
+int set_device(comm_ctx* ctx) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  return COMM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* comm_last_error(void) { return g_last_error.c_str(); }
+
+int comm_create(int device, size_t workspace_limit_bytes, comm_ctx** out) {
+  return guarded([&]() -> int {
+    if (!out) return fail(COMM_EINVAL, "out is NULL");
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(COMM_EINVAL, "device %d of %d", device, count);
+    comm_ctx* c = new comm_ctx();
+    c->device = device;
+    c->limit = workspace_limit_bytes;
+    *out = c;
+    return COMM_OK;
+  });
+}
+
+int comm_destroy(comm_ctx* ctx) {
+  return guarded([&]() -> int {
+    if (!ctx) return COMM_OK;
+    int rc = COMM_OK;
+    if (ctx->ws) {
+      hipSetDevice(ctx->device);
+      hipStreamSynchronize(ctx->last_stream);
+      hipError_t e = hipFree(ctx->ws);
+      if (e != hipSuccess) rc = fail(COMM_EHIP, "hipFree: %s", hipGetErrorString(e));
+    }
+    delete ctx;
+    return rc;
+  });
+}
+
+size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op) {
+  if (check_dense(x) || !model || !opts) return 0;
+  if (model->kind == COMM_CP) {
+    const bool cache = op == 1 && opts->beta != 1.0 && opts->cache_pq;
+    return cp_layout(x, nullptr, cache).bytes;
+  }
+  return tucker_workspace_bytes(x, model, opts, op);
+}
+
+int comm_cp_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int block, const comm_opts* opts,
+                   void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_opts(opts, false);
+    if (!rc) rc = check_dense(x);
+    if (!rc) rc = check_cp_model(model, x->ndim);
+    if (rc) return rc;
+    if (block < -1 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = cp_bcomm(ctx, x, model, block, opts, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
+                     double* obj_ref_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_opts(opts, true);
+    if (!rc) rc = check_dense(x);
+    if (rc) return rc;
+    if (!model) return fail(COMM_EINVAL, "model is NULL");
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (model->kind == COMM_CP) {
+      if ((rc = check_cp_model(model, x->ndim))) return rc;
+      rc = cp_jcomm(ctx, x, model, opts, obj_ref_dev, st);
+    } else if (model->kind == COMM_TUCKER) {
+      if ((rc = tucker_check_model(model, x))) return rc;
+      rc = tucker_jcomm(ctx, x, model, opts, obj_ref_dev, st);
+    } else {
+      return fail(COMM_EINVAL, "model kind %d", model->kind);
+    }
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts,
+                        double* out_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (!out_dev) return fail(COMM_EINVAL, "out_dev is NULL");
+    int rc = check_opts(opts, false);
+    if (!rc) rc = check_dense(x);
+    if (rc) return rc;
+    if (!model) return fail(COMM_EINVAL, "model is NULL");
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (model->kind == COMM_CP) {
+      if ((rc = check_cp_model(model, x->ndim))) return rc;
+      rc = cp_objective(ctx, x, model, opts, out_dev, st);
+    } else if (model->kind == COMM_TUCKER) {
+      if ((rc = tucker_check_model(model, x))) return rc;
+      rc = tucker_objective(ctx, x, model, opts, out_dev, st);
+    } else {
+      return fail(COMM_EINVAL, "model kind %d", model->kind);
+    }
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int block, const comm_opts* opts,
+                       void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_opts(opts, false);
+    if (!rc) rc = check_dense(x);
+    if (!rc) rc = tucker_check_model(model, x);
+    if (rc) return rc;
+    if (block < -2 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = tucker_bcomm(ctx, x, model, block, opts, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
+                            double* obj_ref_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_opts(opts, true);
+    if (rc) return rc;
+    if (opts->beta != 1.0) return fail(COMM_EUNSUPPORTED, "sparse COO path requires beta = 1");
+    if (!x) return fail(COMM_EINVAL, "x is NULL");
+    if (x->ndim < 2 || x->ndim > 4) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
+    if (!model || model->kind != COMM_CP) return fail(COMM_EINVAL, "model must be CP");
+    if (model->rank < 1) return fail(COMM_EINVAL, "rank = %d", model->rank);
+    if (model->rank > kRP) return fail(COMM_EUNSUPPORTED, "rank %d > %d", model->rank, kRP);
+    for (int n = 0; n < x->ndim; ++n) {
+      if (x->dims[n] < 1 || x->dims[n] > (1 << 24)) return fail(COMM_EINVAL, "dims[%d]", n);
+      if (!model->factors[n]) return fail(COMM_EINVAL, "factors[%d] is NULL", n);
+      if (x->nnz > 0 && !x->idx[n]) return fail(COMM_EINVAL, "idx[%d] is NULL", n);
+    }
+    if (x->nnz < 0) return fail(COMM_EINVAL, "nnz < 0");
+    if (x->nnz > 0 && !x->val) return fail(COMM_EINVAL, "val is NULL");
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = coo_jcomm_kl(ctx, x, model, opts, obj_ref_dev, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+}  // extern "C"

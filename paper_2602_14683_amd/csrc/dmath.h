@@ -1,0 +1,117 @@
+// Device-side scalar math shared by the dense and sparse kernels: the power
+// step that forms the weights P = X * Xhat^(beta-2), Q = Xhat^(beta-1)
+// (Sec. 4.1 and the reference-powered tensors of Sec. 5.3) and a
+// cancellation-free evaluation of the beta-divergence term d_beta(x | y)
+// (Sec. 3.2, Definition of the beta-divergence).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace comm {
+
+// beta classes with dedicated fast paths; everything else is kGeneral.
+enum BetaClass : int { kIS = 0, kHalf = 1, kKL = 2, kThreeHalf = 3, kGeneral = 4 };
+
+constexpr int kSeriesTerms = 16;  // h(u) series terms u^2 .. u^17
+
+// Per-call constants of the beta-divergence term.
+struct BetaConst {
+  float beta;
+  float inv_bb1;                 // 1 / (beta (beta - 1)) for beta not in {0, 1}
+  float inv_beta;                // 1 / beta (beta > 0)
+  float series[kSeriesTerms];    // c_k, k = 2..17, see dbeta_term
+};
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Weights for one entry: x is the data value (already floored at eps_x when
+// beta = 0), y = max(Xhat, eps).  Returns P in p and Q in q.
+template <int BC>
+__device__ __forceinline__ void weights(float x, float y, float beta, float& p, float& q) {
+  if constexpr (BC == kIS) {
+    float r = fast_rcp(y);
+    q = r;
+    p = x * r * r;
+  } else if constexpr (BC == kHalf) {
+    float rs = fast_rsq(y);
+    q = rs;
+    p = x * rs * rs * rs;
+  } else if constexpr (BC == kKL) {
+    q = 1.0f;
+    p = x * fast_rcp(y);
+  } else if constexpr (BC == kThreeHalf) {
+    q = fast_sqrt(y);
+    p = x * fast_rsq(y);
+  } else {
+    float l = fast_log2(y);
+    q = fast_exp2((beta - 1.0f) * l);
+    p = x * fast_exp2((beta - 2.0f) * l);
+  }
+}
+
+// x^beta for x > 0.
+template <int BC>
+__device__ __forceinline__ float pow_beta(float x, float beta) {
+  if constexpr (BC == kIS) return 1.0f;
+  else if constexpr (BC == kHalf) return fast_sqrt(x);
+  else if constexpr (BC == kKL) return x;
+  else if constexpr (BC == kThreeHalf) return x * fast_sqrt(x);
+  else return fast_exp2(beta * fast_log2(x));
+}
+
+// d_beta(x | y) for x >= 0, y > 0, evaluated without catastrophic
+// cancellation.  With q = y / x and u = log q, d_beta(x | y) = x^beta h(u) where
+//   h(u) = ((beta-1) e^{beta u} - beta e^{(beta-1) u} + 1) / (beta (beta-1))
+//        = sum_{k>=2} (beta^{k-1} - (beta-1)^{k-1}) u^k / k!
+// (expanding both exponentials; beta = 1 gives e^u - 1 - u and beta = 0 gives
+// e^{-u} - 1 + u, the KL and IS branches).  For |u| < 1 the series is summed by
+// Horner (16 terms, truncation below 1e-11 relative for beta < 2); elsewhere
+// the closed form loses at most a few bits.  For |q - 1| < 0.29 the logarithm
+// is taken as 2 atanh(t / (2 + t)), t = q - 1, which keeps u accurate near 0.
+// At x = 0: d = y (beta = 1) or y^beta / beta (beta > 0).
+template <int BC>
+__device__ __forceinline__ float dbeta_term(float x, float y, const BetaConst& bc) {
+  if (!(x > 0.0f)) {
+    if constexpr (BC == kKL) return y;
+    else return pow_beta<BC>(y, bc.beta) * bc.inv_beta;
+  }
+  const float rx = fast_rcp(x);
+  const float t = (y - x) * rx;
+  const float q = y * rx;
+  float u;
+  if (fabsf(t) < 0.29f) {
+    float s = t * fast_rcp(2.0f + t);
+    float s2 = s * s;
+    float a = fmaf(s2, 1.0f / 9.0f, 1.0f / 7.0f);
+    a = fmaf(s2, a, 1.0f / 5.0f);
+    a = fmaf(s2, a, 1.0f / 3.0f);
+    a = fmaf(s2, a, 1.0f);
+    u = 2.0f * s * a;
+  } else {
+    u = fast_log2(q) * 0.69314718055994531f;
+  }
+  float h;
+  if (fabsf(u) < 1.0f) {
+    float acc = bc.series[kSeriesTerms - 1];
+#pragma unroll
+    for (int k = kSeriesTerms - 2; k >= 0; --k) acc = fmaf(acc, u, bc.series[k]);
+    h = acc * u * u;
+  } else {
+    if constexpr (BC == kKL) {
+      h = (q - 1.0f) - u;
+    } else if constexpr (BC == kIS) {
+      h = (fast_rcp(q) - 1.0f) + u;
+    } else {
+      float qb = fast_exp2(bc.beta * u * 1.4426950408889634f);
+      float qb1 = qb * fast_rcp(q);
+      h = ((bc.beta - 1.0f) * qb - bc.beta * qb1 + 1.0f) * bc.inv_bb1;
+    }
+  }
+  return pow_beta<BC>(x, bc.beta) * h;
+}
+
+}  // namespace comm

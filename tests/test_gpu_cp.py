@@ -1,0 +1,194 @@
+"""GPU parity of the dense CP path against the FP64 oracle, through the C ABI.
+
+Inputs are float32 on the GPU; the oracle runs in float64 on the same float32
+values.  Bars (FP32 path): 1e-5 relative per factor entry after one update,
+1e-4 relative on every entry of an objective trace."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cp as ocp
+from oracle.divergence import objective as oobjective
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2602_14683_amd as comm  # noqa: E402
+from tests.gpu_util import dev, f32, host64, max_rel  # noqa: E402
+
+BETAS = [0.0, 0.5, 1.0, 1.5, 0.7, 1.3]
+SHAPES = [((30, 40, 50), 5), ((37, 70, 90), 32), ((16, 32, 64), 8)]
+TOL_UPDATE = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = comm.Context(0)
+    yield c
+    c.close()
+
+
+def _problem(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    planted = [rng.uniform(0.0, 1.0, size=(d, R)) for d in dims]
+    X = rng.poisson(ocp.rebuild(planted) * 4.0).astype(np.float64)
+    init = [f32(rng.uniform(0.1, 1.0, size=(d, R))) for d in dims]
+    return X, init
+
+
+def _xf(X, beta):
+    return np.maximum(X, 1e-12) if beta == 0.0 else X
+
+
+@pytest.mark.parametrize("dims,R", SHAPES)
+@pytest.mark.parametrize("beta", BETAS)
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_cp_block_update_matches_oracle(ctx, dims, R, beta, n):
+    X, init = _problem(dims, R, 1)
+    Xd = dev(X)
+    fac = [dev(a) for a in init]
+    ctx.cp_update(Xd, fac, block=n, beta=beta)
+    torch.cuda.synchronize()
+    want = ocp.block_update(X, init, n, beta)
+    assert max_rel(host64(fac[n]), want) < TOL_UPDATE
+    for m in range(3):
+        if m != n:
+            assert np.array_equal(host64(fac[m]), init[m])
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 1.5])
+def test_cp_bcomm_sweep_matches_oracle(ctx, beta):
+    X, init = _problem((37, 70, 90), 32, 2)
+    fac = [dev(a) for a in init]
+    ctx.cp_update(dev(X), fac, block=-1, beta=beta)
+    torch.cuda.synchronize()
+    want = ocp.bcomm_sweep(X, init, beta)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < 3 * TOL_UPDATE
+
+
+@pytest.mark.parametrize("dims,R", SHAPES)
+@pytest.mark.parametrize("beta", BETAS)
+@pytest.mark.parametrize("L", [1, 3])
+@pytest.mark.parametrize("cache", [False, True])
+def test_cp_jcomm_outer_matches_oracle(ctx, dims, R, beta, L, cache):
+    if cache and beta == 1.0:
+        pytest.skip("beta = 1 never caches P~ / Q~")
+    X, init = _problem(dims, R, 3)
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(dev(X), fac, beta=beta, L=L, cache_pq=cache, obj_out=obj)
+    torch.cuda.synchronize()
+    want, fref = ocp.jcomm_outer(X, init, beta, L=L, return_ref_obj=True)
+    tol = TOL_UPDATE * (1 if L == 1 else 3)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < tol
+    assert abs(obj.item() - fref) / fref < 1e-5
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_beta_objective_matches_oracle(ctx, beta):
+    X, init = _problem((37, 70, 90), 32, 4)
+    out = ctx.beta_objective(dev(X), [dev(a) for a in init], beta=beta)
+    torch.cuda.synchronize()
+    want = oobjective(X, ocp.rebuild(init), beta)
+    assert abs(out.item() - want) / want < 1e-5
+
+
+def test_objective_trace_config1(ctx):
+    """30x40x50 Poisson tensor, rank 5, beta = 1, B-CoMM, 100 iterations: every
+    entry of the GPU objective trace within 1e-4 of the oracle's."""
+    d = workloads.cp_small(0)
+    init = [f32(a) for a in d.init]
+    _, want = ocp.run(d.X, init, 1.0, 100, method="bcomm")
+    Xd = dev(d.X)
+    fac = [dev(a) for a in init]
+    got = []
+    for t in range(101):
+        got.append(ctx.beta_objective(Xd, fac, beta=1.0).item())
+        if t < 100:
+            ctx.cp_update(Xd, fac, block=-1, beta=1.0)
+    torch.cuda.synchronize()
+    assert max_rel(got, want) < 1e-4
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.5])
+def test_jcomm_objective_trace(ctx, beta):
+    d = workloads.cp_dense(0, dims=(40, 48, 56), rank=8)
+    init = [f32(a) for a in d.init]
+    _, want = ocp.run(d.X, init, beta, 30, method="jcomm", L=2)
+    Xd = dev(d.X)
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    got = []
+    for t in range(30):
+        ctx.jcomm_outer(Xd, fac, beta=beta, L=2, obj_out=obj)
+        got.append(obj.item())
+    got.append(ctx.beta_objective(Xd, fac, beta=beta).item())
+    assert max_rel(got, want) < 1e-4
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(got, got[1:]))
+
+
+def test_deterministic_bitwise(ctx):
+    X, init = _problem((37, 70, 90), 32, 5)
+    outs = []
+    for _ in range(2):
+        fac = [dev(a) for a in init]
+        obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.jcomm_outer(dev(X), fac, beta=0.5, L=2, obj_out=obj)
+        outs.append([host64(a) for a in fac] + [obj.item()])
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_full_size_headline_jcomm_kl(ctx):
+    """256^3, rank 32, beta = 1, L = 5 (the measured workload): one outer
+    iteration, every factor entry against the oracle."""
+    d = workloads.cp_dense(0)
+    init = [f32(a) for a in d.init]
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(dev(d.X), fac, beta=1.0, L=5, obj_out=obj)
+    torch.cuda.synchronize()
+    want, fref = ocp.jcomm_outer(d.X, init, 1.0, L=5, return_ref_obj=True)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < 3 * TOL_UPDATE
+    assert abs(obj.item() - fref) / fref < 1e-5
+
+
+def test_eps_clip_row(ctx):
+    X, init = _problem((30, 40, 50), 5, 6)
+    X[3] = 0.0
+    fac = [dev(a) for a in init]
+    ctx.cp_update(dev(X), fac, block=0, beta=1.0, eps=1e-9)
+    torch.cuda.synchronize()
+    got = host64(fac[0])
+    assert np.allclose(got[3], np.float32(1e-9))
+    assert max_rel(got, ocp.block_update(X, init, 0, 1.0, eps=1e-9)) < TOL_UPDATE
+
+
+def test_invalid_arguments_leave_buffers_untouched(ctx):
+    X, init = _problem((30, 40, 50), 5, 7)
+    fac = [dev(a) for a in init]
+    Xd = dev(X)
+    for kwargs, code in [(dict(beta=2.0), comm.COMM_EINVAL), (dict(beta=-0.1), comm.COMM_EINVAL),
+                         (dict(beta=1.0, eps=0.0), comm.COMM_EINVAL)]:
+        with pytest.raises(comm.CommError) as e:
+            ctx.cp_update(Xd, fac, block=0, **kwargs)
+        assert e.value.code == code
+    with pytest.raises(comm.CommError) as e:
+        ctx.jcomm_outer(Xd, fac, beta=1.0, L=0)
+    assert e.value.code == comm.COMM_EINVAL
+    with pytest.raises(comm.CommError) as e:
+        ctx.cp_update(Xd, fac, block=3, beta=1.0)
+    assert e.value.code == comm.COMM_EINVAL
+    big = [dev(np.ones((d, 40))) for d in (30, 40, 50)]
+    with pytest.raises(comm.CommError) as e:
+        ctx.cp_update(Xd, big, block=0, beta=1.0)
+    assert e.value.code == comm.COMM_EUNSUPPORTED
+    torch.cuda.synchronize()
+    for a, b in zip(fac, init):
+        assert np.array_equal(host64(a), b)
