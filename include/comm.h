@@ -121,6 +121,15 @@ const char* comm_last_error(void);
  * 2 = beta_objective. */
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op);
 
+/* Measurement hooks.  While enabled, the context records a pair of HIP events
+ * on the call's stream around every launch of the fused dense pass kernel
+ * (the kernel that streams X).  comm_profile_query() waits for the recorded
+ * events, returns the summed kernel time in milliseconds and the number of
+ * launches since the last enable/query, and resets the record.  Enabling also
+ * resets it. */
+int comm_profile_enable(comm_ctx* ctx, int on);
+int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches);
+
 /* Block-MM (B-CoMM) update of a CP model (Theorem "CP block multiplicative
  * update"; Algorithm B-CoMM).  block in 0..N-1 updates that factor; block = -1
  * runs one full sweep over modes 1..N, rebuilding Xhat and P, Q before every

@@ -25,7 +25,8 @@ COMM_OK, COMM_EINVAL, COMM_EUNSUPPORTED, COMM_ENOMEM, COMM_EHIP = 0, 1, 2, 3, 4
 COMM_CP, COMM_TUCKER = 0, 1
 COMM_FP32 = 0
 
-EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_cp_update",
+EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_profile_enable",
+            "comm_profile_query", "comm_cp_update",
             "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo"]
 
 
@@ -81,7 +82,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                         ctypes.c_void_p]
     lib.comm_cp_jcomm_outer_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
                                             ctypes.c_void_p]
-    for name in ["comm_create", "comm_destroy", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
+    lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
+    for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
                  "comm_beta_objective", "comm_cp_jcomm_outer_coo"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -180,6 +183,18 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+    # ---------------------------------------------------------------- measurement
+
+    def profile_enable(self, on: bool = True) -> None:
+        _check(self._lib.comm_profile_enable(self._h, 1 if on else 0))
+
+    def profile_query(self):
+        """(total kernel milliseconds, launches) of the fused dense pass since enable / last query."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self._lib.comm_profile_query(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     # ---------------------------------------------------------------- entry points
 

@@ -24,6 +24,10 @@ struct comm_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t last_stream = nullptr;
+  // measurement: event pairs around every fused dense pass launch
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
 };
 
 namespace {
@@ -134,9 +138,9 @@ int check_cp_model(const comm_model* m, int ndim) {
 
 // ---------------------------------------------------------------------------------------- CP dense
 
+// Padded workspace copies of three factors, [rows_p][32].
 struct FactorSet {
-  float* pad[3];   // [rows_p][32]
-  float* padT[3];  // [32][rows_p]
+  float* pad[3];
 };
 
 struct CpWs {
@@ -146,17 +150,11 @@ struct CpWs {
   float *m3n, *m1n, *m2n, *m3d, *m1d, *m2d;
   double* obj_part;
   float* c[3];
+  float* stats[3];
   float* dprod;
   float *Pc, *Qc;
   size_t bytes;
 };
-
-void carve_set(Carve& cv, FactorSet& s, const int* rows_p) {
-  for (int n = 0; n < 3; ++n) {
-    s.pad[n] = cv.take<float>((size_t)rows_p[n] * kRP);
-    s.padT[n] = cv.take<float>((size_t)rows_p[n] * kRP);
-  }
-}
 
 CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
   CpWs w = {};
@@ -167,10 +165,8 @@ CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
   w.rows_p[2] = w.g.Kp;
   Carve cv;
   cv.base = base;
-  carve_set(cv, w.ref, w.rows_p);
-  carve_set(cv, w.cur, w.rows_p);
-  carve_set(cv, w.num, w.rows_p);
-  carve_set(cv, w.den, w.rows_p);
+  for (FactorSet* s : {&w.ref, &w.cur, &w.num, &w.den})
+    for (int n = 0; n < 3; ++n) s->pad[n] = cv.take<float>((size_t)w.rows_p[n] * kRP);
   const CpGrid& g = w.g;
   w.m3n = cv.take<float>((size_t)g.m3_slots() * g.Kp * kRP);
   w.m1n = cv.take<float>((size_t)g.m1_slots() * g.Ip * kRP);
@@ -179,7 +175,10 @@ CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
   w.m1d = cv.take<float>((size_t)g.m1_slots() * g.Ip * kRP);
   w.m2d = cv.take<float>((size_t)g.m2_slots() * g.Jp * kRP);
   w.obj_part = cv.take<double>((size_t)g.wgs());
-  for (int n = 0; n < 3; ++n) w.c[n] = cv.take<float>((size_t)w.rows_p[n] * kRP);
+  for (int n = 0; n < 3; ++n) {
+    w.c[n] = cv.take<float>((size_t)w.rows_p[n] * kRP);
+    w.stats[n] = cv.take<float>((size_t)((w.rows_p[n] + kSlotRows - 1) / kSlotRows) * 96);
+  }
   w.dprod = cv.take<float>(kRP);
   if (cache) {
     const size_t total = (size_t)w.dims[0] * w.dims[1] * w.dims[2];
@@ -189,6 +188,31 @@ CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
   w.bytes = cv.off + 256;
   return w;
 }
+
+// Launch a fused dense pass, bracketed by timing events when profiling is on.
+int run_pass(comm_ctx* ctx, const CpPassArgs& a, const CpGrid& g, int bc, bool den, hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profiling) {
+    if (ctx->events_used == ctx->events.size()) {
+      hipEvent_t a0, a1;
+      HIP_TRY(hipEventCreate(&a0));
+      HIP_TRY(hipEventCreate(&a1));
+      ctx->events.emplace_back(a0, a1);
+    }
+    e0 = ctx->events[ctx->events_used].first;
+    e1 = ctx->events[ctx->events_used].second;
+    ++ctx->events_used;
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  HIP_TRY(launch_cp_pass(a, g, bc, den, st));
+  if (e1) HIP_TRY(hipEventRecord(e1, st));
+  return COMM_OK;
+}
+
+FView user_view(const comm_model* m, int n) { return FView{m->factors[n], m->rank, m->rank}; }
+FView pad_view(const float* p) { return FView{p, kRP, kRP}; }
+FSet user_set(const comm_model* m) { return FSet{user_view(m, 0), user_view(m, 1), user_view(m, 2)}; }
+FSet pad_set(const FactorSet& s) { return FSet{pad_view(s.pad[0]), pad_view(s.pad[1]), pad_view(s.pad[2])}; }
 
 CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
   CpPassArgs a = {};
@@ -208,22 +232,6 @@ CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
   return a;
 }
 
-void set_rebuild(CpPassArgs& a, const FactorSet& s) {
-  a.Ar = s.pad[0]; a.Br = s.pad[1]; a.Cr = s.pad[2];
-}
-void set_num(CpPassArgs& a, const FactorSet& s) {
-  a.An = s.pad[0]; a.Bn = s.pad[1]; a.Ctn = s.padT[2];
-}
-void set_den(CpPassArgs& a, const FactorSet& s) {
-  a.Ad = s.pad[0]; a.Bd = s.pad[1]; a.Ctd = s.padT[2];
-}
-
-int pad_user(const comm_model* m, const CpWs& w, const FactorSet& s, hipStream_t st) {
-  for (int n = 0; n < 3; ++n)
-    HIP_TRY(launch_pad_factor(m->factors[n], w.dims[n], m->rank, m->rank, w.rows_p[n], s.pad[n], s.padT[n], st));
-  return COMM_OK;
-}
-
 // Partial-slot view of mode n.
 void slots_of(const CpWs& w, int n, bool den, const float** part, int* slots, int* rows_total) {
   const CpGrid& g = w.g;
@@ -232,33 +240,37 @@ void slots_of(const CpWs& w, int n, bool den, const float** part, int* slots, in
   else { *part = den ? w.m3d : w.m3n; *slots = g.m3_slots(); *rows_total = g.Kp; }
 }
 
-// One block update of mode n from the partial slots just written by a pass.
-int cp_apply_update(const comm_model* m, const CpWs& w, int n, const float* anchor, bool closed_den,
-                    const FactorSet& cur, float gamma, float eps, hipStream_t st) {
-  UpdateArgs u = {};
-  slots_of(w, n, false, &u.num_part, &u.num_slots, &u.rows_total);
-  if (closed_den) {
-    const float* F[2];
+// Block update of mode n from the partial slots just written by a pass:
+// max(anchor * (Num/Den)^gamma, eps), written to the caller's factor and, if
+// given, to a padded copy.  Den is either its own slots or, at beta = 1, the
+// product of the column sums of the other two factors (views `others`).
+int cp_apply_update(const comm_model* m, const CpWs& w, int n, FView anchor, const FView* closed_others,
+                    float* out_pad, float gamma, float eps, hipStream_t st) {
+  SlotUpdateArgs u = {};
+  u.njobs = 1;
+  SlotJob& J = u.job[0];
+  J.mode = kSlotUpdate;
+  slots_of(w, n, false, &J.num_part, &J.num_slots, &J.rows_total);
+  if (closed_others) {
     int rows[2], k = 0;
     for (int q = 0; q < 3; ++q)
-      if (q != n) { F[k] = cur.pad[q]; rows[k] = w.dims[q]; ++k; }
-    HIP_TRY(launch_colsum_prod(F, rows, 2, w.dprod, st));
-    u.den_closed = w.dprod;
+      if (q != n) rows[k++] = w.dims[q];
+    HIP_TRY(launch_colsum_prod(closed_others, rows, 2, w.dprod, st));
+    J.den_closed = w.dprod;
   } else {
     int rt;
-    slots_of(w, n, true, &u.den_part, &u.den_slots, &rt);
+    slots_of(w, n, true, &J.den_part, &J.den_slots, &rt);
   }
-  u.rows = w.dims[n];
-  u.cols = m->rank;
-  u.anchor = anchor;
-  u.gamma = gamma;
-  u.eps = eps;
-  u.out_pad = cur.pad[n];
-  u.out_padT = cur.padT[n];
-  u.rows_p = w.rows_p[n];
-  u.out_user = m->factors[n];
-  u.ld_user = m->rank;
-  HIP_TRY(launch_update(u, st));
+  J.rows = w.dims[n];
+  J.cols = m->rank;
+  J.rows_p = w.rows_p[n];
+  J.anchor = anchor;
+  J.gamma = gamma;
+  J.eps = eps;
+  J.out_pad = out_pad;
+  J.out_user = m->factors[n];
+  J.ld_user = m->rank;
+  HIP_TRY(launch_slot_update(u, st));
   return COMM_OK;
 }
 
@@ -267,20 +279,24 @@ int cp_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
   w = cp_layout(x, ctx->ws, false);
-  rc = pad_user(m, w, w.cur, st);
-  if (rc) return rc;
   const bool kl = o->beta == 1.0;
   const int bc = beta_class_of(o->beta);
   const int first = block < 0 ? 0 : block, last = block < 0 ? 2 : block;
+  const FSet cur = user_set(m);  // the caller's factors are the current blocks
   for (int n = first; n <= last; ++n) {
     CpPassArgs a = base_pass(x, w, o);
-    set_rebuild(a, w.cur);
-    set_num(a, w.cur);
-    set_den(a, w.cur);
+    a.r = cur;
+    a.n = cur;
+    a.d = cur;
     a.want_v = n < 2;
     a.want_m3 = n == 2;
-    HIP_TRY(launch_cp_pass(a, w.g, bc, !kl, st));
-    rc = cp_apply_update(m, w, n, w.cur.pad[n], kl, w.cur, gamma_of(o->beta), (float)o->eps, st);
+    if ((rc = run_pass(ctx, a, w.g, bc, !kl, st))) return rc;
+    FView others[2];
+    int k = 0;
+    for (int q = 0; q < 3; ++q)
+      if (q != n) others[k++] = user_view(m, q);
+    rc = cp_apply_update(m, w, n, user_view(m, n), kl ? others : nullptr, nullptr, gamma_of(o->beta),
+                         (float)o->eps, st);
     if (rc) return rc;
   }
   return COMM_OK;
@@ -293,83 +309,108 @@ int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts*
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
   w = cp_layout(x, ctx->ws, cache);
-  rc = pad_user(m, w, w.ref, st);
-  if (rc) return rc;
   const int bc = beta_class_of(o->beta);
   const float eps = (float)o->eps;
 
   if (kl) {
-    // Reference pass: Xhat~, P~ = X / Xhat~, all three numerators against
-    // chi_1 = A~, the objective at the reference.
+    // Reference pass straight from the caller's factors: Xhat~, P~ = X / Xhat~,
+    // all three numerators against chi_1 = A~, and the objective at the
+    // reference.  Then c^(n) = A~^(n) Num_J^(n) with column statistics, and the
+    // inner sweeps, which overwrite the caller's factors last.
     CpPassArgs a = base_pass(x, w, o);
-    set_rebuild(a, w.ref);
-    set_num(a, w.ref);
+    a.r = user_set(m);
+    a.n = a.r;
     a.want_v = 1;
     a.want_m3 = 1;
     a.want_obj = obj != nullptr;
-    HIP_TRY(launch_cp_pass(a, w.g, bc, false, st));
-    if (obj) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+    if ((rc = run_pass(ctx, a, w.g, bc, false, st))) return rc;
+    SlotUpdateArgs su = {};
+    su.njobs = 3;
     KlLoopArgs k = {};
     k.N = 3;
     k.R = m->rank;
     k.L = o->inner_sweeps;
     k.eps = eps;
     for (int n = 0; n < 3; ++n) {
-      const float* part;
-      int slots, rows_total;
-      slots_of(w, n, false, &part, &slots, &rows_total);
-      HIP_TRY(launch_scale_reduce(part, slots, rows_total, w.dims[n], m->rank, w.ref.pad[n], w.rows_p[n], w.c[n], st));
+      SlotJob& J = su.job[n];
+      J.mode = kSlotScale;
+      slots_of(w, n, false, &J.num_part, &J.num_slots, &J.rows_total);
+      J.rows = w.dims[n];
+      J.cols = m->rank;
+      J.rows_p = w.rows_p[n];
+      J.anchor = user_view(m, n);
+      J.out_pad = w.c[n];
+      J.stats = w.stats[n];
       k.c[n] = w.c[n];
-      k.ref[n] = w.ref.pad[n];
+      k.stats[n] = w.stats[n];
+      k.nblk[n] = (w.rows_p[n] + kSlotRows - 1) / kSlotRows;
       k.rows[n] = w.dims[n];
-      k.rows_p[n] = w.rows_p[n];
-      k.cur_pad[n] = w.cur.pad[n];
-      k.cur_padT[n] = nullptr;
+      k.cur_pad[n] = nullptr;
       k.user[n] = m->factors[n];
     }
-    HIP_TRY(launch_kl_loop(k, st));
+    if (obj) {
+      k.obj_part = w.obj_part;
+      k.obj_n = w.g.wgs();
+      k.obj_out = obj;
+    }
+    HIP_TRY(launch_slot_update(su, st));
+    HIP_TRY(launch_kl_apply(k, st));
     return COMM_OK;
   }
 
-  // beta != 1: current inner iterate starts at the reference.
-  for (int n = 0; n < 3; ++n) {
-    HIP_TRY(hipMemcpyAsync(w.cur.pad[n], w.ref.pad[n], (size_t)w.rows_p[n] * kRP * 4, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(w.cur.padT[n], w.ref.padT[n], (size_t)w.rows_p[n] * kRP * 4, hipMemcpyDeviceToDevice, st));
+  // beta != 1: padded copies of the reference (kept fixed) and of the current
+  // inner iterate (starts at the reference).
+  {
+    PadArgs p = {};
+    p.nf = 3;
+    p.cols = m->rank;
+    p.ld = m->rank;
+    for (int n = 0; n < 3; ++n) {
+      p.src[n] = m->factors[n];
+      p.rows[n] = w.dims[n];
+      p.rows_p[n] = w.rows_p[n];
+      p.dst[n] = w.ref.pad[n];
+      p.dst2[n] = w.cur.pad[n];
+    }
+    HIP_TRY(launch_pad_factors(p, st));
   }
+  const FSet ref = pad_set(w.ref);
   bool obj_pending = obj != nullptr;
   if (cache) {
     CpPassArgs a = base_pass(x, w, o);
-    set_rebuild(a, w.ref);
-    set_num(a, w.ref);
+    a.r = ref;
+    a.n = ref;
     a.cache_mode = 1;
     a.Pw = w.Pc;
     a.Qw = w.Qc;
     a.want_obj = obj_pending;
-    HIP_TRY(launch_cp_pass(a, w.g, bc, false, st));
+    if ((rc = run_pass(ctx, a, w.g, bc, false, st))) return rc;
     if (obj_pending) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
     obj_pending = false;
   }
   for (int l = 0; l < o->inner_sweeps; ++l) {
     for (int n = 0; n < 3; ++n) {
+      ChiArgs ca = {};
+      ca.beta = (float)o->beta;
       for (int q = 0; q < 3; ++q) {
         if (q == n) continue;
-        HIP_TRY(launch_chi(w.cur.pad[q], w.ref.pad[q], w.rows_p[q], (float)o->beta, w.num.pad[q], w.den.pad[q],
-                           q == 2 ? w.num.padT[q] : nullptr, q == 2 ? w.den.padT[q] : nullptr, st));
+        const int f = ca.nf++;
+        ca.cur[f] = w.cur.pad[q];
+        ca.ref[f] = w.ref.pad[q];
+        ca.rows_p[f] = w.rows_p[q];
+        ca.x1[f] = w.num.pad[q];
+        ca.x2[f] = w.den.pad[q];
       }
+      HIP_TRY(launch_chi(ca, st));
       CpPassArgs a = base_pass(x, w, o);
-      set_rebuild(a, w.ref);
-      set_num(a, w.num);
-      set_den(a, w.den);
-      if (n == 2) {  // mode 3 contracts with modes 1 and 2 only; the C operand is unused
-        a.Ctn = w.ref.padT[2];
-        a.Ctd = w.ref.padT[2];
-      } else if (n == 0) {
-        a.An = w.ref.pad[0];  // A rows are read but do not enter the mode-1 result
-        a.Ad = w.ref.pad[0];
-      } else {
-        a.Bn = w.ref.pad[1];
-        a.Bd = w.ref.pad[1];
-      }
+      a.r = ref;
+      a.n = pad_set(w.num);
+      a.d = pad_set(w.den);
+      // the active mode's own block does not enter its contraction; point it at
+      // the reference so that no stale buffer is read
+      if (n == 0) { a.n.A = ref.A; a.d.A = ref.A; }
+      if (n == 1) { a.n.B = ref.B; a.d.B = ref.B; }
+      if (n == 2) { a.n.C = ref.C; a.d.C = ref.C; }
       a.want_v = n < 2;
       a.want_m3 = n == 2;
       if (cache) {
@@ -379,12 +420,13 @@ int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts*
       } else {
         a.want_obj = obj_pending;
       }
-      HIP_TRY(launch_cp_pass(a, w.g, bc, true, st));
+      if ((rc = run_pass(ctx, a, w.g, bc, true, st))) return rc;
       if (obj_pending) {
         HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
         obj_pending = false;
       }
-      rc = cp_apply_update(m, w, n, w.ref.pad[n], false, w.cur, gamma_of(o->beta), eps, st);
+      const FView anchor = n == 0 ? ref.A : n == 1 ? ref.B : ref.C;  // anchored at the reference block
+      rc = cp_apply_update(m, w, n, anchor, nullptr, w.cur.pad[n], gamma_of(o->beta), eps, st);
       if (rc) return rc;
     }
   }
@@ -397,13 +439,11 @@ int cp_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const 
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
   w = cp_layout(x, ctx->ws, false);
-  rc = pad_user(m, w, w.cur, st);
-  if (rc) return rc;
   CpPassArgs a = base_pass(x, w, o);
-  set_rebuild(a, w.cur);
-  set_num(a, w.cur);
+  a.r = user_set(m);
+  a.n = a.r;
   a.want_obj = 1;
-  HIP_TRY(launch_cp_pass(a, w.g, beta_class_of(o->beta), false, st));
+  if ((rc = run_pass(ctx, a, w.g, beta_class_of(o->beta), false, st))) return rc;
   HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, out, st));
   return COMM_OK;
 }
@@ -450,14 +490,44 @@ int comm_destroy(comm_ctx* ctx) {
   return guarded([&]() -> int {
     if (!ctx) return COMM_OK;
     int rc = COMM_OK;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->last_stream);
     if (ctx->ws) {
-      hipSetDevice(ctx->device);
-      hipStreamSynchronize(ctx->last_stream);
       hipError_t e = hipFree(ctx->ws);
       if (e != hipSuccess) rc = fail(COMM_EHIP, "hipFree: %s", hipGetErrorString(e));
     }
+    for (auto& pr : ctx->events) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
     delete ctx;
     return rc;
+  });
+}
+
+int comm_profile_enable(comm_ctx* ctx, int on) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    ctx->profiling = on != 0;
+    ctx->events_used = 0;
+    return COMM_OK;
+  });
+}
+
+int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
+  return guarded([&]() -> int {
+    if (!ctx || !total_ms || !launches) return fail(COMM_EINVAL, "NULL argument");
+    double sum = 0.0;
+    for (size_t k = 0; k < ctx->events_used; ++k) {
+      HIP_TRY(hipEventSynchronize(ctx->events[k].second));
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->events[k].first, ctx->events[k].second));
+      sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (int64_t)ctx->events_used;
+    ctx->events_used = 0;
+    return COMM_OK;
   });
 }
 

@@ -1,0 +1,10 @@
+// Fused dense CP pass instantiated for one beta class.
+#include "cp3_impl.h"
+
+namespace comm {
+
+hipError_t launch_bc_is(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s) {
+  return launch_bc<kIS>(a, g, den, s);
+}
+
+}  // namespace comm

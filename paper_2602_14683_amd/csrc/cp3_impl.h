@@ -1,0 +1,487 @@
+// Fused dense 3-way CP pass for gfx950 (MI355X).
+//
+// One pass streams X once and, per 32 (i,j)-pairs x 32 k tile held by one
+// wavefront:
+//   1. rebuilds Xhat on the matrix cores, Xhat[m][k] = sum_r W[m][r] C[k][r]
+//      with W[m][r] = A[i(m)][r] B[j(m)][r] (Sec. 3.3; the Khatri-Rao row is
+//      formed in registers, never stored);
+//   2. forms the weights P = X * Xhat^(beta-2), Q = Xhat^(beta-1) in registers
+//      (Sec. 4.1 / Sec. 5.3, with max(Xhat, eps) and the beta = 0 data floor);
+//   3. optionally accumulates d_beta(X | Xhat) in float64 (Sec. 3.2);
+//   4. contracts P (and Q) back onto the factors (CPContr of Sec. 6.1):
+//        mode 3:   M3[k][r] = sum_m P[m][k] W'[m][r]          (matrix cores)
+//        modes 1,2: V[m][r]  = sum_k P[m][k] C'[k][r]          (matrix cores)
+//                   M1[i][r] = sum_j V[(i,j)][r] B'[j][r],  M2[j][r] = sum_i V[(i,j)][r] A'[i][r]
+//      where the primed factors are the contraction set: the current factors
+//      for block-MM, chi_1 / chi_2 of the current and reference factors for
+//      J-CoMM (Sec. 5.3, CP inner update).
+// Neither Xhat, P, Q nor any Khatri-Rao product is written to memory (P / Q
+// only when the caller asks for the J-CoMM cache).
+//
+// MFMA: v_mfma_f32_32x32x2_f32.  A operand lane l supplies A[l%32][l/32], B
+// operand B[l/32][l%32]; the 32x32 result sits in 16 registers per lane with
+// D[8*(v/4) + 4*(l/32) + v%4][l%32] in register v.  Reductions over r or k use
+// a permuted order that both operands agree on, so the Xhat tile produced by
+// one chain is consumed by the mode-3 chain straight from registers; the
+// modes-1/2 chain needs the tile with m in the lane index, which goes through
+// a per-wave LDS transpose.
+//
+// Workgroup = 4 waves over a 16 (i) x 32 (j) x 64 (k) tile: wave w takes the
+// 32-wide k slice (w & 1) and 8 of the 16 (4 i x 8 j) pair blocks (w >> 1).
+// Results leave the workgroup as partial sums in fixed slots (no atomics), so
+// every reduction has a fixed order and the pass is bitwise deterministic.
+
+#pragma once
+
+#include "kernels.h"
+
+namespace comm {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kLdsT = 36;  // row stride of the per-wave transpose buffer (16-byte aligned rows)
+
+inline CpGrid cp_grid_impl(int I, int J, int K) {
+  CpGrid g;
+  g.gi = (I + kCpTI - 1) / kCpTI;
+  g.gj = (J + kCpTJ - 1) / kCpTJ;
+  g.gk = (K + kCpTK - 1) / kCpTK;
+  g.Ip = g.gi * kCpTI;
+  g.Jp = g.gj * kCpTJ;
+  g.Kp = g.gk * kCpTK;
+  return g;
+}
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void load16(const float* p, float (&v)[16]) {
+  const f32x4* q = reinterpret_cast<const f32x4*>(p);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 x = q[t];
+    v[4 * t + 0] = x[0];
+    v[4 * t + 1] = x[1];
+    v[4 * t + 2] = x[2];
+    v[4 * t + 3] = x[3];
+  }
+}
+
+// Row of the 32x32 result held in register v by lane half h.
+__device__ __forceinline__ int out_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// d_1(x | y) = y - x - x log(y / x) without cancellation: with
+// s = (y - x) / (y + x), log(y / x) = 2 atanh(s), which gives
+// d_1 = s^2 [(x + y) - 2 x s S(s^2)],  S(z) = sum_{k>=0} z^k / (2k + 3).
+// Nine terms keep the truncation below 1e-7 relative for |s| < 1/2.  Entries
+// with |s| >= 1/2 ("far") take the direct form, which there loses at most a
+// couple of bits (kl_direct).  x = 0 gives y.  `rsum` is 1 / (x + y).
+__device__ __forceinline__ float kl_series(float x, float y, float rsum, bool& far) {
+  const float sum = x + y, diff = y - x;
+  const float s = diff * rsum;
+  const float z = s * s;
+  float S = 1.0f / 19.0f;
+  S = fmaf(S, z, 1.0f / 17.0f);
+  S = fmaf(S, z, 1.0f / 15.0f);
+  S = fmaf(S, z, 1.0f / 13.0f);
+  S = fmaf(S, z, 1.0f / 11.0f);
+  S = fmaf(S, z, 1.0f / 9.0f);
+  S = fmaf(S, z, 1.0f / 7.0f);
+  S = fmaf(S, z, 1.0f / 5.0f);
+  S = fmaf(S, z, 1.0f / 3.0f);
+  far = z >= 0.25f && x > 0.0f;
+  const float d = z * fmaf(-2.0f * x * s, S, sum);
+  return x > 0.0f ? d : y;
+}
+
+__device__ __forceinline__ float kl_direct(float x, float y) {
+  return (y - x) - x * (fast_log2(y * fast_rcp(x)) * 0.69314718055994531f);
+}
+
+// Weights and (optionally) the objective term of one entry.  At beta = 1 one
+// reciprocal of y (x + y) serves both P = x / y and the objective's s; `far`
+// flags an entry whose term must be recomputed with kl_direct.
+template <int BC, bool kObj>
+__device__ __forceinline__ void entry(float x, float y, const BetaConst& bc, float& p, float& q, float& d,
+                                      bool& far) {
+  far = false;
+  if constexpr (BC == kKL) {
+    q = 1.0f;
+    if constexpr (kObj) {
+      const float sum = x + y;
+      const float r = fast_rcp(y * sum);
+      p = x * (sum * r);
+      d = kl_series(x, y, y * r, far);
+    } else {
+      p = x * fast_rcp(y);
+    }
+  } else {
+    weights<BC>(x, y, bc.beta, p, q);
+    if constexpr (kObj) d = dbeta_term<BC>(x, y, bc);
+  }
+}
+
+// Contract one weight tile (P or Q) of pair block (ib, jb) with a contraction
+// set.  wv: tile in the Xhat layout (lane = k, 16 m's); ag/bq: A'/B' entries
+// (column = lane) of the block's 4 i's and this lane half's 4 j's; ct: this
+// wave's 16 transposed C' values (k = 16h + s).
+__device__ __forceinline__ void contract_tile(const float (&wv)[16], const float (&ag)[4], const float (&bq)[4],
+                                              const float (&ct)[16], bool want_m3, bool want_v, f32x16& m3acc,
+                                              float (&m1loc)[4], float (&m2acc)[4], float* ldsT, int col, int h) {
+  if (want_m3) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) m3acc = mfma32(ag[s >> 2] * bq[s & 3], wv[s], m3acc);
+  }
+  if (want_v) {
+    // transpose the tile through LDS: row m, column k
+#pragma unroll
+    for (int v = 0; v < 16; ++v) ldsT[out_row(v, h) * kLdsT + col] = wv[v];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    float pr[16];
+    load16(ldsT + col * kLdsT + 16 * h, pr);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    f32x16 vacc = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) vacc = mfma32(pr[s], ct[s], vacc);
+    __builtin_amdgcn_wave_barrier();
+    // vacc[4g+q] = V[(i = ib*4+g, j = jb*8 + 4h + q)][r = col]
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        m1loc[g] = fmaf(vacc[4 * g + q], bq[q], m1loc[g]);
+        m2acc[q] = fmaf(vacc[4 * g + q], ag[g], m2acc[q]);
+      }
+    }
+  }
+}
+
+// kNumOnly: contract P;  kNumDen: contract P and Q;  kCacheNumDen: P~ / Q~ read
+// from the cache instead of X + rebuild, both contracted;  kCacheWrite: rebuild,
+// write P~ / Q~ to the cache, no contraction.
+enum PassVariant : int { kNumOnly = 0, kNumDen = 1, kCacheNumDen = 2, kCacheWrite = 3 };
+
+constexpr int kSA = 36;  // row stride of the staged rebuild rows (bank spread for 16-byte reads)
+
+struct PassShared {
+  float t[kWaves][32 * kLdsT];      // per-wave transpose buffers
+  float m1[2][2][kCpTI * 32];        // [num/den][k-slice][i][r]
+  float red[kWaves][32 * 32];        // cross-wave reduction
+  float ra[kCpTI * kSA];             // rebuild rows of A (i0 .. i0+15)
+  float rb[kCpTJ * kSA];             // rebuild rows of B (j0 .. j0+31)
+  float na[kCpTI * 32], nb[kCpTJ * 32];  // contraction rows for P
+  float da[kCpTI * 32], db[kCpTJ * 32];  // contraction rows for Q
+  double obj[kWaves];
+};
+
+// X (or cached P/Q) values of pair block (ib, jb) in the Xhat layout.
+template <bool kInterior>
+__device__ __forceinline__ void load_tile(const float* __restrict__ base, int ib, int jb, unsigned lane_off,
+                                          int i0, int j0, int I, int J, int K, bool kvalid, int h,
+                                          float (&x)[16]) {
+  // uniform part of the address in scalar registers, lane part a 32-bit offset
+  const int sK = K, sJK = J * K;
+  const float* blk = base + ((size_t)(i0 + ib * 4) * J + (j0 + jb * 8)) * K;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const float* rowp = blk + (size_t)((v >> 2) * sJK + (v & 3) * sK);
+    if (kInterior) {
+      x[v] = rowp[lane_off];
+    } else {
+      const int i = i0 + ib * 4 + (v >> 2);
+      const int j = j0 + jb * 8 + 4 * h + (v & 3);
+      x[v] = (kvalid && i < I && j < J) ? rowp[lane_off] : 0.0f;
+    }
+  }
+}
+
+template <int BC, int kVar, bool kObj, bool kInterior>
+__device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, int wg, int bi, int bj, int bk,
+                                          int gj, int gk) {
+  constexpr bool kDen = kVar == kNumDen || kVar == kCacheNumDen;
+  constexpr bool kCache = kVar == kCacheNumDen;
+  constexpr bool kWrite = kVar == kCacheWrite;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int col = lane & 31;
+  const int h = lane >> 5;
+  const int kt = w & 1;
+  const int mg = w >> 1;
+  const int i0 = bi * kCpTI, j0 = bj * kCpTJ, k0 = bk * kCpTK;
+  const int I = a.I, J = a.J, K = a.K;
+  const int kslice = k0 + kt * 32;
+  const int kcol = kslice + col;
+  const bool kvalid = kcol < K;
+  const unsigned lane_off = (unsigned)(4 * h * K + kt * 32 + col) + (unsigned)k0;
+
+  // ---- stage the workgroup's factor rows in LDS (zero outside rows x cols)
+  for (int e = tid; e < kCpTI * 32; e += kThreads) {
+    const int r = e >> 5, c = e & 31;
+    const int i = i0 + r;
+    if (!kCache) sh.ra[r * kSA + c] = a.r.A.at(i, c, I);
+    sh.na[e] = a.n.A.at(i, c, I);
+    if (kDen) sh.da[e] = a.d.A.at(i, c, I);
+  }
+  for (int e = tid; e < kCpTJ * 32; e += kThreads) {
+    const int r = e >> 5, c = e & 31;
+    const int j = j0 + r;
+    if (!kCache) sh.rb[r * kSA + c] = a.r.B.at(j, c, J);
+    sh.nb[e] = a.n.B.at(j, c, J);
+    if (kDen) sh.db[e] = a.d.B.at(j, c, J);
+  }
+  __syncthreads();
+
+  // ---- per-wave operands that do not depend on the pair block:
+  // rebuild C rows (k = kcol, r = 16h + s) and contraction C columns
+  // (r = col, k = kslice + 16h + s)
+  float crow[16], ctn[16], ctd[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    if (!kCache) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
+    ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
+    if (kDen) ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
+  }
+
+  f32x16 m3n = {}, m3d = {};
+  float m2n[4][4] = {}, m2d[4][4] = {};
+  float m1n[4] = {}, m1d[4] = {};
+  double obj = 0.0;
+  const bool want_m3 = !kWrite && a.want_m3, want_v = !kWrite && a.want_v;
+
+  const float* src0 = kCache ? a.Pc : a.X;
+  float xb[2][16], qb[2][16];
+  load_tile<kInterior>(src0, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, xb[0]);
+  if (kCache) load_tile<kInterior>(a.Qc, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, qb[0]);
+
+  for (int ibl = 0; ibl < 2; ++ibl) {
+  const int ib = 2 * mg + ibl;
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const int t = ibl * 4 + jb;
+    if (t + 1 < 8) {
+      // prefetch the next pair block (the next i block after jb = 3)
+      const int ibn = 2 * mg + ((t + 1) >> 2), jbn = (jb + 1) & 3;
+      load_tile<kInterior>(src0, ibn, jbn, lane_off, i0, j0, I, J, K, kvalid, h, xb[(jb + 1) & 1]);
+      if (kCache) load_tile<kInterior>(a.Qc, ibn, jbn, lane_off, i0, j0, I, J, K, kvalid, h, qb[(jb + 1) & 1]);
+    }
+    const float(&xv)[16] = xb[jb & 1];
+
+    bool valid[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      if (kInterior) {
+        valid[v] = true;
+      } else {
+        const int i = i0 + ib * 4 + (v >> 2);
+        const int j = j0 + jb * 8 + 4 * h + (v & 3);
+        valid[v] = kvalid && i < I && j < J;
+      }
+    }
+
+    float pv[16], qv[16];
+    if (kCache) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        pv[v] = xv[v];
+        qv[v] = qb[jb & 1][v];
+      }
+    } else {
+      // rebuild operand: lane = pair row m = col, r = 16h + s
+      float arow[16], brow[16];
+      load16(sh.ra + (ib * 4 + (col >> 3)) * kSA + 16 * h, arow);
+      load16(sh.rb + (jb * 8 + (col & 7)) * kSA + 16 * h, brow);
+      f32x16 xh = {};
+#pragma unroll
+      for (int s = 0; s < 16; ++s) xh = mfma32(arow[s] * brow[s], crow[s], xh);
+      float yv[16];
+      bool anyfar = false;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        float x = xv[v];
+        if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
+        const float y = fmaxf(xh[v], a.eps);
+        yv[v] = y;
+        float p, q, d = 0.0f;
+        bool far;
+        entry<BC, kObj>(x, y, a.bc, p, q, d, far);
+        pv[v] = valid[v] ? p : 0.f;
+        qv[v] = valid[v] ? q : 0.f;
+        if (kObj) obj += (double)(valid[v] ? d : 0.0f);
+        anyfar |= far && valid[v];
+        // the general objective is long; keep the scheduler from interleaving all
+        // sixteen entries (register pressure)
+        if constexpr (kObj && BC != kKL) {
+          if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if constexpr (kObj && BC == kKL) {
+        // rare: entries with |s| >= 1/2 replace their series term by the direct form
+        if (__builtin_amdgcn_ballot_w64(anyfar)) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const float x = xv[v], y = yv[v];
+            const float sum = x + y;
+            bool far;
+            const float ds = kl_series(x, y, fast_rcp(sum), far);
+            if (far && valid[v]) obj += (double)kl_direct(x, y) - (double)ds;
+          }
+        }
+      }
+      if (kWrite) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          if (valid[v]) {
+            const int i = i0 + ib * 4 + (v >> 2);
+            const int j = j0 + jb * 8 + 4 * h + (v & 3);
+            const size_t off = ((size_t)i * J + j) * K + kcol;
+            a.Pw[off] = pv[v];
+            a.Qw[off] = qv[v];
+          }
+        }
+      }
+    }
+
+    if (!kWrite && (want_m3 || want_v)) {
+      float ag[4], bq[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) ag[g] = sh.na[(ib * 4 + g) * 32 + col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bq[q] = sh.nb[(jb * 8 + 4 * h + q) * 32 + col];
+      contract_tile(pv, ag, bq, ctn, want_m3, want_v, m3n, m1n, m2n[jb], sh.t[w], col, h);
+      if (kDen) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) ag[g] = sh.da[(ib * 4 + g) * 32 + col];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bq[q] = sh.db[(jb * 8 + 4 * h + q) * 32 + col];
+        contract_tile(qv, ag, bq, ctd, want_m3, want_v, m3d, m1d, m2d[jb], sh.t[w], col, h);
+      }
+    }
+    if (jb == 3 && want_v) {
+      // this wave's M1 rows ib*4+g: combine the two lane halves (different j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float o = __shfl_xor(m1n[g], 32);
+        if (h == 0) sh.m1[0][kt][(ib * 4 + g) * 32 + col] = m1n[g] + o;
+        m1n[g] = 0.0f;
+        if (kDen) {
+          const float od = __shfl_xor(m1d[g], 32);
+          if (h == 0) sh.m1[1][kt][(ib * 4 + g) * 32 + col] = m1d[g] + od;
+          m1d[g] = 0.0f;
+        }
+      }
+    }
+  }
+  }
+
+  // ---------------------------------------------------------------- objective partial
+  if (kObj) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
+    if (lane == 0) sh.obj[w] = obj;
+  }
+  __syncthreads();
+  if (kObj && tid == 0) {
+    double s = sh.obj[0];
+    for (int q = 1; q < kWaves; ++q) s += sh.obj[q];
+    a.obj_part[wg] = s;
+  }
+
+  // ---------------------------------------------------------------- cross-wave reductions
+  constexpr int nsides = kDen ? 2 : 1;
+#pragma unroll
+  for (int side = 0; side < nsides; ++side) {
+    if (want_m3) {
+      const f32x16& acc = side == 0 ? m3n : m3d;
+      // acc[v] = M3[k = col][r = out_row(v, h)] over this wave's pair blocks
+#pragma unroll
+      for (int v = 0; v < 16; ++v) sh.red[w][col * 32 + out_row(v, h)] = acc[v];
+      __syncthreads();
+      float* dst = side == 0 ? a.m3n : a.m3d;
+      const size_t slot = (size_t)(bi * gj + bj);
+      for (int e = tid; e < 2 * 32 * 32; e += kThreads) {
+        const int ks = e >> 10;  // k slice
+        const int kk = (e >> 5) & 31;
+        const int r = e & 31;
+        const int k = k0 + ks * 32 + kk;
+        const float s = sh.red[ks][kk * 32 + r] + sh.red[2 + ks][kk * 32 + r];
+        if (k < K) dst[(slot * a.Kp + k) * kRP + r] = s;
+      }
+      __syncthreads();
+    }
+    if (want_v) {
+      float(&m2)[4][4] = side == 0 ? m2n : m2d;
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh.red[w][(jb * 8 + 4 * h + q) * 32 + col] = m2[jb][q];
+      __syncthreads();
+      float* d2 = side == 0 ? a.m2n : a.m2d;
+      float* d1 = side == 0 ? a.m1n : a.m1d;
+      const size_t slot2 = (size_t)(bi * gk + bk);
+      const size_t slot1 = (size_t)(bj * gk + bk);
+      for (int e = tid; e < 32 * 32; e += kThreads) {
+        const int jl = e >> 5, r = e & 31;
+        const float s = ((sh.red[0][e] + sh.red[1][e]) + sh.red[2][e]) + sh.red[3][e];
+        if (j0 + jl < J) d2[(slot2 * a.Jp + j0 + jl) * kRP + r] = s;
+      }
+      for (int e = tid; e < kCpTI * 32; e += kThreads) {
+        const int il = e >> 5, r = e & 31;
+        const float s = sh.m1[side][0][e] + sh.m1[side][1][e];
+        if (i0 + il < I) d1[(slot1 * a.Ip + i0 + il) * kRP + r] = s;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int BC, int kVar, bool kObj>
+__global__ void __launch_bounds__(kThreads) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
+  __shared__ PassShared sh;
+  const int wg = blockIdx.x;
+  const int bk = wg % gk;
+  const int bij = wg / gk;
+  const int bj = bij % gj;
+  const int bi = bij / gj;
+  const bool interior =
+      (bi + 1) * kCpTI <= a.I && (bj + 1) * kCpTJ <= a.J && (bk + 1) * kCpTK <= a.K;
+  if (interior)
+    pass_body<BC, kVar, kObj, true>(a, sh, wg, bi, bj, bk, gj, gk);
+  else
+    pass_body<BC, kVar, kObj, false>(a, sh, wg, bi, bj, bk, gj, gk);
+}
+
+template <int BC, int kVar, bool kObj>
+hipError_t launch_v(const CpPassArgs& a, const CpGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s, a, g.gj,
+                     g.gk);
+  return hipGetLastError();
+}
+
+// Dispatch for one beta class; instantiated once per translation unit cp3_bc*.hip.
+template <int BC>
+hipError_t launch_bc(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s) {
+  if (a.cache_mode == 1)
+    return a.want_obj ? launch_v<BC, kCacheWrite, true>(a, g, s) : launch_v<BC, kCacheWrite, false>(a, g, s);
+  if (den) return a.want_obj ? launch_v<BC, kNumDen, true>(a, g, s) : launch_v<BC, kNumDen, false>(a, g, s);
+  return a.want_obj ? launch_v<BC, kNumOnly, true>(a, g, s) : launch_v<BC, kNumOnly, false>(a, g, s);
+}
+
+// beta = 1 never contracts Q (its denominators are closed-form) and never
+// caches: only the P-only variants exist.
+template <>
+hipError_t launch_bc<kKL>(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
+
+hipError_t launch_bc_is(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
+hipError_t launch_bc_half(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
+hipError_t launch_bc_kl(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
+hipError_t launch_bc_threehalf(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
+hipError_t launch_bc_general(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
+hipError_t launch_cache_read(const CpPassArgs& a, const CpGrid& g, hipStream_t s);
+
+}  // namespace comm

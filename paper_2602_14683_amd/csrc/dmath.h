@@ -73,45 +73,46 @@ __device__ __forceinline__ float pow_beta(float x, float beta) {
 // the closed form loses at most a few bits.  For |q - 1| < 0.29 the logarithm
 // is taken as 2 atanh(t / (2 + t)), t = q - 1, which keeps u accurate near 0.
 // At x = 0: d = y (beta = 1) or y^beta / beta (beta > 0).
+// Every path is evaluated and the right one selected (no divergent branches).
 template <int BC>
 __device__ __forceinline__ float dbeta_term(float x, float y, const BetaConst& bc) {
-  if (!(x > 0.0f)) {
-    if constexpr (BC == kKL) return y;
-    else return pow_beta<BC>(y, bc.beta) * bc.inv_beta;
-  }
-  const float rx = fast_rcp(x);
-  const float t = (y - x) * rx;
+  const bool zero = !(x > 0.0f);
+  const float xs = zero ? 1.0f : x;
+  const float rx = fast_rcp(xs);
+  const float t = (y - xs) * rx;
   const float q = y * rx;
-  float u;
-  if (fabsf(t) < 0.29f) {
-    float s = t * fast_rcp(2.0f + t);
-    float s2 = s * s;
-    float a = fmaf(s2, 1.0f / 9.0f, 1.0f / 7.0f);
-    a = fmaf(s2, a, 1.0f / 5.0f);
-    a = fmaf(s2, a, 1.0f / 3.0f);
-    a = fmaf(s2, a, 1.0f);
-    u = 2.0f * s * a;
-  } else {
-    u = fast_log2(q) * 0.69314718055994531f;
-  }
-  float h;
-  if (fabsf(u) < 1.0f) {
-    float acc = bc.series[kSeriesTerms - 1];
+  // u = log q, from the atanh series near q = 1, else from log2
+  const float s = t * fast_rcp(2.0f + t);
+  const float s2 = s * s;
+  float a = fmaf(s2, 1.0f / 9.0f, 1.0f / 7.0f);
+  a = fmaf(s2, a, 1.0f / 5.0f);
+  a = fmaf(s2, a, 1.0f / 3.0f);
+  a = fmaf(s2, a, 1.0f);
+  const float u_near = 2.0f * s * a;
+  const float u_far = fast_log2(q) * 0.69314718055994531f;
+  const float u = fabsf(t) < 0.29f ? u_near : u_far;
+  // h(u): series for |u| < 1, closed form otherwise
+  float acc = bc.series[kSeriesTerms - 1];
 #pragma unroll
-    for (int k = kSeriesTerms - 2; k >= 0; --k) acc = fmaf(acc, u, bc.series[k]);
-    h = acc * u * u;
+  for (int k = kSeriesTerms - 2; k >= 0; --k) acc = fmaf(acc, u, bc.series[k]);
+  const float h_series = acc * u * u;
+  float h_closed;
+  if constexpr (BC == kKL) {
+    h_closed = (q - 1.0f) - u;
+  } else if constexpr (BC == kIS) {
+    h_closed = (fast_rcp(q) - 1.0f) + u;
   } else {
-    if constexpr (BC == kKL) {
-      h = (q - 1.0f) - u;
-    } else if constexpr (BC == kIS) {
-      h = (fast_rcp(q) - 1.0f) + u;
-    } else {
-      float qb = fast_exp2(bc.beta * u * 1.4426950408889634f);
-      float qb1 = qb * fast_rcp(q);
-      h = ((bc.beta - 1.0f) * qb - bc.beta * qb1 + 1.0f) * bc.inv_bb1;
-    }
+    const float qb = fast_exp2(bc.beta * u * 1.4426950408889634f);
+    const float qb1 = qb * fast_rcp(q);
+    h_closed = ((bc.beta - 1.0f) * qb - bc.beta * qb1 + 1.0f) * bc.inv_bb1;
   }
-  return pow_beta<BC>(x, bc.beta) * h;
+  const float h = fabsf(u) < 1.0f ? h_series : h_closed;
+  const float d = pow_beta<BC>(xs, bc.beta) * h;
+  float d0;
+  if constexpr (BC == kKL) d0 = y;
+  else if constexpr (BC == kIS) d0 = 0.0f;  // unreachable: x is floored at eps_x > 0
+  else d0 = pow_beta<BC>(y, bc.beta) * bc.inv_beta;
+  return zero ? d0 : d;
 }
 
 }  // namespace comm

@@ -30,6 +30,22 @@ struct CpGrid {
 
 CpGrid cp_grid(int I, int J, int K);
 
+// Read-only view of a factor matrix: `rows` x `cols` valid entries, row-major
+// with row stride ld; entries outside read as zero.  Views cover both caller
+// buffers (ld = R) and the padded workspace copies (ld = 32).
+struct FView {
+  const float* p;
+  int ld;
+  int cols;
+  __device__ __forceinline__ float at(int row, int c, int rows) const {
+    return (row < rows && c < cols) ? p[(size_t)row * ld + c] : 0.0f;
+  }
+};
+
+struct FSet {
+  FView A, B, C;  // modes 1, 2, 3
+};
+
 struct CpPassArgs {
   const float* X;          // I x J x K, row-major (unused when reading the cache)
   const float* Pc;         // cached P~ (cache_mode 2)
@@ -38,17 +54,10 @@ struct CpPassArgs {
   float* Qw;
   int cache_mode;          // 0 none, 1 write P/Q, 2 read P/Q instead of X + rebuild
   int I, J, K;
-  int Ip, Jp, Kp;          // padded extents: rows of one partial slot; Kp is also the
-                           // row stride of the transposed operands
-  const float* Ar;         // rebuild set, [Ip][32], [Jp][32], [Kp][32]
-  const float* Br;
-  const float* Cr;
-  const float* An;         // contraction set for P: [Ip][32], [Jp][32], transposed C [32][Kp]
-  const float* Bn;
-  const float* Ctn;
-  const float* Ad;         // contraction set for Q
-  const float* Bd;
-  const float* Ctd;
+  int Ip, Jp, Kp;          // padded extents: rows of one partial slot
+  FSet r;                  // rebuild set
+  FSet n;                  // contraction set for P
+  FSet d;                  // contraction set for Q
   float eps, eps_x;
   int want_v;              // numerators / denominators of modes 1 and 2
   int want_m3;             // numerator / denominator of mode 3
@@ -66,71 +75,100 @@ struct CpPassArgs {
 hipError_t launch_cp_pass(const CpPassArgs& a, const CpGrid& g, int beta_class, bool den, hipStream_t s);
 
 // ----------------------------------------------------------------------------------------
-// Small factor-side kernels
+// Small factor-side kernels (kernels_small.hip)
 // ----------------------------------------------------------------------------------------
 
-// dst[row][c] = src[row * ld + c] for row < rows, c < cols, zero elsewhere in
-// [rows_p][32]; optionally also the transposed copy dstT[c][row] ([32][rows_p]).
-hipError_t launch_pad_factor(const float* src, int rows, int cols, int ld, int rows_p,
-                             float* dst, float* dstT, hipStream_t s);
-
-// Column sums of padded factors: out[f*32 + c] = sum_row F_f[row][c] for the
-// nf factors (fixed summation order).
-hipError_t launch_colsums(const float* const* F, const int* rows, int nf, float* out, hipStream_t s);
-
-// J-CoMM transformed blocks (Sec. 5.3): x1 = chi_1(cur, ref), x2 = chi_2(cur, ref),
-// over [rows_p][32] padded buffers; entries with ref == 0 (padding) stay zero.
-// Optional transposed copies x1T / x2T ([32][rows_p]).
-hipError_t launch_chi(const float* cur, const float* ref, int rows_p, float beta,
-                      float* x1, float* x2, float* x1T, float* x2T, hipStream_t s);
-
-struct UpdateArgs {
-  const float* num_part;  int num_slots;  // partial slots [slots][rows_total][32]
-  const float* den_part;  int den_slots;  // ignored when den_closed
-  int rows_total;          // row count of one slot
-  int rows;                // valid rows of this factor
-  int cols;                // valid columns (rank)
-  const float* anchor;     // [rows_p][32] multiplicative pre-factor (current or reference block)
-  const float* den_closed; // if not NULL: den[c] = den_closed[c] for every row
-  float gamma;
-  float eps;
-  float* out_pad;          // [rows_p][32]
-  float* out_padT;         // optional transposed copy [32][rows_p]
-  int rows_p;
-  float* out_user;         // optional caller buffer, row stride ld_user
-  int ld_user;
+// dst[f][row][c] = src[f][row * ld + c] for row < rows[f], c < cols, zero elsewhere
+// in [rows_p][32]; optional transposed copy dstT[f][c][row] and second copies.
+struct PadArgs {
+  int nf;
+  int cols, ld;
+  const float* src[4];
+  int rows[4];
+  int rows_p[4];
+  float* dst[4];
+  float* dstT[4];
+  float* dst2[4];
+  float* dst2T[4];
 };
-// Block update max(anchor * (Num / Den)^gamma, eps) with Num / Den summed over
-// the partial slots in a fixed order.
-hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
+hipError_t launch_pad_factors(const PadArgs& a, hipStream_t s);
 
 // prod[c] = prod_f colsum(F_f)[c] (closed-form beta = 1 denominator: Q = 1 makes
 // Den^(n) = prod_{m != n} colsum(A^(m))).  One workgroup, fixed order.
-hipError_t launch_colsum_prod(const float* const* F, const int* rows, int nf, float* prod, hipStream_t s);
+hipError_t launch_colsum_prod(const FView* F, const int* rows, int nf, float* prod, hipStream_t s);
 
-// out[row][c] = anchor[row][c] * sum_s part[s][row][c] over the slots (fixed order),
-// zero outside rows x cols.
-hipError_t launch_scale_reduce(const float* part, int slots, int rows_total, int rows, int cols,
-                               const float* anchor, int rows_p, float* out, hipStream_t s);
+// J-CoMM transformed blocks (Sec. 5.3): x1 = chi_1(cur, ref), x2 = chi_2(cur, ref)
+// over [rows_p][32] padded buffers; entries with ref == 0 (padding) stay zero.
+struct ChiArgs {
+  int nf;
+  float beta;
+  const float* cur[4];
+  const float* ref[4];
+  int rows_p[4];
+  float* x1[4];
+  float* x2[4];
+  float* x1T[4];   // optional transposed copies [32][rows_p]
+  float* x2T[4];
+};
+hipError_t launch_chi(const ChiArgs& a, hipStream_t s);
+
+// beta = 1 J-CoMM inner loop for CP.  At beta = 1, chi_1(A, A~) = A~ and
+// chi_2(A, A~) = A with Q~ = 1, so Num_J^(n) depends only on the reference and
+// Den_J^(n)(i, r) = prod_{m != n} S^(m)(r), S the column sums of the current
+// inner blocks; the update is A^(n) = max(c^(n) / Den^(n), eps) with
+// c^(n) = A~^(n) * Num_J^(n), whose column sums are T^(n) / Den when no entry of
+// the column clips (min c >= eps Den) and are summed exactly otherwise.  The L
+// sweeps reduce to recurrences on 32-wide vectors; kl_apply runs them (every
+// workgroup redundantly, from the per-block column statistics of the slot
+// reduction) and writes max(c / Den_last, eps).
+struct KlLoopArgs {
+  int N, R, L;
+  float eps;
+  const float* c[4];       // [rows_p][32]
+  const float* stats[4];   // [nblk][3][32]
+  int nblk[4];
+  int rows[4];
+  float* cur_pad[4];       // optional padded outputs [rows_p][32]
+  float* user[4];          // caller buffers (row stride R)
+  const double* obj_part;  // optional: objective partials to sum into *obj_out
+  int64_t obj_n;
+  double* obj_out;
+};
+hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s);
+
+// Reduction of partial slots [slots][rows_total][32] (fixed order) fused with
+//   kSlotScale:  out = anchor * Num, plus per-block column statistics
+//                (sum of out, min of out over valid rows, sum of anchor)
+//   kSlotUpdate: out = max(anchor * (Num / Den)^gamma, eps), Den from its own
+//                slots or den_closed[c]
+// A workgroup covers kSlotRows rows x 32 columns of one job.
+constexpr int kSlotRows = 2;
+enum SlotMode : int { kSlotScale = 0, kSlotUpdate = 1 };
+struct SlotJob {
+  int mode;
+  const float* num_part;  int num_slots;
+  const float* den_part;  int den_slots;   // NULL: use den_closed
+  const float* den_closed;
+  int rows_total;          // rows of one slot
+  int rows, cols;          // valid extent
+  int rows_p;              // rows written to out_pad (>= rows)
+  FView anchor;            // multiplicative pre-factor
+  float gamma, eps;
+  float* out_pad;          // optional [rows_p][32]
+  float* out_padT;         // optional [32][rows_p]
+  float* out_user;         // optional caller buffer (valid rows x cols), row stride ld_user
+  int ld_user;
+  float* stats;            // scale mode: [ceil(rows_p / kSlotRows)][3][32]
+};
+struct SlotUpdateArgs {
+  int njobs;
+  SlotJob job[4];
+};
+hipError_t launch_slot_update(const SlotUpdateArgs& a, hipStream_t s);
 
 // Sum of n float64 partials in a fixed order; writes *out (device).  If add_to
 // is not NULL its value is added.
 hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, double* out, hipStream_t s);
 
-// beta = 1 J-CoMM inner loop for CP (kernels_small.hip): given
-// c^(n) = A~^(n) * Num_J^(n) for every mode, runs L sweeps and writes the new
-// factors.
-struct KlLoopArgs {
-  int N, R, L;
-  float eps;
-  const float* c[4];       // [rows_p][32]
-  const float* ref[4];     // padded reference factors
-  int rows[4];
-  int rows_p[4];
-  float* cur_pad[4];       // padded outputs
-  float* cur_padT[4];      // optional transposed outputs
-  float* user[4];          // optional caller buffers (row stride R)
-};
-hipError_t launch_kl_loop(const KlLoopArgs& a, hipStream_t s);
 
 }  // namespace comm

@@ -1,188 +1,126 @@
 // Factor-side kernels: padding copies, column sums, the J-CoMM transforms
-// chi_1 / chi_2 (Sec. 5.3), the multiplicative block update with the eps
-// floor (Theorem "CP block multiplicative update"; Sec. 5.3 inner update), the
-// fixed-order float64 reduction of objective partials, and the beta = 1 inner
-// loop of J-CoMM for CP.  All reductions have a fixed order (deterministic).
+// chi_1 / chi_2 (Sec. 5.3), the reduction of the pass's partial slots fused
+// with the multiplicative block update and its eps floor (Theorem "CP block
+// multiplicative update"; Sec. 5.3 inner update), the fixed-order float64
+// reduction of objective partials, and the beta = 1 inner loop of J-CoMM for
+// CP.  Every reduction has a fixed order, so results are bitwise
+// deterministic.
 
 #include "kernels.h"
 
 namespace comm {
 
 // ----------------------------------------------------------------------------------------
+// Padding copies of up to 4 factors in one launch.
 
-__global__ void pad_factor_kernel(const float* __restrict__ src, int rows, int cols, int ld, int rows_p,
-                                  float* __restrict__ dst, float* __restrict__ dstT) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)rows_p * kRP) return;
+__global__ void pad_factors_kernel(PadArgs a) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int f = 0;
+  while (f < a.nf && e >= (int64_t)a.rows_p[f] * kRP) {
+    e -= (int64_t)a.rows_p[f] * kRP;
+    ++f;
+  }
+  if (f >= a.nf) return;
   const int row = (int)(e / kRP), c = (int)(e % kRP);
-  const float v = (row < rows && c < cols) ? src[(int64_t)row * ld + c] : 0.0f;
-  dst[e] = v;
-  if (dstT) dstT[(int64_t)c * rows_p + row] = v;
+  const float v = (row < a.rows[f] && c < a.cols) ? a.src[f][(int64_t)row * a.ld + c] : 0.0f;
+  a.dst[f][e] = v;
+  if (a.dstT[f]) a.dstT[f][(int64_t)c * a.rows_p[f] + row] = v;
+  if (a.dst2[f]) a.dst2[f][e] = v;
+  if (a.dst2T[f]) a.dst2T[f][(int64_t)c * a.rows_p[f] + row] = v;
 }
 
-hipError_t launch_pad_factor(const float* src, int rows, int cols, int ld, int rows_p, float* dst, float* dstT,
-                             hipStream_t s) {
-  const int64_t n = (int64_t)rows_p * kRP;
-  hipLaunchKernelGGL(pad_factor_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, rows, cols, ld,
-                     rows_p, dst, dstT);
+hipError_t launch_pad_factors(const PadArgs& a, hipStream_t s) {
+  int64_t n = 0;
+  for (int f = 0; f < a.nf; ++f) n += (int64_t)a.rows_p[f] * kRP;
+  hipLaunchKernelGGL(pad_factors_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------------------
-// Column sums: one workgroup per factor, 8 row groups x 32 columns, fixed order.
+// Column sums: one workgroup, 8 row groups x 32 columns, fixed order.
 
 struct ColsumArgs {
-  const float* F[4];
+  FView F[4];
   int rows[4];
   int nf;
-  float* out;        // [nf][32] column sums (may be NULL)
-  float* prod;       // if not NULL: prod[c] = product over the nf factors of the column sums
+  float* prod;       // prod[c] = product over the nf factors of the column sums
 };
 
-__device__ void colsum_block(const float* F, int rows, float* lds8x32, float* result32) {
-  const int t = threadIdx.x;
-  const int c = t & 31, g = t >> 5;
-  float s = 0.0f;
-  for (int r = g; r < rows; r += 8) s += F[(int64_t)r * kRP + c];
-  lds8x32[g * 32 + c] = s;
-  __syncthreads();
-  if (t < 32) {
-    float acc = lds8x32[t];
-    for (int q = 1; q < 8; ++q) acc += lds8x32[q * 32 + t];
-    result32[t] = acc;
-  }
-  __syncthreads();
-}
-
-__global__ void __launch_bounds__(256) colsum_kernel(ColsumArgs a) {
+__global__ void __launch_bounds__(256) colsum_prod_kernel(ColsumArgs a) {
   __shared__ float part[8 * 32];
   __shared__ float res[4][32];
-  for (int f = 0; f < a.nf; ++f) colsum_block(a.F[f], a.rows[f], part, res[f]);
   const int t = threadIdx.x;
+  const int c = t & 31, g = t >> 5;
+  for (int f = 0; f < a.nf; ++f) {
+    float s = 0.0f;
+    for (int r = g; r < a.rows[f]; r += 8) s += a.F[f].at(r, c, a.rows[f]);
+    part[g * 32 + c] = s;
+    __syncthreads();
+    if (t < 32) {
+      float acc = part[t];
+      for (int q = 1; q < 8; ++q) acc += part[q * 32 + t];
+      res[f][t] = acc;
+    }
+    __syncthreads();
+  }
   if (t < 32) {
     float p = 1.0f;
-    for (int f = 0; f < a.nf; ++f) {
-      if (a.out) a.out[f * 32 + t] = res[f][t];
-      p *= res[f][t];
-    }
-    if (a.prod) a.prod[t] = p;
+    for (int f = 0; f < a.nf; ++f) p *= res[f][t];
+    a.prod[t] = p;
   }
 }
 
-hipError_t launch_colsums(const float* const* F, const int* rows, int nf, float* out, hipStream_t s) {
+hipError_t launch_colsum_prod(const FView* F, const int* rows, int nf, float* prod, hipStream_t s) {
   ColsumArgs a = {};
-  for (int f = 0; f < nf; ++f) { a.F[f] = F[f]; a.rows[f] = rows[f]; }
-  a.nf = nf; a.out = out; a.prod = nullptr;
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_colsum_prod(const float* const* F, const int* rows, int nf, float* prod, hipStream_t s) {
-  ColsumArgs a = {};
-  for (int f = 0; f < nf; ++f) { a.F[f] = F[f]; a.rows[f] = rows[f]; }
-  a.nf = nf; a.out = nullptr; a.prod = prod;
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, a);
+  for (int f = 0; f < nf; ++f) {
+    a.F[f] = F[f];
+    a.rows[f] = rows[f];
+  }
+  a.nf = nf;
+  a.prod = prod;
+  hipLaunchKernelGGL(colsum_prod_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------------------
-// chi transforms
+// chi transforms of up to 4 factors in one launch
 
-__global__ void chi_kernel(const float* __restrict__ cur, const float* __restrict__ ref, int rows_p, float beta,
-                           float* __restrict__ x1, float* __restrict__ x2, float* __restrict__ x1T,
-                           float* __restrict__ x2T) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)rows_p * kRP) return;
-  const float z = cur[e], zr = ref[e];
+__global__ void chi_kernel(ChiArgs a) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int f = 0;
+  while (f < a.nf && e >= (int64_t)a.rows_p[f] * kRP) {
+    e -= (int64_t)a.rows_p[f] * kRP;
+    ++f;
+  }
+  if (f >= a.nf) return;
+  const float beta = a.beta;
+  const float z = a.cur[f][e], zr = a.ref[f][e];
   float c1 = 0.0f, c2 = 0.0f;
   if (zr > 0.0f) {
     // chi_1 = Z~ (Z/Z~)^(beta-1);  chi_2 = Z (beta < 1) or Z~ (Z/Z~)^beta
     const float u = z / zr;
     const float lu = __builtin_amdgcn_logf(u);
     c1 = (beta == 1.0f) ? zr : zr * __builtin_amdgcn_exp2f((beta - 1.0f) * lu);
-    c2 = (beta < 1.0f) ? z : (beta == 1.0f ? z : zr * __builtin_amdgcn_exp2f(beta * lu));
+    c2 = (beta <= 1.0f) ? z : zr * __builtin_amdgcn_exp2f(beta * lu);
   }
-  x1[e] = c1;
-  x2[e] = c2;
+  a.x1[f][e] = c1;
+  a.x2[f][e] = c2;
   const int row = (int)(e / kRP), c = (int)(e % kRP);
-  if (x1T) x1T[(int64_t)c * rows_p + row] = c1;
-  if (x2T) x2T[(int64_t)c * rows_p + row] = c2;
+  if (a.x1T[f]) a.x1T[f][(int64_t)c * a.rows_p[f] + row] = c1;
+  if (a.x2T[f]) a.x2T[f][(int64_t)c * a.rows_p[f] + row] = c2;
 }
 
-hipError_t launch_chi(const float* cur, const float* ref, int rows_p, float beta, float* x1, float* x2, float* x1T,
-                      float* x2T, hipStream_t s) {
-  const int64_t n = (int64_t)rows_p * kRP;
-  hipLaunchKernelGGL(chi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cur, ref, rows_p, beta, x1, x2,
-                     x1T, x2T);
-  return hipGetLastError();
-}
-
-// ----------------------------------------------------------------------------------------
-// Multiplicative block update
-
-__device__ __forceinline__ float pow_gamma(float ratio, float gamma) {
-  if (gamma == 1.0f) return ratio;
-  if (gamma == 0.5f) return __builtin_amdgcn_sqrtf(ratio);
-  return ratio > 0.0f ? __builtin_amdgcn_exp2f(gamma * __builtin_amdgcn_logf(ratio)) : 0.0f;
-}
-
-__global__ void update_kernel(UpdateArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)a.rows_p * kRP) return;
-  const int row = (int)(e / kRP), c = (int)(e % kRP);
-  float v = 0.0f;
-  if (row < a.rows && c < a.cols) {
-    float num = 0.0f;
-    for (int s = 0; s < a.num_slots; ++s) num += a.num_part[((int64_t)s * a.rows_total + row) * kRP + c];
-    float den;
-    if (a.den_closed) {
-      den = a.den_closed[c];
-    } else {
-      den = 0.0f;
-      for (int s = 0; s < a.den_slots; ++s) den += a.den_part[((int64_t)s * a.rows_total + row) * kRP + c];
-    }
-    v = fmaxf(a.anchor[e] * pow_gamma(num / den, a.gamma), a.eps);
-    if (a.out_user) a.out_user[(int64_t)row * a.ld_user + c] = v;
-  }
-  a.out_pad[e] = v;
-  if (a.out_padT) a.out_padT[(int64_t)c * a.rows_p + row] = v;
-}
-
-hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
-  const int64_t n = (int64_t)a.rows_p * kRP;
-  hipLaunchKernelGGL(update_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-// out[row][c] = anchor[row][c] * sum_s part[s][row][c] (rows < rows, else 0).
-__global__ void scale_reduce_kernel(const float* __restrict__ part, int slots, int rows_total, int rows, int cols,
-                                    const float* __restrict__ anchor, int rows_p, float* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)rows_p * kRP) return;
-  const int row = (int)(e / kRP), c = (int)(e % kRP);
-  float v = 0.0f;
-  if (row < rows && c < cols) {
-    float s = 0.0f;
-    for (int t = 0; t < slots; ++t) s += part[((int64_t)t * rows_total + row) * kRP + c];
-    v = anchor[e] * s;
-  }
-  out[e] = v;
-}
-
-hipError_t launch_scale_reduce(const float* part, int slots, int rows_total, int rows, int cols, const float* anchor,
-                               int rows_p, float* out, hipStream_t s) {
-  const int64_t n = (int64_t)rows_p * kRP;
-  hipLaunchKernelGGL(scale_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, slots,
-                     rows_total, rows, cols, anchor, rows_p, out);
+hipError_t launch_chi(const ChiArgs& a, hipStream_t s) {
+  int64_t n = 0;
+  for (int f = 0; f < a.nf; ++f) n += (int64_t)a.rows_p[f] * kRP;
+  hipLaunchKernelGGL(chi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------------------
 // float64 sum of partials, fixed order
 
-__global__ void __launch_bounds__(1024) sum_f64_kernel(const double* __restrict__ part, int64_t n,
-                                                       const double* __restrict__ add_to, double* __restrict__ out) {
-  __shared__ double lds[1024];
+__device__ double block_sum_f64(const double* __restrict__ part, int64_t n, double* lds) {
   const int t = threadIdx.x;
   double s = 0.0;
   for (int64_t e = t; e < n; e += 1024) s += part[e];
@@ -192,7 +130,14 @@ __global__ void __launch_bounds__(1024) sum_f64_kernel(const double* __restrict_
     if (t < w) lds[t] += lds[t + w];
     __syncthreads();
   }
-  if (t == 0) out[0] = lds[0] + (add_to ? add_to[0] : 0.0);
+  return lds[0];
+}
+
+__global__ void __launch_bounds__(1024) sum_f64_kernel(const double* __restrict__ part, int64_t n,
+                                                       const double* __restrict__ add_to, double* __restrict__ out) {
+  __shared__ double lds[1024];
+  const double s = block_sum_f64(part, n, lds);
+  if (threadIdx.x == 0) out[0] = s + (add_to ? add_to[0] : 0.0);
 }
 
 hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, double* out, hipStream_t s) {
@@ -212,104 +157,257 @@ hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, d
 // S^(n)(r) = sum_i max(c^(n)(i, r) / Den(r), eps), which equals T^(n)(r) / Den(r)
 // with T^(n) = sum_i c^(n)(i, r) whenever no entry of column r is clipped
 // (min_i c^(n)(i, r) >= eps Den(r)); otherwise the column is summed exactly.
-// The L sweeps thus reduce to recurrences on 32-wide vectors plus one final
-// elementwise pass; one workgroup runs them.
+// The L sweeps thus reduce to recurrences on 32-wide vectors, run by one
+// wavefront, plus one final elementwise pass.
 
-__global__ void __launch_bounds__(1024) kl_loop_kernel(KlLoopArgs a) {
-  __shared__ float red[32][33];
-  __shared__ float S[4][32], T[4][32], Cmin[4][32], DenLast[4][32], Den[32];
-  __shared__ int flag[32];
-  __shared__ int any_flag;
+// Recurrence of the beta = 1 inner loop: reduces the column statistics of
+// every block (all loads in one round), sums the objective partials, runs the L
+// sweeps on 32-wide vectors in wavefront 0, and leaves the last denominators in
+// den_last.  Every workgroup of kl_apply runs it on the same data in the same
+// order, so all of them agree bitwise without synchronising.
+__device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
+  __shared__ float red[12][32][33];
+  __shared__ float S[4][32], T[4][32], Cmin[4][32];
+  __shared__ double lds64[1024];
   const int t = threadIdx.x;
-  const int c = t & 31, g = t >> 5;  // 32 row groups x 32 columns
-
-  for (int n = 0; n < a.N; ++n) {
-    // T, min of c; S = colsum(ref)
-    float st = 0.0f, sm = 3.402823e38f, sr = 0.0f;
-    for (int r = g; r < a.rows[n]; r += 32) {
-      const float v = a.c[n][(int64_t)r * kRP + c];
-      st += v;
-      sm = fminf(sm, v);
-      sr += a.ref[n][(int64_t)r * kRP + c];
-    }
-    red[g][c] = st;
-    __syncthreads();
-    if (t < 32) {
-      float s = 0.0f;
-      for (int q = 0; q < 32; ++q) s += red[q][t];
-      T[n][t] = s;
-    }
-    __syncthreads();
-    red[g][c] = sm;
-    __syncthreads();
-    if (t < 32) {
-      float s = red[0][t];
-      for (int q = 1; q < 32; ++q) s = fminf(s, red[q][t]);
-      Cmin[n][t] = s;
-    }
-    __syncthreads();
-    red[g][c] = sr;
-    __syncthreads();
-    if (t < 32) {
-      float s = 0.0f;
-      for (int q = 0; q < 32; ++q) s += red[q][t];
-      S[n][t] = s;
-    }
-    __syncthreads();
+  const int c = t & 31, g = t >> 5;
+  int nblk_max = 0;
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+    if (n < a.N) nblk_max = max(nblk_max, a.nblk[n]);
+  float acc[4][3];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    acc[n][0] = 0.0f;
+    acc[n][1] = 3.402823e38f;
+    acc[n][2] = 0.0f;
   }
-
-  for (int l = 0; l < a.L; ++l) {
-    for (int n = 0; n < a.N; ++n) {
-      if (t < 32) {
-        float d = 1.0f;
-        for (int m = 0; m < a.N; ++m)
-          if (m != n) d *= S[m][t];
-        Den[t] = d;
-        DenLast[n][t] = d;
-        flag[t] = (t < a.R) && (Cmin[n][t] < a.eps * d);
-      }
-      __syncthreads();
-      if (t == 0) {
-        int f = 0;
-        for (int q = 0; q < 32; ++q) f |= flag[q];
-        any_flag = f;
-      }
-      __syncthreads();
-      if (any_flag) {
-        // exact column sums of max(c / Den, eps) for the clipped columns
-        float s = 0.0f;
-        if (flag[c])
-          for (int r = g; r < a.rows[n]; r += 32) s += fmaxf(a.c[n][(int64_t)r * kRP + c] / Den[c], a.eps);
-        red[g][c] = s;
-        __syncthreads();
-        if (t < 32 && flag[t]) {
-          float acc = 0.0f;
-          for (int q = 0; q < 32; ++q) acc += red[q][t];
-          S[n][t] = acc;
+  double objs = 0.0;
+  if (a.obj_part)
+    for (int64_t e = t; e < a.obj_n; e += 1024) objs += a.obj_part[e];
+  for (int b0 = g; b0 < nblk_max; b0 += 4 * 32) {
+    float v[4][4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int b = b0 + 32 * u;
+          v[u][n][k] = (n < a.N && b < a.nblk[n]) ? a.stats[n][(int64_t)b * 96 + 32 * k + c]
+                                                 : (k == 1 ? 3.402823e38f : 0.0f);
         }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        acc[n][0] += v[u][n][0];
+        acc[n][1] = fminf(acc[n][1], v[u][n][1]);
+        acc[n][2] += v[u][n][2];
       }
-      if (t < 32 && !flag[t]) S[n][t] = (t < a.R) ? T[n][t] / Den[t] : 0.0f;
-      __syncthreads();
+  }
+  lds64[t] = objs;
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[3 * n + k][g][c] = acc[n][k];
+  __syncthreads();
+  if (t < 12 * 32) {
+    const int q = t >> 5;
+    const int n = q / 3, k = q % 3;
+    float s = red[q][0][c];
+    for (int gg = 1; gg < 32; ++gg) s = (k == 1) ? fminf(s, red[q][gg][c]) : s + red[q][gg][c];
+    if (n < a.N) {
+      if (k == 0) T[n][c] = s;
+      else if (k == 1) Cmin[n][c] = s;
+      else S[n][c] = s;
     }
   }
+  for (int w = 512; w > 0; w >>= 1) {
+    __syncthreads();
+    if (t < w) lds64[t] += lds64[t + w];
+  }
+  __syncthreads();
+  if (a.obj_part && t == 0 && blockIdx.x == 0) a.obj_out[0] = lds64[0];
 
-  for (int n = 0; n < a.N; ++n) {
-    const int64_t total = (int64_t)a.rows_p[n] * kRP;
-    for (int64_t e = t; e < total; e += 1024) {
-      const int row = (int)(e / kRP), cc = (int)(e % kRP);
-      float v = 0.0f;
-      if (row < a.rows[n] && cc < a.R) {
-        v = fmaxf(a.c[n][e] / DenLast[n][cc], a.eps);
-        if (a.user[n]) a.user[n][(int64_t)row * a.R + cc] = v;
+  if (t < 64) {
+    const int col = t & 31;
+    const bool real = col < a.R;
+    float Sr[4], Tr[4], Cr[4], Dl[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      Sr[n] = n < a.N ? S[n][col] : 1.0f;
+      Tr[n] = n < a.N ? T[n][col] : 0.0f;
+      Cr[n] = n < a.N ? Cmin[n][col] : 0.0f;
+      Dl[n] = 1.0f;
+    }
+    for (int l = 0; l < a.L; ++l) {
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        if (n >= a.N) break;
+        float d = 1.0f;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if (m != n && m < a.N) d *= Sr[m];
+        const bool clip = real && (Cr[n] < a.eps * d);
+        float snew = real ? Tr[n] / d : 0.0f;
+        if (__any(clip)) {
+          // exact column sum of max(c / Den, eps) for clipped columns; the two
+          // lane halves take alternate rows, combined in order
+          float s = 0.0f;
+          if (clip)
+            for (int r = t >> 5; r < a.rows[n]; r += 2) s += fmaxf(a.c[n][(int64_t)r * kRP + col] / d, a.eps);
+          const float other = __shfl_xor(s, 32);
+          const float exact = (t < 32) ? s + other : other + s;
+          if (clip) snew = exact;
+        }
+        Sr[n] = snew;
+        Dl[n] = d;
       }
-      a.cur_pad[n][e] = v;
-      if (a.cur_padT[n]) a.cur_padT[n][(int64_t)cc * a.rows_p[n] + row] = v;
+    }
+    if (t < 32) {
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        if (n < a.N) den_last[n][col] = Dl[n];
     }
   }
 }
 
-hipError_t launch_kl_loop(const KlLoopArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(kl_loop_kernel, dim3(1), dim3(1024), 0, s, a);
+// A^(n) = max(c^(n) / Den_last^(n), eps) for all modes; each workgroup first
+// runs the recurrence itself.
+__global__ void __launch_bounds__(1024) kl_apply_kernel(KlLoopArgs a) {
+  __shared__ float den_last[4][32];
+  kl_recurrence(a, den_last);
+  __syncthreads();
+  int64_t total = 0;
+  for (int n = 0; n < a.N; ++n) total += (int64_t)a.rows[n] * kRP;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < total;
+       e0 += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = e0;
+    int n = 0;
+    while (n < a.N && e >= (int64_t)a.rows[n] * kRP) {
+      e -= (int64_t)a.rows[n] * kRP;
+      ++n;
+    }
+    const int row = (int)(e / kRP), cc = (int)(e % kRP);
+    if (cc >= a.R) continue;
+    const float v = fmaxf(a.c[n][e] / den_last[n][cc], a.eps);
+    a.user[n][(int64_t)row * a.R + cc] = v;
+    if (a.cur_pad[n]) a.cur_pad[n][e] = v;
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// Slot reduction + update.  A workgroup covers kSlotRows rows x 32 columns of
+// one job with kSlotGroups groups of threads; group g sums slots g,
+// g + kSlotGroups, ... with eight loads in flight per batch, and the groups are
+// combined in order 0, 1, ... (fixed order: bitwise deterministic).
+
+__device__ __forceinline__ float pow_gamma(float ratio, float gamma) {
+  if (gamma == 1.0f) return ratio;
+  if (gamma == 0.5f) return __builtin_amdgcn_sqrtf(ratio);
+  return ratio > 0.0f ? __builtin_amdgcn_exp2f(gamma * __builtin_amdgcn_logf(ratio)) : 0.0f;
+}
+
+constexpr int kSlotOut = kSlotRows * 32;
+constexpr int kSlotGroups = 1024 / kSlotOut;
+
+__device__ __forceinline__ float sum_slots(const float* __restrict__ part, int slots, int64_t slot_stride, int64_t e,
+                                           int g) {
+  float acc = 0.0f;
+  for (int s0 = g; s0 < slots; s0 += 8 * kSlotGroups) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int s = s0 + u * kSlotGroups;
+      v[u] = s < slots ? part[(int64_t)s * slot_stride + e] : 0.0f;
+    }
+    acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  }
+  return acc;
+}
+
+__device__ __forceinline__ float combine_groups(const float (*l)[kSlotOut], int o) {
+  float s = l[0][o];
+#pragma unroll
+  for (int q = 1; q < kSlotGroups; ++q) s += l[q][o];
+  return s;
+}
+
+__global__ void __launch_bounds__(1024) slot_update_kernel(SlotUpdateArgs a) {
+  __shared__ float lnum[kSlotGroups][kSlotOut];
+  __shared__ float lden[kSlotGroups][kSlotOut];
+  __shared__ float lc[kSlotOut], la[kSlotOut];
+  int b = blockIdx.x;
+  int j = 0;
+  while (j < a.njobs && b >= (a.job[j].rows_p + kSlotRows - 1) / kSlotRows) {
+    b -= (a.job[j].rows_p + kSlotRows - 1) / kSlotRows;
+    ++j;
+  }
+  if (j >= a.njobs) return;
+  const SlotJob& J = a.job[j];
+  const int t = threadIdx.x;
+  const int g = t / kSlotOut, o = t % kSlotOut;
+  const int row = kSlotRows * b + (o >> 5), c = o & 31;
+  const bool live = row < J.rows && c < J.cols;
+  const int64_t e = (int64_t)row * kRP + c;
+  const int64_t stride = (int64_t)J.rows_total * kRP;
+  float anc = 0.0f;
+  if (g == 0 && live) anc = J.anchor.p[(int64_t)row * J.anchor.ld + c];
+  lnum[g][o] = live ? sum_slots(J.num_part, J.num_slots, stride, e, g) : 0.0f;
+  if (J.den_part) lden[g][o] = live ? sum_slots(J.den_part, J.den_slots, stride, e, g) : 0.0f;
+  __syncthreads();
+  if (g == 0) {
+    float v = 0.0f;
+    if (live) {
+      const float num = combine_groups(lnum, o);
+      if (J.mode == kSlotScale) {
+        v = anc * num;
+      } else {
+        const float den = J.den_part ? combine_groups(lden, o) : J.den_closed[c];
+        v = fmaxf(anc * pow_gamma(num / den, J.gamma), J.eps);
+      }
+      if (J.out_user) J.out_user[(int64_t)row * J.ld_user + c] = v;
+    }
+    if (row < J.rows_p) {
+      if (J.out_pad) J.out_pad[e] = v;
+      if (J.out_padT) J.out_padT[(int64_t)c * J.rows_p + row] = v;
+    }
+    lc[o] = v;
+    la[o] = anc;
+  }
+  if (J.stats) {
+    __syncthreads();
+    if (t < 32) {
+      float st = 0.0f, sm = 3.402823e38f, sa = 0.0f;
+      for (int r = 0; r < kSlotRows; ++r) {
+        if (kSlotRows * b + r < J.rows) {
+          st += lc[r * 32 + t];
+          sm = fminf(sm, lc[r * 32 + t]);
+          sa += la[r * 32 + t];
+        }
+      }
+      float* out = J.stats + (int64_t)b * 96;
+      out[t] = st;
+      out[32 + t] = sm;
+      out[64 + t] = sa;
+    }
+  }
+}
+
+hipError_t launch_slot_update(const SlotUpdateArgs& a, hipStream_t s) {
+  int blocks = 0;
+  for (int j = 0; j < a.njobs; ++j) blocks += (a.job[j].rows_p + kSlotRows - 1) / kSlotRows;
+  hipLaunchKernelGGL(slot_update_kernel, dim3(blocks), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s) {
+  int64_t n = 0;
+  for (int q = 0; q < a.N; ++q) n += (int64_t)a.rows[q] * kRP;
+  int blocks = (int)((n + 1023) / 1024);
+  if (blocks > 64) blocks = 64;
+  hipLaunchKernelGGL(kl_apply_kernel, dim3(blocks), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
