@@ -12,99 +12,14 @@
 #include <vector>
 
 #include "../../include/comm.h"
+#include "host_util.h"
 #include "kernels.h"
 #include "tucker3.h"
 #include "sparse.h"
 
 using namespace comm;
 
-struct comm_ctx {
-  int device = 0;
-  size_t limit = 0;
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  hipStream_t last_stream = nullptr;
-  // measurement: event pairs around every fused dense pass launch
-  bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-  size_t events_used = 0;
-};
-
-namespace {
-
 thread_local std::string g_last_error = "no error";
-
-int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_last_error = buf;
-  return code;
-}
-
-#define HIP_TRY(expr)                                                                        \
-  do {                                                                                       \
-    hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess) return fail(COMM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
-  } while (0)
-
-// Bump allocator over the context workspace (256-byte aligned pieces).
-struct Carve {
-  size_t off = 0;
-  char* base = nullptr;
-  template <class T>
-  T* take(size_t count) {
-    off = (off + 255) & ~size_t(255);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += count * sizeof(T);
-    return p;
-  }
-};
-
-int ensure_ws(comm_ctx* ctx, size_t bytes, hipStream_t stream) {
-  if (bytes <= ctx->ws_bytes) return COMM_OK;
-  if (ctx->limit && bytes > ctx->limit)
-    return fail(COMM_ENOMEM, "workspace of %zu bytes exceeds the context limit of %zu", bytes, ctx->limit);
-  if (ctx->ws) {
-    HIP_TRY(hipStreamSynchronize(ctx->last_stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    HIP_TRY(hipFree(ctx->ws));
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-  }
-  size_t want = bytes + bytes / 4;
-  if (ctx->limit && want > ctx->limit) want = ctx->limit;
-  hipError_t e = hipMalloc(&ctx->ws, want);
-  if (e != hipSuccess) return fail(COMM_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
-  ctx->ws_bytes = want;
-  return COMM_OK;
-}
-
-int beta_class_of(double beta) {
-  if (beta == 0.0) return kIS;
-  if (beta == 0.5) return kHalf;
-  if (beta == 1.0) return kKL;
-  if (beta == 1.5) return kThreeHalf;
-  return kGeneral;
-}
-
-BetaConst make_beta_const(double beta) {
-  BetaConst bc = {};
-  bc.beta = (float)beta;
-  bc.inv_bb1 = (beta != 0.0 && beta != 1.0) ? (float)(1.0 / (beta * (beta - 1.0))) : 0.0f;
-  bc.inv_beta = beta > 0.0 ? (float)(1.0 / beta) : 0.0f;
-  // c_k = (beta^(k-1) - (beta-1)^(k-1)) / k!, k = 2..17
-  double fact = 1.0;
-  for (int k = 1; k <= 17; ++k) {
-    fact *= k;
-    if (k >= 2) bc.series[k - 2] = (float)((std::pow(beta, k - 1) - std::pow(beta - 1.0, k - 1)) / fact);
-  }
-  return bc;
-}
-
-float gamma_of(double beta) { return beta < 1.0 ? (float)(1.0 / (2.0 - beta)) : 1.0f; }
 
 int check_opts(const comm_opts* o, bool need_L) {
   if (!o) return fail(COMM_EINVAL, "opts is NULL");
@@ -125,6 +40,9 @@ int check_dense(const comm_dense* x) {
   if (x->ndim != 3) return fail(COMM_EUNSUPPORTED, "dense tensors of order %d are not supported (3 only)", x->ndim);
   return COMM_OK;
 }
+
+
+namespace {
 
 int check_cp_model(const comm_model* m, int ndim) {
   if (!m) return fail(COMM_EINVAL, "model is NULL");
@@ -189,24 +107,8 @@ CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
   return w;
 }
 
-// Launch a fused dense pass, bracketed by timing events when profiling is on.
 int run_pass(comm_ctx* ctx, const CpPassArgs& a, const CpGrid& g, int bc, bool den, hipStream_t st) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->profiling) {
-    if (ctx->events_used == ctx->events.size()) {
-      hipEvent_t a0, a1;
-      HIP_TRY(hipEventCreate(&a0));
-      HIP_TRY(hipEventCreate(&a1));
-      ctx->events.emplace_back(a0, a1);
-    }
-    e0 = ctx->events[ctx->events_used].first;
-    e1 = ctx->events[ctx->events_used].second;
-    ++ctx->events_used;
-    HIP_TRY(hipEventRecord(e0, st));
-  }
-  HIP_TRY(launch_cp_pass(a, g, bc, den, st));
-  if (e1) HIP_TRY(hipEventRecord(e1, st));
-  return COMM_OK;
+  return profiled(ctx, st, [&] { return launch_cp_pass(a, g, bc, den, st); });
 }
 
 FView user_view(const comm_model* m, int n) { return FView{m->factors[n], m->rank, m->rank}; }

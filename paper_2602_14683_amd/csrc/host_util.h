@@ -1,0 +1,127 @@
+// Host-side utilities shared by the C ABI implementation files: the context,
+// error reporting, workspace management and beta helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/comm.h"
+#include "kernels.h"
+
+struct comm_ctx {
+  int device = 0;
+  size_t limit = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t last_stream = nullptr;
+  // measurement: event pairs around every fused dense pass launch
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+};
+
+extern thread_local std::string g_last_error;
+
+inline int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(COMM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// Bump allocator over the context workspace (256-byte aligned pieces).
+struct Carve {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+inline int ensure_ws(comm_ctx* ctx, size_t bytes, hipStream_t stream) {
+  if (bytes <= ctx->ws_bytes) return COMM_OK;
+  if (ctx->limit && bytes > ctx->limit)
+    return fail(COMM_ENOMEM, "workspace of %zu bytes exceeds the context limit of %zu", bytes, ctx->limit);
+  if (ctx->ws) {
+    HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  if (ctx->limit && want > ctx->limit) want = ctx->limit;
+  hipError_t e = hipMalloc(&ctx->ws, want);
+  if (e != hipSuccess) return fail(COMM_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+  ctx->ws_bytes = want;
+  return COMM_OK;
+}
+
+inline int beta_class_of(double beta) {
+  if (beta == 0.0) return comm::kIS;
+  if (beta == 0.5) return comm::kHalf;
+  if (beta == 1.0) return comm::kKL;
+  if (beta == 1.5) return comm::kThreeHalf;
+  return comm::kGeneral;
+}
+
+inline comm::BetaConst make_beta_const(double beta) {
+  comm::BetaConst bc = {};
+  bc.beta = (float)beta;
+  bc.inv_bb1 = (beta != 0.0 && beta != 1.0) ? (float)(1.0 / (beta * (beta - 1.0))) : 0.0f;
+  bc.inv_beta = beta > 0.0 ? (float)(1.0 / beta) : 0.0f;
+  // c_k = (beta^(k-1) - (beta-1)^(k-1)) / k!, k = 2..17
+  double fact = 1.0;
+  for (int k = 1; k <= 17; ++k) {
+    fact *= k;
+    if (k >= 2) bc.series[k - 2] = (float)((std::pow(beta, k - 1) - std::pow(beta - 1.0, k - 1)) / fact);
+  }
+  return bc;
+}
+
+inline float gamma_of(double beta) { return beta < 1.0 ? (float)(1.0 / (2.0 - beta)) : 1.0f; }
+
+
+// Launch `launch()` bracketed by timing events when profiling is on (used for
+// every kernel that streams the dense tensor).
+template <class F>
+int profiled(comm_ctx* ctx, hipStream_t st, F&& launch) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profiling) {
+    if (ctx->events_used == ctx->events.size()) {
+      hipEvent_t a0, a1;
+      HIP_TRY(hipEventCreate(&a0));
+      HIP_TRY(hipEventCreate(&a1));
+      ctx->events.emplace_back(a0, a1);
+    }
+    e0 = ctx->events[ctx->events_used].first;
+    e1 = ctx->events[ctx->events_used].second;
+    ++ctx->events_used;
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  HIP_TRY(launch());
+  if (e1) HIP_TRY(hipEventRecord(e1, st));
+  return COMM_OK;
+}
+
+int check_opts(const comm_opts* o, bool need_L);
+int check_dense(const comm_dense* x);

@@ -171,4 +171,68 @@ hipError_t launch_slot_update(const SlotUpdateArgs& a, hipStream_t s);
 hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, double* out, hipStream_t s);
 
 
+// ----------------------------------------------------------------------------------------
+// Dense 3-way Tucker (tucker3_impl.h, tucker3.hip)
+// ----------------------------------------------------------------------------------------
+
+// A Tucker model as seen by the kernels: core entry (a, b, c) at
+// G[(a * J2 + b) * ldG + c]; factors as views with cols = J_n.
+struct TkModel {
+  const float* G;
+  int ldG;
+  FView A, B, C;
+  int J1, J2, J3;
+};
+
+struct TkPassArgs {
+  const float* X;          // I x J x K
+  const float* Wc;         // cached weight tensor (cache read)
+  float* Pw;               // cache targets (cache write)
+  float* Qw;
+  int I, J, K, Kp;
+  TkModel r;               // rebuild model
+  TkModel n;               // contraction set
+  float eps, eps_x;
+  int use_q;               // contract Q instead of P
+  int want_v, want_m3;
+  BetaConst bc;
+  float* V;                // [I][J][32]
+  float* m3;               // [workgroups][Kp][32] partial slots
+  double* obj_part;        // one float64 partial per workgroup
+};
+
+struct TkGrid {
+  int gi, gj;
+  int wgs() const { return gi * gj; }
+};
+TkGrid tk_grid(int I, int J);
+// mode (bits 0-1): 0 = from X, 1 = read the cached weight Wc, 2 = from X and
+// write P~ / Q~; bit 2 set: also accumulate the objective (not with mode 1).
+hipError_t launch_tk_pass(const TkPassArgs& a, const TkGrid& g, int beta_class, int mode, hipStream_t s);
+
+// Small strided GEMM with split-K partial slots (fixed order, deterministic):
+//   out[split][batch][m][n] = sum_{k in split} A(batch, m, k) B(batch, k, n)
+// with A(b, m, k) = A[b * sab + m * sam + (k / akin) * sako + (k % akin) * saki]
+// and  B(b, k, n) = B[b * sbb + (k / bkin) * sbko + (k % bkin) * sbki + n * sbn];
+// out row stride ldo, batch stride sob, split stride sos.
+struct GemmArgs {
+  const float* A;
+  int64_t sab, sam, sako, saki;
+  int akin;
+  const float* B;
+  int64_t sbb, sbko, sbki, sbn;
+  int bkin;
+  float* out;
+  int64_t sob, sos, ldo;
+  int M, N, K, batch, splits;
+};
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
+
+// Closed-form beta = 1 Tucker denominators from the column sums S of the
+// denominator set (Q = 1): den[0][a] = sum_bc G[a][b][c] S_B[b] S_C[c],
+// den[1][b] = sum_ac G S_A S_C, den[2][c] = sum_ab G S_A S_B and
+// dcore[(a J2 + b)][c] = S_A[a] S_B[b] S_C[c].
+hipError_t launch_tk_den_closed(const TkModel& m, int I, int J, int K, float* den /*[3][32]*/,
+                                float* dcore /*[J1 J2][32]*/, hipStream_t s);
+
 }  // namespace comm
