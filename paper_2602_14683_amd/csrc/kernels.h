@@ -132,18 +132,20 @@ struct KlLoopArgs {
   float* user[4];          // caller buffers (row stride R)
   const double* obj_part;  // optional: objective partials to sum into *obj_out
   int64_t obj_n;
-  double* obj_out;
+  double* obj_out;         // written if not NULL
+  int obj_add_model_mass;  // also add sum_r prod_n colsum(A~^(n))_r (sparse objective)
 };
 hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s);
 
 // Reduction of partial slots [slots][rows_total][32] (fixed order) fused with
 //   kSlotScale:  out = anchor * Num, plus per-block column statistics
 //                (sum of out, min of out over valid rows, sum of anchor)
+//   kSlotCopy:   out = Num, with the same statistics
 //   kSlotUpdate: out = max(anchor * (Num / Den)^gamma, eps), Den from its own
 //                slots or den_closed[c]
 // A workgroup covers kSlotRows rows x 32 columns of one job.
 constexpr int kSlotRows = 2;
-enum SlotMode : int { kSlotScale = 0, kSlotUpdate = 1 };
+enum SlotMode : int { kSlotScale = 0, kSlotUpdate = 1, kSlotCopy = 2 };
 struct SlotJob {
   int mode;
   const float* num_part;  int num_slots;

@@ -228,7 +228,20 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
     if (t < w) lds64[t] += lds64[t + w];
   }
   __syncthreads();
-  if (a.obj_part && t == 0 && blockIdx.x == 0) a.obj_out[0] = lds64[0];
+  if (a.obj_out && t == 0 && blockIdx.x == 0) {
+    double s = lds64[0];
+    if (a.obj_add_model_mass) {
+      // sum over all cells of the reference model: sum_r prod_n colsum(A~^(n))_r
+      double mass = 0.0;
+      for (int r = 0; r < a.R; ++r) {
+        double p = 1.0;
+        for (int n = 0; n < a.N; ++n) p *= (double)S[n][r];
+        mass += p;
+      }
+      s += mass;
+    }
+    a.obj_out[0] = s;
+  }
 
   if (t < 64) {
     const int col = t & 31;
@@ -363,6 +376,8 @@ __global__ void __launch_bounds__(1024) slot_update_kernel(SlotUpdateArgs a) {
       const float num = combine_groups(lnum, o);
       if (J.mode == kSlotScale) {
         v = anc * num;
+      } else if (J.mode == kSlotCopy) {
+        v = num;
       } else {
         const float den = J.den_part ? combine_groups(lden, o) : J.den_closed[c];
         v = fmaxf(anc * pow_gamma(num / den, J.gamma), J.eps);
