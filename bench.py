@@ -14,6 +14,9 @@ Prints ONE JSON line: outer iterations/s, the roofline of the dominant kernel
 stream), and the FP64 oracle timed on the host cores on a bounded sample.
 
   python bench.py [--gpus 1] [--steps 200] [--warmup 5]
+  python bench.py --workload tucker [--beta 0|1.5]   # 200^3 Tucker, 16^3 core, J-CoMM L = 1
+  python bench.py --workload coo                     # 3.3M-nonzero 4-way COO counts, beta = 1
+  python bench.py --workload serving                 # Poisson stream of mixed requests, solves/s, p50/p99
   python bench.py --calibrate-copy   # plain device copy of known size, for counter scaling
 """
 from __future__ import annotations
@@ -33,12 +36,18 @@ METRIC = "J-CoMM outer iters/s (CP 256³ R32 β=1) + %roofline; batched solves/s
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cp3_pass_kl_256_r32_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2602_14683_amd", "csrc", "cp3.hip")
+# sources that define the timed pass kernel; the stored counter figures are
+# trusted only while these files are unchanged
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2602_14683_amd", "csrc", f)
+               for f in ("cp3_impl.h", "cp3_bc_kl.hip", "dmath.h", "kernels.h")]
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -72,6 +81,36 @@ def cpu_baseline(X64, init, beta, L, iters):
                       f"256x256x256 rank-32 tensor, NumPy float64 einsum, {dt:.1f} s"}
 
 
+def comparisons(ctx, X, init32, steps):
+    """Config-2 companions on the same tensor and GPU: J-CoMM at beta = 0.5 and
+    the plain block-MM (B-CoMM) sweep at beta = 1 and 0.5, each from the same
+    initial factors, in iterations per second (wall clock around `steps`)."""
+    import torch
+
+    def rate(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return round(steps / (time.perf_counter() - t0), 2)
+
+    res = {}
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for beta in (0.5,):
+        fac = [torch.from_numpy(a).cuda() for a in init32]
+        res[f"jcomm_beta{beta}_L5_obj_it_s"] = rate(
+            lambda: ctx.jcomm_outer(X, fac, beta=beta, L=5, obj_out=obj))
+    for beta in (1.0, 0.5):
+        fac = [torch.from_numpy(a).cuda() for a in init32]
+        res[f"bcomm_beta{beta}_sweep_it_s"] = rate(lambda: ctx.cp_update(X, fac, block=-1, beta=beta))
+    res["note"] = ("B-CoMM sweeps rebuild Xhat before each of the 3 blocks and compute no objective; "
+                   f"{steps} timed iterations each")
+    return res
+
+
 def calibrate_copy():
     import torch
     n = 64 * 1024 * 1024  # 256 MiB of float32
@@ -83,14 +122,227 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
 
 
+def timed_loop(ctx, step, warmup, steps):
+    """Warm up, then time `steps` calls of step(t) between synchronisations;
+    the library records HIP events around every pass-kernel launch on the
+    launch stream meanwhile.  Returns (elapsed s, pass-kernel ms, launches)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for t in range(warmup):
+        step(t)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for t in range(steps):
+        step(warmup + t)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches = ctx.profile_query()
+    ctx.profile_enable(False)
+    return max(wall, ev0.elapsed_time(ev1) / 1e3), kernel_ms, launches
+
+
+def monotone(tr):
+    import numpy as np
+    return bool(np.all(np.diff(tr) <= np.abs(tr[:-1]) * 1e-6))
+
+
+def base_line(args, elapsed, unit="outer it/s"):
+    return {"metric": METRIC, "value": round(args.steps / elapsed, 2), "unit": unit,
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "fp32"}
+
+
+def run_cp(args, ctx):
+    import numpy as np
+    import torch
+    import workloads
+
+    beta, L, R = 1.0, 5, 32
+    d = workloads.cp_dense(0, dims=(256, 256, 256), rank=R)
+    X32 = d.X.astype(np.float32)
+    init32 = [a.astype(np.float32) for a in d.init]
+    X = torch.from_numpy(X32).cuda()
+    fac = [torch.from_numpy(a).cuda() for a in init32]
+    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+
+    def step(t):
+        ctx.jcomm_outer(X, fac, beta=beta, L=L, obj_out=trace[t:t + 1])
+
+    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    tr = trace.cpu().numpy()
+    steps_tr = tr[args.warmup:args.warmup + args.steps]
+
+    entries = 256 ** 3
+    avg_ms = kernel_ms / max(launches, 1)
+    flops = 6.0 * R * entries           # rebuild 2R + mode-3 2R + shared modes-1/2 2R per entry
+    achieved_tflops = flops / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved_tflops, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "cp3_pass_kernel<KL> (fused rebuild + P~ + 3 numerators + FP64 objective)",
+                "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 4 * entries,
+                "hbm_gbs_algorithmic": round(4 * entries / (avg_ms * 1e-3) / 1e9, 1)}
+    out = base_line(args, elapsed)
+    out.update({"data": "synthetic (seeded Poisson around a planted Gamma(1,1) rank-32 CP model)",
+                "config": {"workload": "jcomm_cp_dense_256x256x256_r32_beta1_L5_obj", "dims": [256, 256, 256],
+                           "rank": R, "beta": beta, "inner_sweeps": L, "objective_every_iteration": True,
+                           "parallelism": "single GPU"},
+                "roofline": roofline,
+                "objective": {"first": float(tr[0]), "last": float(steps_tr[-1]), "monotone": monotone(steps_tr)}})
+    if not args.no_comparisons:
+        out["same_gpu_comparisons"] = comparisons(ctx, X, init32, args.comparison_steps)
+    if not args.no_cpu_baseline:
+        X64 = X32.astype(np.float64)
+        init64 = [a.astype(np.float64) for a in init32]
+        out["cpu_baseline"] = cpu_baseline(X64, init64, beta, L, args.cpu_iters)
+    return out
+
+
+def run_tucker(args, ctx):
+    """Dense 200^3 Tucker, 16^3 core, J-CoMM L = 1 with the objective."""
+    import numpy as np
+    import torch
+    import workloads
+
+    beta = args.beta if args.beta is not None else 0.0
+    d = workloads.tucker_dense(0)
+    X = torch.from_numpy(d.X.astype(np.float32)).cuda()
+    G = torch.from_numpy(d.init_core.astype(np.float32)).cuda()
+    F = [torch.from_numpy(a.astype(np.float32)).cuda() for a in d.init_factors]
+    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+
+    def step(t):
+        ctx.jcomm_outer(X, F, core=G, beta=beta, L=1, obj_out=trace[t:t + 1])
+
+    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
+    entries = 200 ** 3
+    J = 16
+    avg_ms = kernel_ms / max(launches, 1)
+    bytes_ = 4 * entries                 # X streamed once per pass
+    flops = 4.0 * J * entries            # rebuild 2J + one contraction chain 2J per entry
+    gbs = bytes_ / (avg_ms * 1e-3) / 1e9
+    out = base_line(args, elapsed)
+    out.update({"data": "synthetic (Gamma(shape 10) around a planted 16^3-core Tucker model)",
+                "config": {"workload": f"jcomm_tucker_dense_200x200x200_core16_beta{beta}_L1_obj",
+                           "dims": [200, 200, 200], "core": [16, 16, 16], "beta": beta, "inner_sweeps": 1,
+                           "parallelism": "single GPU"},
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                             "kernel": "tk_pass_kernel (fused rebuild + P~ or Q~ + one contraction)",
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "algorithmic_bytes_per_launch": bytes_, "algorithmic_flops_per_launch": flops,
+                             "tflops_algorithmic": round(flops / (avg_ms * 1e-3) / 1e12, 2)},
+                "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    return out
+
+
+def run_coo(args, ctx):
+    """Sparse 183x24x1140x1717 counts, 3.3M nonzeros, CP rank 32, beta = 1, L = 1."""
+    import numpy as np
+    import torch
+    import workloads
+
+    s = workloads.sparse_counts(0)
+    idx = [torch.tensor(s.idx[:, n].astype(np.int32), device="cuda") for n in range(4)]
+    val = torch.from_numpy(s.val.astype(np.float32)).cuda()
+    fac = [torch.from_numpy(a.astype(np.float32)).cuda() for a in s.init]
+    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+
+    def step(t):
+        ctx.cp_jcomm_outer_coo(idx, val, s.dims, fac, L=1, obj_out=trace[t:t + 1])
+
+    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
+    nnz = int(val.numel())
+    avg_ms = kernel_ms / max(launches, 1)
+    bytes_ = 20 * nnz                    # 4 int32 indices + 1 float value per nonzero
+    gbs = bytes_ / (avg_ms * 1e-3) / 1e9
+    out = base_line(args, elapsed)
+    out.update({"data": "synthetic (Zipf lat/lon, diurnal hour, Poisson(2)+1 counts)",
+                "config": {"workload": "jcomm_cp_coo_183x24x1140x1717_nnz3.3M_r32_beta1_L1_obj",
+                           "dims": list(s.dims), "nnz": nnz, "rank": 32, "beta": 1.0, "inner_sweeps": 1,
+                           "parallelism": "single GPU"},
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                             "kernel": "coo_pass_kernel (gather, model value, scatter of 4 numerators)",
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "algorithmic_bytes_per_launch": bytes_},
+                "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    return out
+
+
+def serving_stream(args, ctx):
+    """A Poisson stream of CP / Tucker requests (dims U{16..256}, rank or core
+    size in {4, 8, 16, 32}, beta in {0, 1/2, 1, 3/2}), each run to a relative
+    objective change <= 1e-4 (or max_iters), served twice on the same GPU:
+    continuous batching (graph-replayed batched step) and the plain per-request
+    FP32 loop.  Request tensors are drawn on the host before the clock starts;
+    copying them to the device is part of each request's service."""
+    import workloads
+    from paper_2602_14683_amd import serving
+
+    specs = workloads.serving_specs(seed=0, count=args.serve_requests, rate=args.serve_rate)
+    decs = [serving.from_workload(workloads.materialize(s)) for s in specs]
+    reqs = [serving.ServeRequest(s.rid, s.arrival, d) for s, d in zip(specs, decs)]
+    budget = int(args.serve_hbm_gib * (1 << 30))
+    res = {}
+    for name, ex, slots in (("batched", serving.BatchedExecutor(ctx, args.serve_slots, graph=True), args.serve_slots),
+                            ("per_request_fp32", serving.SingleExecutor(ctx, 1), 1)):
+        srv = serving.Server(ex, budget, slots, tol=1e-4, max_iters=args.serve_max_iters)
+        done = srv.run(reqs)
+        st = serving.summarize(done)
+        st.update({"peak_slots": srv.peak_slots, "peak_bytes": srv.peak_bytes, "steps": srv.steps})
+        res[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    res["speedup_solves_per_s"] = round(res["batched"]["solves_per_s"] / res["per_request_fp32"]["solves_per_s"], 3)
+    res["stream"] = {"requests": len(reqs), "rate_per_s": args.serve_rate, "tol": 1e-4,
+                     "max_iters": args.serve_max_iters, "slots": args.serve_slots,
+                     "hbm_budget_gib": args.serve_hbm_gib,
+                     "cp": sum(s.model == "cp" for s in specs), "tucker": sum(s.model == "tucker" for s in specs)}
+    return res
+
+
+def run_serving(args, ctx):
+    res = serving_stream(args, ctx)
+    b = res["batched"]
+    out = {"metric": METRIC, "value": b["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "steps": b["steps"], "warmup": 0, "ms_per_step": round(b["span_s"] / max(b["steps"], 1) * 1e3, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+           "data": "synthetic (planted U(0,1) CP / Tucker models plus Poisson noise, Poisson arrivals)",
+           "config": {"workload": f"serving_stream_{res['stream']['requests']}req_rate{args.serve_rate:g}",
+                      "parallelism": "single GPU"},
+           "serving": res}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving"], default="cp",
+                    help="cp: the headline 256^3 rank-32 CP workload; tucker / coo: the other pass kernels")
+    ap.add_argument("--beta", type=float, default=None, help="beta for --workload tucker (default 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="skip the beta = 0.5 and block-MM rates on the same tensor")
+    ap.add_argument("--comparison-steps", type=int, default=40)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream in the default run")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-rate", type=float, default=100.0, help="arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-max-iters", type=int, default=500)
+    ap.add_argument("--serve-hbm-gib", type=float, default=64.0, help="device memory budget for admission")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -101,74 +353,11 @@ def main() -> int:
         calibrate_copy()
         return 0
 
-    import numpy as np
-    import torch
-
     import paper_2602_14683_amd as comm
-    import workloads
-
-    beta, L, R = 1.0, 5, 32
-    d = workloads.cp_dense(0, dims=(256, 256, 256), rank=R)
-    X32 = d.X.astype(np.float32)
-    init32 = [a.astype(np.float32) for a in d.init]
-    X = torch.from_numpy(X32).cuda()
-    fac = [torch.from_numpy(a).cuda() for a in init32]
-    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
     ctx = comm.Context(0)
-    stream = torch.cuda.current_stream()
-
-    for t in range(args.warmup):
-        ctx.jcomm_outer(X, fac, beta=beta, L=L, obj_out=trace[t:t + 1])
-    torch.cuda.synchronize()
-
-    ctx.profile_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for t in range(args.steps):
-        k = args.warmup + t
-        ctx.jcomm_outer(X, fac, beta=beta, L=L, obj_out=trace[k:k + 1])
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms, launches = ctx.profile_query()
-    ctx.profile_enable(False)
-    gpu_ms = ev0.elapsed_time(ev1)
-    elapsed = max(wall, gpu_ms / 1e3)
-
-    tr = trace.cpu().numpy()
-    steps_tr = tr[args.warmup:args.warmup + args.steps]
-    monotone = bool(np.all(np.diff(steps_tr) <= np.abs(steps_tr[:-1]) * 1e-6))
-
-    entries = 256 ** 3
-    avg_ms = kernel_ms / max(launches, 1)
-    flops = 6.0 * R * entries           # rebuild 2R + mode-3 2R + shared modes-1/2 2R per entry
-    achieved_tflops = flops / (avg_ms * 1e-3) / 1e12
-    traffic = measured_traffic()
-    roofline = {"bound": "mfma", "achieved": round(achieved_tflops, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
-                "traffic": traffic,
-                "kernel": "cp3_pass_kernel<KL> (fused rebuild + P~ + 3 numerators + FP64 objective)",
-                "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
-                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 4 * entries,
-                "hbm_gbs_algorithmic": round(4 * entries / (avg_ms * 1e-3) / 1e9, 1)}
-
-    out = {"metric": METRIC, "value": round(args.steps / elapsed, 2), "unit": "outer it/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
-           "data": "synthetic (seeded Poisson around a planted Gamma(1,1) rank-32 CP model)",
-           "config": {"workload": "jcomm_cp_dense_256x256x256_r32_beta1_L5_obj", "dims": [256, 256, 256],
-                      "rank": R, "beta": beta, "inner_sweeps": L, "objective_every_iteration": True,
-                      "parallelism": "single GPU"},
-           "roofline": roofline,
-           "objective": {"first": float(tr[0]), "last": float(steps_tr[-1]), "monotone": monotone}}
-    if not args.no_cpu_baseline:
-        X64 = X32.astype(np.float64)
-        init64 = [a.astype(np.float64) for a in init32]
-        out["cpu_baseline"] = cpu_baseline(X64, init64, beta, L, args.cpu_iters)
+    out = {"cp": run_cp, "tucker": run_tucker, "coo": run_coo, "serving": run_serving}[args.workload](args, ctx)
+    if args.workload == "cp" and not args.no_serving:
+        out["serving"] = serving_stream(args, ctx)
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0

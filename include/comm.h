@@ -105,6 +105,17 @@ typedef struct {
   const float* val;
 } comm_coo;
 
+/* One problem of a batched call: the arguments of comm_jcomm_outer. */
+typedef struct {
+  const comm_dense* x;
+  comm_model* model;
+  const comm_opts* opts;
+  double* obj_ref_dev; /* may be NULL */
+} comm_problem;
+
+/* Flags of comm_jcomm_outer_batched. */
+#define COMM_BATCH_GRAPH 1 /* capture the batch into a HIP graph; replay it while the problem list is unchanged */
+
 /* Create a context on HIP device `device`.  The context owns a scratch
  * workspace that grows on demand up to `workspace_limit_bytes` (0 = no limit).
  * Returns COMM_OK and sets *out, or an error code. */
@@ -118,7 +129,9 @@ const char* comm_last_error(void);
 
 /* Workspace bytes a call with these arguments would need (0 on invalid
  * arguments).  `op` is 0 = cp_update / tucker_update, 1 = jcomm_outer,
- * 2 = beta_objective. */
+ * 2 = beta_objective.  Only shapes, model kind, rank / core sizes and options
+ * are read; buffer pointers may be NULL (a server sizes requests before
+ * loading them). */
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op);
 
 /* Measurement hooks.  While enabled, the context records a pair of HIP events
@@ -154,6 +167,28 @@ int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, in
  * that device address. */
 int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
                      double* obj_ref_dev, void* stream);
+
+/* One J-CoMM outer iteration (as comm_jcomm_outer) for each of `count`
+ * independent problems of any mix of shapes, ranks, core sizes, beta and L:
+ * the batched step of a decomposition server (not a passage of the paper; the
+ * per-problem arithmetic is that of comm_jcomm_outer).
+ *   - Each problem runs the same kernels with the same launch shapes and
+ *     reduction order as a single call, on its own slice of a batch workspace,
+ *     so its results are bitwise identical to comm_jcomm_outer on it alone,
+ *     whatever else is in the batch.
+ *   - Problems are spread over internal streams forked from and joined back to
+ *     `stream`, so their kernels overlap on the device.  Problems must not
+ *     share parameter or objective buffers.
+ *   - flags = COMM_BATCH_GRAPH: the launches are captured once into a HIP graph
+ *     and the graph is replayed on `stream` by every later call with the same
+ *     problem list (same buffers, shapes and options, compared field by field);
+ *     a different list waits for earlier replays and is captured anew.
+ *   - The batch workspace is the sum of comm_workspace_bytes(..., op = 1) over
+ *     the problems (each rounded up to 256 bytes) and grows on demand within
+ *     the context limit; growing it waits for earlier batched work.
+ *   - Validation covers every problem before anything is launched; the message
+ *     names the first bad problem. */
+int comm_jcomm_outer_batched(comm_ctx* ctx, const comm_problem* problems, int count, int flags, void* stream);
 
 /* D_beta(X, Xhat(model)) summed over all entries (Sec. 3.2, Definition of the
  * beta-divergence), accumulated in float64, written to the device address

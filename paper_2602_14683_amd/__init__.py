@@ -10,7 +10,7 @@ raises an error rather than falling back to anything else.
 
 Entry points (same names as the C ABI in ``include/comm.h``):
 ``cp_update``, ``tucker_update``, ``jcomm_outer``, ``beta_objective``,
-``cp_jcomm_outer_coo``.
+``cp_jcomm_outer_coo``, ``jcomm_outer_batched`` (with :class:`Batch`).
 """
 from __future__ import annotations
 
@@ -24,10 +24,12 @@ LIB_PATH = os.path.join(HERE, "libcomm.so")
 COMM_OK, COMM_EINVAL, COMM_EUNSUPPORTED, COMM_ENOMEM, COMM_EHIP = 0, 1, 2, 3, 4
 COMM_CP, COMM_TUCKER = 0, 1
 COMM_FP32 = 0
+COMM_BATCH_GRAPH = 1
 
 EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_profile_enable",
             "comm_profile_query", "comm_cp_update",
-            "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo"]
+            "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo",
+            "comm_jcomm_outer_batched"]
 
 
 class CommError(RuntimeError):
@@ -53,6 +55,11 @@ class Opts(ctypes.Structure):
 class Coo(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * 4), ("nnz", ctypes.c_int64),
                 ("idx", ctypes.c_void_p * 4), ("val", ctypes.c_void_p)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("x", ctypes.POINTER(Dense)), ("model", ctypes.POINTER(Model)), ("opts", ctypes.POINTER(Opts)),
+                ("obj_ref_dev", ctypes.c_void_p)]
 
 
 _lib = None
@@ -82,10 +89,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                         ctypes.c_void_p]
     lib.comm_cp_jcomm_outer_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
                                             ctypes.c_void_p]
+    lib.comm_jcomm_outer_batched.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
-                 "comm_beta_objective", "comm_cp_jcomm_outer_coo"]:
+                 "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -158,6 +167,45 @@ def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq:
     return o
 
 
+class Batch:
+    """A problem list for :meth:`Context.jcomm_outer_batched`, marshalled once.
+
+    Each item is a dict with the arguments of :meth:`Context.jcomm_outer`:
+    ``X``, ``factors`` and optionally ``core``, ``beta``, ``L``, ``eps``,
+    ``eps_x``, ``cache_pq`` and ``obj_out`` (a float64 device view of one
+    element).  The structures keep the tensors' device pointers, so the
+    tensors must stay alive and in place while the batch is in use."""
+
+    def __init__(self, items: Sequence[dict]):
+        import torch
+        self.items = list(items)
+        n = len(self.items)
+        self._dense = [None] * n
+        self._model = [None] * n
+        self._opts = [None] * n
+        self.array = (Problem * max(n, 1))()
+        for k, it in enumerate(self.items):
+            d = _dense(it["X"])
+            m = _model(it["factors"], it.get("core"))
+            o = _opts(it.get("beta", 1.0), it.get("eps", 1e-12), it.get("eps_x"), it.get("L", 1),
+                      it.get("cache_pq", False))
+            self._dense[k], self._model[k], self._opts[k] = d, m, o
+            pr = self.array[k]
+            pr.x = ctypes.pointer(d)
+            pr.model = ctypes.pointer(m)
+            pr.opts = ctypes.pointer(o)
+            obj = it.get("obj_out")
+            if obj is not None:
+                if obj.dtype != torch.float64:
+                    raise TypeError("obj_out must be float64")
+                pr.obj_ref_dev = _ptr(obj, "obj_out")
+            else:
+                pr.obj_ref_dev = None
+
+    def __len__(self) -> int:
+        return len(self.items)
+
+
 class Context:
     """A library context on one device; owns the scratch workspace."""
 
@@ -196,6 +244,25 @@ class Context:
         _check(self._lib.comm_profile_query(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def workspace_bytes(self, dims: Sequence[int], rank: int = 0, core_dims: Optional[Sequence[int]] = None,
+                        beta: float = 1.0, L: int = 1, cache_pq: bool = False, op: int = 1) -> int:
+        """Workspace bytes of one call on a tensor of shape `dims` (op 0 update,
+        1 jcomm_outer, 2 objective): CP of `rank`, or Tucker with `core_dims`.
+        Needs no buffers; 0 if the arguments are invalid."""
+        d = Dense()
+        d.ndim = len(dims)
+        for n, v in enumerate(dims):
+            d.dims[n] = int(v)
+        m = Model()
+        if core_dims is None:
+            m.kind, m.rank = COMM_CP, int(rank)
+        else:
+            m.kind = COMM_TUCKER
+            for n, v in enumerate(core_dims):
+                m.core_dims[n] = int(v)
+        o = _opts(beta, 1e-12, None, L, cache_pq)
+        return int(self._lib.comm_workspace_bytes(ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), int(op)))
+
     # ---------------------------------------------------------------- entry points
 
     def cp_update(self, X, factors, block: int = -1, beta: float = 1.0, eps: float = 1e-12,
@@ -224,6 +291,15 @@ class Context:
             optr = _ptr(obj_out, "obj_out")
         _check(self._lib.comm_jcomm_outer(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), optr,
                                           _stream(stream)))
+
+    def jcomm_outer_batched(self, batch: "Batch", graph: bool = False, stream=None) -> None:
+        """One J-CoMM outer iteration for every problem of `batch`, each with the
+        result it would have alone; graph=True captures the batch into a HIP graph
+        once and replays it while the same Batch object's problems are passed."""
+        if not isinstance(batch, Batch):
+            batch = Batch(batch)
+        _check(self._lib.comm_jcomm_outer_batched(self._h, batch.array, len(batch),
+                                                  COMM_BATCH_GRAPH if graph else 0, _stream(stream)))
 
     def beta_objective(self, X, factors, core=None, beta: float = 1.0, eps: float = 1e-12,
                        eps_x: Optional[float] = None, out=None, stream=None):
@@ -285,3 +361,7 @@ def beta_objective(X, factors, core=None, beta=1.0, eps=1e-12, eps_x=None, out=N
 
 def cp_jcomm_outer_coo(idx, val, dims, factors, L=1, eps=1e-12, obj_out=None, stream=None):
     default_context().cp_jcomm_outer_coo(idx, val, dims, factors, L, eps, obj_out, stream)
+
+
+def jcomm_outer_batched(batch, graph=False, stream=None):
+    default_context().jcomm_outer_batched(batch, graph, stream)

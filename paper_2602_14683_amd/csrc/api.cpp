@@ -31,13 +31,20 @@ int check_opts(const comm_opts* o, bool need_L) {
   return COMM_OK;
 }
 
-int check_dense(const comm_dense* x) {
+// Shape of a dense tensor only (the size query needs no buffers).
+int check_dense_shape(const comm_dense* x) {
   if (!x) return fail(COMM_EINVAL, "x is NULL");
-  if (!x->X) return fail(COMM_EINVAL, "x->X is NULL");
   if (x->ndim < 1 || x->ndim > 4) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
   for (int n = 0; n < x->ndim; ++n)
     if (x->dims[n] < 1 || x->dims[n] > (1 << 24)) return fail(COMM_EINVAL, "dims[%d] = %lld", n, (long long)x->dims[n]);
   if (x->ndim != 3) return fail(COMM_EUNSUPPORTED, "dense tensors of order %d are not supported (3 only)", x->ndim);
+  return COMM_OK;
+}
+
+int check_dense(const comm_dense* x) {
+  int rc = check_dense_shape(x);
+  if (rc) return rc;
+  if (!x->X) return fail(COMM_EINVAL, "x->X is NULL");
   return COMM_OK;
 }
 
@@ -366,6 +373,203 @@ int set_device(comm_ctx* ctx) {
   return COMM_OK;
 }
 
+// ---------------------------------------------------------------------------------------- J-CoMM, one or many
+
+int jcomm_check(const comm_dense* x, const comm_model* model, const comm_opts* opts) {
+  int rc = check_opts(opts, true);
+  if (!rc) rc = check_dense(x);
+  if (rc) return rc;
+  if (!model) return fail(COMM_EINVAL, "model is NULL");
+  if (model->kind == COMM_CP) return check_cp_model(model, x->ndim);
+  if (model->kind == COMM_TUCKER) return tucker_check_model(model, x);
+  return fail(COMM_EINVAL, "model kind %d", model->kind);
+}
+
+size_t jcomm_ws_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts) {
+  if (model->kind == COMM_CP) return cp_layout(x, nullptr, opts->beta != 1.0 && opts->cache_pq).bytes;
+  return tucker_workspace_bytes(x, model, opts, 1);
+}
+
+int jcomm_run(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts, double* obj,
+              hipStream_t st) {
+  return model->kind == COMM_CP ? cp_jcomm(ctx, x, model, opts, obj, st) : tucker_jcomm(ctx, x, model, opts, obj, st);
+}
+
+// A batch runs every problem with the kernels and launch shapes of a single
+// call, on a private slice of the batch workspace, so its result does not
+// depend on what else is in the batch.  Problems are spread round-robin over
+// kBatchStreams internal streams (default priority) forked from and joined
+// back to the caller's stream, so the small problems' kernels overlap.
+constexpr int kBatchStreams = 4;
+
+struct BatchItem {
+  comm_dense x;
+  comm_model m;
+  comm_opts o;
+  double* obj;
+  size_t off, bytes;
+};
+
+int batch_resources(comm_ctx* ctx) {
+  if (!ctx->bstreams.empty()) return COMM_OK;
+  for (int s = 0; s < kBatchStreams; ++s) {
+    hipStream_t q;
+    HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    ctx->bstreams.push_back(q);
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->bjoin.push_back(e);
+  }
+  HIP_TRY(hipStreamCreateWithFlags(&ctx->bcapture, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&ctx->bfork, hipEventDisableTiming));
+  return COMM_OK;
+}
+
+int batch_sync_all(comm_ctx* ctx, hipStream_t st) {
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ctx->glast) HIP_TRY(hipStreamSynchronize(ctx->glast));
+  for (hipStream_t q : ctx->bstreams) HIP_TRY(hipStreamSynchronize(q));
+  return COMM_OK;
+}
+
+int batch_drop_graph(comm_ctx* ctx) {
+  if (ctx->gexec) HIP_TRY(hipGraphExecDestroy(ctx->gexec));
+  if (ctx->graph) HIP_TRY(hipGraphDestroy(ctx->graph));
+  ctx->gexec = nullptr;
+  ctx->graph = nullptr;
+  ctx->gkey.clear();
+  return COMM_OK;
+}
+
+int batch_ensure_ws(comm_ctx* ctx, size_t bytes, hipStream_t st) {
+  if (bytes <= ctx->bws_bytes) return COMM_OK;
+  if (ctx->limit && bytes > ctx->limit)
+    return fail(COMM_ENOMEM, "batch workspace of %zu bytes exceeds the context limit of %zu", bytes, ctx->limit);
+  int rc = batch_sync_all(ctx, st);
+  if (rc) return rc;
+  if ((rc = batch_drop_graph(ctx))) return rc;  // the cached graph points into the old workspace
+  if (ctx->bws) HIP_TRY(hipFree(ctx->bws));
+  ctx->bws = nullptr;
+  ctx->bws_bytes = 0;
+  size_t want = bytes + bytes / 4;
+  if (ctx->limit && want > ctx->limit) want = ctx->limit;
+  hipError_t e = hipMalloc(&ctx->bws, want);
+  if (e != hipSuccess) return fail(COMM_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+  ctx->bws_bytes = want;
+  return COMM_OK;
+}
+
+// Everything that decides the launches of a batch, word by word.
+std::vector<int64_t> batch_key(const std::vector<BatchItem>& items, const char* ws) {
+  std::vector<int64_t> k;
+  auto word = [&](int64_t v) { k.push_back(v); };
+  auto dbl = [&](double v) {
+    int64_t b;
+    std::memcpy(&b, &v, sizeof b);
+    k.push_back(b);
+  };
+  word((int64_t)(intptr_t)ws);
+  for (const BatchItem& it : items) {
+    word(it.x.ndim);
+    for (int n = 0; n < 4; ++n) word(it.x.dims[n]);
+    word((int64_t)(intptr_t)it.x.X);
+    word(it.m.kind);
+    word(it.m.rank);
+    for (int n = 0; n < 4; ++n) word(it.m.core_dims[n]);
+    for (int n = 0; n < 4; ++n) word((int64_t)(intptr_t)it.m.factors[n]);
+    word((int64_t)(intptr_t)it.m.core);
+    dbl(it.o.beta);
+    dbl(it.o.eps);
+    dbl(it.o.eps_x);
+    word(it.o.inner_sweeps);
+    word(it.o.precision);
+    word(it.o.cache_pq);
+    word((int64_t)(intptr_t)it.obj);
+    word((int64_t)it.off);
+  }
+  return k;
+}
+
+// Fork from `origin`, issue every problem on its stream, join back to `origin`.
+int batch_issue(comm_ctx* ctx, std::vector<BatchItem>& items, hipStream_t origin) {
+  const int S = (int)ctx->bstreams.size();
+  HIP_TRY(hipEventRecord(ctx->bfork, origin));
+  for (hipStream_t q : ctx->bstreams) HIP_TRY(hipStreamWaitEvent(q, ctx->bfork, 0));
+  for (size_t p = 0; p < items.size(); ++p) {
+    BatchItem& it = items[p];
+    comm_ctx sub;
+    sub.device = ctx->device;
+    sub.ws = ctx->bws + it.off;
+    sub.ws_bytes = it.bytes;
+    sub.limit = it.bytes;  // a slice never grows: a larger need is an error, not an allocation
+    int rc = jcomm_run(&sub, &it.x, &it.m, &it.o, it.obj, ctx->bstreams[p % S]);
+    if (rc) return rc;
+  }
+  for (int q = 0; q < S; ++q) {
+    HIP_TRY(hipEventRecord(ctx->bjoin[q], ctx->bstreams[q]));
+    HIP_TRY(hipStreamWaitEvent(origin, ctx->bjoin[q], 0));
+  }
+  return COMM_OK;
+}
+
+int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags, hipStream_t st) {
+  std::vector<BatchItem> items((size_t)count);
+  size_t total = 0;
+  for (int p = 0; p < count; ++p) {
+    const comm_problem& q = probs[p];
+    if (!q.x || !q.model || !q.opts) return fail(COMM_EINVAL, "problem %d: x, model and opts must not be NULL", p);
+    int rc = jcomm_check(q.x, q.model, q.opts);
+    if (rc) {
+      std::string msg = g_last_error;
+      return fail(rc, "problem %d: %s", p, msg.c_str());
+    }
+    BatchItem& it = items[(size_t)p];
+    it.x = *q.x;
+    it.m = *q.model;
+    it.o = *q.opts;
+    it.obj = q.obj_ref_dev;
+    it.bytes = (jcomm_ws_bytes(q.x, q.model, q.opts) + 255) & ~size_t(255);
+    it.off = total;
+    total += it.bytes;
+  }
+  if (count == 0) return COMM_OK;
+  int rc = batch_resources(ctx);
+  if (rc) return rc;
+  if ((rc = batch_ensure_ws(ctx, total, st))) return rc;
+  if (!(flags & COMM_BATCH_GRAPH)) {
+    rc = batch_issue(ctx, items, st);
+    ctx->glast = st;
+    return rc;
+  }
+  std::vector<int64_t> key = batch_key(items, ctx->bws);
+  if (!ctx->gexec || key != ctx->gkey) {
+    // a different problem list: wait for the old graph's replays, then capture anew
+    if (ctx->gexec) {
+      if ((rc = batch_sync_all(ctx, st))) return rc;
+      if ((rc = batch_drop_graph(ctx))) return rc;
+    }
+    HIP_TRY(hipStreamBeginCapture(ctx->bcapture, hipStreamCaptureModeThreadLocal));
+    rc = batch_issue(ctx, items, ctx->bcapture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->bcapture, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(COMM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    ctx->graph = g;
+    e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      batch_drop_graph(ctx);
+      return fail(COMM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    ctx->gkey = std::move(key);
+  }
+  HIP_TRY(hipGraphLaunch(ctx->gexec, st));
+  ctx->glast = st;
+  return COMM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------- C ABI
@@ -402,6 +606,17 @@ int comm_destroy(comm_ctx* ctx) {
       hipEventDestroy(pr.first);
       hipEventDestroy(pr.second);
     }
+    if (ctx->glast) hipStreamSynchronize(ctx->glast);
+    for (hipStream_t q : ctx->bstreams) hipStreamSynchronize(q);
+    batch_drop_graph(ctx);
+    if (ctx->bws) {
+      hipError_t e = hipFree(ctx->bws);
+      if (e != hipSuccess) rc = fail(COMM_EHIP, "hipFree: %s", hipGetErrorString(e));
+    }
+    for (hipStream_t q : ctx->bstreams) hipStreamDestroy(q);
+    for (hipEvent_t e : ctx->bjoin) hipEventDestroy(e);
+    if (ctx->bcapture) hipStreamDestroy(ctx->bcapture);
+    if (ctx->bfork) hipEventDestroy(ctx->bfork);
     delete ctx;
     return rc;
   });
@@ -434,7 +649,7 @@ int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
 }
 
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op) {
-  if (check_dense(x) || !model || !opts) return 0;
+  if (check_dense_shape(x) || !model || !opts) return 0;
   if (model->kind == COMM_CP) {
     const bool cache = op == 1 && opts->beta != 1.0 && opts->cache_pq;
     return cp_layout(x, nullptr, cache).bytes;
@@ -463,21 +678,26 @@ int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, cons
                      double* obj_ref_dev, void* stream) {
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
-    int rc = check_opts(opts, true);
-    if (!rc) rc = check_dense(x);
+    int rc = jcomm_check(x, model, opts);
     if (rc) return rc;
-    if (!model) return fail(COMM_EINVAL, "model is NULL");
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (model->kind == COMM_CP) {
-      if ((rc = check_cp_model(model, x->ndim))) return rc;
-      rc = cp_jcomm(ctx, x, model, opts, obj_ref_dev, st);
-    } else if (model->kind == COMM_TUCKER) {
-      if ((rc = tucker_check_model(model, x))) return rc;
-      rc = tucker_jcomm(ctx, x, model, opts, obj_ref_dev, st);
-    } else {
-      return fail(COMM_EINVAL, "model kind %d", model->kind);
-    }
+    rc = jcomm_run(ctx, x, model, opts, obj_ref_dev, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_jcomm_outer_batched(comm_ctx* ctx, const comm_problem* problems, int count, int flags, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (count < 0 || (count > 0 && !problems)) return fail(COMM_EINVAL, "count = %d with problems = %p", count,
+                                                           (const void*)problems);
+    if (flags & ~COMM_BATCH_GRAPH) return fail(COMM_EINVAL, "unknown flags 0x%x", flags);
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = jcomm_batched(ctx, problems, count, flags, st);
     ctx->last_stream = st;
     return rc;
   });

@@ -24,6 +24,19 @@ struct comm_ctx {
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
+  // batched calls: one workspace holding every problem's own slice, internal
+  // streams the problems are spread over, and the cached graph of the last
+  // captured problem list
+  char* bws = nullptr;
+  size_t bws_bytes = 0;
+  std::vector<hipStream_t> bstreams;
+  hipStream_t bcapture = nullptr;
+  hipEvent_t bfork = nullptr;
+  std::vector<hipEvent_t> bjoin;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gkey;
+  hipStream_t glast = nullptr;
 };
 
 extern thread_local std::string g_last_error;
