@@ -228,7 +228,8 @@ def run_tucker(args, ctx):
     J = 16
     avg_ms = kernel_ms / max(launches, 1)
     bytes_ = 4 * entries                 # X streamed once per pass
-    flops = 4.0 * J * entries            # rebuild 2J + one contraction chain 2J per entry
+    chains = 2 if beta == 1.0 else 3     # rebuild + numerator (+ denominator) per entry
+    flops = 2.0 * J * chains * entries
     gbs = bytes_ / (avg_ms * 1e-3) / 1e9
     out = base_line(args, elapsed)
     out.update({"data": "synthetic (Gamma(shape 10) around a planted 16^3-core Tucker model)",
@@ -237,7 +238,7 @@ def run_tucker(args, ctx):
                            "parallelism": "single GPU"},
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                             "kernel": "tk_pass_kernel (fused rebuild + P~ or Q~ + one contraction)",
+                             "kernel": "tk_v_kernel / tk_m3_kernel (fused rebuild + P~, Q~ + numerator and denominator contractions)",
                              "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
                              "algorithmic_bytes_per_launch": bytes_, "algorithmic_flops_per_launch": flops,
                              "tflops_algorithmic": round(flops / (avg_ms * 1e-3) / 1e12, 2)},

@@ -272,9 +272,9 @@ int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts*
   {
     PadArgs p = {};
     p.nf = 3;
-    p.cols = m->rank;
-    p.ld = m->rank;
     for (int n = 0; n < 3; ++n) {
+      p.cols[n] = m->rank;
+      p.ld[n] = m->rank;
       p.src[n] = m->factors[n];
       p.rows[n] = w.dims[n];
       p.rows_p[n] = w.rows_p[n];

@@ -82,7 +82,7 @@ hipError_t launch_cp_pass(const CpPassArgs& a, const CpGrid& g, int beta_class, 
 // in [rows_p][32]; optional transposed copy dstT[f][c][row] and second copies.
 struct PadArgs {
   int nf;
-  int cols, ld;
+  int cols[4], ld[4];      // valid columns and row stride of each source
   const float* src[4];
   int rows[4];
   int rows_p[4];
@@ -186,47 +186,72 @@ struct TkModel {
   int J1, J2, J3;
 };
 
+// T2[(i, j)][c] = sum_{a,b} A[i][a] B[j][b] G[a][b][c] for every pair, row
+// stride 32 (zero past J3): the Tucker reconstruction is X^[(i,j)][k] =
+// sum_c T2[(i,j)][c] C[k][c].
+// sets = 1 or 2 models (m[0] -> T2[0], m[1] -> T2[1]) in one launch.  The
+// factor B of each model must be a padded [J][32] copy.  T2T[set], when not
+// NULL, also receives the transposed [32][Pp] layout, zero for pairs >= I J.
+hipError_t launch_tk_t2(const TkModel* m, float* const* T2, float* const* T2T, int sets, int I, int J, int64_t Pp,
+                        hipStream_t s);
+
+// Arguments of the two Tucker pass kernels.  X is read as an (I J) x K matrix:
+// row (i, j) is the mode-3 fibre of pair (i, j).
 struct TkPassArgs {
-  const float* X;          // I x J x K
-  const float* Wc;         // cached weight tensor (cache read)
+  const float* X;
+  const float* Pc;         // cached P~ / Q~ (cache read)
+  const float* Qc;
   float* Pw;               // cache targets (cache write)
   float* Qw;
   int I, J, K, Kp;
-  TkModel r;               // rebuild model
-  TkModel n;               // contraction set
+  const float* T2r;        // rebuild T2 [(I J)][32]
+  FView C;                 // rebuild mode-3 factor
+  const float* CnT;        // V pass: mode-3 factor of the numerator / denominator set,
+  const float* CdT;        //   transposed [32][Kp], zero for k >= K
+  const float* T2nT;       // mode-3 pass: T2 of the numerator / denominator set,
+  const float* T2dT;       //   transposed [32][Pp], zero for pairs >= I J
+  int64_t Pp;              // I J rounded up to a multiple of 32
   float eps, eps_x;
-  int use_q;               // contract Q instead of P
-  int want_v, want_m3;
   BetaConst bc;
-  float* V;                // [I][J][32]
-  float* m3;               // [workgroups][Kp][32] partial slots
-  double* obj_part;        // one float64 partial per workgroup
+  float* Vn;               // V pass outputs [(I J)][32]
+  float* Vd;
+  float* m3n;              // mode-3 pass outputs: partial slots [npg][Kp][32]
+  float* m3d;
+  double* obj_part;        // one float64 partial per workgroup of the V pass
+  int tpw, npg;            // mode-3 pass: pair tiles per wave, pair groups
 };
 
-struct TkGrid {
-  int gi, gj;
-  int wgs() const { return gi * gj; }
-};
-TkGrid tk_grid(int I, int J);
-// mode (bits 0-1): 0 = from X, 1 = read the cached weight Wc, 2 = from X and
-// write P~ / Q~; bit 2 set: also accumulate the objective (not with mode 1).
-hipError_t launch_tk_pass(const TkPassArgs& a, const TkGrid& g, int beta_class, int mode, hipStream_t s);
+enum TkMode : int { kTkFromX = 0, kTkCacheRead = 1, kTkCacheWrite = 2 };
 
-// Small strided GEMM with split-K partial slots (fixed order, deterministic):
-//   out[split][batch][m][n] = sum_{k in split} A(batch, m, k) B(batch, k, n)
-// with A(b, m, k) = A[b * sab + m * sam + (k / akin) * sako + (k % akin) * saki]
-// and  B(b, k, n) = B[b * sbb + (k / bkin) * sbko + (k % bkin) * sbki + n * sbn];
+// V pass, one workgroup per 32 pairs, its four waves splitting K:
+//   Vn[(i,j)][c] = sum_k P[(i,j)][k] Cn[k][c]
+//   Vd[(i,j)][c] = sum_k Q[(i,j)][k] Cd[k][c]   (sets = 2)
+// sets = 0 computes only the objective (obj) or only the cache (cache write).
+// Workgroups: ceil(I J / 32); obj_part gets one value per workgroup.
+int64_t tk_v_workgroups(int I, int J);
+hipError_t launch_tk_v(const TkPassArgs& a, int beta_class, int mode, bool obj, int sets, hipStream_t s);
+
+// Mode-3 pass: m3n[g][k][c] = sum over pair group g of P[(i,j)][k] T2n[(i,j)][c]
+// (and m3d with Q and T2d when sets = 2).
+void tk_m3_tiling(int I, int J, int* tpw, int* npg);
+hipError_t launch_tk_m3(const TkPassArgs& a, int beta_class, int mode, int sets, hipStream_t s);
+
+// Small strided GEMMs on the matrix cores, split-K partial slots (fixed order,
+// deterministic), for one or two operand sets at once:
+//   out[set][split][batch][m][n] = sum_{k in split} A_set(batch, m, k) B_set(batch, k, n)
+// with A(b, m, k) = A[b * sab + m * sam + (k >> akin_log2) * sako + (k & (2^akin_log2 - 1)) * saki]
+// and  B(b, k, n) = B[b * sbb + (k >> bkin_log2) * sbko + (k & (2^bkin_log2 - 1)) * sbki + n * sbn];
 // out row stride ldo, batch stride sob, split stride sos.
 struct GemmArgs {
-  const float* A;
+  const float* A[2];
   int64_t sab, sam, sako, saki;
-  int akin;
-  const float* B;
+  int akin_log2;
+  const float* B[2];
   int64_t sbb, sbko, sbki, sbn;
-  int bkin;
-  float* out;
+  int bkin_log2;
+  float* out[2];
   int64_t sob, sos, ldo;
-  int M, N, K, batch, splits;
+  int M, N, K, batch, splits, sets;
 };
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 

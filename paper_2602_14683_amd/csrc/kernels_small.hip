@@ -22,7 +22,7 @@ __global__ void pad_factors_kernel(PadArgs a) {
   }
   if (f >= a.nf) return;
   const int row = (int)(e / kRP), c = (int)(e % kRP);
-  const float v = (row < a.rows[f] && c < a.cols) ? a.src[f][(int64_t)row * a.ld + c] : 0.0f;
+  const float v = (row < a.rows[f] && c < a.cols[f]) ? a.src[f][(int64_t)row * a.ld[f] + c] : 0.0f;
   a.dst[f][e] = v;
   if (a.dstT[f]) a.dstT[f][(int64_t)c * a.rows_p[f] + row] = v;
   if (a.dst2[f]) a.dst2[f][e] = v;

@@ -1,14 +1,15 @@
-// Dense 3-way Tucker: B-CoMM and J-CoMM orchestration, the small contraction
-// GEMMs that turn the pass's V into the mode-1, mode-2 and core numerators,
-// and the closed-form beta = 1 denominators.
+// Dense 3-way Tucker: B-CoMM and J-CoMM orchestration, the T2 kernel that the
+// passes rebuild from, the small contraction GEMMs that turn the V pass's
+// output into the mode-1, mode-2 and core numerators, and the closed-form
+// beta = 1 denominators.
 //
-// With V[i][j][c] = sum_k W[i][j][k] C'[k][c] (W = P or Q, from the fused pass):
+// With V[i][j][c] = sum_k W[i][j][k] C'[k][c] (W = P or Q, from the V pass):
 //   U[i][b][c]   = sum_j B'[j][b] V[i][j][c]
 //   Num1[i][a]   = sum_{b,c} G'[a][b][c] U[i][b][c]                 (factor A, App. C)
 //   Ncore[a][b][c] = sum_i A'[i][a] U[i][b][c]                       (core, App. C)
 //   H[i][b][c]   = sum_a A'[i][a] G'[a][b][c]
 //   Num2[j][b]   = sum_{i,c} V[i][j][c] H[i][b][c]                   (factor B)
-// and the mode-3 numerator comes from the pass directly.  These are the
+// and the mode-3 numerator comes from the mode-3 pass directly.  These are the
 // direct-form contractions of App. C / App. E: the partial tensor B^(n) is
 // never formed; only V (J3/K of the size of X) and the I x J2 x J3 U / H.
 
@@ -18,74 +19,160 @@
 
 namespace comm {
 
-TkGrid tk_grid(int I, int J) {
-  TkGrid g;
-  g.gi = (I + kTkTI - 1) / kTkTI;
-  g.gj = (J + kTkTJ - 1) / kTkTJ;
-  return g;
+int64_t tk_v_workgroups(int I, int J) { return ((int64_t)I * J + kTkPairsPerWg - 1) / kTkPairsPerWg; }
+
+// Mode-3 pass tiling: at most 128 pair groups (partial slots), each of 4
+// waves x tpw pair tiles of 32.
+void tk_m3_tiling(int I, int J, int* tpw, int* npg) {
+  const int64_t tiles = ((int64_t)I * J + 31) / 32;
+  const int64_t t = std::max<int64_t>(1, (tiles + 4 * 128 - 1) / (4 * 128));
+  *tpw = (int)t;
+  *npg = (int)((tiles + 4 * t - 1) / (4 * t));
+}
+
+// ---------------------------------------------------------------------------------------- T2
+
+struct T2Args {
+  TkModel m[2];
+  float* out[2];
+  float* outT[2];
+  int I, J;
+  int64_t Pp;
+};
+
+// Workgroup (i, set): T1[b][c] = sum_a A[i][a] G[a][b][c] in LDS, then
+// T2[(i,j)][c] = sum_b B[j][b] T1[b][c] on the matrix cores, one 32-wide j tile
+// per wave at a time, computed transposed (lane = j) so that both the row
+// layout and the transposed copy are written with coalesced stores (zero for
+// c >= J3).
+__global__ void __launch_bounds__(256) tk_t2_kernel(T2Args t) {
+  __shared__ float t1[32][33];
+  const int i = blockIdx.x % t.I, set = blockIdx.x / t.I;
+  const TkModel& m = t.m[set];
+  const int I = t.I, J = t.J;
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int b = e >> 5, c = e & 31;
+    const bool live = b < m.J2 && c < m.J3;
+    float g[32];
+#pragma unroll
+    for (int a = 0; a < 32; ++a) g[a] = (live && a < m.J1) ? m.G[((int64_t)a * m.J2 + b) * m.ldG + c] : 0.0f;
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 32; ++a)
+      if (a < m.J1) s = fmaf(m.A.at(i, a, I), g[a], s);
+    t1[b][c] = s;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, w = threadIdx.x >> 6;
+  float* out = t.out[set] + (int64_t)i * J * kRP;
+  float* outT = t.outT[set];
+  for (int j0 = 32 * w; j0 < J; j0 += 32 * kWaves) {
+    // T2^T[c][j] = sum_b T1[b][c] B[j][b]: A operand T1 (lane: c), B operand B rows (lane: j)
+    float brow[16];
+    row16(m.B.p + (int64_t)(j0 + col) * kRP + 16 * h, j0 + col < J, brow);
+    f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = mfma32(t1[16 * h + s][col], brow[s], acc);
+    // acc[v] = T2[j = j0 + col][c = out_row(v, h)]
+    const int j = j0 + col;
+    if (j < J) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        f32x4 q = {acc[4 * g], acc[4 * g + 1], acc[4 * g + 2], acc[4 * g + 3]};
+        *reinterpret_cast<f32x4*>(out + (int64_t)j * kRP + 8 * g + 4 * h) = q;
+      }
+      if (outT) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) outT[(int64_t)out_row(v, h) * t.Pp + (int64_t)i * J + j] = acc[v];
+      }
+    }
+  }
+  // the transposed copy's padding past the last pair reads as zero
+  if (outT && i == I - 1) {
+    const int64_t np = (int64_t)I * J;
+    const int pad = (int)(t.Pp - np);
+    for (int e = threadIdx.x; e < 32 * pad; e += 256) outT[(int64_t)(e / pad) * t.Pp + np + e % pad] = 0.0f;
+  }
+}
+
+hipError_t launch_tk_t2(const TkModel* m, float* const* T2, float* const* T2T, int sets, int I, int J, int64_t Pp,
+                        hipStream_t s) {
+  T2Args t = {};
+  for (int k = 0; k < sets; ++k) {
+    t.m[k] = m[k];
+    t.out[k] = T2[k];
+    t.outT[k] = T2T ? T2T[k] : nullptr;
+  }
+  t.I = I;
+  t.J = J;
+  t.Pp = Pp;
+  hipLaunchKernelGGL(tk_t2_kernel, dim3((unsigned)(I * sets)), dim3(256), 0, s, t);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------- GEMM
 
-constexpr int kGT = 32;   // output tile
-constexpr int kGK = 32;   // k chunk
+// One workgroup per 32 x 32 output tile (per set, split and batch); its four
+// waves split the tile's k range and their partial tiles are summed in a
+// fixed order.  Each matrix-core step consumes two k (lane half h supplies
+// k = 2 s + h); operands of 16 steps are loaded before they are used.
+constexpr int kGemmBatch = 16;
 
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-  __shared__ float As[kGK][kGT + 1];
-  __shared__ float Bs[kGK][kGT + 1];
-  const int tiles_m = (g.M + kGT - 1) / kGT, tiles_n = (g.N + kGT - 1) / kGT;
-  int id = blockIdx.x;
-  const int tn = id % tiles_n;
+  __shared__ float red[kWaves][32 * 33];
+  const int tiles_m = (g.M + 31) / 32, tiles_n = (g.N + 31) / 32;
+  int64_t id = blockIdx.x;
+  const int tn = (int)(id % tiles_n);
   id /= tiles_n;
-  const int tm = id % tiles_m;
+  const int tm = (int)(id % tiles_m);
   id /= tiles_m;
-  const int bat = id % g.batch;
-  const int split = id / g.batch;
+  const int bat = (int)(id % g.batch);
+  id /= g.batch;
+  const int split = (int)(id % g.splits);
+  const int set = (int)(id / g.splits);
   const int kc = (g.K + g.splits - 1) / g.splits;
-  const int k0 = split * kc, k1 = min(g.K, k0 + kc);
-  const int t = threadIdx.x;
-  const int tx = t & 15, ty = t >> 4;
-  float acc[2][2] = {};
-  for (int kb = k0; kb < k1; kb += kGK) {
-    for (int e = t; e < kGK * kGT; e += 256) {
-      const int kk = e / kGT, mm = e % kGT;
-      const int m = tm * kGT + mm, k = kb + kk;
-      float va = 0.0f;
-      if (m < g.M && k < k1)
-        va = g.A[(int64_t)bat * g.sab + (int64_t)m * g.sam + (int64_t)(k / g.akin) * g.sako +
-                 (int64_t)(k % g.akin) * g.saki];
-      As[kk][mm] = va;
-      const int n = tn * kGT + mm;
-      float vb = 0.0f;
-      if (n < g.N && k < k1)
-        vb = g.B[(int64_t)bat * g.sbb + (int64_t)(k / g.bkin) * g.sbko + (int64_t)(k % g.bkin) * g.sbki +
-                 (int64_t)n * g.sbn];
-      Bs[kk][mm] = vb;
+  const int ks = split * kc, ke = min(g.K, ks + kc);
+  const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, w = threadIdx.x >> 6;
+  // wave w: k in [k0, k1), a quarter of the split, rounded to whole steps
+  const int steps_all = max(0, (ke - ks + 1) / 2);
+  const int per = (steps_all + kWaves - 1) / kWaves;
+  const int s_begin = min(steps_all, w * per), s_end = min(steps_all, s_begin + per);
+  const int m = tm * 32 + col, n = tn * 32 + col;
+  const float* A = g.A[set] + (int64_t)bat * g.sab + (int64_t)m * g.sam;
+  const float* B = g.B[set] + (int64_t)bat * g.sbb + (int64_t)n * g.sbn;
+  const int amask = (1 << g.akin_log2) - 1, bmask = (1 << g.bkin_log2) - 1;
+  const bool mok = m < g.M, nok = n < g.N;
+  f32x16 acc = {};
+  for (int s0 = s_begin; s0 < s_end; s0 += kGemmBatch) {
+    float av[kGemmBatch], bv[kGemmBatch];
+#pragma unroll
+    for (int u = 0; u < kGemmBatch; ++u) {
+      const int k = ks + 2 * (s0 + u) + h;
+      const bool kok = s0 + u < s_end && k < ke;
+      av[u] = (mok && kok) ? A[(int64_t)(k >> g.akin_log2) * g.sako + (int64_t)(k & amask) * g.saki] : 0.0f;
+      bv[u] = (nok && kok) ? B[(int64_t)(k >> g.bkin_log2) * g.sbko + (int64_t)(k & bmask) * g.sbki] : 0.0f;
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < kGK; ++kk) {
-      const float a0 = As[kk][2 * ty], a1 = As[kk][2 * ty + 1];
-      const float b0 = Bs[kk][2 * tx], b1 = Bs[kk][2 * tx + 1];
-      acc[0][0] = fmaf(a0, b0, acc[0][0]);
-      acc[0][1] = fmaf(a0, b1, acc[0][1]);
-      acc[1][0] = fmaf(a1, b0, acc[1][0]);
-      acc[1][1] = fmaf(a1, b1, acc[1][1]);
-    }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kGemmBatch; ++u) acc = mfma32(av[u], bv[u], acc);
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int m = tm * kGT + 2 * ty + u, n = tn * kGT + 2 * tx + v;
-      if (m < g.M && n < g.N) g.out[(int64_t)split * g.sos + (int64_t)bat * g.sob + (int64_t)m * g.ldo + n] = acc[u][v];
+  for (int v = 0; v < 16; ++v) red[w][out_row(v, h) * 33 + col] = acc[v];
+  __syncthreads();
+  float* out = g.out[set] + (int64_t)split * g.sos + (int64_t)bat * g.sob;
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    const int row = tm * 32 + r, cn = tn * 32 + c;
+    if (row < g.M && cn < g.N) {
+      float sum = red[0][r * 33 + c];
+      for (int q = 1; q < kWaves; ++q) sum += red[q][r * 33 + c];
+      out[(int64_t)row * g.ldo + cn] = sum;
     }
+  }
 }
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
-  const int tiles = ((g.M + kGT - 1) / kGT) * ((g.N + kGT - 1) / kGT) * g.batch * g.splits;
-  hipLaunchKernelGGL(gemm_kernel, dim3(tiles), dim3(256), 0, s, g);
+  const int64_t tiles = (int64_t)((g.M + 31) / 32) * ((g.N + 31) / 32) * g.batch * g.splits * g.sets;
+  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)tiles), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -158,20 +245,30 @@ using namespace comm;
 namespace {
 
 // Padded copies of a Tucker model: core [J1 J2][32], factors [I_n][32].
+// The mode-3 factor copy has Kp rows (zero past K); cur, num and den also keep
+// it transposed, [32][Kp], for the V pass.
 struct TkCopy {
   float* core;
   float* fac[3];
+  float* facT2;
 };
 
 struct TkWs {
   int dims[3], J[3];
-  TkGrid g;
-  int Kp;
-  float* V;
-  float* m3[2];      // mode-3 partial slots of the numerator / denominator pass
+  int Kp, tpw, npg;
+  int64_t vwgs;
+  float* T2r;        // T2 of the rebuild model
+  float* T2n;        // T2 of the numerator / denominator sets (mode-3 block)
+  float* T2d;
+  float* T2nT;       // the same, transposed [32][Pp]
+  float* T2dT;
+  int64_t Pp;
+  float* Vn;         // V of the numerator / denominator set
+  float* Vd;
+  float* m3[2];      // mode-3 partial slots of the numerator / denominator
   double* obj_part;
-  float* U;
-  float* H;
+  float* U[2];       // per set: numerator, denominator
+  float* H[2];
   float* slots[2];   // numerator / denominator split-K outputs
   size_t slot_floats;
   float* den_vec;    // [3][32]
@@ -181,7 +278,7 @@ struct TkWs {
   size_t bytes;
 };
 
-constexpr int kSplitCore = 8, kSplit1 = 4, kSplit2 = 16;
+constexpr int kSplitCore = 8, kSplit1 = 8, kSplit2 = 32;
 
 TkWs tk_layout(const comm_dense* x, const comm_model* m, char* base, bool cache) {
   TkWs w = {};
@@ -191,16 +288,27 @@ TkWs tk_layout(const comm_dense* x, const comm_model* m, char* base, bool cache)
   }
   const int I = w.dims[0], J = w.dims[1], K = w.dims[2];
   const int J1 = w.J[0], J2 = w.J[1];
-  w.g = tk_grid(I, J);
+  const size_t pairs = (size_t)I * J;
   w.Kp = (K + 31) / 32 * 32;
+  w.Pp = ((int64_t)pairs + 31) / 32 * 32;
+  tk_m3_tiling(I, J, &w.tpw, &w.npg);
+  w.vwgs = tk_v_workgroups(I, J);
   Carve cv;
   cv.base = base;
-  w.V = cv.take<float>((size_t)I * J * kRP);
-  w.m3[0] = cv.take<float>((size_t)w.g.wgs() * w.Kp * kRP);
-  w.m3[1] = cv.take<float>((size_t)w.g.wgs() * w.Kp * kRP);
-  w.obj_part = cv.take<double>((size_t)w.g.wgs());
-  w.U = cv.take<float>((size_t)I * J2 * kRP);
-  w.H = cv.take<float>((size_t)I * J2 * kRP);
+  w.T2r = cv.take<float>(pairs * kRP);
+  w.T2n = cv.take<float>(pairs * kRP);
+  w.T2d = cv.take<float>(pairs * kRP);
+  w.T2nT = cv.take<float>((size_t)w.Pp * kRP);
+  w.T2dT = cv.take<float>((size_t)w.Pp * kRP);
+  w.Vn = cv.take<float>(pairs * kRP);
+  w.Vd = cv.take<float>(pairs * kRP);
+  w.m3[0] = cv.take<float>((size_t)w.npg * w.Kp * kRP);
+  w.m3[1] = cv.take<float>((size_t)w.npg * w.Kp * kRP);
+  w.obj_part = cv.take<double>((size_t)w.vwgs);
+  for (int k = 0; k < 2; ++k) {
+    w.U[k] = cv.take<float>((size_t)I * J2 * kRP);
+    w.H[k] = cv.take<float>((size_t)I * J2 * kRP);
+  }
   size_t s = (size_t)kSplitCore * J1 * J2 * kRP;
   s = std::max(s, (size_t)kSplit1 * I * kRP);
   s = std::max(s, (size_t)kSplit2 * J * kRP);
@@ -211,10 +319,13 @@ TkWs tk_layout(const comm_dense* x, const comm_model* m, char* base, bool cache)
   w.dcore = cv.take<float>((size_t)J1 * J2 * kRP);
   for (TkCopy* c : {&w.ref, &w.cur, &w.num, &w.den, &w.user_pad}) {
     c->core = cv.take<float>((size_t)J1 * J2 * kRP);
-    for (int n = 0; n < 3; ++n) c->fac[n] = cv.take<float>((size_t)w.dims[n] * kRP);
+    for (int n = 0; n < 2; ++n) c->fac[n] = cv.take<float>((size_t)w.dims[n] * kRP);
+    c->fac[2] = cv.take<float>((size_t)w.Kp * kRP);
+    c->facT2 = nullptr;
   }
+  for (TkCopy* c : {&w.cur, &w.num, &w.den}) c->facT2 = cv.take<float>((size_t)w.Kp * kRP);
   if (cache) {
-    const size_t total = (size_t)I * J * K;
+    const size_t total = pairs * K;
     w.Pc = cv.take<float>(total);
     w.Qc = cv.take<float>(total);
   }
@@ -235,30 +346,33 @@ TkModel model_of(const TkWs& w, const TkCopy& c) {
   return t;
 }
 
-// Copy the caller's model into padded buffers (and optionally a second copy).
+// Copy the caller's model into padded buffers (and optionally a second copy),
+// core and three factors in one launch.
 int tk_pad(const comm_model* m, const TkWs& w, const TkCopy& dst, const TkCopy* dst2, hipStream_t st) {
   PadArgs p = {};
-  p.nf = 1;
-  p.cols = w.J[2];
-  p.ld = w.J[2];
+  p.nf = 4;
+  p.cols[0] = w.J[2];
+  p.ld[0] = w.J[2];
   p.src[0] = m->core;
   p.rows[0] = w.J[0] * w.J[1];
   p.rows_p[0] = p.rows[0];
   p.dst[0] = dst.core;
   p.dst2[0] = dst2 ? dst2->core : nullptr;
-  HIP_TRY(launch_pad_factors(p, st));
   for (int n = 0; n < 3; ++n) {
-    PadArgs q = {};
-    q.nf = 1;
-    q.cols = w.J[n];
-    q.ld = w.J[n];
-    q.src[0] = m->factors[n];
-    q.rows[0] = w.dims[n];
-    q.rows_p[0] = w.dims[n];
-    q.dst[0] = dst.fac[n];
-    q.dst2[0] = dst2 ? dst2->fac[n] : nullptr;
-    HIP_TRY(launch_pad_factors(q, st));
+    const int f = n + 1;
+    p.cols[f] = w.J[n];
+    p.ld[f] = w.J[n];
+    p.src[f] = m->factors[n];
+    p.rows[f] = w.dims[n];
+    p.rows_p[f] = n == 2 ? w.Kp : w.dims[n];
+    p.dst[f] = dst.fac[n];
+    p.dst2[f] = dst2 ? dst2->fac[n] : nullptr;
+    if (n == 2) {
+      p.dstT[f] = dst.facT2;
+      p.dst2T[f] = dst2 ? dst2->facT2 : nullptr;
+    }
   }
+  HIP_TRY(launch_pad_factors(p, st));
   return COMM_OK;
 }
 
@@ -268,103 +382,92 @@ struct Slots {
   int rows_total;
 };
 
-// Numerator (use_q = 0) or denominator (use_q = 1) of block `blk` (-1 core,
-// 0..2 factor) contracted against the set `cs`, from X rebuilt with `rb` or
-// from the cached weight.  Returns the partial slots.
-int tk_contract(comm_ctx* ctx, const comm_dense* x, const comm_opts* o, const TkWs& w, int blk, bool use_q,
-                const TkModel& rb, const TkModel& cs, const float* cached, bool want_obj, float* slot_buf,
-                Slots* out, hipStream_t st) {
-  const int I = w.dims[0], J = w.dims[1], K = w.dims[2];
-  const int J1 = w.J[0], J2 = w.J[1];
+TkPassArgs pass_args(const comm_dense* x, const comm_opts* o, const TkWs& w) {
   TkPassArgs a = {};
   a.X = x->X;
-  a.Wc = cached;
-  a.I = I;
-  a.J = J;
-  a.K = K;
+  a.I = w.dims[0];
+  a.J = w.dims[1];
+  a.K = w.dims[2];
   a.Kp = w.Kp;
-  a.r = rb;
-  a.n = cs;
   a.eps = (float)o->eps;
   a.eps_x = (float)o->eps_x;
-  a.use_q = use_q;
-  a.want_v = blk != 2;
-  a.want_m3 = blk == 2;
   a.bc = make_beta_const(o->beta);
-  a.V = w.V;
-  a.m3 = w.m3[use_q ? 1 : 0];
+  a.Vn = w.Vn;
+  a.Vd = w.Vd;
+  a.m3n = w.m3[0];
+  a.m3d = w.m3[1];
   a.obj_part = w.obj_part;
-  const int mode = cached ? 1 : 0;
-  const int bc = beta_class_of(o->beta);
-  TkModel rb2 = rb;
-  (void)rb2;
-  int rc = profiled(ctx, st, [&] {
-    TkPassArgs b = a;
-    if (want_obj) b.obj_part = w.obj_part;
-    return launch_tk_pass(b, w.g, bc, mode | (want_obj ? 4 : 0), st);
-  });
-  if (rc) return rc;
-  if (blk == 2) {
-    *out = Slots{a.m3, w.g.wgs(), w.Kp};
-    return COMM_OK;
-  }
+  a.tpw = w.tpw;
+  a.npg = w.npg;
+  a.Pp = w.Pp;
+  return a;
+}
+
+// Numerator slots of block blk (-1 core, 0, 1) from V of the contraction set
+// cs[0] (into out[0]) and, when sets = 2, the denominator from V of cs[1].
+int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hipStream_t st) {
+  const int I = w.dims[0], J = w.dims[1];
+  const int J1 = w.J[0], J2 = w.J[1];
+  constexpr int kNoWrap = 30, kWrap32 = 5;
+  const float* V[2] = {w.Vn, w.Vd};
+  auto set_ptrs = [&](GemmArgs& g, auto fa, auto fb, auto fo) {
+    g.sets = sets;
+    for (int k = 0; k < sets; ++k) {
+      g.A[k] = fa(k);
+      g.B[k] = fb(k);
+      g.out[k] = fo(k);
+    }
+  };
   if (blk == -1 || blk == 0) {
     // U[i][b][c] = sum_j B'[j][b] V[i][j][c]
     GemmArgs g = {};
-    g.A = cs.B.p;
-    g.sab = 0; g.sam = 1; g.akin = 1 << 30; g.sako = 0; g.saki = cs.B.ld;
-    g.B = w.V;
-    g.sbb = (int64_t)J * kRP; g.bkin = 1 << 30; g.sbko = 0; g.sbki = kRP; g.sbn = 1;
-    g.out = w.U;
+    g.sab = 0; g.sam = 1; g.akin_log2 = kNoWrap; g.sako = 0; g.saki = kRP;
+    g.sbb = (int64_t)J * kRP; g.bkin_log2 = kNoWrap; g.sbko = 0; g.sbki = kRP; g.sbn = 1;
     g.sob = (int64_t)J2 * kRP; g.sos = 0; g.ldo = kRP;
     g.M = J2; g.N = kRP; g.K = J; g.batch = I; g.splits = 1;
+    set_ptrs(g, [&](int k) { return cs[k].B.p; }, [&](int k) { return V[k]; }, [&](int k) { return w.U[k]; });
     HIP_TRY(launch_gemm(g, st));
   }
   if (blk == 0) {
     // Num1[i][a] = sum_{(b,c)} U[i][(b,c)] G'[a][(b,c)]
     GemmArgs g = {};
-    g.A = w.U;
-    g.sab = 0; g.sam = (int64_t)J2 * kRP; g.akin = 1 << 30; g.sako = 0; g.saki = 1;
-    g.B = cs.G;
-    g.sbb = 0; g.bkin = 1 << 30; g.sbko = 0; g.sbki = 1; g.sbn = (int64_t)J2 * kRP;
-    g.out = slot_buf;
+    g.sab = 0; g.sam = (int64_t)J2 * kRP; g.akin_log2 = kNoWrap; g.sako = 0; g.saki = 1;
+    g.sbb = 0; g.bkin_log2 = kNoWrap; g.sbko = 0; g.sbki = 1; g.sbn = (int64_t)J2 * kRP;
     g.sob = 0; g.sos = (int64_t)I * kRP; g.ldo = kRP;
     g.M = I; g.N = J1; g.K = J2 * kRP; g.batch = 1; g.splits = kSplit1;
+    set_ptrs(g, [&](int k) { return (const float*)w.U[k]; }, [&](int k) { return cs[k].G; },
+             [&](int k) { return w.slots[k]; });
     HIP_TRY(launch_gemm(g, st));
-    *out = Slots{slot_buf, kSplit1, I};
+    for (int k = 0; k < sets; ++k) out[k] = Slots{w.slots[k], kSplit1, I};
   } else if (blk == -1) {
     // Ncore[a][(b,c)] = sum_i A'[i][a] U[i][(b,c)]
     GemmArgs g = {};
-    g.A = cs.A.p;
-    g.sab = 0; g.sam = 1; g.akin = 1 << 30; g.sako = 0; g.saki = cs.A.ld;
-    g.B = w.U;
-    g.sbb = 0; g.bkin = 1 << 30; g.sbko = 0; g.sbki = (int64_t)J2 * kRP; g.sbn = 1;
-    g.out = slot_buf;
+    g.sab = 0; g.sam = 1; g.akin_log2 = kNoWrap; g.sako = 0; g.saki = kRP;
+    g.sbb = 0; g.bkin_log2 = kNoWrap; g.sbko = 0; g.sbki = (int64_t)J2 * kRP; g.sbn = 1;
     g.sob = 0; g.sos = (int64_t)J1 * J2 * kRP; g.ldo = (int64_t)J2 * kRP;
     g.M = J1; g.N = J2 * kRP; g.K = I; g.batch = 1; g.splits = kSplitCore;
+    set_ptrs(g, [&](int k) { return cs[k].A.p; }, [&](int k) { return (const float*)w.U[k]; },
+             [&](int k) { return w.slots[k]; });
     HIP_TRY(launch_gemm(g, st));
-    *out = Slots{slot_buf, kSplitCore, J1 * J2};
+    for (int k = 0; k < sets; ++k) out[k] = Slots{w.slots[k], kSplitCore, J1 * J2};
   } else {
     // H[i][(b,c)] = sum_a A'[i][a] G'[a][(b,c)];  Num2[j][b] = sum_{(i,c)} V[i][j][c] H[i][b][c]
     GemmArgs g = {};
-    g.A = cs.A.p;
-    g.sab = 0; g.sam = cs.A.ld; g.akin = 1 << 30; g.sako = 0; g.saki = 1;
-    g.B = cs.G;
-    g.sbb = 0; g.bkin = 1 << 30; g.sbko = 0; g.sbki = (int64_t)J2 * kRP; g.sbn = 1;
-    g.out = w.H;
+    g.sab = 0; g.sam = kRP; g.akin_log2 = kNoWrap; g.sako = 0; g.saki = 1;
+    g.sbb = 0; g.bkin_log2 = kNoWrap; g.sbko = 0; g.sbki = (int64_t)J2 * kRP; g.sbn = 1;
     g.sob = 0; g.sos = 0; g.ldo = (int64_t)J2 * kRP;
     g.M = I; g.N = J2 * kRP; g.K = J1; g.batch = 1; g.splits = 1;
+    set_ptrs(g, [&](int k) { return cs[k].A.p; }, [&](int k) { return cs[k].G; }, [&](int k) { return w.H[k]; });
     HIP_TRY(launch_gemm(g, st));
     GemmArgs h = {};
-    h.A = w.V;
-    h.sab = 0; h.sam = kRP; h.akin = kRP; h.sako = (int64_t)J * kRP; h.saki = 1;
-    h.B = w.H;
-    h.sbb = 0; h.bkin = kRP; h.sbko = (int64_t)J2 * kRP; h.sbki = 1; h.sbn = kRP;
-    h.out = slot_buf;
+    h.sab = 0; h.sam = kRP; h.akin_log2 = kWrap32; h.sako = (int64_t)J * kRP; h.saki = 1;
+    h.sbb = 0; h.bkin_log2 = kWrap32; h.sbko = (int64_t)J2 * kRP; h.sbki = 1; h.sbn = kRP;
     h.sob = 0; h.sos = (int64_t)J * kRP; h.ldo = kRP;
     h.M = J; h.N = J2; h.K = I * kRP; h.batch = 1; h.splits = kSplit2;
+    set_ptrs(h, [&](int k) { return V[k]; }, [&](int k) { return (const float*)w.H[k]; },
+             [&](int k) { return w.slots[k]; });
     HIP_TRY(launch_gemm(h, st));
-    *out = Slots{slot_buf, kSplit2, J};
+    for (int k = 0; k < sets; ++k) out[k] = Slots{w.slots[k], kSplit2, J};
   }
   return COMM_OK;
 }
@@ -372,7 +475,8 @@ int tk_contract(comm_ctx* ctx, const comm_dense* x, const comm_opts* o, const Tk
 // One block update: max(anchor * (Num/Den)^gamma, eps) into the caller's
 // block (and a padded copy).  blk -1 = core.
 int tk_apply(const comm_model* m, const TkWs& w, int blk, const Slots& num, const Slots* den,
-             const float* den_closed_vec, FView anchor, float* out_pad, float gamma, float eps, hipStream_t st) {
+             const float* den_closed_vec, FView anchor, float* out_pad, float* out_padT, float gamma, float eps,
+             hipStream_t st) {
   SlotUpdateArgs u = {};
   u.njobs = 1;
   SlotJob& Jb = u.job[0];
@@ -397,11 +501,12 @@ int tk_apply(const comm_model* m, const TkWs& w, int blk, const Slots& num, cons
     Jb.out_user = m->factors[blk];
     Jb.ld_user = w.J[blk];
   }
-  Jb.rows_p = Jb.rows;
+  Jb.rows_p = blk == 2 ? w.Kp : Jb.rows;
   Jb.anchor = anchor;
   Jb.gamma = gamma;
   Jb.eps = eps;
   Jb.out_pad = out_pad;
+  Jb.out_padT = blk == 2 ? out_padT : nullptr;
   HIP_TRY(launch_slot_update(u, st));
   return COMM_OK;
 }
@@ -426,23 +531,68 @@ int tk_closed_den(const TkWs& w, int blk, const TkModel& ds, Slots* core_den, co
   return COMM_OK;
 }
 
+// Update of block blk: numerator (and, unless beta = 1, denominator) against
+// the sets ns / ds with X rebuilt from rb (its T2 in w.T2r) or read from the
+// cached P~ / Q~; t2n / t2d are the sets' T2 for the mode-3 block.
 int tk_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, const TkWs& w, int blk,
-             const TkModel& rb, const TkModel& ns, const TkModel& ds, const float* cacheP, const float* cacheQ,
-             bool want_obj, FView anchor, float* out_pad, double* obj, hipStream_t st) {
+             const TkModel& rb, const TkModel& ns, const TkModel& ds, const float* cnT, const float* cdT,
+             bool cached, bool want_obj, FView anchor, float* out_pad, double* obj, hipStream_t st) {
   const bool kl = o->beta == 1.0;
+  const int sets = kl ? 1 : 2;
+  const int bc = beta_class_of(o->beta);
+  const int mode = cached ? kTkCacheRead : kTkFromX;
+  TkPassArgs a = pass_args(x, o, w);
+  a.T2r = w.T2r;
+  a.C = rb.C;
+  if (cached) {
+    a.Pc = w.Pc;
+    a.Qc = w.Qc;
+  }
   Slots num, den;
-  int rc = tk_contract(ctx, x, o, w, blk, false, rb, ns, cacheP, want_obj, w.slots[0], &num, st);
-  if (rc) return rc;
-  if (want_obj && obj) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+  int rc;
+  if (blk == 2) {
+    a.T2nT = w.T2nT;
+    a.T2dT = w.T2dT;
+    rc = profiled(ctx, st, [&] { return launch_tk_m3(a, bc, mode, sets, st); });
+    if (rc) return rc;
+    num = Slots{w.m3[0], w.npg, w.Kp};
+    den = Slots{w.m3[1], w.npg, w.Kp};
+  } else {
+    a.CnT = cnT;
+    a.CdT = cdT;
+    rc = profiled(ctx, st, [&] { return launch_tk_v(a, bc, mode, want_obj, sets, st); });
+    if (rc) return rc;
+    if (want_obj && obj) HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, obj, st));
+    const TkModel cs[2] = {ns, ds};
+    Slots nd[2];
+    if ((rc = tk_gemms(w, blk, cs, sets, nd, st))) return rc;
+    num = nd[0];
+    den = nd[1];
+  }
   const float* vec = nullptr;
   Slots* denp = &den;
   if (kl) {
     if ((rc = tk_closed_den(w, blk, ds, &den, &vec, st))) return rc;
     if (blk != -1) denp = nullptr;
-  } else {
-    if ((rc = tk_contract(ctx, x, o, w, blk, true, rb, ds, cacheQ, false, w.slots[1], &den, st))) return rc;
   }
-  return tk_apply(m, w, blk, num, denp, vec, anchor, out_pad, gamma_of(o->beta), (float)o->eps, st);
+  return tk_apply(m, w, blk, num, denp, vec, anchor, out_pad, w.cur.facT2, gamma_of(o->beta), (float)o->eps, st);
+}
+
+// T2 of one model into T2 (and its transposed copy into T2T unless NULL).
+int tk_t2(const TkWs& w, const TkModel& md, float* T2, float* T2T, hipStream_t st) {
+  float* out[1] = {T2};
+  float* outT[1] = {T2T};
+  HIP_TRY(launch_tk_t2(&md, out, outT, 1, w.dims[0], w.dims[1], w.Pp, st));
+  return COMM_OK;
+}
+
+// T2 of the numerator and denominator sets for the mode-3 block.
+int tk_t2_pair(const TkWs& w, const TkModel& m0, const TkModel& m1, hipStream_t st) {
+  const TkModel m[2] = {m0, m1};
+  float* out[2] = {w.T2n, w.T2d};
+  float* outT[2] = {w.T2nT, w.T2dT};
+  HIP_TRY(launch_tk_t2(m, out, outT, 2, w.dims[0], w.dims[1], w.Pp, st));
+  return COMM_OK;
 }
 
 }  // namespace
@@ -460,7 +610,7 @@ int tucker_check_model(const comm_model* m, const comm_dense* x) {
 }
 
 size_t tucker_workspace_bytes(const comm_dense* x, const comm_model* m, const comm_opts* o, int op) {
-  const bool cache = op == 1 && o->cache_pq;
+  const bool cache = op == 1 && o->cache_pq && o->beta != 1.0;
   return tk_layout(x, m, nullptr, cache).bytes;
 }
 
@@ -477,41 +627,44 @@ int tucker_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, c
   if (block == -2) blocks = {-1, 0, 1, 2};
   else blocks = {block};
   for (int blk : blocks) {
-    rc = tk_block(ctx, x, m, o, w, blk, cur, cur, cur, nullptr, nullptr, false, block_view(cur, blk),
-                  copy_block(w.cur, blk), nullptr, st);
+    // block-MM rebuilds from the current model before every block; the
+    // contraction sets are the current model too
+    if ((rc = tk_t2(w, cur, w.T2r, blk == 2 ? w.T2nT : nullptr, st))) return rc;
+    if (blk == 2) {
+      TkWs w2 = w;
+      w2.T2dT = w.T2nT;
+      rc = tk_block(ctx, x, m, o, w2, blk, cur, cur, cur, nullptr, nullptr, false, false, block_view(cur, blk),
+                    copy_block(w.cur, blk), nullptr, st);
+    } else {
+      rc = tk_block(ctx, x, m, o, w, blk, cur, cur, cur, w.cur.facT2, w.cur.facT2, false, false,
+                    block_view(cur, blk), copy_block(w.cur, blk), nullptr, st);
+    }
     if (rc) return rc;
   }
   return COMM_OK;
 }
 
 int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
-  const bool cache = o->cache_pq && o->beta != 1.0;
+  const bool kl = o->beta == 1.0;
+  const bool cache = o->cache_pq && !kl;
   TkWs w = tk_layout(x, m, nullptr, cache);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
   w = tk_layout(x, m, ctx->ws, cache);
   if ((rc = tk_pad(m, w, w.ref, &w.cur, st))) return rc;
   const TkModel ref = model_of(w, w.ref);
-  const TkModel cur = model_of(w, w.cur);
+  // the reference model, and so its T2, is fixed for the whole outer iteration
+  if ((rc = tk_t2(w, ref, w.T2r, nullptr, st))) return rc;
   bool obj_pending = obj != nullptr;
   if (cache) {
-    TkPassArgs a = {};
-    a.X = x->X;
+    TkPassArgs a = pass_args(x, o, w);
+    a.T2r = w.T2r;
+    a.C = ref.C;
     a.Pw = w.Pc;
     a.Qw = w.Qc;
-    a.I = w.dims[0];
-    a.J = w.dims[1];
-    a.K = w.dims[2];
-    a.Kp = w.Kp;
-    a.r = ref;
-    a.n = ref;
-    a.eps = (float)o->eps;
-    a.eps_x = (float)o->eps_x;
-    a.bc = make_beta_const(o->beta);
-    a.obj_part = w.obj_part;
-    rc = profiled(ctx, st, [&] { return launch_tk_pass(a, w.g, beta_class_of(o->beta), 2 | (obj_pending ? 4 : 0), st); });
+    rc = profiled(ctx, st, [&] { return launch_tk_v(a, beta_class_of(o->beta), kTkCacheWrite, obj_pending, 0, st); });
     if (rc) return rc;
-    if (obj_pending) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+    if (obj_pending) HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, obj, st));
     obj_pending = false;
   }
   const float beta = (float)o->beta;
@@ -530,7 +683,13 @@ int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_o
       };
       if (blk != -1) add(w.cur.core, w.ref.core, w.J[0] * w.J[1], w.num.core, w.den.core);
       for (int q = 0; q < 3; ++q)
-        if (q != blk) add(w.cur.fac[q], w.ref.fac[q], w.dims[q], w.num.fac[q], w.den.fac[q]);
+        if (q != blk) {
+          add(w.cur.fac[q], w.ref.fac[q], q == 2 ? w.Kp : w.dims[q], w.num.fac[q], w.den.fac[q]);
+          if (q == 2) {
+            ca.x1T[ca.nf - 1] = w.num.facT2;
+            ca.x2T[ca.nf - 1] = w.den.facT2;
+          }
+        }
       HIP_TRY(launch_chi(ca, st));
       TkModel ns = model_of(w, w.num), ds = model_of(w, w.den);
       // the active block does not enter its own contraction
@@ -538,13 +697,16 @@ int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_o
       else if (blk == 0) { ns.A = ref.A; ds.A = ref.A; }
       else if (blk == 1) { ns.B = ref.B; ds.B = ref.B; }
       else { ns.C = ref.C; ds.C = ref.C; }
-      rc = tk_block(ctx, x, m, o, w, blk, ref, ns, ds, cache ? w.Pc : nullptr, cache ? w.Qc : nullptr, obj_pending,
+      if (blk == 2) {
+        rc = kl ? tk_t2(w, ns, w.T2n, w.T2nT, st) : tk_t2_pair(w, ns, ds, st);
+        if (rc) return rc;
+      }
+      rc = tk_block(ctx, x, m, o, w, blk, ref, ns, ds, w.num.facT2, w.den.facT2, cache, obj_pending,
                     block_view(ref, blk), copy_block(w.cur, blk), obj, st);
       if (rc) return rc;
       obj_pending = false;
     }
   }
-  (void)cur;
   return COMM_OK;
 }
 
@@ -556,22 +718,12 @@ int tucker_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, co
   w = tk_layout(x, m, ctx->ws, false);
   if ((rc = tk_pad(m, w, w.cur, nullptr, st))) return rc;
   const TkModel cur = model_of(w, w.cur);
-  TkPassArgs a = {};
-  a.X = x->X;
-  a.I = w.dims[0];
-  a.J = w.dims[1];
-  a.K = w.dims[2];
-  a.Kp = w.Kp;
-  a.r = cur;
-  a.n = cur;
-  a.eps = (float)o->eps;
-  a.eps_x = (float)o->eps_x;
-  a.bc = make_beta_const(o->beta);
-  a.V = w.V;
-  a.m3 = w.m3[0];
-  a.obj_part = w.obj_part;
-  rc = profiled(ctx, st, [&] { return launch_tk_pass(a, w.g, beta_class_of(o->beta), 0 | 4, st); });
+  if ((rc = tk_t2(w, cur, w.T2r, nullptr, st))) return rc;
+  TkPassArgs a = pass_args(x, o, w);
+  a.T2r = w.T2r;
+  a.C = cur.C;
+  rc = profiled(ctx, st, [&] { return launch_tk_v(a, beta_class_of(o->beta), kTkFromX, true, 0, st); });
   if (rc) return rc;
-  HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, out, st));
+  HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, out, st));
   return COMM_OK;
 }

@@ -1,26 +1,30 @@
-// Fused dense 3-way Tucker pass for gfx950 (MI355X).
+// Fused dense 3-way Tucker passes for gfx950 (MI355X).
 //
-// The Tucker reconstruction (App. C, eq. tucker_entry) is, for every (i, j)
-// pair, a contraction over the third core index:
+// The Tucker reconstruction (App. C, eq. tucker_entry) of pair (i, j) is a
+// 32-term contraction over the third core index,
 //   Xhat[(i,j)][k] = sum_c T2[(i,j)][c] C[k][c],
-//   T2[(i,j)][c]   = sum_b B[j][b] T1[i][b][c],  T1[i][b][c] = sum_a A[i][a] G[a][b][c].
-// A workgroup owns 8 i x 16 j pairs and all of K.  It first stages T2 for its
-// 128 pairs in LDS (for the rebuild model and, separately, for the
-// contraction set), then streams X in 32 (pairs) x 32 (k) tiles per wavefront
-// with the same matrix-core chains as the CP pass:
-//   rebuild  Xhat = T2 C^T                         (v_mfma_f32_32x32x2_f32)
-//   weights  W = P or Q in registers (Sec. 4.1, Sec. 5.3), objective optional
-//   mode 3   Num3[k][c] = sum_m W[m][k] T2'[m][c]   (factor numerator of mode 3,
-//                                                     App. C eqs. block_factor_num,
-//                                                     jmm_factor_num, direct form)
-//   V        V[m][c]    = sum_k W[m][k] C'[k][c]     (complete per pair: the
-//                                                     workgroup covers all of K)
-// V is the only intermediate written (I x J x 32 floats, a fraction J3/K of
-// X); the mode-1, mode-2 and core numerators follow from it in small kernels
-// (tucker3.hip) without ever forming the partial tensor B^(n) or Xhat.
-// Waves take k tiles w, w+4, ...; each k tile belongs to one wave, so the
-// mode-3 partial of a tile is final within the workgroup, and V is combined
-// across the four waves in a fixed order.  No atomics: deterministic.
+//   T2[(i,j)][c]   = sum_{a,b} A[i][a] B[j][b] G[a][b][c],
+// so X, read as an (I J) x K matrix with one mode-3 fibre per row, is streamed
+// with the same matrix-core tiles as the CP pass once T2 is known.  T2 is
+// built per model by tk_t2_kernel (I J x 32 floats, J3 / K of the size of X).
+//
+// V pass (core, mode-1 and mode-2 blocks): a workgroup owns 32 pairs and its
+// four waves split K in 32-wide tiles, in the transposed orientation (lane =
+// pair, registers = k), so that
+//   rebuild  Xhat^T[k][m] = sum_c C[k][c] T2[m][c]            (v_mfma_f32_32x32x2_f32)
+//   weights  P, Q in registers (Sec. 4.1, Sec. 5.3), objective optional
+//   V^T      V^T[c][m]   += sum_k C'[k][c] W[m][k]             (W straight from registers)
+// need no transpose; the waves' partial V are summed in a fixed order in LDS
+// (the numerator and the denominator set are contracted in the same pass).
+// The mode-1, mode-2 and core numerators follow from V with small GEMMs
+// (tucker3.hip); the partial tensor B^(n) of App. C is never formed.
+//
+// Mode-3 pass: a workgroup owns a 32-wide k tile and a group of pairs, in the
+// CP orientation (lane = k, registers = pairs):
+//   Num3[k][c] = sum_m W[m][k] T2'[m][c]
+// with the rebuilt weight tile consumed from registers; the four waves'
+// partials are combined in a fixed order and written to the group's slot.
+// Every reduction has a fixed order: the passes are bitwise deterministic.
 
 #pragma once
 
@@ -28,205 +32,307 @@
 
 namespace comm {
 
-constexpr int kTkTI = 8;    // i per workgroup
-constexpr int kTkTJ = 16;   // j per workgroup
-constexpr int kTkPairs = kTkTI * kTkTJ;
-constexpr int kTkStride = 36;
+constexpr int kTkPairsPerWg = 32;
 
-enum TkMode : int { kTkFromX = 0, kTkCacheRead = 1, kTkCacheWrite = 2 };
-
-struct TkShared {
-  float t1[32 * 32];                  // T1 of one i (J2 x J3, padded)
-  float t2r[kTkPairs * kTkStride];    // rebuild T2 rows
-  float t2n[kTkPairs * 32];           // contraction T2' rows
-  float t[kWaves][32 * kLdsT];        // per-wave transpose buffers
-  float vred[kTkPairs * 32];          // V combined across waves
-  double obj[kWaves];
-};
-
-// T2[(il, jl)][c] for the workgroup's pairs into dst (row stride ld).
-__device__ __forceinline__ void stage_t2(const TkModel& m, int i0, int j0, int I, int J, float* t1, float* dst,
-                                         int ld) {
-  const int tid = threadIdx.x;
-  for (int il = 0; il < kTkTI; ++il) {
-    const int i = i0 + il;
-    for (int e = tid; e < 32 * 32; e += kThreads) {
-      const int b = e >> 5, c = e & 31;
-      float s = 0.0f;
-      if (i < I && b < m.J2 && c < m.J3)
-        for (int a = 0; a < m.J1; ++a) s = fmaf(m.A.at(i, a, I), m.G[((size_t)a * m.J2 + b) * m.ldG + c], s);
-      t1[e] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < kTkTJ * 32; e += kThreads) {
-      const int jl = e >> 5, c = e & 31;
-      const int j = j0 + jl;
-      float s = 0.0f;
-      if (j < J)
-        for (int b = 0; b < m.J2; ++b) s = fmaf(m.B.at(j, b, J), t1[b * 32 + c], s);
-      dst[(il * kTkTJ + jl) * ld + c] = s;
-    }
-    __syncthreads();
+// 16 consecutive floats of a 16-byte aligned row, or zeros.
+__device__ __forceinline__ void row16(const float* p, bool ok, float (&v)[16]) {
+  if (ok) {
+    load16(p, v);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) v[s] = 0.0f;
   }
 }
 
-template <int BC, int kMode, bool kObj>
-__global__ void __launch_bounds__(kThreads) tk_pass_kernel(TkPassArgs a, int gj) {
-  __shared__ TkShared sh;
-  const int tid = threadIdx.x;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const int col = lane & 31;
-  const int h = lane >> 5;
-  const int wg = blockIdx.x;
-  const int bj = wg % gj, bi = wg / gj;
-  const int i0 = bi * kTkTI, j0 = bj * kTkTJ;
-  const int I = a.I, J = a.J, K = a.K;
-  constexpr bool kRebuild = kMode != kTkCacheRead;
-  const bool want_m3 = kMode != kTkCacheWrite && a.want_m3;
-  const bool want_v = kMode != kTkCacheWrite && a.want_v;
-
-  if (kRebuild) stage_t2(a.r, i0, j0, I, J, sh.t1, sh.t2r, kTkStride);
-  if (want_m3) stage_t2(a.n, i0, j0, I, J, sh.t1, sh.t2n, 32);
-
-  f32x16 vacc[4] = {};
-  double obj = 0.0;
-  const int nkt = (K + 31) / 32;
-  for (int kt = w; kt < nkt; kt += kWaves) {
-    const int kslice = kt * 32;
-    const int kcol = kslice + col;
-    const bool kvalid = kcol < K;
-    float crow[16], ctn[16];
+// X[m][k0 + out_row(v, h)] for the lane's row m (transposed orientation):
+// four runs of four consecutive k.
+template <bool kVec>
+__device__ __forceinline__ void load_fibre(const float* __restrict__ row, int64_t k0, int64_t K, int h, bool ok,
+                                           float (&x)[16]) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      if (kRebuild) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
-      ctn[s] = want_v ? a.n.C.at(kslice + 16 * h + s, col, K) : 0.0f;
+  for (int g = 0; g < 4; ++g) {
+    const int64_t kb = k0 + 8 * g + 4 * h;
+    if constexpr (kVec) {
+      f32x4 t = ok ? *reinterpret_cast<const f32x4*>(row + kb) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      x[4 * g + 0] = t[0];
+      x[4 * g + 1] = t[1];
+      x[4 * g + 2] = t[2];
+      x[4 * g + 3] = t[3];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[4 * g + u] = (ok && kb + u < K) ? row[kb + u] : 0.0f;
     }
-    f32x16 m3acc = {};
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      // tile rows: pair m = out_row(v, h) of block mb, i.e. il = 2 mb + (m >> 4), jl = m & 15
+  }
+}
+
+template <int BC, int kMode, bool kObj, int kSets>
+__global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
+  __shared__ float red[kWaves][kSets > 0 ? kSets : 1][32 * 33];
+  __shared__ double sobj[kWaves];
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31, h = lane >> 5;
+  const int w = threadIdx.x >> 6;
+  const int64_t npairs = (int64_t)a.I * a.J;
+  const int64_t p0 = (int64_t)blockIdx.x * 32;
+  const int64_t pm = p0 + col;  // this lane's pair
+  const bool pvalid = pm < npairs;
+  const int K = a.K;
+  constexpr bool kRebuild = kMode != kTkCacheRead;
+  // vector loads of the fibre need 16-byte aligned rows
+  const bool vec = (K & 3) == 0;
+
+  float t2[16];
+  if constexpr (kRebuild) row16(a.T2r + pm * kRP + 16 * h, pvalid, t2);
+  f32x16 vn = {}, vd = {};
+  double obj = 0.0;
+  const float* xrow = a.X + pm * (int64_t)K;
+  const float* prow = kMode == kTkCacheRead ? a.Pc + pm * (int64_t)K : nullptr;
+  const float* qrow = kMode == kTkCacheRead && kSets == 2 ? a.Qc + pm * (int64_t)K : nullptr;
+
+  // the four waves share the workgroup's 32 pairs and split the k tiles
+  for (int k0 = 32 * w; k0 < K; k0 += 32 * kWaves) {
+    const bool full = k0 + 32 <= K;
+    float pv[16], qv[16];
+    if constexpr (kMode == kTkCacheRead) {
+      if (vec && full) {
+        load_fibre<true>(prow, k0, K, h, pvalid, pv);
+        if constexpr (kSets == 2) load_fibre<true>(qrow, k0, K, h, pvalid, qv);
+      } else {
+        load_fibre<false>(prow, k0, K, h, pvalid, pv);
+        if constexpr (kSets == 2) load_fibre<false>(qrow, k0, K, h, pvalid, qv);
+      }
+    } else {
       float xv[16];
-      bool valid[16];
-      const float* src = kMode == kTkCacheRead ? a.Wc : a.X;
+      if (vec && full) load_fibre<true>(xrow, k0, K, h, pvalid, xv);
+      else load_fibre<false>(xrow, k0, K, h, pvalid, xv);
+      // rebuild: A = C rows (lane: k = k0 + col), B = T2 rows (lane: pair)
+      float crow[16];
+      row16(a.C.p + (int64_t)(k0 + col) * kRP + 16 * h, k0 + col < K, crow);
+      f32x16 xh = {};
+#pragma unroll
+      for (int s = 0; s < 16; ++s) xh = mfma32(crow[s], t2[s], xh);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int m = out_row(v, h);
-        const int i = i0 + 2 * mb + (m >> 4), j = j0 + (m & 15);
-        valid[v] = kvalid && i < I && j < J;
-        xv[v] = valid[v] ? src[((size_t)i * J + j) * K + kcol] : 0.0f;
+        const int k = k0 + out_row(v, h);
+        const bool ok = pvalid && k < K;
+        float x = xv[v];
+        if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
+        const float y = fmaxf(xh[v], a.eps);
+        float p, q, d = 0.0f;
+        bool far;
+        entry<BC, kObj>(x, y, a.bc, p, q, d, far);
+        if constexpr (kObj) {
+          if (BC == kKL && far) d = kl_direct(x, y);
+          obj += (double)(ok ? d : 0.0f);
+        }
+        pv[v] = ok ? p : 0.0f;
+        qv[v] = ok ? q : 0.0f;
       }
-      float wv[16];
-      if (kMode == kTkCacheRead) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) wv[v] = xv[v];
-      } else {
-        float arow[16];
-        load16(sh.t2r + (32 * mb + col) * kTkStride + 16 * h, arow);
-        f32x16 xh = {};
-#pragma unroll
-        for (int s = 0; s < 16; ++s) xh = mfma32(arow[s], crow[s], xh);
+      if constexpr (kMode == kTkCacheWrite) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          float x = xv[v];
-          if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
-          const float y = fmaxf(xh[v], a.eps);
-          float p, q, d = 0.0f;
-          bool far;
-          entry<BC, kObj>(x, y, a.bc, p, q, d, far);
-          if constexpr (kObj) {
-            if (BC == kKL && far) d = kl_direct(x, y);
-            obj += (double)(valid[v] ? d : 0.0f);
+          const int k = k0 + out_row(v, h);
+          if (pvalid && k < K) {
+            a.Pw[pm * (int64_t)K + k] = pv[v];
+            a.Qw[pm * (int64_t)K + k] = qv[v];
           }
-          p = valid[v] ? p : 0.0f;
-          q = valid[v] ? q : 0.0f;
-          if (kMode == kTkCacheWrite && valid[v]) {
-            const int m = out_row(v, h);
-            const size_t off = ((size_t)(i0 + 2 * mb + (m >> 4)) * J + (j0 + (m & 15))) * K + kcol;
-            a.Pw[off] = p;
-            a.Qw[off] = q;
-          }
-          wv[v] = a.use_q ? q : p;
         }
       }
-      if (want_m3) {
-        // A operand: lane (c = col, h) supplies T2'[32 mb + out_row(s, h)][col]
-#pragma unroll
-        for (int s = 0; s < 16; ++s) m3acc = mfma32(sh.t2n[(32 * mb + out_row(s, h)) * 32 + col], wv[s], m3acc);
-      }
-      if (want_v) {
-        float* ldsT = sh.t[w];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) ldsT[out_row(v, h) * kLdsT + col] = wv[v];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        float pr[16];
-        load16(ldsT + col * kLdsT + 16 * h, pr);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-        for (int s = 0; s < 16; ++s) vacc[mb] = mfma32(pr[s], ctn[s], vacc[mb]);
-        __builtin_amdgcn_wave_barrier();
-      }
     }
-    if (want_m3 && kvalid) {
-      // m3acc[v] = Num3[k = kcol][c = out_row(v, h)] over this workgroup's pairs
-      float* dst = a.m3 + ((size_t)wg * a.Kp + kcol) * kRP;
+    if constexpr (kSets >= 1) {
+      // V^T[c][m] += sum_k C'[k][c] W[m][k], k taken in the order out_row(s, h):
+      // the lane's C' column comes from the transposed copy as four runs of four
+      float cn[16], cd[16];
+      load_fibre<true>(a.CnT + (int64_t)col * a.Kp, k0, a.Kp, h, true, cn);
+      if constexpr (kSets == 2) load_fibre<true>(a.CdT + (int64_t)col * a.Kp, k0, a.Kp, h, true, cd);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) dst[out_row(v, h)] = m3acc[v];
+      for (int s = 0; s < 16; ++s) {
+        vn = mfma32(cn[s], pv[s], vn);
+        if constexpr (kSets == 2) vd = mfma32(cd[s], qv[s], vd);
+      }
     }
   }
 
-  // objective partial
-  if (kObj) {
+  if constexpr (kSets >= 1) {
+    // vn[v] = partial V[pair = col][c = out_row(v, h)]; combine the waves in order 0..3
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      red[w][0][col * 33 + out_row(v, h)] = vn[v];
+      if constexpr (kSets == 2) red[w][1][col * 33 + out_row(v, h)] = vd[v];
+    }
+  }
+  if constexpr (kObj) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) sh.obj[w] = obj;
+    if (lane == 0) sobj[w] = obj;
   }
   __syncthreads();
-  if (kObj && tid == 0) {
-    double s = sh.obj[0];
-    for (int q = 1; q < kWaves; ++q) s += sh.obj[q];
-    a.obj_part[wg] = s;
-  }
-
-  // V: combine the waves in order 0..3, then write the valid pairs
-  if (want_v) {
-    for (int q = 0; q < kWaves; ++q) {
-      if (w == q) {
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            float& dst = sh.vred[(32 * mb + out_row(v, h)) * 32 + col];
-            dst = (q == 0) ? vacc[mb][v] : dst + vacc[mb][v];
-          }
+  if constexpr (kSets >= 1) {
+    for (int e = threadIdx.x; e < 32 * 32; e += kThreads) {
+      const int r = e >> 5, c = e & 31;
+      if (p0 + r < npairs) {
+        float sn = red[0][0][r * 33 + c];
+        for (int q = 1; q < kWaves; ++q) sn += red[q][0][r * 33 + c];
+        a.Vn[(p0 + r) * kRP + c] = sn;
+        if constexpr (kSets == 2) {
+          float sd = red[0][1][r * 33 + c];
+          for (int q = 1; q < kWaves; ++q) sd += red[q][1][r * 33 + c];
+          a.Vd[(p0 + r) * kRP + c] = sd;
+        }
       }
-      __syncthreads();
     }
-    for (int e = tid; e < kTkPairs * 32; e += kThreads) {
-      const int p = e >> 5, c = e & 31;
-      const int i = i0 + (p >> 4), j = j0 + (p & 15);
-      if (i < I && j < J) a.V[((size_t)i * J + j) * kRP + c] = sh.vred[e];
+  }
+  if constexpr (kObj) {
+    if (threadIdx.x == 0) {
+      double s = sobj[0];
+      for (int q = 1; q < kWaves; ++q) s += sobj[q];
+      a.obj_part[blockIdx.x] = s;
     }
   }
 }
 
-template <int BC, int kMode, bool kObj>
-hipError_t launch_tk(const TkPassArgs& a, const TkGrid& g, hipStream_t s) {
-  hipLaunchKernelGGL((tk_pass_kernel<BC, kMode, kObj>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s, a, g.gj);
+// Mode-3 pass.  Workgroup (kt, g): k tile kt, pair group g of 4 * tpw pair
+// tiles; wave w takes tiles g * 4 * tpw + w * tpw + t, t < tpw.
+template <int BC, int kMode, int kSets>
+__global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
+  __shared__ float red[kWaves][2][32 * 33];
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31, h = lane >> 5;
+  const int w = threadIdx.x >> 6;
+  const int K = a.K;
+  const int nkt = (K + 31) / 32;
+  const int kt = blockIdx.x % nkt, g = blockIdx.x / nkt;
+  const int k0 = kt * 32;
+  const int kcol = k0 + col;
+  const bool kvalid = kcol < K;
+  const int64_t npairs = (int64_t)a.I * a.J;
+  constexpr bool kRebuild = kMode != kTkCacheRead;
+
+  float crow[16];
+  if constexpr (kRebuild) row16(a.C.p + (int64_t)kcol * kRP + 16 * h, kvalid, crow);
+  f32x16 an = {}, ad = {};
+  const int64_t pbase = (int64_t)(g * kWaves + w) * a.tpw * 32;
+  // the fibre entries of the next pair tile are loaded while the current one is processed
+  auto fetch = [&](int64_t p0, float (&dst)[16], const float* src) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t m = p0 + out_row(v, h);
+      dst[v] = (kvalid && m < npairs) ? src[m * K + kcol] : 0.0f;
+    }
+  };
+  const float* src0 = kMode == kTkCacheRead ? a.Pc : a.X;
+  float nx[16];
+  fetch(pbase, nx, src0);
+  for (int t = 0; t < a.tpw; ++t) {
+    const int64_t p0 = pbase + (int64_t)t * 32;
+    if (p0 >= npairs) break;
+    float cur[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) cur[v] = nx[v];
+    if (t + 1 < a.tpw) fetch(p0 + 32, nx, src0);
+    float pv[16], qv[16];
+    if constexpr (kMode == kTkCacheRead) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) pv[v] = cur[v];
+      if constexpr (kSets == 2) fetch(p0, qv, a.Qc);
+    } else {
+      // rebuild: A = T2 rows (lane: pair p0 + col), B = C rows (lane: k)
+      float t2[16];
+      row16(a.T2r + (p0 + col) * kRP + 16 * h, p0 + col < npairs, t2);
+      f32x16 xh = {};
+#pragma unroll
+      for (int s = 0; s < 16; ++s) xh = mfma32(t2[s], crow[s], xh);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t m = p0 + out_row(v, h);
+        const bool ok = kvalid && m < npairs;
+        float x = cur[v];
+        if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
+        const float y = fmaxf(xh[v], a.eps);
+        float p, q, d;
+        bool far;
+        entry<BC, false>(x, y, a.bc, p, q, d, far);
+        pv[v] = ok ? p : 0.0f;
+        qv[v] = ok ? q : 0.0f;
+      }
+    }
+    // Num3[k][c] += sum_m W[m][k] T2'[m][c], m taken in the order out_row(s, h):
+    // the lane's T2' column comes from the transposed copy as four runs of four
+    float tn[16], td[16];
+    load_fibre<true>(a.T2nT + (int64_t)col * a.Pp, p0, a.Pp, h, true, tn);
+    if constexpr (kSets == 2) load_fibre<true>(a.T2dT + (int64_t)col * a.Pp, p0, a.Pp, h, true, td);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      an = mfma32(pv[s], tn[s], an);
+      if constexpr (kSets == 2) ad = mfma32(qv[s], td[s], ad);
+    }
+  }
+  // an[v] = Num3[k0 + out_row(v, h)][c = col]; combine the waves in order 0..3
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    red[w][0][out_row(v, h) * 33 + col] = an[v];
+    if constexpr (kSets == 2) red[w][1][out_row(v, h) * 33 + col] = ad[v];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += kThreads) {
+    const int r = e >> 5, c = e & 31;
+    float sn = red[0][0][r * 33 + c];
+    for (int q = 1; q < kWaves; ++q) sn += red[q][0][r * 33 + c];
+    a.m3n[((int64_t)g * a.Kp + k0 + r) * kRP + c] = sn;
+    if constexpr (kSets == 2) {
+      float sd = red[0][1][r * 33 + c];
+      for (int q = 1; q < kWaves; ++q) sd += red[q][1][r * 33 + c];
+      a.m3d[((int64_t)g * a.Kp + k0 + r) * kRP + c] = sd;
+    }
+  }
+}
+
+template <int BC, int kMode, bool kObj, int kSets>
+hipError_t launch_v(const TkPassArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((tk_v_kernel<BC, kMode, kObj, kSets>), dim3((unsigned)tk_v_workgroups(a.I, a.J)),
+                     dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-template <int BC>
-hipError_t launch_tk_bc(const TkPassArgs& a, const TkGrid& g, int mode, bool obj, hipStream_t s) {
-  if (mode == kTkCacheWrite) {
-    if constexpr (BC == kKL) return hipErrorInvalidValue;  // beta = 1 never caches
-    else return obj ? launch_tk<BC, kTkCacheWrite, true>(a, g, s) : launch_tk<BC, kTkCacheWrite, false>(a, g, s);
-  }
-  return obj ? launch_tk<BC, kTkFromX, true>(a, g, s) : launch_tk<BC, kTkFromX, false>(a, g, s);
+template <int BC, int kMode, int kSets>
+hipError_t launch_m3(const TkPassArgs& a, hipStream_t s) {
+  const int nkt = (a.K + 31) / 32;
+  hipLaunchKernelGGL((tk_m3_kernel<BC, kMode, kSets>), dim3((unsigned)(nkt * a.npg)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
 }
 
-hipError_t launch_tk_a(const TkPassArgs& a, const TkGrid& g, int bc, int mode, bool obj, hipStream_t s);
-hipError_t launch_tk_b(const TkPassArgs& a, const TkGrid& g, int bc, int mode, bool obj, hipStream_t s);
+// Variants used per beta class: beta = 1 contracts P only (its denominators
+// are closed-form) and never caches; the other classes contract P and Q.
+template <int BC>
+hipError_t launch_tk_v_bc(const TkPassArgs& a, int mode, bool obj, int sets, hipStream_t s) {
+  if (sets == 0) {
+    if (mode == kTkCacheWrite) {
+      if constexpr (BC == kKL) return hipErrorInvalidValue;
+      else return obj ? launch_v<BC, kTkCacheWrite, true, 0>(a, s) : launch_v<BC, kTkCacheWrite, false, 0>(a, s);
+    }
+    return launch_v<BC, kTkFromX, true, 0>(a, s);
+  }
+  if constexpr (BC == kKL) {
+    if (sets != 1) return hipErrorInvalidValue;
+    return obj ? launch_v<BC, kTkFromX, true, 1>(a, s) : launch_v<BC, kTkFromX, false, 1>(a, s);
+  } else {
+    if (sets != 2) return hipErrorInvalidValue;
+    return obj ? launch_v<BC, kTkFromX, true, 2>(a, s) : launch_v<BC, kTkFromX, false, 2>(a, s);
+  }
+}
+
+template <int BC>
+hipError_t launch_tk_m3_bc(const TkPassArgs& a, int sets, hipStream_t s) {
+  if constexpr (BC == kKL) {
+    return sets == 1 ? launch_m3<BC, kTkFromX, 1>(a, s) : hipErrorInvalidValue;
+  } else {
+    return sets == 2 ? launch_m3<BC, kTkFromX, 2>(a, s) : hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tk_v_a(const TkPassArgs& a, int bc, int mode, bool obj, int sets, hipStream_t s);
+hipError_t launch_tk_v_b(const TkPassArgs& a, int bc, int mode, bool obj, int sets, hipStream_t s);
+hipError_t launch_tk_m3_a(const TkPassArgs& a, int bc, int sets, hipStream_t s);
+hipError_t launch_tk_m3_b(const TkPassArgs& a, int bc, int sets, hipStream_t s);
 
 }  // namespace comm

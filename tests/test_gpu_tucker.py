@@ -21,7 +21,10 @@ import paper_2602_14683_amd as comm  # noqa: E402
 from tests.gpu_util import dev, f32, host64, max_rel  # noqa: E402
 
 BETAS = [0.0, 0.5, 1.0, 1.5, 0.7]
-SHAPES = [((20, 24, 28), (3, 4, 5)), ((37, 45, 70), (8, 6, 5)), ((64, 48, 40), (16, 16, 16))]
+# ragged tails in every mode; K = 96 takes the vector fibre loads throughout and
+# 100 x 90 pairs split the mode-3 pass over several pair tiles per wave
+SHAPES = [((20, 24, 28), (3, 4, 5)), ((37, 45, 70), (8, 6, 5)), ((64, 48, 40), (16, 16, 16)),
+          ((100, 90, 96), (5, 7, 9))]
 
 
 @pytest.fixture(scope="module")
