@@ -257,9 +257,14 @@ def run_coo(args, ctx):
     val = torch.from_numpy(s.val.astype(np.float32)).cuda()
     fac = [torch.from_numpy(a.astype(np.float32)).cuda() for a in s.init]
     trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+    # the sorted copies are built once per tensor, outside the timed region
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    plan = ctx.coo_plan(idx, val, s.dims)
+    plan_s = time.perf_counter() - tp
 
     def step(t):
-        ctx.cp_jcomm_outer_coo(idx, val, s.dims, fac, L=1, obj_out=trace[t:t + 1])
+        ctx.cp_jcomm_outer_coo_plan(plan, fac, L=1, obj_out=trace[t:t + 1])
 
     elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
@@ -274,10 +279,12 @@ def run_coo(args, ctx):
                            "parallelism": "single GPU"},
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                             "kernel": "coo_pass_kernel (gather, model value, scatter of 4 numerators)",
+                             "kernel": "coo_pass_kernel (two passes over the sorted copies: gather, model value, run sums)",
                              "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
                              "algorithmic_bytes_per_launch": bytes_},
+                "plan_build_s": round(plan_s, 4),
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    plan.close()
     return out
 
 

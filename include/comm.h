@@ -24,11 +24,13 @@
  *   - No C++ exception crosses this interface.
  *   - Calls sharing one context must not overlap in time (the context owns
  *     the scratch workspace); use one context per concurrent stream.
- *   - Reductions are deterministic: the same inputs give bitwise identical
- *     outputs on the same device.
+ *   - Dense reductions are deterministic: the same inputs give bitwise
+ *     identical outputs on the same device.
  *
  * Supported in this version: dense 3-way tensors; CP rank R <= 32; Tucker core
- * sizes J_n <= 32.  Other shapes return COMM_EUNSUPPORTED.
+ * sizes J_n <= 32; sparse COO of order 2 to 4 (CP, beta = 1).  Other shapes
+ * return COMM_EUNSUPPORTED.  The sparse paths accumulate with float atomics
+ * and are reproducible to rounding only; the dense paths are deterministic.
  */
 #ifndef COMM_H_
 #define COMM_H_
@@ -204,6 +206,30 @@ int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* mo
  * model value, summed in closed form). */
 int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
                             double* obj_ref_dev, void* stream);
+
+/* A sparse COO tensor prepared for repeated J-CoMM iterations (CP, beta = 1):
+ * two device copies of the nonzeros, sorted by the coordinates of modes 1
+ * and 2 and by those of modes 3 and 4 (order 3: mode 3), so that every
+ * mode's numerator accumulates over runs of equal coordinates instead of one
+ * scattered add per nonzero.  Memory: 2 x (4 ndim + 4) bytes per nonzero,
+ * owned by the plan.  Not a passage of the paper: a data layout for the
+ * sparse numerators of Sec. 6.4. */
+typedef struct comm_coo_plan comm_coo_plan;
+
+/* Build a plan from the caller's COO (any order of the nonzeros; at most
+ * 2^31 - 1 of them).  Sorts on the device on `stream`, waits for it, and
+ * keeps no reference to the caller's buffers.  Nonzeros with a coordinate
+ * outside [0, dims) are kept and skipped by every pass, as in
+ * comm_cp_jcomm_outer_coo. */
+int comm_coo_plan_create(comm_ctx* ctx, const comm_coo* x, comm_coo_plan** out, void* stream);
+
+/* Free a plan (NULL is a no-op).  Work using it must have completed. */
+int comm_coo_plan_destroy(comm_coo_plan* plan);
+
+/* comm_cp_jcomm_outer_coo on a planned tensor: same result up to float
+ * rounding order (both paths add with hardware float atomics). */
+int comm_cp_jcomm_outer_coo_plan(comm_ctx* ctx, const comm_coo_plan* plan, comm_model* model,
+                                 const comm_opts* opts, double* obj_ref_dev, void* stream);
 
 #ifdef __cplusplus
 }

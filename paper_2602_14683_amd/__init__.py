@@ -29,7 +29,8 @@ COMM_BATCH_GRAPH = 1
 EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_profile_enable",
             "comm_profile_query", "comm_cp_update",
             "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo",
-            "comm_jcomm_outer_batched"]
+            "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
+            "comm_cp_jcomm_outer_coo_plan"]
 
 
 class CommError(RuntimeError):
@@ -91,10 +92,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                             ctypes.c_void_p]
     lib.comm_jcomm_outer_batched.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_int, ctypes.c_int,
                                              ctypes.c_void_p]
+    lib.comm_coo_plan_create.argtypes = [ctypes.c_void_p, P(Coo), P(ctypes.c_void_p), ctypes.c_void_p]
+    lib.comm_coo_plan_destroy.argtypes = [ctypes.c_void_p]
+    lib.comm_cp_jcomm_outer_coo_plan.argtypes = [ctypes.c_void_p, ctypes.c_void_p, P(Model), P(Opts),
+                                                 ctypes.c_void_p, ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
-                 "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched"]:
+                 "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched",
+                 "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -165,6 +171,46 @@ def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq:
     o.precision = COMM_FP32
     o.cache_pq = 1 if cache_pq else 0
     return o
+
+
+def _coo(idx: Sequence, val, dims: Sequence[int]) -> Coo:
+    import torch
+    c = Coo()
+    c.ndim = len(dims)
+    for n, dn in enumerate(dims):
+        c.dims[n] = int(dn)
+    c.nnz = int(val.numel())
+    if len(idx) != len(dims):
+        raise ValueError("one index tensor per mode")
+    for n, ix in enumerate(idx):
+        if ix.dtype != torch.int32:
+            raise TypeError("idx must be int32")
+        if ix.numel() != c.nnz:
+            raise ValueError(f"idx[{n}] has {ix.numel()} entries, val {c.nnz}")
+        c.idx[n] = _ptr(ix, f"idx[{n}]")
+    c.val = _f32(val, "val")
+    return c
+
+
+class CooPlan:
+    """Handle of a ``comm_coo_plan`` (device copies owned by the library)."""
+
+    def __init__(self, lib, handle, dims, nnz):
+        self._lib = lib
+        self.handle = handle
+        self.dims = dims
+        self.nnz = nnz
+
+    def close(self) -> None:
+        if self.handle:
+            _check(self._lib.comm_coo_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
@@ -315,21 +361,26 @@ class Context:
     def cp_jcomm_outer_coo(self, idx: Sequence, val, dims: Sequence[int], factors, L: int = 1,
                            eps: float = 1e-12, obj_out=None, stream=None) -> None:
         """One beta = 1 J-CoMM outer iteration on COO data (idx: per-mode int32 tensors)."""
-        import torch
-        c = Coo()
-        c.ndim = len(dims)
-        for n, dn in enumerate(dims):
-            c.dims[n] = int(dn)
-        c.nnz = int(val.numel())
-        for n, ix in enumerate(idx):
-            if ix.dtype != torch.int32:
-                raise TypeError("idx must be int32")
-            c.idx[n] = _ptr(ix, f"idx[{n}]")
-        c.val = _f32(val, "val")
+        c = _coo(idx, val, dims)
         m, o = _model(factors), _opts(1.0, eps, None, L)
         optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
         _check(self._lib.comm_cp_jcomm_outer_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o), optr,
                                                  _stream(stream)))
+
+    def coo_plan(self, idx: Sequence, val, dims: Sequence[int], stream=None) -> "CooPlan":
+        """Sorted device copies of a COO tensor for repeated beta = 1 J-CoMM iterations."""
+        c = _coo(idx, val, dims)
+        h = ctypes.c_void_p()
+        _check(self._lib.comm_coo_plan_create(self._h, ctypes.byref(c), ctypes.byref(h), _stream(stream)))
+        return CooPlan(self._lib, h, tuple(int(d) for d in dims), int(val.numel()))
+
+    def cp_jcomm_outer_coo_plan(self, plan: "CooPlan", factors, L: int = 1, eps: float = 1e-12, obj_out=None,
+                                stream=None) -> None:
+        """cp_jcomm_outer_coo on a planned tensor."""
+        m, o = _model(factors), _opts(1.0, eps, None, L)
+        optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
+        _check(self._lib.comm_cp_jcomm_outer_coo_plan(self._h, plan.handle, ctypes.byref(m), ctypes.byref(o), optr,
+                                                      _stream(stream)))
 
 
 _default_ctx = None

@@ -373,6 +373,33 @@ int set_device(comm_ctx* ctx) {
   return COMM_OK;
 }
 
+// ---------------------------------------------------------------------------------------- sparse checks
+
+int check_coo(const comm_coo* x) {
+  if (!x) return fail(COMM_EINVAL, "x is NULL");
+  if (x->ndim < 2 || x->ndim > 4) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
+  if (x->nnz < 0) return fail(COMM_EINVAL, "nnz < 0");
+  for (int n = 0; n < x->ndim; ++n) {
+    if (x->dims[n] < 1 || x->dims[n] > (1 << 24)) return fail(COMM_EINVAL, "dims[%d]", n);
+    if (x->nnz > 0 && !x->idx[n]) return fail(COMM_EINVAL, "idx[%d] is NULL", n);
+  }
+  if (x->nnz > 0 && !x->val) return fail(COMM_EINVAL, "val is NULL");
+  return COMM_OK;
+}
+
+int check_coo_job(int ndim, const int64_t* dims, const comm_model* model, const comm_opts* opts) {
+  (void)dims;
+  int rc = check_opts(opts, true);
+  if (rc) return rc;
+  if (opts->beta != 1.0) return fail(COMM_EUNSUPPORTED, "sparse COO path requires beta = 1");
+  if (!model || model->kind != COMM_CP) return fail(COMM_EINVAL, "model must be CP");
+  if (model->rank < 1) return fail(COMM_EINVAL, "rank = %d", model->rank);
+  if (model->rank > kRP) return fail(COMM_EUNSUPPORTED, "rank %d > %d", model->rank, kRP);
+  for (int n = 0; n < ndim; ++n)
+    if (!model->factors[n]) return fail(COMM_EINVAL, "factors[%d] is NULL", n);
+  return COMM_OK;
+}
+
 // ---------------------------------------------------------------------------------------- J-CoMM, one or many
 
 int jcomm_check(const comm_dense* x, const comm_model* model, const comm_opts* opts) {
@@ -749,24 +776,48 @@ int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model,
                             double* obj_ref_dev, void* stream) {
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
-    int rc = check_opts(opts, true);
+    int rc = check_coo(x);
+    if (!rc) rc = check_coo_job(x->ndim, x->dims, model, opts);
     if (rc) return rc;
-    if (opts->beta != 1.0) return fail(COMM_EUNSUPPORTED, "sparse COO path requires beta = 1");
-    if (!x) return fail(COMM_EINVAL, "x is NULL");
-    if (x->ndim < 2 || x->ndim > 4) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
-    if (!model || model->kind != COMM_CP) return fail(COMM_EINVAL, "model must be CP");
-    if (model->rank < 1) return fail(COMM_EINVAL, "rank = %d", model->rank);
-    if (model->rank > kRP) return fail(COMM_EUNSUPPORTED, "rank %d > %d", model->rank, kRP);
-    for (int n = 0; n < x->ndim; ++n) {
-      if (x->dims[n] < 1 || x->dims[n] > (1 << 24)) return fail(COMM_EINVAL, "dims[%d]", n);
-      if (!model->factors[n]) return fail(COMM_EINVAL, "factors[%d] is NULL", n);
-      if (x->nnz > 0 && !x->idx[n]) return fail(COMM_EINVAL, "idx[%d] is NULL", n);
-    }
-    if (x->nnz < 0) return fail(COMM_EINVAL, "nnz < 0");
-    if (x->nnz > 0 && !x->val) return fail(COMM_EINVAL, "val is NULL");
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
     rc = coo_jcomm_kl(ctx, x, model, opts, obj_ref_dev, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_coo_plan_create(comm_ctx* ctx, const comm_coo* x, comm_coo_plan** out, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (!out) return fail(COMM_EINVAL, "out is NULL");
+    int rc = check_coo(x);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = coo_plan_build(ctx, x, out, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_coo_plan_destroy(comm_coo_plan* plan) {
+  return guarded([&]() -> int { return coo_plan_free(plan); });
+}
+
+int comm_cp_jcomm_outer_coo_plan(comm_ctx* ctx, const comm_coo_plan* plan, comm_model* model, const comm_opts* opts,
+                                 double* obj_ref_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (!plan) return fail(COMM_EINVAL, "plan is NULL");
+    int64_t dims[4] = {0, 0, 0, 0};
+    const int N = coo_plan_ndim(plan);
+    for (int n = 0; n < N; ++n) dims[n] = coo_plan_dim(plan, n);
+    int rc = check_coo_job(N, dims, model, opts);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = coo_jcomm_kl_plan(ctx, plan, model, opts, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
   });

@@ -211,6 +211,7 @@ struct TkPassArgs {
   const float* T2nT;       // mode-3 pass: T2 of the numerator / denominator set,
   const float* T2dT;       //   transposed [32][Pp], zero for pairs >= I J
   int64_t Pp;              // I J rounded up to a multiple of 32
+  int xvec;                // fibres may be read as 16-byte vectors (K % 4 == 0, X 16-byte aligned)
   float eps, eps_x;
   BetaConst bc;
   float* Vn;               // V pass outputs [(I J)][32]

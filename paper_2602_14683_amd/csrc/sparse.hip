@@ -8,119 +8,204 @@
 // the product c^(n) = A~^(n) * Num_J^(n) that drives the beta = 1 inner loop
 // (kernels_small.hip) is M^(n) itself.
 //
-// Mapping: one nonzero per half wavefront, lane = rank component; the four
-// factor rows are gathered with coalesced 128-byte loads and X~ is a
-// half-wave reduction.  The COO is sorted lexicographically, so modes 1 and 2
-// come in runs: each half wave keeps a running sum per mode and adds it to
-// global memory when the index changes.  Modes 3 and 4 are added per nonzero
-// with hardware float atomics, so this path is reproducible only to rounding
-// (not bitwise).  Nonzeros with an index outside [0, dims) are skipped.
+// Mapping: one nonzero per half wavefront, lane = rank component.  A wave
+// loads 64 nonzeros' coordinates and values with coalesced loads (validity
+// checked once, kept as a ballot mask) and hands them to its halves by lane
+// permutes, four nonzeros per half at a time so that their factor-row
+// gathers (128-byte rows that stay in L2) are in flight together; X~ is a
+// half-wave reduction (DPP, then one permute), and the objective is evaluated
+// once per 64 nonzeros with one nonzero per lane.  Modes
+// whose coordinate the stream is sorted by come in runs: each half keeps a
+// running sum per such mode and adds it to global memory when the
+// coordinate changes.  Other modes are added per nonzero.  Both use hardware
+// float atomics, so this path is reproducible to rounding, not bitwise.
+// Nonzeros with a coordinate outside [0, dims) are skipped.
+//
+// Without a plan (comm_cp_jcomm_outer_coo) one pass over the caller's COO
+// accumulates modes 1 and 2 by runs (the COO is expected sorted) and the
+// others per nonzero; per-nonzero atomics on a heavily repeated coordinate
+// serialise.  A plan (comm_coo_plan_create) keeps two device copies of the
+// COO, sorted by (i1, i2) and by (i3, i4), and each outer iteration makes one
+// pass over each, every mode accumulated by runs.
 //
 // Objective at the reference: nonzero cells contribute d_1(x | X~) (stable
 // form), zero cells contribute X~, which sums in closed form over all cells as
 // sum_r prod_n colsum(A~^(n))_r minus the nonzero cells' X~.
 
+#include <hipcub/hipcub.hpp>
+
 #include "host_util.h"
 #include "sparse.h"
 #include "cp3_impl.h"
+
+struct comm_coo_plan {
+  int device = 0;
+  int ndim = 0;
+  int64_t dims[4] = {0, 0, 0, 0};
+  int64_t nnz = 0;
+  int copies = 0;                 // 1 (order 2) or 2
+  int order[2][4] = {};           // copy c holds mode order[c][q] in its slot q
+  int runs[2] = {0, 0};           // leading modes of copy c it is sorted by
+  int32_t* idx[2][4] = {};
+  float* val[2] = {};
+  char* mem = nullptr;
+};
 
 namespace comm {
 
 struct CooPassArgs {
   int N, R;
   int64_t nnz;
-  int dims[4];
+  int dims[4];            // in the stream's slot order
   const int32_t* idx[4];
   const float* val;
-  const float* A[4];     // caller's factors, row stride R
-  float* M[4];           // [dims][32] accumulators, zeroed before the pass
+  const float* A[4];      // factors, slot order, row stride R
+  float* M[4];            // [dims][32] accumulators, slot order
+  int run_modes;          // slots [0, run_modes) accumulated by runs
+  int atom_modes;         // slots [run_modes, run_modes + atom_modes) per nonzero
   float eps;
-  int64_t chunk;         // nonzeros per wavefront
-  double* obj_part;      // per workgroup: sum d_1(x | X~) - sum X~ over its nonzeros
+  int64_t chunk;          // nonzeros per wavefront, a multiple of 64
+  double* obj_part;       // per workgroup: sum d_1(x | X~) - sum X~ (NULL: no objective)
 };
 
 constexpr int kCooThreads = 256;
+constexpr int kCooBatch = 4;   // nonzeros per half wave whose gathers are issued together
 
+// Sum over the 32 lanes of a half wave (all receive it): xor 1 and xor 2 in
+// the quad, the mirrored lane of the other quad, the mirrored lane of the
+// other half row (DPP), then the other row of 16 (lane permute).
 __device__ __forceinline__ float half_sum(float v) {
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
+  return v + __shfl_xor(v, 16);
 }
 
+template <int N, int kRuns, int kAtoms>
 __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
   __shared__ double lobj[kCooThreads / 64];
   const int lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
-  const int wave = (int)((blockIdx.x * (int64_t)kCooThreads + threadIdx.x) >> 6);
-  const int64_t t0 = (int64_t)wave * a.chunk;
+  const int64_t wave = ((int64_t)blockIdx.x * kCooThreads + threadIdx.x) >> 6;
+  const int64_t t0 = wave * a.chunk;
   const int64_t t1 = min(a.nnz, t0 + a.chunk);
-  const bool rlive = r < a.R;
-  const int N = a.N;
+  const int R = a.R;
+  const bool rlive = r < R;
 
-  int cur0 = -1, cur1 = -1;
-  float acc0 = 0.0f, acc1 = 0.0f;
+  int cur[2] = {-1, -1};
+  float acc[2] = {0.0f, 0.0f};
   double obj = 0.0;
-  // each half wave walks its own nonzeros; the shuffles stay within a half
-  for (int64_t t = t0 + h; t < t1; t += 2) {
-    int ii[4] = {0, 0, 0, 0};
-    bool ok = true;
+  for (int64_t tb = t0; tb < t1; tb += 64) {
+    const int cnt = (int)min((int64_t)64, t1 - tb);
+    // 64 nonzeros, one per lane, coalesced; validity once per nonzero; the
+    // coordinates travel as row offsets
+    int my[4] = {0, 0, 0, 0};
+    float myx = 0.0f;
+    bool valid = lane < cnt;
+    if (valid) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      if (m < N) {
-        ii[m] = a.idx[m][t];
-        ok = ok && ii[m] >= 0 && ii[m] < a.dims[m];
+      for (int m = 0; m < N; ++m) {
+        const int i = a.idx[m][tb + lane];
+        valid = valid && i >= 0 && i < a.dims[m];
+        my[m] = i;
+      }
+      myx = a.val[tb + lane];
+    }
+    const uint64_t okmask = __ballot(valid);
+    float myy = 1.0f;   // X~ of this lane's own nonzero, for the objective
+    for (int j0 = 0; j0 < 32; j0 += kCooBatch) {
+      if (2 * j0 >= cnt) break;
+      int ii[kCooBatch][4];
+      float xs[kCooBatch], zs[kCooBatch];
+      bool oks[kCooBatch];
+#pragma unroll
+      for (int u = 0; u < kCooBatch; ++u) {
+        const int src = 2 * (j0 + u) + h;
+        oks[u] = (okmask >> src) & 1;
+#pragma unroll
+        for (int m = 0; m < N; ++m) ii[u][m] = __shfl(my[m], src);
+        xs[u] = __shfl(myx, src);
+      }
+#pragma unroll
+      for (int u = 0; u < kCooBatch; ++u) {
+        float z = 0.0f;
+        if (oks[u] && rlive) {
+          z = a.A[0][(int64_t)ii[u][0] * R + r];
+#pragma unroll
+          for (int m = 1; m < N; ++m) z *= a.A[m][(int64_t)ii[u][m] * R + r];
+        }
+        zs[u] = z;
+      }
+      float y[kCooBatch];
+#pragma unroll
+      for (int u = 0; u < kCooBatch; ++u) y[u] = fmaxf(half_sum(zs[u]), a.eps);
+#pragma unroll
+      for (int u = 0; u < kCooBatch; ++u) {
+        // lane 2 j + hh owns the nonzero that half hh handled at step j
+        const float yg = __shfl(y[u], 32 * (lane & 1));
+        if ((lane >> 1) == j0 + u) myy = yg;
+      }
+#pragma unroll
+      for (int u = 0; u < kCooBatch; ++u) {
+        if (!oks[u]) continue;
+        const float w = zs[u] * (xs[u] * fast_rcp(y[u]));
+#pragma unroll
+        for (int q = 0; q < kRuns; ++q) {
+          if (ii[u][q] != cur[q]) {
+            if (cur[q] >= 0 && rlive) unsafeAtomicAdd(&a.M[q][(int64_t)cur[q] * kRP + r], acc[q]);
+            cur[q] = ii[u][q];
+            acc[q] = 0.0f;
+          }
+          acc[q] += w;
+        }
+        if (rlive) {
+#pragma unroll
+          for (int q = kRuns; q < kRuns + kAtoms; ++q) unsafeAtomicAdd(&a.M[q][(int64_t)ii[u][q] * kRP + r], w);
+        }
       }
     }
-    const float x = a.val[t];
-    float z = 0.0f;
-    if (ok && rlive) {
-      z = 1.0f;
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-        if (m < N) z *= a.A[m][(int64_t)ii[m] * a.R + r];
-    }
-    const float xt = fmaxf(half_sum(z), a.eps);
-    const float w = ok ? x * z / xt : 0.0f;
-    if (ok && r == 0) {
-      const float sum = x + xt;
+    if (a.obj_part && valid) {
       bool far;
-      float d = kl_series(x, xt, fast_rcp(sum), far);
-      if (far) d = kl_direct(x, xt);
-      obj += (double)d - (double)xt;
-    }
-    if (!ok) continue;
-    // modes 1 and 2: runs of equal index (sorted COO)
-    if (ii[0] != cur0) {
-      if (cur0 >= 0 && rlive) unsafeAtomicAdd(&a.M[0][(int64_t)cur0 * kRP + r], acc0);
-      cur0 = ii[0];
-      acc0 = 0.0f;
-    }
-    acc0 += w;
-    if (N > 1) {
-      if (ii[1] != cur1) {
-        if (cur1 >= 0 && rlive) unsafeAtomicAdd(&a.M[1][(int64_t)cur1 * kRP + r], acc1);
-        cur1 = ii[1];
-        acc1 = 0.0f;
-      }
-      acc1 += w;
-    }
-    if (rlive) {
-      if (N > 2) unsafeAtomicAdd(&a.M[2][(int64_t)ii[2] * kRP + r], w);
-      if (N > 3) unsafeAtomicAdd(&a.M[3][(int64_t)ii[3] * kRP + r], w);
+      float d = kl_series(myx, myy, fast_rcp(myx + myy), far);
+      if (far) d = kl_direct(myx, myy);
+      obj += (double)d - (double)myy;
     }
   }
   if (rlive) {
-    if (cur0 >= 0) unsafeAtomicAdd(&a.M[0][(int64_t)cur0 * kRP + r], acc0);
-    if (N > 1 && cur1 >= 0) unsafeAtomicAdd(&a.M[1][(int64_t)cur1 * kRP + r], acc1);
+#pragma unroll
+    for (int q = 0; q < kRuns; ++q)
+      if (cur[q] >= 0) unsafeAtomicAdd(&a.M[q][(int64_t)cur[q] * kRP + r], acc[q]);
   }
-  // objective partial (lanes 0 and 32 hold the values)
-  obj += __shfl_xor(obj, 32);
-  if (lane == 0) lobj[threadIdx.x >> 6] = obj;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int q = 0; q < kCooThreads / 64; ++q) s += lobj[q];
-    a.obj_part[blockIdx.x] = s;
+  if (a.obj_part) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
+    if (lane == 0) lobj[threadIdx.x >> 6] = obj;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int q = 0; q < kCooThreads / 64; ++q) s += lobj[q];
+      a.obj_part[blockIdx.x] = s;
+    }
+  }
+}
+
+template <int N>
+hipError_t launch_coo_n(const CooPassArgs& a, int blocks, hipStream_t st) {
+  const dim3 grid((unsigned)blocks), block(kCooThreads);
+  if (a.run_modes == 2 && a.atom_modes == N - 2) hipLaunchKernelGGL((coo_pass_kernel<N, 2, N - 2>), grid, block, 0, st, a);
+  else if (a.run_modes == 2 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 2, 0>), grid, block, 0, st, a);
+  else if (a.run_modes == 1 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 1, 0>), grid, block, 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_coo(const CooPassArgs& a, int blocks, hipStream_t st) {
+  switch (a.N) {
+    case 2: return launch_coo_n<2>(a, blocks, st);
+    case 3: return launch_coo_n<3>(a, blocks, st);
+    case 4: return launch_coo_n<4>(a, blocks, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -129,89 +214,139 @@ __global__ void fill_zero_kernel(float* p, int64_t n) {
   if (e < n) p[e] = 0.0f;
 }
 
+// Sort keys of a plan copy: the coordinates of its leading modes, mixed radix.
+__global__ void coo_key_kernel(const int32_t* i0, const int32_t* i1, int64_t d1, int64_t nnz, uint64_t* key,
+                               int32_t* pos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnz) return;
+  const uint64_t a = (uint64_t)(uint32_t)i0[t];
+  const uint64_t b = i1 ? (uint64_t)(uint32_t)i1[t] : 0;
+  key[t] = a * (uint64_t)d1 + b;
+  pos[t] = (int32_t)t;
+}
+
+struct GatherArgs {
+  int N;
+  int64_t nnz;
+  const int32_t* perm;
+  const int32_t* src[4];   // caller's coordinates, in the copy's slot order
+  const float* val;
+  int32_t* dst[4];
+  float* dval;
+};
+
+__global__ void coo_gather_kernel(GatherArgs g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nnz) return;
+  const int64_t p = g.perm[t];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q < g.N) g.dst[q][t] = g.src[q][p];
+  g.dval[t] = g.val[p];
+}
+
 }  // namespace comm
 
 using namespace comm;
 
-int coo_jcomm_kl(comm_ctx* ctx, const comm_coo* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
-  const int N = x->ndim, R = m->rank;
-  int dims[4] = {0, 0, 0, 0};
-  for (int n = 0; n < N; ++n) dims[n] = (int)x->dims[n];
-  const int64_t chunk = 256;
-  const int64_t waves = (x->nnz + chunk - 1) / chunk;
-  const int blocks = (int)std::max<int64_t>(1, (waves + kCooThreads / 64 - 1) / (kCooThreads / 64));
-  // workspace: accumulators M^(n) [dims][32], stats, objective partials
-  Carve cv;
-  float* M[4] = {};
-  float* stats[4] = {};
-  int64_t total_rows = 0;
-  for (int n = 0; n < N; ++n) {
-    M[n] = cv.take<float>((size_t)dims[n] * kRP);
-    stats[n] = cv.take<float>((size_t)((dims[n] + kSlotRows - 1) / kSlotRows) * 96);
-    total_rows += dims[n];
-  }
-  double* obj_part = cv.take<double>((size_t)blocks);
-  const size_t need = cv.off + 256;
-  int rc = ensure_ws(ctx, need, st);
-  if (rc) return rc;
-  Carve real;
-  real.base = ctx->ws;
-  for (int n = 0; n < N; ++n) {
-    M[n] = real.take<float>((size_t)dims[n] * kRP);
-    stats[n] = real.take<float>((size_t)((dims[n] + kSlotRows - 1) / kSlotRows) * 96);
-  }
-  obj_part = real.take<double>((size_t)blocks);
+namespace {
 
-  // zero the accumulators (one contiguous range)
-  {
-    const int64_t n = (int64_t)(reinterpret_cast<char*>(stats[N - 1]) - reinterpret_cast<char*>(M[0])) / 4;
-    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M[0], n);
-    HIP_TRY(hipGetLastError());
+int bits_for(uint64_t n) {
+  int b = 1;
+  while (b < 64 && (n >> b) != 0) ++b;
+  return b;
+}
+
+struct CooWs {
+  float* M[4];
+  float* stats[4];
+  double* obj_part;
+  size_t bytes;
+};
+
+CooWs coo_layout(int N, const int* dims, int blocks, char* base) {
+  CooWs w = {};
+  Carve cv;
+  cv.base = base;
+  for (int n = 0; n < N; ++n) {
+    w.M[n] = cv.take<float>((size_t)dims[n] * kRP);
+    w.stats[n] = cv.take<float>((size_t)((dims[n] + kSlotRows - 1) / kSlotRows) * 96);
   }
+  w.obj_part = cv.take<double>((size_t)blocks);
+  w.bytes = cv.off + 256;
+  return w;
+}
+
+constexpr int64_t kCooChunk = 256;
+
+int coo_blocks(int64_t nnz) {
+  const int64_t waves = (nnz + kCooChunk - 1) / kCooChunk;
+  return (int)std::max<int64_t>(1, (waves + kCooThreads / 64 - 1) / (kCooThreads / 64));
+}
+
+// One pass over a stream whose slot q holds mode order[q].
+int coo_pass(comm_ctx* ctx, int N, const int* order, const int32_t* const* idx, const float* val, int64_t nnz,
+             const int* dims, const comm_model* m, const CooWs& w, int run_modes, int atom_modes, bool obj, float eps,
+             hipStream_t st) {
+  if (nnz <= 0) return COMM_OK;
   CooPassArgs a = {};
   a.N = N;
-  a.R = R;
-  a.nnz = x->nnz;
-  for (int n = 0; n < N; ++n) {
-    a.dims[n] = dims[n];
-    a.idx[n] = x->idx[n];
-    a.A[n] = m->factors[n];
-    a.M[n] = M[n];
+  a.R = m->rank;
+  a.nnz = nnz;
+  for (int q = 0; q < N; ++q) {
+    const int n = order[q];
+    a.dims[q] = dims[n];
+    a.idx[q] = idx[q];
+    a.A[q] = m->factors[n];
+    a.M[q] = w.M[n];
   }
-  a.val = x->val;
-  a.eps = (float)o->eps;
-  a.chunk = chunk;
-  a.obj_part = obj_part;
-  if (x->nnz > 0) {
-    rc = profiled(ctx, st, [&] {
-      hipLaunchKernelGGL(coo_pass_kernel, dim3(blocks), dim3(kCooThreads), 0, st, a);
-      return hipGetLastError();
-    });
-    if (rc) return rc;
+  a.val = val;
+  a.run_modes = run_modes;
+  a.atom_modes = atom_modes;
+  a.eps = eps;
+  a.chunk = kCooChunk;
+  a.obj_part = obj ? w.obj_part : nullptr;
+  return profiled(ctx, st, [&] { return launch_coo(a, coo_blocks(nnz), st); });
+}
+
+// Zero the accumulators, run `passes`, then the beta = 1 inner loop.
+template <class Passes>
+int coo_outer(comm_ctx* ctx, int N, const int* dims, int64_t nnz, comm_model* m, const comm_opts* o, double* obj,
+              hipStream_t st, Passes&& passes) {
+  const int blocks = coo_blocks(nnz);
+  CooWs w = coo_layout(N, dims, blocks, nullptr);
+  int rc = ensure_ws(ctx, w.bytes, st);
+  if (rc) return rc;
+  w = coo_layout(N, dims, blocks, ctx->ws);
+  {
+    const int64_t n = (int64_t)(reinterpret_cast<char*>(w.stats[N - 1]) - reinterpret_cast<char*>(w.M[0])) / 4;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.M[0], n);
+    HIP_TRY(hipGetLastError());
   }
+  if ((rc = passes(w))) return rc;
 
   // c^(n) = M^(n) with column statistics, then the beta = 1 inner loop
   SlotUpdateArgs su = {};
   su.njobs = N;
   KlLoopArgs k = {};
   k.N = N;
-  k.R = R;
+  k.R = m->rank;
   k.L = o->inner_sweeps;
   k.eps = (float)o->eps;
   for (int n = 0; n < N; ++n) {
     SlotJob& J = su.job[n];
     J.mode = kSlotCopy;
-    J.num_part = M[n];
+    J.num_part = w.M[n];
     J.num_slots = 1;
     J.rows_total = dims[n];
     J.rows = dims[n];
-    J.cols = R;
+    J.cols = m->rank;
     J.rows_p = dims[n];
-    J.anchor = FView{m->factors[n], R, R};
+    J.anchor = FView{m->factors[n], m->rank, m->rank};
     J.out_pad = nullptr;
-    J.stats = stats[n];
-    k.c[n] = M[n];
-    k.stats[n] = stats[n];
+    J.stats = w.stats[n];
+    k.c[n] = w.M[n];
+    k.stats[n] = w.stats[n];
     k.nblk[n] = (dims[n] + kSlotRows - 1) / kSlotRows;
     k.rows[n] = dims[n];
     k.cur_pad[n] = nullptr;
@@ -219,12 +354,170 @@ int coo_jcomm_kl(comm_ctx* ctx, const comm_coo* x, comm_model* m, const comm_opt
   }
   HIP_TRY(launch_slot_update(su, st));
   if (obj) {
-    k.obj_part = x->nnz > 0 ? obj_part : nullptr;
-    k.obj_n = x->nnz > 0 ? blocks : 0;
+    k.obj_part = nnz > 0 ? w.obj_part : nullptr;
+    k.obj_n = nnz > 0 ? blocks : 0;
     k.obj_out = obj;
     k.obj_add_model_mass = 1;
   }
   HIP_TRY(launch_kl_apply(k, st));
-  (void)total_rows;
   return COMM_OK;
 }
+
+}  // namespace
+
+int coo_jcomm_kl(comm_ctx* ctx, const comm_coo* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+  const int N = x->ndim;
+  int dims[4] = {0, 0, 0, 0};
+  for (int n = 0; n < N; ++n) dims[n] = (int)x->dims[n];
+  const int order[4] = {0, 1, 2, 3};
+  const int runs = std::min(N, 2);
+  return coo_outer(ctx, N, dims, x->nnz, m, o, obj, st, [&](const CooWs& w) {
+    return coo_pass(ctx, N, order, x->idx, x->val, x->nnz, dims, m, w, runs, N - runs, obj != nullptr,
+                    (float)o->eps, st);
+  });
+}
+
+int coo_jcomm_kl_plan(comm_ctx* ctx, const comm_coo_plan* p, comm_model* m, const comm_opts* o, double* obj,
+                      hipStream_t st) {
+  const int N = p->ndim;
+  int dims[4] = {0, 0, 0, 0};
+  for (int n = 0; n < N; ++n) dims[n] = (int)p->dims[n];
+  return coo_outer(ctx, N, dims, p->nnz, m, o, obj, st, [&](const CooWs& w) {
+    int rc = COMM_OK;
+    for (int c = 0; c < p->copies && !rc; ++c)
+      rc = coo_pass(ctx, N, p->order[c], p->idx[c], p->val[c], p->nnz, dims, m, w, p->runs[c], 0,
+                    c == 0 && obj != nullptr, (float)o->eps, st);
+    return rc;
+  });
+}
+
+// Two device copies of the COO: copy 0 sorted by (i1, i2) with the modes in
+// their own order, copy 1 (order >= 3) sorted by (i3, i4) with slots
+// (3, 4, 1, 2) (or (3, 1, 2) for order 3).  Stable sorts of (key, position)
+// pairs, so the plan is a deterministic function of the input.
+int coo_plan_build(comm_ctx* ctx, const comm_coo* x, comm_coo_plan** out, hipStream_t st) {
+  (void)ctx;
+  const int N = x->ndim;
+  const int64_t nnz = x->nnz;
+  if (nnz > INT32_MAX) return fail(COMM_EUNSUPPORTED, "plans hold at most 2^31 - 1 nonzeros");
+  comm_coo_plan* p = new comm_coo_plan();
+  p->ndim = N;
+  p->nnz = nnz;
+  for (int n = 0; n < N; ++n) p->dims[n] = x->dims[n];
+  p->copies = N >= 3 ? 2 : 1;
+  for (int q = 0; q < 4; ++q) p->order[0][q] = q;
+  p->runs[0] = std::min(N, 2);
+  if (N == 4) {
+    const int o1[4] = {2, 3, 0, 1};
+    for (int q = 0; q < 4; ++q) p->order[1][q] = o1[q];
+    p->runs[1] = 2;
+  } else if (N == 3) {
+    const int o1[4] = {2, 0, 1, 3};
+    for (int q = 0; q < 4; ++q) p->order[1][q] = o1[q];
+    p->runs[1] = 1;
+  }
+  HIP_TRY(hipGetDevice(&p->device));
+  // plan memory: per copy N coordinate arrays and the values
+  Carve cv;
+  for (int c = 0; c < p->copies; ++c) {
+    for (int q = 0; q < N; ++q) cv.take<int32_t>((size_t)nnz);
+    cv.take<float>((size_t)nnz);
+  }
+  const size_t plan_bytes = cv.off + 256;
+  hipError_t e = hipMalloc(&p->mem, plan_bytes);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(COMM_ENOMEM, "hipMalloc(%zu) for the COO plan: %s", plan_bytes, hipGetErrorString(e));
+  }
+  Carve real;
+  real.base = p->mem;
+  for (int c = 0; c < p->copies; ++c) {
+    for (int q = 0; q < N; ++q) p->idx[c][q] = real.take<int32_t>((size_t)nnz);
+    p->val[c] = real.take<float>((size_t)nnz);
+  }
+  if (nnz == 0) {
+    *out = p;
+    return COMM_OK;
+  }
+  // scratch: keys and positions, in and out, plus the sort's temporary storage
+  size_t temp_bytes = 0;
+  e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                         (const int32_t*)nullptr, (int32_t*)nullptr, (int)nnz, 0, 64, st);
+  char* scratch = nullptr;
+  Carve sc;
+  sc.take<uint64_t>((size_t)nnz);
+  sc.take<uint64_t>((size_t)nnz);
+  sc.take<int32_t>((size_t)nnz);
+  sc.take<int32_t>((size_t)nnz);
+  sc.take<char>(temp_bytes);
+  const size_t scratch_bytes = sc.off + 256;
+  if (e == hipSuccess) e = hipMalloc(&scratch, scratch_bytes);
+  if (e != hipSuccess) {
+    hipFree(p->mem);
+    delete p;
+    return fail(COMM_ENOMEM, "COO plan scratch of %zu bytes: %s", scratch_bytes, hipGetErrorString(e));
+  }
+  Carve s2;
+  s2.base = scratch;
+  uint64_t* kin = s2.take<uint64_t>((size_t)nnz);
+  uint64_t* kout = s2.take<uint64_t>((size_t)nnz);
+  int32_t* pin = s2.take<int32_t>((size_t)nnz);
+  int32_t* pout = s2.take<int32_t>((size_t)nnz);
+  char* temp = s2.take<char>(temp_bytes);
+  const unsigned grid = (unsigned)((nnz + 255) / 256);
+  int rc = COMM_OK;
+  for (int c = 0; c < p->copies && !rc; ++c) {
+    const int m0 = p->order[c][0];
+    const int m1 = p->runs[c] > 1 ? p->order[c][1] : -1;
+    const int64_t d1 = m1 >= 0 ? x->dims[m1] : 1;
+    hipLaunchKernelGGL(coo_key_kernel, dim3(grid), dim3(256), 0, st, x->idx[m0], m1 >= 0 ? x->idx[m1] : nullptr, d1,
+                       nnz, kin, pin);
+    e = hipGetLastError();
+    const int bits = bits_for((uint64_t)x->dims[m0] * (uint64_t)d1);
+    if (e == hipSuccess)
+      e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, kin, kout, pin, pout, (int)nnz, 0, bits, st);
+    if (e == hipSuccess) {
+      GatherArgs g = {};
+      g.N = N;
+      g.nnz = nnz;
+      g.perm = pout;
+      for (int q = 0; q < N; ++q) {
+        g.src[q] = x->idx[p->order[c][q]];
+        g.dst[q] = p->idx[c][q];
+      }
+      g.val = x->val;
+      g.dval = p->val[c];
+      hipLaunchKernelGGL(coo_gather_kernel, dim3(grid), dim3(256), 0, st, g);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) rc = fail(COMM_EHIP, "COO plan: %s", hipGetErrorString(e));
+  }
+  // the scratch is released once the sorts and gathers are done
+  const hipError_t es = hipStreamSynchronize(st);
+  hipFree(scratch);
+  if (!rc && es != hipSuccess) rc = fail(COMM_EHIP, "COO plan: %s", hipGetErrorString(es));
+  if (rc) {
+    hipFree(p->mem);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return COMM_OK;
+}
+
+int coo_plan_free(comm_coo_plan* p) {
+  if (!p) return COMM_OK;
+  int rc = COMM_OK;
+  // passes still reading the copies must finish first
+  HIP_TRY(hipSetDevice(p->device));
+  HIP_TRY(hipDeviceSynchronize());
+  if (p->mem) {
+    hipError_t e = hipFree(p->mem);
+    if (e != hipSuccess) rc = fail(COMM_EHIP, "hipFree: %s", hipGetErrorString(e));
+  }
+  delete p;
+  return rc;
+}
+
+int coo_plan_ndim(const comm_coo_plan* p) { return p->ndim; }
+int64_t coo_plan_dim(const comm_coo_plan* p, int n) { return p->dims[n]; }

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
   const int K = a.K;
   constexpr bool kRebuild = kMode != kTkCacheRead;
   // vector loads of the fibre need 16-byte aligned rows
-  const bool vec = (K & 3) == 0;
+  const bool vec = a.xvec != 0;
 
   float t2[16];
   if constexpr (kRebuild) row16(a.T2r + pm * kRP + 16 * h, pvalid, t2);

@@ -83,3 +83,117 @@ def test_coo_rejects_beta_other_than_one(ctx):
     import ctypes
     rc = ctx._lib.comm_cp_jcomm_outer_coo(ctx._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o), None, None)
     assert rc == comm.COMM_EUNSUPPORTED
+
+
+# ------------------------------------------------------------------ planned (sorted copies)
+
+def _shuffled(s, seed):
+    """The same COO with its nonzeros in a random order (a plan must not rely
+    on the caller's order)."""
+    perm = np.random.default_rng(seed).permutation(len(s.val))
+    return s.idx[perm], s.val[perm]
+
+
+@pytest.mark.parametrize("dims,density,rank", [((6, 5, 7, 8), 0.05, 3), ((30, 24, 60, 70), 0.01, 8),
+                                               ((40, 30, 50), 0.02, 32), ((50, 70), 0.1, 5)])
+@pytest.mark.parametrize("L", [1, 3])
+def test_coo_plan_matches_oracle(ctx, dims, density, rank, L):
+    s = workloads.sparse_small(4, dims=dims, density=density, rank=rank)
+    init = [f32(a) for a in s.init]
+    sidx, sval = _shuffled(s, 5)
+    idx = [torch.tensor(sidx[:, n].astype(np.int32), device="cuda") for n in range(len(dims))]
+    val = dev(sval)
+    plan = ctx.coo_plan(idx, val, dims)
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.cp_jcomm_outer_coo_plan(plan, fac, L=L, obj_out=obj)
+    torch.cuda.synchronize()
+    want, fref = osp.jcomm_outer_kl(s.idx, s.val, init, L=L, return_ref_obj=True)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < 3e-5
+    assert abs(obj.item() - fref) / fref < 1e-5
+    plan.close()
+
+
+def test_coo_plan_skips_out_of_range_coordinates(ctx):
+    s = workloads.sparse_small(6, dims=(9, 8, 7, 6), density=0.1, rank=4)
+    init = [f32(a) for a in s.init]
+    bad = s.idx.copy()
+    bad[::7, 2] = 7          # one past the end of mode 3
+    bad[3::11, 0] = -1
+    idx = [torch.tensor(bad[:, n].astype(np.int32), device="cuda") for n in range(4)]
+    val = dev(s.val)
+    keep = (bad[:, 2] < 7) & (bad[:, 0] >= 0)
+    want = osp.jcomm_outer_kl(s.idx[keep], s.val[keep], init, L=2)
+    for planned in (False, True):
+        fac = [dev(a) for a in init]
+        if planned:
+            plan = ctx.coo_plan(idx, val, s.dims)
+            ctx.cp_jcomm_outer_coo_plan(plan, fac, L=2)
+        else:
+            ctx.cp_jcomm_outer_coo(idx, val, s.dims, fac, L=2)
+        torch.cuda.synchronize()
+        for a, b in zip(fac, want):
+            assert max_rel(host64(a), b) < 3e-5
+
+
+def test_coo_plan_empty_tensor(ctx):
+    dims = (5, 6, 7)
+    idx = [torch.zeros(0, dtype=torch.int32, device="cuda") for _ in dims]
+    val = torch.zeros(0, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(0)
+    init = [f32(rng.uniform(0.1, 1.0, size=(d, 3))) for d in dims]
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan = ctx.coo_plan(idx, val, dims)
+    ctx.cp_jcomm_outer_coo_plan(plan, fac, L=1, obj_out=obj)
+    torch.cuda.synchronize()
+    empty_idx = np.zeros((0, 3), dtype=np.int64)
+    want, fref = osp.jcomm_outer_kl(empty_idx, np.zeros(0), init, L=1, return_ref_obj=True)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < 1e-5
+    assert abs(obj.item() - fref) / fref < 1e-5
+
+
+def test_coo_plan_day_hour_lat_lon_workload(ctx):
+    """The 3.3M-nonzero workload through a plan: objective and one outer
+    iteration against the oracle, and agreement with the plan-free path."""
+    s = workloads.sparse_counts(0)
+    init = [f32(a) for a in s.init]
+    idx, val = _dev_coo(s)
+    plan = ctx.coo_plan(idx, val, s.dims)
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.cp_jcomm_outer_coo_plan(plan, fac, L=1, obj_out=obj)
+    fac2 = [dev(a) for a in init]
+    ctx.cp_jcomm_outer_coo(idx, val, s.dims, fac2, L=1)
+    torch.cuda.synchronize()
+    fref = osp.objective_kl(s.idx, s.val, init)
+    assert abs(obj.item() - fref) / fref < 1e-5
+    want = osp.jcomm_outer_kl(s.idx, s.val, init, L=1)
+    # both float32 paths are held to the oracle; between themselves they differ
+    # only in summation order over rows of up to ~6e5 nonzeros (sqrt(n) * 2^-24
+    # is ~5e-5), so they are compared at the same 1e-4 bar
+    for a, b, c in zip(fac, want, fac2):
+        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), host64(c)) < 1e-4
+
+
+def test_coo_unaligned_factors(ctx):
+    """Factors whose base address is 4 bytes past a 16-byte boundary (views into
+    a larger buffer) take the scalar gathers and give the same result."""
+    s = workloads.sparse_small(7, dims=(20, 12, 30, 25), density=0.05, rank=8)
+    init = [f32(a) for a in s.init]
+    idx, val = _dev_coo(s)
+    fac = []
+    for a in init:
+        buf = torch.zeros(a.size + 1, dtype=torch.float32, device="cuda")
+        v = buf[1:].view(a.shape)
+        v.copy_(torch.tensor(a, dtype=torch.float32))
+        fac.append(v)
+    plan = ctx.coo_plan(idx, val, s.dims)
+    ctx.cp_jcomm_outer_coo_plan(plan, fac, L=2)
+    torch.cuda.synchronize()
+    want = osp.jcomm_outer_kl(s.idx, s.val, init, L=2)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < 3e-5

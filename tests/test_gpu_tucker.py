@@ -150,3 +150,21 @@ def test_tucker_deterministic(ctx):
         outs.append([host64(G)] + [host64(a) for a in F])
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+def test_tucker_unaligned_tensor(ctx):
+    """X whose base address is 4 bytes past a 16-byte boundary takes the scalar
+    fibre loads (K = 64 would otherwise use vector loads)."""
+    X, core, fac = _problem((30, 20, 64), (5, 4, 6), 6)
+    buf = torch.zeros(X.size + 1, dtype=torch.float32, device="cuda")
+    Xd = buf[1:].view(X.shape)
+    Xd.copy_(torch.tensor(X, dtype=torch.float32))
+    G, F = _dev_model(core, fac)
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(Xd, F, core=G, beta=0.5, L=1, obj_out=obj)
+    torch.cuda.synchronize()
+    wc, wf, fref = otk.jcomm_outer(X, core, fac, 0.5, L=1, return_ref_obj=True)
+    assert max_rel(host64(G), wc) < 1e-4
+    for a, b in zip(F, wf):
+        assert max_rel(host64(a), b) < 1e-4
+    assert abs(obj.item() - fref) / fref < 1e-5
