@@ -103,11 +103,25 @@ def comparisons(ctx, X, init32, steps):
         fac = [torch.from_numpy(a).cuda() for a in init32]
         res[f"jcomm_beta{beta}_L5_obj_it_s"] = rate(
             lambda: ctx.jcomm_outer(X, fac, beta=beta, L=5, obj_out=obj))
+    # the headline iteration with bf16 matrix-core tiles, and its objective
+    # against the float32 path after the same number of iterations
+    fac = [torch.from_numpy(a).cuda() for a in init32]
+    res["jcomm_beta1_L5_obj_bf16_it_s"] = rate(lambda: ctx.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=obj,
+                                                                       precision="bf16"))
+    fb = [torch.from_numpy(a).cuda() for a in init32]
+    ff = [torch.from_numpy(a).cuda() for a in init32]
+    for _ in range(50):
+        ctx.jcomm_outer(X, fb, beta=1.0, L=5, precision="bf16")
+        ctx.jcomm_outer(X, ff, beta=1.0, L=5)
+    ob = ctx.beta_objective(X, fb, beta=1.0).item()
+    of = ctx.beta_objective(X, ff, beta=1.0).item()
+    res["bf16_objective_rel_diff_after_50_it"] = abs(ob - of) / of
     for beta in (1.0, 0.5):
         fac = [torch.from_numpy(a).cuda() for a in init32]
         res[f"bcomm_beta{beta}_sweep_it_s"] = rate(lambda: ctx.cp_update(X, fac, block=-1, beta=beta))
     res["note"] = ("B-CoMM sweeps rebuild Xhat before each of the 3 blocks and compute no objective; "
-                   f"{steps} timed iterations each")
+                   f"{steps} timed iterations each; bf16 = contraction tiles in bf16, reconstruction in "
+                   "split bf16, objective compared with the float32 run after 50 outer iterations")
     return res
 
 

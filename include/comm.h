@@ -53,9 +53,19 @@ extern "C" {
 #define COMM_CP 0
 #define COMM_TUCKER 1
 
-/* Arithmetic of the contraction tiles.  Power step and updates are float32 in
- * both; the objective is accumulated in float64 in both. */
+/* Arithmetic of the matrix-core tiles.  Power step, updates and all
+ * reductions outside the tiles are float32 in both; the objective is
+ * accumulated in float64 in both.
+ *   COMM_FP32: float32 tiles.
+ *   COMM_BF16: contraction tiles (numerators, denominators) with bf16
+ *              operands and float32 accumulation; the reconstruction tile
+ *              with split-bf16 operands (x = hi + lo, three products), about
+ *              16 significant bits per operand, because the power step and
+ *              the objective read it.  Dense CP only (other paths return
+ *              COMM_EUNSUPPORTED); the sparse path has no matrix-core tiles
+ *              and computes in float32 either way. */
 #define COMM_FP32 0
+#define COMM_BF16 1
 
 typedef struct comm_ctx comm_ctx;
 
@@ -84,7 +94,7 @@ typedef struct {
  *                 also enters powers, logs and divisions as max(Xhat, eps).
  *   eps_x         at beta = 0 the data enter as max(X, eps_x) (> 0).
  *   inner_sweeps  L >= 1, inner sweeps per J-CoMM outer iteration.
- *   precision     COMM_FP32.
+ *   precision     COMM_FP32 or COMM_BF16 (see above).
  *   cache_pq      J-CoMM at beta != 1: 1 = store P~ and Q~ once per outer
  *                 iteration in the workspace and stream them in the inner
  *                 passes; 0 = recompute them from X and the reference. */

@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(HERE, "libcomm.so")
 COMM_OK, COMM_EINVAL, COMM_EUNSUPPORTED, COMM_ENOMEM, COMM_EHIP = 0, 1, 2, 3, 4
 COMM_CP, COMM_TUCKER = 0, 1
 COMM_FP32 = 0
+COMM_BF16 = 1
+PRECISIONS = {"fp32": COMM_FP32, "bf16": COMM_BF16}
 COMM_BATCH_GRAPH = 1
 
 EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_profile_enable",
@@ -162,13 +164,16 @@ def _model(factors: Sequence, core=None) -> Model:
     return m
 
 
-def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq: bool = False) -> Opts:
+def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq: bool = False,
+          precision: str = "fp32") -> Opts:
     o = Opts()
     o.beta = float(beta)
     o.eps = float(eps)
     o.eps_x = float(eps if eps_x is None else eps_x)
     o.inner_sweeps = int(L)
-    o.precision = COMM_FP32
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    o.precision = PRECISIONS[precision]
     o.cache_pq = 1 if cache_pq else 0
     return o
 
@@ -218,7 +223,7 @@ class Batch:
 
     Each item is a dict with the arguments of :meth:`Context.jcomm_outer`:
     ``X``, ``factors`` and optionally ``core``, ``beta``, ``L``, ``eps``,
-    ``eps_x``, ``cache_pq`` and ``obj_out`` (a float64 device view of one
+    ``eps_x``, ``cache_pq``, ``precision`` and ``obj_out`` (a float64 device view of one
     element).  The structures keep the tensors' device pointers, so the
     tensors must stay alive and in place while the batch is in use."""
 
@@ -234,7 +239,7 @@ class Batch:
             d = _dense(it["X"])
             m = _model(it["factors"], it.get("core"))
             o = _opts(it.get("beta", 1.0), it.get("eps", 1e-12), it.get("eps_x"), it.get("L", 1),
-                      it.get("cache_pq", False))
+                      it.get("cache_pq", False), it.get("precision", "fp32"))
             self._dense[k], self._model[k], self._opts[k] = d, m, o
             pr = self.array[k]
             pr.x = ctypes.pointer(d)
@@ -312,9 +317,9 @@ class Context:
     # ---------------------------------------------------------------- entry points
 
     def cp_update(self, X, factors, block: int = -1, beta: float = 1.0, eps: float = 1e-12,
-                  eps_x: Optional[float] = None, stream=None) -> None:
+                  eps_x: Optional[float] = None, stream=None, precision: str = "fp32") -> None:
         """B-CoMM block update(s) of a CP model in place (block -1: full sweep)."""
-        d, m, o = _dense(X), _model(factors), _opts(beta, eps, eps_x)
+        d, m, o = _dense(X), _model(factors), _opts(beta, eps, eps_x, precision=precision)
         _check(self._lib.comm_cp_update(self._h, ctypes.byref(d), ctypes.byref(m), int(block), ctypes.byref(o),
                                         _stream(stream)))
 
@@ -326,9 +331,10 @@ class Context:
                                             ctypes.byref(o), _stream(stream)))
 
     def jcomm_outer(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
-                    eps_x: Optional[float] = None, cache_pq: bool = False, obj_out=None, stream=None) -> None:
+                    eps_x: Optional[float] = None, cache_pq: bool = False, obj_out=None, stream=None,
+                    precision: str = "fp32") -> None:
         """One J-CoMM outer iteration in place; F(reference) into obj_out[0] (float64) if given."""
-        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, L, cache_pq)
+        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, L, cache_pq, precision)
         optr = None
         if obj_out is not None:
             import torch
@@ -348,12 +354,12 @@ class Context:
                                                   COMM_BATCH_GRAPH if graph else 0, _stream(stream)))
 
     def beta_objective(self, X, factors, core=None, beta: float = 1.0, eps: float = 1e-12,
-                       eps_x: Optional[float] = None, out=None, stream=None):
+                       eps_x: Optional[float] = None, out=None, stream=None, precision: str = "fp32"):
         """D_beta(X, Xhat) in float64, written to out[0] (allocated if None)."""
         import torch
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=X.device)
-        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x)
+        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, precision=precision)
         _check(self._lib.comm_beta_objective(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o),
                                              _ptr(out, "out"), _stream(stream)))
         return out

@@ -27,7 +27,8 @@ int check_opts(const comm_opts* o, bool need_L) {
   if (!(o->eps > 0.0)) return fail(COMM_EINVAL, "eps must be > 0");
   if (o->beta == 0.0 && !(o->eps_x > 0.0)) return fail(COMM_EINVAL, "eps_x must be > 0 at beta = 0");
   if (need_L && o->inner_sweeps < 1) return fail(COMM_EINVAL, "inner_sweeps must be >= 1");
-  if (o->precision != COMM_FP32) return fail(COMM_EUNSUPPORTED, "precision %d not supported", o->precision);
+  if (o->precision != COMM_FP32 && o->precision != COMM_BF16)
+    return fail(COMM_EINVAL, "precision %d is neither COMM_FP32 nor COMM_BF16", o->precision);
   return COMM_OK;
 }
 
@@ -138,6 +139,7 @@ CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
   a.m3n = w.m3n; a.m1n = w.m1n; a.m2n = w.m2n;
   a.m3d = w.m3d; a.m1d = w.m1d; a.m2d = w.m2d;
   a.obj_part = w.obj_part;
+  a.bf16 = o->precision == COMM_BF16;
   return a;
 }
 
@@ -408,7 +410,10 @@ int jcomm_check(const comm_dense* x, const comm_model* model, const comm_opts* o
   if (rc) return rc;
   if (!model) return fail(COMM_EINVAL, "model is NULL");
   if (model->kind == COMM_CP) return check_cp_model(model, x->ndim);
-  if (model->kind == COMM_TUCKER) return tucker_check_model(model, x);
+  if (model->kind == COMM_TUCKER) {
+    if (opts->precision != COMM_FP32) return fail(COMM_EUNSUPPORTED, "Tucker models take COMM_FP32 only");
+    return tucker_check_model(model, x);
+  }
   return fail(COMM_EINVAL, "model kind %d", model->kind);
 }
 
@@ -745,6 +750,7 @@ int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* mo
       if ((rc = check_cp_model(model, x->ndim))) return rc;
       rc = cp_objective(ctx, x, model, opts, out_dev, st);
     } else if (model->kind == COMM_TUCKER) {
+      if (opts->precision != COMM_FP32) return fail(COMM_EUNSUPPORTED, "Tucker models take COMM_FP32 only");
       if ((rc = tucker_check_model(model, x))) return rc;
       rc = tucker_objective(ctx, x, model, opts, out_dev, st);
     } else {
@@ -762,6 +768,7 @@ int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, in
     int rc = check_opts(opts, false);
     if (!rc) rc = check_dense(x);
     if (!rc) rc = tucker_check_model(model, x);
+    if (!rc && opts->precision != COMM_FP32) rc = fail(COMM_EUNSUPPORTED, "Tucker models take COMM_FP32 only");
     if (rc) return rc;
     if (block < -2 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
     if ((rc = set_device(ctx))) return rc;

@@ -59,6 +59,57 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// bf16 matrix cores (v_mfma_f32_32x32x16_bf16): lane l supplies eight values
+// of A row l%32 and of B column l%32 along the reduction; as with the fp32
+// tiles, any order of the reduction index that both operands share is valid.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// v[o .. o+7] rounded to bf16 (to nearest even).
+__device__ __forceinline__ bf16x8 pack_bf16(const float* v) {
+  bf16x8 r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r[j] = (__bf16)v[j];
+  return r;
+}
+
+// Split v = hi + lo with hi = bf16(v), lo = bf16(v - hi): the three products
+// hi*hi + hi*lo + lo*hi carry about 16 bits of each operand.
+__device__ __forceinline__ void split_bf16(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 t = (__bf16)v[j];
+    hi[j] = t;
+    lo[j] = (__bf16)(v[j] - (float)t);
+  }
+}
+
+// sum_{s<16} a[s] b[s] over the tile's reduction index with split-bf16
+// operands (b already split, two halves of eight).
+__device__ __forceinline__ f32x16 chain_bf16x3(const float (&a)[16], const bf16x8 (&bh)[2], const bf16x8 (&bl)[2],
+                                               f32x16 acc) {
+  bf16x8 ah[2], al[2];
+  split_bf16(a, ah[0], al[0]);
+  split_bf16(a + 8, ah[1], al[1]);
+  // small terms first
+  acc = mfma_bf16(al[0], bh[0], acc);
+  acc = mfma_bf16(al[1], bh[1], acc);
+  acc = mfma_bf16(ah[0], bl[0], acc);
+  acc = mfma_bf16(ah[1], bl[1], acc);
+  acc = mfma_bf16(ah[0], bh[0], acc);
+  acc = mfma_bf16(ah[1], bh[1], acc);
+  return acc;
+}
+
+// The same with plain bf16 operands.
+__device__ __forceinline__ f32x16 chain_bf16(const float (&a)[16], const bf16x8 (&b)[2], f32x16 acc) {
+  acc = mfma_bf16(pack_bf16(a), b[0], acc);
+  return mfma_bf16(pack_bf16(a + 8), b[1], acc);
+}
+
 __device__ __forceinline__ void load16(const float* p, float (&v)[16]) {
   const f32x4* q = reinterpret_cast<const f32x4*>(p);
 #pragma unroll
@@ -129,12 +180,22 @@ __device__ __forceinline__ void entry(float x, float y, const BetaConst& bc, flo
 // set.  wv: tile in the Xhat layout (lane = k, 16 m's); ag/bq: A'/B' entries
 // (column = lane) of the block's 4 i's and this lane half's 4 j's; ct: this
 // wave's 16 transposed C' values (k = 16h + s).
+template <bool kBf>
 __device__ __forceinline__ void contract_tile(const float (&wv)[16], const float (&ag)[4], const float (&bq)[4],
-                                              const float (&ct)[16], bool want_m3, bool want_v, f32x16& m3acc,
-                                              float (&m1loc)[4], float (&m2acc)[4], float* ldsT, int col, int h) {
+                                              const float (&ct)[16], const bf16x8 (&ctb)[2], bool want_m3,
+                                              bool want_v, f32x16& m3acc, float (&m1loc)[4], float (&m2acc)[4],
+                                              float* ldsT, int col, int h) {
   if (want_m3) {
+    if constexpr (kBf) {
+      float wa[16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) m3acc = mfma32(ag[s >> 2] * bq[s & 3], wv[s], m3acc);
+      for (int s = 0; s < 16; ++s) wa[s] = ag[s >> 2] * bq[s & 3];
+      bf16x8 wb[2] = {pack_bf16(wv), pack_bf16(wv + 8)};
+      m3acc = chain_bf16(wa, wb, m3acc);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) m3acc = mfma32(ag[s >> 2] * bq[s & 3], wv[s], m3acc);
+    }
   }
   if (want_v) {
     // transpose the tile through LDS: row m, column k
@@ -146,8 +207,12 @@ __device__ __forceinline__ void contract_tile(const float (&wv)[16], const float
     load16(ldsT + col * kLdsT + 16 * h, pr);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     f32x16 vacc = {};
+    if constexpr (kBf) {
+      vacc = chain_bf16(pr, ctb, vacc);
+    } else {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) vacc = mfma32(pr[s], ct[s], vacc);
+      for (int s = 0; s < 16; ++s) vacc = mfma32(pr[s], ct[s], vacc);
+    }
     __builtin_amdgcn_wave_barrier();
     // vacc[4g+q] = V[(i = ib*4+g, j = jb*8 + 4h + q)][r = col]
 #pragma unroll
@@ -200,7 +265,7 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ base, int ib
   }
 }
 
-template <int BC, int kVar, bool kObj, bool kInterior>
+template <int BC, int kVar, bool kObj, bool kInterior, bool kBf>
 __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, int wg, int bi, int bj, int bk,
                                           int gj, int gk) {
   constexpr bool kDen = kVar == kNumDen || kVar == kCacheNumDen;
@@ -246,6 +311,20 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
     if (!kCache) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
     ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
     if (kDen) ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
+  }
+  // bf16 forms of the per-wave operands (split for the rebuild)
+  bf16x8 crh[2], crl[2], ctnb[2], ctdb[2];
+  if constexpr (kBf) {
+    if (!kCache) {
+      split_bf16(crow, crh[0], crl[0]);
+      split_bf16(crow + 8, crh[1], crl[1]);
+    }
+    ctnb[0] = pack_bf16(ctn);
+    ctnb[1] = pack_bf16(ctn + 8);
+    if (kDen) {
+      ctdb[0] = pack_bf16(ctd);
+      ctdb[1] = pack_bf16(ctd + 8);
+    }
   }
 
   f32x16 m3n = {}, m3d = {};
@@ -297,8 +376,15 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       load16(sh.ra + (ib * 4 + (col >> 3)) * kSA + 16 * h, arow);
       load16(sh.rb + (jb * 8 + (col & 7)) * kSA + 16 * h, brow);
       f32x16 xh = {};
+      if constexpr (kBf) {
+        float av[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) xh = mfma32(arow[s] * brow[s], crow[s], xh);
+        for (int s = 0; s < 16; ++s) av[s] = arow[s] * brow[s];
+        xh = chain_bf16x3(av, crh, crl, xh);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) xh = mfma32(arow[s] * brow[s], crow[s], xh);
+      }
       float yv[16];
       bool anyfar = false;
 #pragma unroll
@@ -353,13 +439,13 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       for (int g = 0; g < 4; ++g) ag[g] = sh.na[(ib * 4 + g) * 32 + col];
 #pragma unroll
       for (int q = 0; q < 4; ++q) bq[q] = sh.nb[(jb * 8 + 4 * h + q) * 32 + col];
-      contract_tile(pv, ag, bq, ctn, want_m3, want_v, m3n, m1n, m2n[jb], sh.t[w], col, h);
+      contract_tile<kBf>(pv, ag, bq, ctn, ctnb, want_m3, want_v, m3n, m1n, m2n[jb], sh.t[w], col, h);
       if (kDen) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) ag[g] = sh.da[(ib * 4 + g) * 32 + col];
 #pragma unroll
         for (int q = 0; q < 4; ++q) bq[q] = sh.db[(jb * 8 + 4 * h + q) * 32 + col];
-        contract_tile(qv, ag, bq, ctd, want_m3, want_v, m3d, m1d, m2d[jb], sh.t[w], col, h);
+        contract_tile<kBf>(qv, ag, bq, ctd, ctdb, want_m3, want_v, m3d, m1d, m2d[jb], sh.t[w], col, h);
       }
     }
     if (jb == 3 && want_v) {
@@ -440,7 +526,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   }
 }
 
-template <int BC, int kVar, bool kObj>
+template <int BC, int kVar, bool kObj, bool kBf>
 __global__ void __launch_bounds__(kThreads) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
   __shared__ PassShared sh;
   const int wg = blockIdx.x;
@@ -451,15 +537,19 @@ __global__ void __launch_bounds__(kThreads) cp3_pass_kernel(CpPassArgs a, int gj
   const bool interior =
       (bi + 1) * kCpTI <= a.I && (bj + 1) * kCpTJ <= a.J && (bk + 1) * kCpTK <= a.K;
   if (interior)
-    pass_body<BC, kVar, kObj, true>(a, sh, wg, bi, bj, bk, gj, gk);
+    pass_body<BC, kVar, kObj, true, kBf>(a, sh, wg, bi, bj, bk, gj, gk);
   else
-    pass_body<BC, kVar, kObj, false>(a, sh, wg, bi, bj, bk, gj, gk);
+    pass_body<BC, kVar, kObj, false, kBf>(a, sh, wg, bi, bj, bk, gj, gk);
 }
 
 template <int BC, int kVar, bool kObj>
 hipError_t launch_v(const CpPassArgs& a, const CpGrid& g, hipStream_t s) {
-  hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s, a, g.gj,
-                     g.gk);
+  if (a.bf16)
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, true>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s, a,
+                       g.gj, g.gk);
+  else
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s, a,
+                       g.gj, g.gk);
   return hipGetLastError();
 }
 

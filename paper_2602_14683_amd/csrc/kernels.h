@@ -62,6 +62,7 @@ struct CpPassArgs {
   int want_v;              // numerators / denominators of modes 1 and 2
   int want_m3;             // numerator / denominator of mode 3
   int want_obj;
+  int bf16;                // 1: rebuild in split bf16 (three products), contractions in bf16
   BetaConst bc;
   float* m3n;              // partial slots: m3 [gi*gj][Kp][32], m1 [gj*gk][Ip][32], m2 [gi*gk][Jp][32]
   float* m1n;

@@ -1,0 +1,149 @@
+"""COMM_BF16 on the dense CP path, against the FP64 oracle, with bounds that
+follow from the arithmetic.
+
+* The reconstruction uses split-bf16 operands (x = hi + lo, three products):
+  about 16 significant bits per operand, so Xhat is within ~2^-15 relative of
+  the float32 value and the objective computed from it stays within 2e-4.
+* Contraction operands are rounded to bf16 (8 significant bits, relative
+  error <= 2^-9 each, so <= 2^-8 per product).  Numerators and denominators are
+  sums of nonnegative products and keep that relative bound, so one block
+  update A <- A (Num / Den)^gamma is within gamma * 2 * 2^-8 < 8e-3 of the
+  exact update (plus float32 noise).  Typical errors average out far below
+  the bound; the median is held to 5e-4.
+* Run to a relative objective change of 1e-4, the bf16 path's objective is
+  within 1e-3 of the FP64 oracle run on the same problem.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cp as ocp
+from oracle.divergence import objective as oobjective
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2602_14683_amd as comm  # noqa: E402
+from tests.gpu_util import dev, f32, host64  # noqa: E402
+
+BETAS = [0.0, 0.5, 1.0, 1.5, 0.7]
+UPDATE_BOUND = 8e-3
+MEDIAN_BOUND = 5e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = comm.Context(0)
+    yield c
+    c.close()
+
+
+def _problem(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    fac = [rng.uniform(0.0, 1.0, size=(d, R)) for d in dims]
+    X = rng.poisson(ocp.rebuild(fac) * 3.0).astype(np.float64)
+    X = np.maximum(X, 1e-12)
+    init = [f32(rng.uniform(0.1, 1.0, size=(d, R))) for d in dims]
+    return X, init
+
+
+def _rel(got, want):
+    return np.abs(got - want) / np.abs(want)
+
+
+@pytest.mark.parametrize("beta", BETAS)
+@pytest.mark.parametrize("block", [0, 1, 2])
+def test_bf16_block_update_within_bound(ctx, beta, block):
+    X, init = _problem((37, 45, 70), 12, 1)
+    F = [dev(a) for a in init]
+    ctx.cp_update(dev(X), F, block=block, beta=beta, precision="bf16")
+    torch.cuda.synchronize()
+    want = ocp.block_update(X, [a.copy() for a in init], block, beta)
+    rel = _rel(host64(F[block]), want)
+    assert rel.max() < UPDATE_BOUND
+    assert np.median(rel) < MEDIAN_BOUND
+
+
+@pytest.mark.parametrize("beta", [0.5, 1.0, 1.5])
+@pytest.mark.parametrize("cache", [False, True])
+def test_bf16_jcomm_outer_within_bound(ctx, beta, cache):
+    if cache and beta == 1.0:
+        pytest.skip("beta = 1 never caches")
+    X, init = _problem((64, 48, 40), 32, 2)
+    F = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(dev(X), F, beta=beta, L=1, cache_pq=cache, obj_out=obj, precision="bf16")
+    torch.cuda.synchronize()
+    want, fref = ocp.jcomm_outer(X, init, beta, L=1, return_ref_obj=True)
+    for a, b in zip(F, want):
+        # three chained block updates, each within the single-update bound
+        rel = _rel(host64(a), b)
+        assert rel.max() < 3 * UPDATE_BOUND
+        assert np.median(rel) < 3 * MEDIAN_BOUND
+    assert abs(obj.item() - fref) / fref < 2e-4
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_bf16_objective(ctx, beta):
+    X, init = _problem((37, 45, 70), 12, 3)
+    out = ctx.beta_objective(dev(X), [dev(a) for a in init], beta=beta, precision="bf16")
+    torch.cuda.synchronize()
+    want = oobjective(X, ocp.rebuild(init), beta)
+    assert abs(out.item() - want) / want < 2e-4
+
+
+@pytest.mark.parametrize("beta", [0.5, 1.0])
+def test_bf16_converged_objective_matches_fp64(ctx, beta):
+    """Run both to a relative objective change of 1e-4 (at most 300 outer
+    iterations); the bf16 run's final objective is within 1e-3 of the FP64
+    oracle run's."""
+    d = workloads.cp_small(0)
+    init = [f32(a) for a in d.init]
+    Xd = dev(d.X)
+    F = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prev, gpu_final = None, None
+    for _ in range(300):
+        ctx.jcomm_outer(Xd, F, beta=beta, L=1, obj_out=obj, precision="bf16")
+        f = obj.item()
+        if prev is not None and abs(prev - f) <= 1e-4 * abs(prev):
+            break
+        prev = f
+    gpu_final = ctx.beta_objective(Xd, F, beta=beta).item()
+    cur = [a.copy() for a in init]
+    prev = None
+    for _ in range(300):
+        cur, f = ocp.jcomm_outer(d.X, cur, beta, L=1, return_ref_obj=True)
+        if prev is not None and abs(prev - f) <= 1e-4 * abs(prev):
+            break
+        prev = f
+    cpu_final = oobjective(d.X, ocp.rebuild(cur), beta)
+    assert abs(gpu_final - cpu_final) / cpu_final < 1e-3
+
+
+def test_bf16_full_size_jcomm(ctx):
+    """The 256^3 rank-32 workload at beta = 1: one outer iteration."""
+    d = workloads.cp_dense(0)
+    init = [f32(a) for a in d.init]
+    F = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(dev(d.X), F, beta=1.0, L=5, obj_out=obj, precision="bf16")
+    torch.cuda.synchronize()
+    want, fref = ocp.jcomm_outer(d.X, init, 1.0, L=5, return_ref_obj=True)
+    for a, b in zip(F, want):
+        rel = _rel(host64(a), b)
+        assert rel.max() < 3 * UPDATE_BOUND
+        assert np.median(rel) < 3 * MEDIAN_BOUND
+    assert abs(obj.item() - fref) / fref < 2e-4
+
+
+def test_bf16_rejected_for_tucker(ctx):
+    X = dev(np.ones((8, 9, 10)))
+    G = dev(np.ones((2, 2, 2)))
+    F = [dev(np.ones((n, 2))) for n in (8, 9, 10)]
+    with pytest.raises(comm.CommError) as e:
+        ctx.jcomm_outer(X, F, core=G, beta=1.0, precision="bf16")
+    assert e.value.code == comm.COMM_EUNSUPPORTED
