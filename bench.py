@@ -231,6 +231,7 @@ def run_tucker(args, ctx):
     X = torch.from_numpy(d.X.astype(np.float32)).cuda()
     G = torch.from_numpy(d.init_core.astype(np.float32)).cuda()
     F = [torch.from_numpy(a.astype(np.float32)).cuda() for a in d.init_factors]
+    G0, F0 = G.clone(), [a.clone() for a in F]
     trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
 
     def step(t):
@@ -257,6 +258,24 @@ def run_tucker(args, ctx):
                              "algorithmic_bytes_per_launch": bytes_, "algorithmic_flops_per_launch": flops,
                              "tflops_algorithmic": round(flops / (avg_ms * 1e-3) / 1e12, 2)},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    # the same iteration with bf16 tiles, and its objective against the
+    # float32 path after the same number of iterations
+    Gb, Fb = G0.clone(), [a.clone() for a in F0]
+    Gf, Ff = G0.clone(), [a.clone() for a in F0]
+
+    def bf16_step(t):
+        ctx.jcomm_outer(X, Fb, core=Gb, beta=beta, L=1, obj_out=trace[t:t + 1], precision="bf16")
+
+    el_b, _, _ = timed_loop(ctx, bf16_step, 2, args.steps)
+    Gb.copy_(G0)
+    for a, b in zip(Fb, F0):
+        a.copy_(b)
+    for _ in range(30):
+        ctx.jcomm_outer(X, Fb, core=Gb, beta=beta, L=1, precision="bf16")
+        ctx.jcomm_outer(X, Ff, core=Gf, beta=beta, L=1)
+    ob = ctx.beta_objective(X, Fb, core=Gb, beta=beta).item()
+    of = ctx.beta_objective(X, Ff, core=Gf, beta=beta).item()
+    out["bf16"] = {"outer_it_s": round(args.steps / el_b, 2), "objective_rel_diff_vs_fp32_after_30_it": abs(ob - of) / of}
     return out
 
 
@@ -305,27 +324,38 @@ def run_coo(args, ctx):
 def serving_stream(args, ctx):
     """A Poisson stream of CP / Tucker requests (dims U{16..256}, rank or core
     size in {4, 8, 16, 32}, beta in {0, 1/2, 1, 3/2}), each run to a relative
-    objective change <= 1e-4 (or max_iters), served twice on the same GPU:
-    continuous batching (graph-replayed batched step) and the plain per-request
-    FP32 loop.  Request tensors are drawn on the host before the clock starts;
-    copying them to the device is part of each request's service."""
+    objective change <= 1e-4 (or max_iters), served three ways on the same GPU:
+    continuous batching with bf16 tiles, continuous batching in float32 (both
+    replaying a captured graph of the batched step), and the plain per-request
+    float32 loop.  Request tensors are drawn on the host before the clock
+    starts; copying them to the device is part of each request's service.
+    Each bf16-served request's final objective is compared with the same
+    request's float32 per-request result."""
     import workloads
     from paper_2602_14683_amd import serving
 
     specs = workloads.serving_specs(seed=0, count=args.serve_requests, rate=args.serve_rate)
-    decs = [serving.from_workload(workloads.materialize(s)) for s in specs]
-    reqs = [serving.ServeRequest(s.rid, s.arrival, d) for s, d in zip(specs, decs)]
+    mats = [workloads.materialize(s) for s in specs]
     budget = int(args.serve_hbm_gib * (1 << 30))
     res = {}
-    for name, ex, slots in (("batched", serving.BatchedExecutor(ctx, args.serve_slots, graph=True), args.serve_slots),
-                            ("per_request_fp32", serving.SingleExecutor(ctx, 1), 1)):
-        srv = serving.Server(ex, budget, slots, tol=1e-4, max_iters=args.serve_max_iters)
+    finals = {}
+    runs = (("batched_bf16", "bf16", lambda: serving.BatchedExecutor(ctx, args.serve_slots, graph=True), args.serve_slots),
+            ("batched_fp32", "fp32", lambda: serving.BatchedExecutor(ctx, args.serve_slots, graph=True), args.serve_slots),
+            ("per_request_fp32", "fp32", lambda: serving.SingleExecutor(ctx, 1), 1))
+    for name, prec, make, slots in runs:
+        reqs = [serving.ServeRequest(s.rid, s.arrival, serving.from_workload(m, prec)) for s, m in zip(specs, mats)]
+        srv = serving.Server(make(), budget, slots, tol=1e-4, max_iters=args.serve_max_iters)
         done = srv.run(reqs)
+        finals[name] = {c.rid: c.objective for c in done}
         st = serving.summarize(done)
         st.update({"peak_slots": srv.peak_slots, "peak_bytes": srv.peak_bytes, "steps": srv.steps})
         res[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
-    res["speedup_solves_per_s"] = round(res["batched"]["solves_per_s"] / res["per_request_fp32"]["solves_per_s"], 3)
-    res["stream"] = {"requests": len(reqs), "rate_per_s": args.serve_rate, "tol": 1e-4,
+    base = res["per_request_fp32"]["solves_per_s"]
+    res["speedup_solves_per_s"] = {k: round(res[k]["solves_per_s"] / base, 3) for k in ("batched_bf16", "batched_fp32")}
+    rel = [abs(finals["batched_bf16"][r] - finals["per_request_fp32"][r]) / abs(finals["per_request_fp32"][r])
+           for r in finals["per_request_fp32"]]
+    res["bf16_final_objective_rel_diff_vs_fp32"] = {"max": max(rel), "median": float(sorted(rel)[len(rel) // 2])}
+    res["stream"] = {"requests": len(specs), "rate_per_s": args.serve_rate, "tol": 1e-4,
                      "max_iters": args.serve_max_iters, "slots": args.serve_slots,
                      "hbm_budget_gib": args.serve_hbm_gib,
                      "cp": sum(s.model == "cp" for s in specs), "tucker": sum(s.model == "tucker" for s in specs)}
@@ -334,10 +364,10 @@ def serving_stream(args, ctx):
 
 def run_serving(args, ctx):
     res = serving_stream(args, ctx)
-    b = res["batched"]
+    b = res["batched_bf16"]
     out = {"metric": METRIC, "value": b["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
            "steps": b["steps"], "warmup": 0, "ms_per_step": round(b["span_s"] / max(b["steps"], 1) * 1e3, 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
            "data": "synthetic (planted U(0,1) CP / Tucker models plus Poisson noise, Poisson arrivals)",
            "config": {"workload": f"serving_stream_{res['stream']['requests']}req_rate{args.serve_rate:g}",
                       "parallelism": "single GPU"},
@@ -360,8 +390,8 @@ def main() -> int:
                     help="skip the beta = 0.5 and block-MM rates on the same tensor")
     ap.add_argument("--comparison-steps", type=int, default=40)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream in the default run")
-    ap.add_argument("--serve-requests", type=int, default=48)
-    ap.add_argument("--serve-rate", type=float, default=100.0, help="arrivals per second")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=400.0, help="arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-max-iters", type=int, default=500)
     ap.add_argument("--serve-hbm-gib", type=float, default=64.0, help="device memory budget for admission")

@@ -61,9 +61,9 @@ extern "C" {
  *              operands and float32 accumulation; the reconstruction tile
  *              with split-bf16 operands (x = hi + lo, three products), about
  *              16 significant bits per operand, because the power step and
- *              the objective read it.  Dense CP only (other paths return
- *              COMM_EUNSUPPORTED); the sparse path has no matrix-core tiles
- *              and computes in float32 either way. */
+ *              the objective read it.  Dense CP and Tucker passes; the
+ *              small Tucker GEMMs that follow the passes, and the sparse
+ *              path (no matrix-core tiles), compute in float32 either way. */
 #define COMM_FP32 0
 #define COMM_BF16 1
 

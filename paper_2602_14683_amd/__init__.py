@@ -324,9 +324,9 @@ class Context:
                                         _stream(stream)))
 
     def tucker_update(self, X, core, factors, block: int = -2, beta: float = 1.0, eps: float = 1e-12,
-                      eps_x: Optional[float] = None, stream=None) -> None:
+                      eps_x: Optional[float] = None, stream=None, precision: str = "fp32") -> None:
         """B-CoMM block update(s) of a Tucker model in place (-1 core, n factor, -2 sweep)."""
-        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x)
+        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, precision=precision)
         _check(self._lib.comm_tucker_update(self._h, ctypes.byref(d), ctypes.byref(m), int(block),
                                             ctypes.byref(o), _stream(stream)))
 

@@ -410,10 +410,7 @@ int jcomm_check(const comm_dense* x, const comm_model* model, const comm_opts* o
   if (rc) return rc;
   if (!model) return fail(COMM_EINVAL, "model is NULL");
   if (model->kind == COMM_CP) return check_cp_model(model, x->ndim);
-  if (model->kind == COMM_TUCKER) {
-    if (opts->precision != COMM_FP32) return fail(COMM_EUNSUPPORTED, "Tucker models take COMM_FP32 only");
-    return tucker_check_model(model, x);
-  }
+  if (model->kind == COMM_TUCKER) return tucker_check_model(model, x);
   return fail(COMM_EINVAL, "model kind %d", model->kind);
 }
 
@@ -750,7 +747,6 @@ int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* mo
       if ((rc = check_cp_model(model, x->ndim))) return rc;
       rc = cp_objective(ctx, x, model, opts, out_dev, st);
     } else if (model->kind == COMM_TUCKER) {
-      if (opts->precision != COMM_FP32) return fail(COMM_EUNSUPPORTED, "Tucker models take COMM_FP32 only");
       if ((rc = tucker_check_model(model, x))) return rc;
       rc = tucker_objective(ctx, x, model, opts, out_dev, st);
     } else {
@@ -768,7 +764,6 @@ int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, in
     int rc = check_opts(opts, false);
     if (!rc) rc = check_dense(x);
     if (!rc) rc = tucker_check_model(model, x);
-    if (!rc && opts->precision != COMM_FP32) rc = fail(COMM_EUNSUPPORTED, "Tucker models take COMM_FP32 only");
     if (rc) return rc;
     if (block < -2 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
     if ((rc = set_device(ctx))) return rc;

@@ -213,6 +213,7 @@ struct TkPassArgs {
   const float* T2dT;       //   transposed [32][Pp], zero for pairs >= I J
   int64_t Pp;              // I J rounded up to a multiple of 32
   int xvec;                // fibres may be read as 16-byte vectors (K % 4 == 0, X 16-byte aligned)
+  int bf16;                // 1: rebuild in split bf16, contraction tiles in bf16
   float eps, eps_x;
   BetaConst bc;
   float* Vn;               // V pass outputs [(I J)][32]

@@ -401,6 +401,7 @@ TkPassArgs pass_args(const comm_dense* x, const comm_opts* o, const TkWs& w) {
   a.npg = w.npg;
   a.Pp = w.Pp;
   a.xvec = (w.dims[2] % 4 == 0) && (reinterpret_cast<uintptr_t>(x->X) % 16 == 0);
+  a.bf16 = o->precision == COMM_BF16;
   return a;
 }
 

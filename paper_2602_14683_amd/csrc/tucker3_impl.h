@@ -65,7 +65,7 @@ __device__ __forceinline__ void load_fibre(const float* __restrict__ row, int64_
   }
 }
 
-template <int BC, int kMode, bool kObj, int kSets>
+template <int BC, int kMode, bool kObj, int kSets, bool kBf>
 __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
   __shared__ float red[kWaves][kSets > 0 ? kSets : 1][32 * 33];
   __shared__ double sobj[kWaves];
@@ -83,6 +83,11 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
 
   float t2[16];
   if constexpr (kRebuild) row16(a.T2r + pm * kRP + 16 * h, pvalid, t2);
+  bf16x8 t2h[2], t2l[2];
+  if constexpr (kRebuild && kBf) {
+    split_bf16(t2, t2h[0], t2l[0]);
+    split_bf16(t2 + 8, t2h[1], t2l[1]);
+  }
   f32x16 vn = {}, vd = {};
   double obj = 0.0;
   const float* xrow = a.X + pm * (int64_t)K;
@@ -109,8 +114,12 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
       float crow[16];
       row16(a.C.p + (int64_t)(k0 + col) * kRP + 16 * h, k0 + col < K, crow);
       f32x16 xh = {};
+      if constexpr (kBf) {
+        xh = chain_bf16x3(crow, t2h, t2l, xh);
+      } else {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) xh = mfma32(crow[s], t2[s], xh);
+        for (int s = 0; s < 16; ++s) xh = mfma32(crow[s], t2[s], xh);
+      }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int k = k0 + out_row(v, h);
@@ -145,10 +154,19 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
       float cn[16], cd[16];
       load_fibre<true>(a.CnT + (int64_t)col * a.Kp, k0, a.Kp, h, true, cn);
       if constexpr (kSets == 2) load_fibre<true>(a.CdT + (int64_t)col * a.Kp, k0, a.Kp, h, true, cd);
+      if constexpr (kBf) {
+        const bf16x8 pb[2] = {pack_bf16(pv), pack_bf16(pv + 8)};
+        vn = chain_bf16(cn, pb, vn);
+        if constexpr (kSets == 2) {
+          const bf16x8 qb[2] = {pack_bf16(qv), pack_bf16(qv + 8)};
+          vd = chain_bf16(cd, qb, vd);
+        }
+      } else {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        vn = mfma32(cn[s], pv[s], vn);
-        if constexpr (kSets == 2) vd = mfma32(cd[s], qv[s], vd);
+        for (int s = 0; s < 16; ++s) {
+          vn = mfma32(cn[s], pv[s], vn);
+          if constexpr (kSets == 2) vd = mfma32(cd[s], qv[s], vd);
+        }
       }
     }
   }
@@ -193,7 +211,7 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
 
 // Mode-3 pass.  Workgroup (kt, g): k tile kt, pair group g of 4 * tpw pair
 // tiles; wave w takes tiles g * 4 * tpw + w * tpw + t, t < tpw.
-template <int BC, int kMode, int kSets>
+template <int BC, int kMode, int kSets, bool kBf>
 __global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
   __shared__ float red[kWaves][2][32 * 33];
   const int lane = threadIdx.x & 63;
@@ -210,6 +228,11 @@ __global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
 
   float crow[16];
   if constexpr (kRebuild) row16(a.C.p + (int64_t)kcol * kRP + 16 * h, kvalid, crow);
+  bf16x8 crh[2], crl[2];
+  if constexpr (kRebuild && kBf) {
+    split_bf16(crow, crh[0], crl[0]);
+    split_bf16(crow + 8, crh[1], crl[1]);
+  }
   f32x16 an = {}, ad = {};
   const int64_t pbase = (int64_t)(g * kWaves + w) * a.tpw * 32;
   // the fibre entries of the next pair tile are loaded while the current one is processed
@@ -240,8 +263,12 @@ __global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
       float t2[16];
       row16(a.T2r + (p0 + col) * kRP + 16 * h, p0 + col < npairs, t2);
       f32x16 xh = {};
+      if constexpr (kBf) {
+        xh = chain_bf16x3(t2, crh, crl, xh);
+      } else {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) xh = mfma32(t2[s], crow[s], xh);
+        for (int s = 0; s < 16; ++s) xh = mfma32(t2[s], crow[s], xh);
+      }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t m = p0 + out_row(v, h);
@@ -261,10 +288,19 @@ __global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
     float tn[16], td[16];
     load_fibre<true>(a.T2nT + (int64_t)col * a.Pp, p0, a.Pp, h, true, tn);
     if constexpr (kSets == 2) load_fibre<true>(a.T2dT + (int64_t)col * a.Pp, p0, a.Pp, h, true, td);
+    if constexpr (kBf) {
+      const bf16x8 tnb[2] = {pack_bf16(tn), pack_bf16(tn + 8)};
+      an = chain_bf16(pv, tnb, an);
+      if constexpr (kSets == 2) {
+        const bf16x8 tdb[2] = {pack_bf16(td), pack_bf16(td + 8)};
+        ad = chain_bf16(qv, tdb, ad);
+      }
+    } else {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      an = mfma32(pv[s], tn[s], an);
-      if constexpr (kSets == 2) ad = mfma32(qv[s], td[s], ad);
+      for (int s = 0; s < 16; ++s) {
+        an = mfma32(pv[s], tn[s], an);
+        if constexpr (kSets == 2) ad = mfma32(qv[s], td[s], ad);
+      }
     }
   }
   // an[v] = Num3[k0 + out_row(v, h)][c = col]; combine the waves in order 0..3
@@ -289,15 +325,18 @@ __global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
 
 template <int BC, int kMode, bool kObj, int kSets>
 hipError_t launch_v(const TkPassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((tk_v_kernel<BC, kMode, kObj, kSets>), dim3((unsigned)tk_v_workgroups(a.I, a.J)),
-                     dim3(kThreads), 0, s, a);
+  const dim3 grid((unsigned)tk_v_workgroups(a.I, a.J)), block(kThreads);
+  if (a.bf16) hipLaunchKernelGGL((tk_v_kernel<BC, kMode, kObj, kSets, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((tk_v_kernel<BC, kMode, kObj, kSets, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
 template <int BC, int kMode, int kSets>
 hipError_t launch_m3(const TkPassArgs& a, hipStream_t s) {
   const int nkt = (a.K + 31) / 32;
-  hipLaunchKernelGGL((tk_m3_kernel<BC, kMode, kSets>), dim3((unsigned)(nkt * a.npg)), dim3(kThreads), 0, s, a);
+  const dim3 grid((unsigned)(nkt * a.npg)), block(kThreads);
+  if (a.bf16) hipLaunchKernelGGL((tk_m3_kernel<BC, kMode, kSets, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((tk_m3_kernel<BC, kMode, kSets, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 

@@ -159,15 +159,17 @@ class Decomposition:
     beta: float = 1.0
     L: int = 1
     eps: float = 1e-12
+    precision: str = "fp32"
 
 
-def from_workload(req) -> Decomposition:
+def from_workload(req, precision: str = "fp32") -> Decomposition:
     """A :class:`Decomposition` from a generated serving request (``workloads.Request``)."""
     s = req.spec
     if s.model == "cp":
-        return Decomposition(req.X.astype(np.float32), [a.astype(np.float32) for a in req.init], None, s.beta)
+        return Decomposition(req.X.astype(np.float32), [a.astype(np.float32) for a in req.init], None, s.beta,
+                             precision=precision)
     return Decomposition(req.X.astype(np.float32), [a.astype(np.float32) for a in req.init[1:]],
-                         req.init[0].astype(np.float32), s.beta)
+                         req.init[0].astype(np.float32), s.beta, precision=precision)
 
 
 class _DeviceBase:
@@ -190,7 +192,8 @@ class _DeviceBase:
         h = {"slot": slot, "X": torch.from_numpy(d.X).cuda(),
              "factors": [torch.from_numpy(a).cuda() for a in d.factors],
              "core": torch.from_numpy(d.core).cuda() if d.core is not None else None,
-             "beta": d.beta, "L": d.L, "eps": d.eps, "obj_out": self.objs[slot:slot + 1]}
+             "beta": d.beta, "L": d.L, "eps": d.eps, "precision": d.precision,
+             "obj_out": self.objs[slot:slot + 1]}
         return h
 
     def unload(self, h: dict) -> dict:
@@ -234,6 +237,6 @@ class SingleExecutor(_DeviceBase):
         out = []
         for h in handles:
             self.ctx.jcomm_outer(h["X"], h["factors"], core=h["core"], beta=h["beta"], L=h["L"], eps=h["eps"],
-                                 obj_out=h["obj_out"])
+                                 obj_out=h["obj_out"], precision=h["precision"])
             out.append(float(h["obj_out"].item()))
         return out

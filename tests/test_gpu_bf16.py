@@ -1,5 +1,5 @@
-"""COMM_BF16 on the dense CP path, against the FP64 oracle, with bounds that
-follow from the arithmetic.
+"""COMM_BF16 on the dense CP and Tucker paths, against the FP64 oracle, with
+bounds that follow from the arithmetic.
 
 * The reconstruction uses split-bf16 operands (x = hi + lo, three products):
   about 16 significant bits per operand, so Xhat is within ~2^-15 relative of
@@ -18,6 +18,7 @@ import pytest
 
 import workloads
 from oracle import cp as ocp
+from oracle import tucker as otk
 from oracle.divergence import objective as oobjective
 
 pytestmark = pytest.mark.gpu
@@ -140,10 +141,58 @@ def test_bf16_full_size_jcomm(ctx):
     assert abs(obj.item() - fref) / fref < 2e-4
 
 
-def test_bf16_rejected_for_tucker(ctx):
-    X = dev(np.ones((8, 9, 10)))
-    G = dev(np.ones((2, 2, 2)))
-    F = [dev(np.ones((n, 2))) for n in (8, 9, 10)]
-    with pytest.raises(comm.CommError) as e:
-        ctx.jcomm_outer(X, F, core=G, beta=1.0, precision="bf16")
-    assert e.value.code == comm.COMM_EUNSUPPORTED
+def _tucker_problem(dims, J, seed):
+    rng = np.random.default_rng(seed)
+    core = rng.uniform(0.0, 1.0, size=J)
+    fac = [rng.uniform(0.0, 1.0, size=(d, j)) for d, j in zip(dims, J)]
+    X = np.maximum(rng.poisson(otk.rebuild(core, fac) * 2.0).astype(np.float64), 1e-12)
+    icore = f32(rng.uniform(0.1, 1.0, size=J))
+    ifac = [f32(rng.uniform(0.1, 1.0, size=(d, j))) for d, j in zip(dims, J)]
+    return X, icore, ifac
+
+
+@pytest.mark.parametrize("beta", BETAS)
+@pytest.mark.parametrize("block", [-1, 0, 1, 2])
+def test_bf16_tucker_block_update_within_bound(ctx, beta, block):
+    """Tucker numerators and denominators: the V and mode-3 tiles round P / Q
+    and C' (or T2') to bf16, the small GEMMs after them are float32, so the
+    same per-update bound holds."""
+    X, core, fac = _tucker_problem((37, 45, 70), (8, 6, 5), 1)
+    G, F = dev(core), [dev(a) for a in fac]
+    ctx.tucker_update(dev(X), G, F, block=block, beta=beta, precision="bf16")
+    torch.cuda.synchronize()
+    if block == -1:
+        got, want = host64(G), otk.block_update_core(X, core, fac, beta)
+    else:
+        got, want = host64(F[block]), otk.block_update_factor(X, core, fac, block, beta)
+    rel = _rel(got, want)
+    assert rel.max() < UPDATE_BOUND
+    assert np.median(rel) < MEDIAN_BOUND
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 1.5])
+@pytest.mark.parametrize("cache", [False, True])
+def test_bf16_tucker_jcomm_outer_within_bound(ctx, beta, cache):
+    if cache and beta == 1.0:
+        pytest.skip("beta = 1 never caches")
+    X, core, fac = _tucker_problem((64, 48, 40), (16, 16, 16), 2)
+    G, F = dev(core), [dev(a) for a in fac]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(dev(X), F, core=G, beta=beta, L=1, cache_pq=cache, obj_out=obj, precision="bf16")
+    torch.cuda.synchronize()
+    wc, wf, fref = otk.jcomm_outer(X, core, fac, beta, L=1, return_ref_obj=True)
+    # four chained block updates
+    for a, b in zip([host64(G)] + [host64(f) for f in F], [wc] + list(wf)):
+        rel = _rel(a, b)
+        assert rel.max() < 4 * UPDATE_BOUND
+        assert np.median(rel) < 4 * MEDIAN_BOUND
+    assert abs(obj.item() - fref) / fref < 2e-4
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 1.5])
+def test_bf16_tucker_objective(ctx, beta):
+    X, core, fac = _tucker_problem((37, 45, 70), (8, 6, 5), 3)
+    out = ctx.beta_objective(dev(X), [dev(a) for a in fac], core=dev(core), beta=beta, precision="bf16")
+    torch.cuda.synchronize()
+    want = oobjective(X, otk.rebuild(core, fac), beta)
+    assert abs(out.item() - want) / want < 2e-4
