@@ -64,21 +64,80 @@ def measured_traffic():
 
 
 def cpu_baseline(X64, init, beta, L, iters):
-    """The FP64 oracle, as it stands, on the same tensor: `iters` outer iterations."""
+    """The FP64 oracle, as it stands, on the same tensor: `iters` outer
+    iterations with the BLAS threads the host gives it, and a shorter run
+    limited to one thread (the paper's own single-thread setting)."""
     from oracle import cp as ocp
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
-    cur = [a.copy() for a in init]
+
+    def run(n):
+        cur = [a.copy() for a in init]
+        t0 = time.perf_counter()
+        for _ in range(n):
+            cur, _ = ocp.jcomm_outer(X64, cur, beta, L=L, return_ref_obj=True)
+        return time.perf_counter() - t0
+
+    dt = run(iters)
+    out = {"value": iters / dt, "unit": "outer it/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{iters} J-CoMM outer iterations (L={L}, beta={beta}, objective included) on the full "
+                     f"256x256x256 rank-32 tensor, NumPy float64 einsum, {dt:.1f} s"}
+    if threadpool_limits is not None:
+        n1 = max(1, iters // 5)
+        with threadpool_limits(limits=1):
+            d1 = run(n1)
+        out["one_thread"] = {"value": n1 / d1, "unit": "outer it/s", "cores": 1,
+                             "sample": f"{n1} outer iterations, {d1:.1f} s"}
+    return out
+
+
+def objective_off_rate(ctx, X, init32, steps):
+    """The headline iteration with the objective switched off (pure update
+    throughput), float32 tiles."""
+    import torch
+    fac = [torch.from_numpy(a).cuda() for a in init32]
+    for _ in range(3):
+        ctx.jcomm_outer(X, fac, beta=1.0, L=5)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(iters):
-        cur, _ = ocp.jcomm_outer(X64, cur, beta, L=L, return_ref_obj=True)
-    dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "outer it/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{iters} J-CoMM outer iterations (L={L}, beta={beta}, objective included) on the full "
-                      f"256x256x256 rank-32 tensor, NumPy float64 einsum, {dt:.1f} s"}
+    for _ in range(steps):
+        ctx.jcomm_outer(X, fac, beta=1.0, L=5)
+    torch.cuda.synchronize()
+    return round(steps / (time.perf_counter() - t0), 2)
+
+
+def control_512(ctx, steps):
+    """The same pass on 512^3 (537 MB of X, beyond the 256 MB last-level
+    cache): pass-kernel time from the library's HIP events and the HBM rate
+    it implies for X."""
+    import numpy as np
+    import torch
+    import workloads
+    d = workloads.cp_dense(0, dims=(512, 512, 512), rank=32)
+    X = torch.from_numpy(d.X.astype(np.float32)).cuda()
+    fac = [torch.from_numpy(a.astype(np.float32)).cuda() for a in d.init]
+    del d
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        ctx.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=obj)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=obj)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = ctx.profile_query()
+    ctx.profile_enable(False)
+    entries = 512 ** 3
+    avg = ms / max(n, 1)
+    return {"outer_it_s": round(steps / wall, 2), "pass_avg_us": round(avg * 1e3, 2),
+            "x_gbs": round(4 * entries / (avg * 1e-3) / 1e9, 1),
+            "tflops": round(6.0 * 32 * entries / (avg * 1e-3) / 1e12, 2), "steps": steps}
 
 
 def comparisons(ctx, X, init32, steps):
@@ -213,6 +272,9 @@ def run_cp(args, ctx):
                 "objective": {"first": float(tr[0]), "last": float(steps_tr[-1]), "monotone": monotone(steps_tr)}})
     if not args.no_comparisons:
         out["same_gpu_comparisons"] = comparisons(ctx, X, init32, args.comparison_steps)
+        out["same_gpu_comparisons"]["jcomm_beta1_L5_no_objective_it_s"] = objective_off_rate(
+            ctx, X, init32, args.comparison_steps)
+        out["control_512"] = control_512(ctx, 20)
     if not args.no_cpu_baseline:
         X64 = X32.astype(np.float64)
         init64 = [a.astype(np.float64) for a in init32]
