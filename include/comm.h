@@ -202,6 +202,39 @@ int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, cons
  *     names the first bad problem. */
 int comm_jcomm_outer_batched(comm_ctx* ctx, const comm_problem* problems, int count, int flags, void* stream);
 
+/* Extrapolation weights of one outer iteration (Sec. "Going beyond:
+ * Majorization-Minimization with Extrapolation"):
+ *   alpha_t = min(alpha_nes, c / (||[Theta^(t) - Theta^(t-1)]_+|| + delta)),
+ * one scalar for all blocks, the norm over every entry of the model.  The
+ * paper fixes none of the three: the caller chooses them (e.g. alpha_nes =
+ * (t - 1) / (t + 2)). */
+typedef struct {
+  double alpha_nes;  /* >= 0 */
+  double c;          /* > 0 */
+  double delta;      /* > 0 */
+} comm_extrap;
+
+/* Extrapolated B-CoMM sweep (items (i) CP and (ii) Tucker of that section).
+ * `prev` has the shapes of `model` (distinct buffers) and holds, per block,
+ * the value the block had before its update in the previous sweep (Theta^(t-1)).
+ * alpha_t is computed on the device from model and prev; then every block, in
+ * the sweep order (Tucker: core first), is moved to
+ * max(A + alpha_t [A - A_prev]_+, eps) just before its own update, and the
+ * block update is taken at, and anchored at, the moved block.  On return prev
+ * holds each block's value before its update in this sweep, ready for the
+ * next call.  alpha_dev (device float, may be NULL) receives alpha_t. */
+int comm_bcomm_sweep_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* model, comm_model* prev,
+                            const comm_opts* opts, const comm_extrap* extrap, float* alpha_dev, void* stream);
+
+/* J-CoMM with outer-reference extrapolation (item (iii)): the whole model is
+ * moved to max(Theta + alpha_t [Theta - Theta_prev]_+, eps), prev receives the
+ * model's value before the move, and one outer iteration of comm_jcomm_outer
+ * runs from the moved model as its reference.  obj_ref_dev receives the
+ * objective at that (extrapolated) reference. */
+int comm_jcomm_outer_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* model, comm_model* prev,
+                            const comm_opts* opts, const comm_extrap* extrap, double* obj_ref_dev,
+                            float* alpha_dev, void* stream);
+
 /* D_beta(X, Xhat(model)) summed over all entries (Sec. 3.2, Definition of the
  * beta-divergence), accumulated in float64, written to the device address
  * out_dev.  Safeguards as in comm_opts. */

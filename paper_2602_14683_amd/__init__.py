@@ -32,7 +32,7 @@ EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_by
             "comm_profile_query", "comm_cp_update",
             "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo",
             "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
-            "comm_cp_jcomm_outer_coo_plan"]
+            "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap"]
 
 
 class CommError(RuntimeError):
@@ -58,6 +58,10 @@ class Opts(ctypes.Structure):
 class Coo(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * 4), ("nnz", ctypes.c_int64),
                 ("idx", ctypes.c_void_p * 4), ("val", ctypes.c_void_p)]
+
+
+class Extrap(ctypes.Structure):
+    _fields_ = [("alpha_nes", ctypes.c_double), ("c", ctypes.c_double), ("delta", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -98,11 +102,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.comm_coo_plan_destroy.argtypes = [ctypes.c_void_p]
     lib.comm_cp_jcomm_outer_coo_plan.argtypes = [ctypes.c_void_p, ctypes.c_void_p, P(Model), P(Opts),
                                                  ctypes.c_void_p, ctypes.c_void_p]
+    lib.comm_bcomm_sweep_extrap.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Model), P(Opts), P(Extrap),
+                                            ctypes.c_void_p, ctypes.c_void_p]
+    lib.comm_jcomm_outer_extrap.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Model), P(Opts), P(Extrap),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
                  "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched",
-                 "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan"]:
+                 "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan",
+                 "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -352,6 +361,32 @@ class Context:
             batch = Batch(batch)
         _check(self._lib.comm_jcomm_outer_batched(self._h, batch.array, len(batch),
                                                   COMM_BATCH_GRAPH if graph else 0, _stream(stream)))
+
+    def bcomm_sweep_extrap(self, X, factors, prev, core=None, prev_core=None, beta: float = 1.0,
+                           alpha_nes: float = 0.0, c: float = 1.0, delta: float = 1e-12, eps: float = 1e-12,
+                           eps_x: Optional[float] = None, alpha_out=None, stream=None, precision: str = "fp32"):
+        """Extrapolated B-CoMM sweep in place; ``prev`` (and ``prev_core``) hold the
+        previous iterate and receive the one for the next call."""
+        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, precision=precision)
+        pm = _model(prev, prev_core)
+        e = Extrap(float(alpha_nes), float(c), float(delta))
+        aptr = _f32(alpha_out, "alpha_out") if alpha_out is not None else None
+        _check(self._lib.comm_bcomm_sweep_extrap(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(pm),
+                                                 ctypes.byref(o), ctypes.byref(e), aptr, _stream(stream)))
+
+    def jcomm_outer_extrap(self, X, factors, prev, core=None, prev_core=None, beta: float = 1.0, L: int = 1,
+                           alpha_nes: float = 0.0, c: float = 1.0, delta: float = 1e-12, eps: float = 1e-12,
+                           eps_x: Optional[float] = None, cache_pq: bool = False, obj_out=None, alpha_out=None,
+                           stream=None, precision: str = "fp32"):
+        """J-CoMM outer iteration from the extrapolated reference, in place."""
+        d, m = _dense(X), _model(factors, core)
+        o = _opts(beta, eps, eps_x, L, cache_pq, precision)
+        pm = _model(prev, prev_core)
+        e = Extrap(float(alpha_nes), float(c), float(delta))
+        optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
+        aptr = _f32(alpha_out, "alpha_out") if alpha_out is not None else None
+        _check(self._lib.comm_jcomm_outer_extrap(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(pm),
+                                                 ctypes.byref(o), ctypes.byref(e), optr, aptr, _stream(stream)))
 
     def beta_objective(self, X, factors, core=None, beta: float = 1.0, eps: float = 1e-12,
                        eps_x: Optional[float] = None, out=None, stream=None, precision: str = "fp32"):

@@ -375,6 +375,93 @@ int set_device(comm_ctx* ctx) {
   return COMM_OK;
 }
 
+// ---------------------------------------------------------------------------------------- extrapolation
+
+// Blocks of a model in update order (Tucker: core first), with entry counts.
+int model_blocks(const comm_dense* x, const comm_model* m, float** ptr, int64_t* count) {
+  int nb = 0;
+  if (m->kind == COMM_TUCKER) {
+    ptr[nb] = m->core;
+    count[nb++] = m->core_dims[0] * m->core_dims[1] * m->core_dims[2];
+  }
+  for (int n = 0; n < x->ndim; ++n) {
+    ptr[nb] = m->factors[n];
+    count[nb++] = x->dims[n] * (m->kind == COMM_CP ? m->rank : m->core_dims[n]);
+  }
+  return nb;
+}
+
+int check_extrap(const comm_dense* x, const comm_model* m, const comm_model* prev, const comm_extrap* e) {
+  if (!e) return fail(COMM_EINVAL, "extrap is NULL");
+  if (!(e->alpha_nes >= 0.0 && std::isfinite(e->alpha_nes))) return fail(COMM_EINVAL, "alpha_nes = %g", e->alpha_nes);
+  if (!(e->c > 0.0 && std::isfinite(e->c))) return fail(COMM_EINVAL, "c must be > 0");
+  if (!(e->delta > 0.0 && std::isfinite(e->delta))) return fail(COMM_EINVAL, "delta must be > 0");
+  if (!prev) return fail(COMM_EINVAL, "prev is NULL");
+  if (prev->kind != m->kind) return fail(COMM_EINVAL, "prev is not the same kind of model");
+  if (m->kind == COMM_CP && prev->rank != m->rank) return fail(COMM_EINVAL, "prev has rank %d, model %d", prev->rank,
+                                                                m->rank);
+  if (m->kind == COMM_TUCKER) {
+    for (int n = 0; n < x->ndim; ++n)
+      if (prev->core_dims[n] != m->core_dims[n]) return fail(COMM_EINVAL, "prev core_dims[%d] differs", n);
+    if (!prev->core) return fail(COMM_EINVAL, "prev core is NULL");
+    if (prev->core == m->core) return fail(COMM_EINVAL, "prev core aliases the model core");
+  }
+  for (int n = 0; n < x->ndim; ++n) {
+    if (!prev->factors[n]) return fail(COMM_EINVAL, "prev factors[%d] is NULL", n);
+    if (prev->factors[n] == m->factors[n]) return fail(COMM_EINVAL, "prev factors[%d] aliases the model", n);
+  }
+  return COMM_OK;
+}
+
+int ensure_aux(comm_ctx* ctx) {
+  if (ctx->aux) return COMM_OK;
+  HIP_TRY(hipMalloc(&ctx->aux, 256));
+  return COMM_OK;
+}
+
+// alpha_t of the whole model into alpha (device).
+int extrap_alpha(const comm_dense* x, comm_model* m, comm_model* prev, const comm_extrap* e, float* alpha,
+                 hipStream_t st) {
+  ExtrapArgs a = {};
+  int64_t cnt[5];
+  a.nb = model_blocks(x, m, a.cur, cnt);
+  float* pp[5];
+  int64_t pc[5];
+  model_blocks(x, prev, pp, pc);
+  for (int b = 0; b < a.nb; ++b) {
+    a.prev[b] = pp[b];
+    a.count[b] = cnt[b];
+  }
+  a.alpha_nes = e->alpha_nes;
+  a.c = e->c;
+  a.delta = e->delta;
+  a.alpha = alpha;
+  HIP_TRY(launch_extrap_alpha(a, st));
+  return COMM_OK;
+}
+
+// Move block b (index in update order; -1 = all blocks).
+int extrap_apply(const comm_dense* x, comm_model* m, comm_model* prev, int b, float* alpha, float eps,
+                 hipStream_t st) {
+  float* cur[5];
+  float* pp[5];
+  int64_t cnt[5], pc[5];
+  const int nb = model_blocks(x, m, cur, cnt);
+  model_blocks(x, prev, pp, pc);
+  ExtrapArgs a = {};
+  for (int q = 0; q < nb; ++q) {
+    if (b >= 0 && q != b) continue;
+    a.cur[a.nb] = cur[q];
+    a.prev[a.nb] = pp[q];
+    a.count[a.nb] = cnt[q];
+    ++a.nb;
+  }
+  a.alpha = alpha;
+  a.eps = eps;
+  HIP_TRY(launch_extrap_apply(a, st));
+  return COMM_OK;
+}
+
 // ---------------------------------------------------------------------------------------- sparse checks
 
 int check_coo(const comm_coo* x) {
@@ -645,6 +732,7 @@ int comm_destroy(comm_ctx* ctx) {
     for (hipStream_t q : ctx->bstreams) hipStreamDestroy(q);
     for (hipEvent_t e : ctx->bjoin) hipEventDestroy(e);
     if (ctx->bcapture) hipStreamDestroy(ctx->bcapture);
+    if (ctx->aux) hipFree(ctx->aux);
     if (ctx->bfork) hipEventDestroy(ctx->bfork);
     delete ctx;
     return rc;
@@ -820,6 +908,58 @@ int comm_cp_jcomm_outer_coo_plan(comm_ctx* ctx, const comm_coo_plan* plan, comm_
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
     rc = coo_jcomm_kl_plan(ctx, plan, model, opts, obj_ref_dev, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_bcomm_sweep_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* model, comm_model* prev,
+                            const comm_opts* opts, const comm_extrap* extrap, float* alpha_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_opts(opts, false);
+    if (!rc) rc = check_dense(x);
+    if (rc) return rc;
+    if (!model) return fail(COMM_EINVAL, "model is NULL");
+    if (model->kind == COMM_CP) rc = check_cp_model(model, x->ndim);
+    else if (model->kind == COMM_TUCKER) rc = tucker_check_model(model, x);
+    else rc = fail(COMM_EINVAL, "model kind %d", model->kind);
+    if (!rc) rc = check_extrap(x, model, prev, extrap);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    if ((rc = ensure_aux(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    float* alpha = alpha_dev ? alpha_dev : ctx->aux;
+    if ((rc = extrap_alpha(x, model, prev, extrap, alpha, st))) return rc;
+    // each block is moved just before its own update (Tucker: core, then modes)
+    const bool tk = model->kind == COMM_TUCKER;
+    const int nb = x->ndim + (tk ? 1 : 0);
+    for (int b = 0; b < nb && !rc; ++b) {
+      if ((rc = extrap_apply(x, model, prev, b, alpha, (float)opts->eps, st))) break;
+      const int blk = tk ? b - 1 : b;
+      rc = tk ? tucker_bcomm(ctx, x, model, blk, opts, st) : cp_bcomm(ctx, x, model, blk, opts, st);
+    }
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_jcomm_outer_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* model, comm_model* prev,
+                            const comm_opts* opts, const comm_extrap* extrap, double* obj_ref_dev, float* alpha_dev,
+                            void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = jcomm_check(x, model, opts);
+    if (!rc) rc = check_extrap(x, model, prev, extrap);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    if ((rc = ensure_aux(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    float* alpha = alpha_dev ? alpha_dev : ctx->aux;
+    if ((rc = extrap_alpha(x, model, prev, extrap, alpha, st))) return rc;
+    // the outer reference is the extrapolated model; the inner iterate starts there
+    if ((rc = extrap_apply(x, model, prev, -1, alpha, (float)opts->eps, st))) return rc;
+    rc = jcomm_run(ctx, x, model, opts, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
   });

@@ -20,6 +20,7 @@ struct comm_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t last_stream = nullptr;
+  float* aux = nullptr;     // small device scratch that outlives workspace growth (extrapolation weight)
   // measurement: event pairs around every fused dense pass launch
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

@@ -169,6 +169,22 @@ struct SlotUpdateArgs {
 };
 hipError_t launch_slot_update(const SlotUpdateArgs& a, hipStream_t s);
 
+// Extrapolation of the parameter blocks (contiguous caller buffers, `count`
+// entries each).  launch_extrap_alpha writes alpha_t to alpha[0]; launch_
+// extrap_apply reads it and moves the listed blocks, saving their old values
+// in prev.
+struct ExtrapArgs {
+  int nb;
+  float* cur[5];
+  float* prev[5];
+  int64_t count[5];
+  double alpha_nes, c, delta;
+  float* alpha;
+  float eps;
+};
+hipError_t launch_extrap_alpha(const ExtrapArgs& a, hipStream_t s);
+hipError_t launch_extrap_apply(const ExtrapArgs& a, hipStream_t s);
+
 // Sum of n float64 partials in a fixed order; writes *out (device).  If add_to
 // is not NULL its value is added.
 hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, double* out, hipStream_t s);

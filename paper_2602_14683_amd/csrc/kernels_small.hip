@@ -426,4 +426,58 @@ hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------------------
+// Extrapolation (Sec. "Going beyond: Majorization-Minimization with Extrapolation")
+
+// alpha = min(alpha_nes, c / (||[cur - prev]_+|| + delta)) over every block,
+// the squared norm summed in float64 in a fixed order; one workgroup.
+__global__ void __launch_bounds__(1024) extrap_alpha_kernel(ExtrapArgs a) {
+  __shared__ double lds[1024];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int b = 0; b < a.nb; ++b) {
+    const float* cur = a.cur[b];
+    const float* prev = a.prev[b];
+    for (int64_t e = t; e < a.count[b]; e += 1024) {
+      const double d = (double)cur[e] - (double)prev[e];
+      if (d > 0.0) s += d * d;
+    }
+  }
+  lds[t] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) lds[t] += lds[t + w];
+    __syncthreads();
+  }
+  if (t == 0) a.alpha[0] = (float)fmin(a.alpha_nes, a.c / (sqrt(lds[0]) + a.delta));
+}
+
+// For the selected blocks: prev <- cur, cur <- max(cur + alpha [cur - prev]_+, eps).
+__global__ void extrap_apply_kernel(ExtrapArgs a) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  while (b < a.nb && e >= a.count[b]) {
+    e -= a.count[b];
+    ++b;
+  }
+  if (b >= a.nb) return;
+  const float alpha = a.alpha[0];
+  const float v = a.cur[b][e], p = a.prev[b][e];
+  a.prev[b][e] = v;
+  a.cur[b][e] = fmaxf(v + alpha * fmaxf(v - p, 0.0f), a.eps);
+}
+
+hipError_t launch_extrap_alpha(const ExtrapArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(extrap_alpha_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_extrap_apply(const ExtrapArgs& a, hipStream_t s) {
+  int64_t n = 0;
+  for (int b = 0; b < a.nb; ++b) n += a.count[b];
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(extrap_apply_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace comm
