@@ -338,11 +338,43 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   load_tile<kInterior>(src0, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, xb[0]);
   if (kCache) load_tile<kInterior>(a.Qc, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, qb[0]);
 
+  // The reconstruction of pair block t + 1 is issued on the matrix cores
+  // before tile t's entries are evaluated, so that a wave's vector work
+  // overlaps its own matrix-core work.
+  auto rebuild = [&](int ibx, int jbx) -> f32x16 {
+    // rebuild operand: lane = pair row m = col, r = 16h + s
+    float arow[16], brow[16];
+    load16(sh.ra + (ibx * 4 + (col >> 3)) * kSA + 16 * h, arow);
+    load16(sh.rb + (jbx * 8 + (col & 7)) * kSA + 16 * h, brow);
+    f32x16 acc = {};
+    if constexpr (kBf) {
+      float av[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) av[s] = arow[s] * brow[s];
+      acc = chain_bf16x3(av, crh, crl, acc);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) acc = mfma32(arow[s] * brow[s], crow[s], acc);
+    }
+    return acc;
+  };
+  // (KL only: its entries are short enough that the second accumulator still
+  // fits two waves per SIMD; the other classes rebuild at the tile itself)
+  constexpr bool kPipe = BC == kKL && !kCache;
+  f32x16 xh_cur = {};
+  if constexpr (kPipe) xh_cur = rebuild(2 * mg, 0);
+
   for (int ibl = 0; ibl < 2; ++ibl) {
   const int ib = 2 * mg + ibl;
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb) {
     const int t = ibl * 4 + jb;
+    f32x16 xh_next = {};
+    if constexpr (kPipe) {
+      if (t + 1 < 8) xh_next = rebuild(2 * mg + ((t + 1) >> 2), (jb + 1) & 3);
+    } else if constexpr (!kCache) {
+      xh_cur = rebuild(ib, jb);
+    }
     if (t + 1 < 8) {
       // prefetch the next pair block (the next i block after jb = 3)
       const int ibn = 2 * mg + ((t + 1) >> 2), jbn = (jb + 1) & 3;
@@ -371,34 +403,22 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
         qv[v] = qb[jb & 1][v];
       }
     } else {
-      // rebuild operand: lane = pair row m = col, r = 16h + s
-      float arow[16], brow[16];
-      load16(sh.ra + (ib * 4 + (col >> 3)) * kSA + 16 * h, arow);
-      load16(sh.rb + (jb * 8 + (col & 7)) * kSA + 16 * h, brow);
-      f32x16 xh = {};
-      if constexpr (kBf) {
-        float av[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) av[s] = arow[s] * brow[s];
-        xh = chain_bf16x3(av, crh, crl, xh);
-      } else {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) xh = mfma32(arow[s] * brow[s], crow[s], xh);
-      }
-      float yv[16];
+      const f32x16& xh = xh_cur;
       bool anyfar = false;
+      // the tile's 16 nonnegative terms per lane are summed in float32 (relative
+      // error <= 15 * 2^-24) before entering the float64 accumulator
+      float objt = 0.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         float x = xv[v];
         if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
         const float y = fmaxf(xh[v], a.eps);
-        yv[v] = y;
         float p, q, d = 0.0f;
         bool far;
         entry<BC, kObj>(x, y, a.bc, p, q, d, far);
         pv[v] = valid[v] ? p : 0.f;
         qv[v] = valid[v] ? q : 0.f;
-        if (kObj) obj += (double)(valid[v] ? d : 0.0f);
+        if (kObj) objt += valid[v] ? d : 0.0f;
         anyfar |= far && valid[v];
         // the general objective is long; keep the scheduler from interleaving all
         // sixteen entries (register pressure)
@@ -406,12 +426,13 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
           if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }
+      if constexpr (kObj) obj += (double)objt;
       if constexpr (kObj && BC == kKL) {
         // rare: entries with |s| >= 1/2 replace their series term by the direct form
         if (__builtin_amdgcn_ballot_w64(anyfar)) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const float x = xv[v], y = yv[v];
+            const float x = xv[v], y = fmaxf(xh[v], a.eps);
             const float sum = x + y;
             bool far;
             const float ds = kl_series(x, y, fast_rcp(sum), far);
@@ -448,6 +469,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
         contract_tile<kBf>(qv, ag, bq, ctd, ctdb, want_m3, want_v, m3d, m1d, m2d[jb], sh.t[w], col, h);
       }
     }
+    if constexpr (kPipe) xh_cur = xh_next;
     if (jb == 3 && want_v) {
       // this wave's M1 rows ib*4+g: combine the two lane halves (different j)
 #pragma unroll
@@ -527,7 +549,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
 }
 
 template <int BC, int kVar, bool kObj, bool kBf>
-__global__ void __launch_bounds__(kThreads) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
+__global__ void __launch_bounds__(kThreads, BC == kKL ? 2 : 1) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
   __shared__ PassShared sh;
   const int wg = blockIdx.x;
   const int bk = wg % gk;

@@ -120,6 +120,8 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
 #pragma unroll
         for (int s = 0; s < 16; ++s) xh = mfma32(crow[s], t2[s], xh);
       }
+      // the tile's 16 nonnegative terms per lane in float32, then float64
+      float objt = 0.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int k = k0 + out_row(v, h);
@@ -132,11 +134,12 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
         entry<BC, kObj>(x, y, a.bc, p, q, d, far);
         if constexpr (kObj) {
           if (BC == kKL && far) d = kl_direct(x, y);
-          obj += (double)(ok ? d : 0.0f);
+          objt += ok ? d : 0.0f;
         }
         pv[v] = ok ? p : 0.0f;
         qv[v] = ok ? q : 0.0f;
       }
+      if constexpr (kObj) obj += (double)objt;
       if constexpr (kMode == kTkCacheWrite) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
