@@ -267,3 +267,24 @@ def test_eps_clip_binds_on_zero_numerator():
     out = cp.block_update(X, fac, 0, 1.0, eps=1e-9)
     assert np.all(out[1] == 1e-9)
     assert np.all(out[0] > 1e-9)
+
+
+# ------------------------------------------------------------ order 4 (the paper's CP shape class)
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_planted_order4_cp_is_fixed_point(beta):
+    d = workloads.planted_exact_cp(13, (5, 4, 3, 6), 3)
+    for out in (cp.bcomm_sweep(d.X, d.init, beta), cp.jcomm_outer(d.X, d.init, beta, L=2)):
+        for a, b in zip(out, d.init):
+            np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_order4_cp_updates_decrease_objective(beta):
+    rng = np.random.default_rng(14)
+    dims, R = (5, 4, 3, 6), 3
+    X = rng.poisson(cp.rebuild([rng.uniform(0, 1, (d, R)) for d in dims]) * 4) + 0.5
+    fac = [rng.uniform(0.1, 1.0, (d, R)) for d in dims]
+    for method in ("bcomm", "jcomm"):
+        _, trace = cp.run(X, fac, beta, 5, method=method, L=2)
+        assert all(b <= a * (1 + 1e-13) for a, b in zip(trace, trace[1:]))
