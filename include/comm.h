@@ -27,10 +27,21 @@
  *   - Dense reductions are deterministic: the same inputs give bitwise
  *     identical outputs on the same device.
  *
- * Supported in this version: dense 3-way tensors; CP rank R <= 32; Tucker core
- * sizes J_n <= 32; sparse COO of order 2 to 4 (CP, beta = 1).  Other shapes
- * return COMM_EUNSUPPORTED.  The sparse paths accumulate with float atomics
- * and are reproducible to rounding only; the dense paths are deterministic.
+ * Supported in this version: dense CP of order 3, 4 and 5 (rank R <= 32; at
+ * orders 4 and 5 the product I_1 ... I_{N-2} must not exceed 2^24); dense
+ * Tucker of order 3 (core sizes J_n <= 32); sparse COO of order 2 to 4 (CP,
+ * beta = 1).  Other shapes return COMM_EUNSUPPORTED.  The sparse paths
+ * accumulate with float atomics and are reproducible to rounding only; the
+ * dense paths are deterministic.
+ *
+ * Dense CP of order N = 4, 5 runs through a 3-way view of the same memory:
+ * modes 1..N-2 form one mode of extent I_1 ... I_{N-2} whose factor is the
+ * row-wise (Khatri-Rao) product of theirs, so the view's CP model rebuilds the
+ * same tensor, and the numerator of each of those modes is the view's
+ * numerator contracted with the other grouped factors (the mode-n
+ * contraction of Sec. 6.1 in two steps).  Per sweep this costs N passes over X
+ * for B-CoMM, and for J-CoMM one pass at beta = 1 and three at beta != 1
+ * (modes 1..N-2 share one).
  */
 #ifndef COMM_H_
 #define COMM_H_
@@ -69,10 +80,13 @@ extern "C" {
 
 typedef struct comm_ctx comm_ctx;
 
+/* Largest order of comm_dense and comm_model. */
+#define COMM_MAX_NDIM 5
+
 /* Dense data tensor X >= 0 (Sec. 3.1).  X points to prod(dims) floats. */
 typedef struct {
   int ndim;
-  int64_t dims[4];
+  int64_t dims[COMM_MAX_NDIM];
   const float* X;
 } comm_dense;
 
@@ -83,8 +97,8 @@ typedef struct {
 typedef struct {
   int kind;
   int rank;
-  int64_t core_dims[4];
-  float* factors[4];
+  int64_t core_dims[COMM_MAX_NDIM];
+  float* factors[COMM_MAX_NDIM];
   float* core;
 } comm_model;
 

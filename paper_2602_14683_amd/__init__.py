@@ -41,13 +41,16 @@ class CommError(RuntimeError):
         self.code = code
 
 
+MAX_NDIM = 5  # COMM_MAX_NDIM
+
+
 class Dense(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * 4), ("X", ctypes.c_void_p)]
+    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * MAX_NDIM), ("X", ctypes.c_void_p)]
 
 
 class Model(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("rank", ctypes.c_int), ("core_dims", ctypes.c_int64 * 4),
-                ("factors", ctypes.c_void_p * 4), ("core", ctypes.c_void_p)]
+    _fields_ = [("kind", ctypes.c_int), ("rank", ctypes.c_int), ("core_dims", ctypes.c_int64 * MAX_NDIM),
+                ("factors", ctypes.c_void_p * MAX_NDIM), ("core", ctypes.c_void_p)]
 
 
 class Opts(ctypes.Structure):
@@ -147,9 +150,11 @@ def _stream(stream) -> Optional[int]:
 
 
 def _dense(X) -> Dense:
+    if X.dim() > MAX_NDIM:
+        raise ValueError(f"tensors of order {X.dim()} exceed the largest supported order {MAX_NDIM}")
     d = Dense()
     d.ndim = X.dim()
-    for n in range(min(4, X.dim())):
+    for n in range(X.dim()):
         d.dims[n] = X.shape[n]
     d.X = _f32(X, "X")
     return d
@@ -166,6 +171,8 @@ def _model(factors: Sequence, core=None) -> Model:
         for n in range(core.dim()):
             m.core_dims[n] = core.shape[n]
         m.core = _f32(core, "core")
+    if len(factors) > MAX_NDIM:
+        raise ValueError(f"at most {MAX_NDIM} factors")
     for n, A in enumerate(factors):
         if A.dim() != 2:
             raise ValueError("factors must be matrices")
@@ -309,6 +316,8 @@ class Context:
         """Workspace bytes of one call on a tensor of shape `dims` (op 0 update,
         1 jcomm_outer, 2 objective): CP of `rank`, or Tucker with `core_dims`.
         Needs no buffers; 0 if the arguments are invalid."""
+        if len(dims) > MAX_NDIM:
+            return 0
         d = Dense()
         d.ndim = len(dims)
         for n, v in enumerate(dims):

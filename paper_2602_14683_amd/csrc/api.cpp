@@ -35,10 +35,17 @@ int check_opts(const comm_opts* o, bool need_L) {
 // Shape of a dense tensor only (the size query needs no buffers).
 int check_dense_shape(const comm_dense* x) {
   if (!x) return fail(COMM_EINVAL, "x is NULL");
-  if (x->ndim < 1 || x->ndim > 4) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
+  if (x->ndim < 1 || x->ndim > COMM_MAX_NDIM) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
   for (int n = 0; n < x->ndim; ++n)
     if (x->dims[n] < 1 || x->dims[n] > (1 << 24)) return fail(COMM_EINVAL, "dims[%d] = %lld", n, (long long)x->dims[n]);
-  if (x->ndim != 3) return fail(COMM_EUNSUPPORTED, "dense tensors of order %d are not supported (3 only)", x->ndim);
+  if (x->ndim < 3) return fail(COMM_EUNSUPPORTED, "dense tensors of order %d are not supported (3 to 5)", x->ndim);
+  if (x->ndim > 3) {
+    // the first N - 2 modes form one mode of the 3-way view
+    int64_t rows = 1;
+    for (int n = 0; n < x->ndim - 2; ++n) rows *= x->dims[n];
+    if (rows > (1 << 24))
+      return fail(COMM_EUNSUPPORTED, "I_1 ... I_%d = %lld exceeds 2^24", x->ndim - 2, (long long)rows);
+  }
   return COMM_OK;
 }
 
@@ -185,7 +192,7 @@ int cp_apply_update(const comm_model* m, const CpWs& w, int n, FView anchor, con
   return COMM_OK;
 }
 
-int cp_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
+int cp3_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
   CpWs w = cp_layout(x, nullptr, false);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
@@ -213,7 +220,7 @@ int cp_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const
   return COMM_OK;
 }
 
-int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
   const bool kl = o->beta == 1.0;
   const bool cache = !kl && o->cache_pq;
   CpWs w = cp_layout(x, nullptr, cache);
@@ -344,7 +351,7 @@ int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts*
   return COMM_OK;
 }
 
-int cp_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
+int cp3_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
                  hipStream_t st) {
   CpWs w = cp_layout(x, nullptr, false);
   int rc = ensure_ws(ctx, w.bytes, st);
@@ -357,6 +364,410 @@ int cp_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const 
   if ((rc = run_pass(ctx, a, w.g, beta_class_of(o->beta), false, st))) return rc;
   HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, out, st));
   return COMM_OK;
+}
+
+// ---------------------------------------------------------------------------------------- CP dense, order 4 and 5
+
+// The caller's order-N tensor (N = 4, 5) as the 3-way tensor
+// (I_1 ... I_G) x I_{N-1} x I_N, G = N - 2, without a copy: mode 0 of the view
+// is the super mode with factor KR(A^(1), ..., A^(G)) (KrArgs); view modes 1
+// and 2 are caller modes N-2 and N-1 (0-based).
+constexpr int kGrpPad = 16;
+
+struct CpnWs {
+  int N, G;
+  int dims[kMaxModes];
+  int grp_p[kMaxGroup];      // padded rows of the grouped modes
+  comm_dense xv;             // the 3-way view
+  CpWs w;                    // its workspace; w.ref.pad[0] etc. hold super factors
+  float* gref[kMaxGroup];    // beta != 1 J-CoMM: padded reference grouped blocks,
+  float* gcur[kMaxGroup];    //   the current inner iterate,
+  float* gx1[kMaxGroup];     //   and chi_1 / chi_2 of it
+  float* gx2[kMaxGroup];
+  float* fnum[kMaxGroup];    // folded numerators / denominators [grp_p][32]
+  float* fden[kMaxGroup];
+  float* gc[kMaxGroup];      // beta = 1 J-CoMM: c = A~ * Num_J and its column statistics
+  float* gstats[kMaxGroup];
+  size_t bytes;
+};
+
+CpnWs cpn_layout(const comm_dense* x, char* base, bool cache) {
+  CpnWs v = {};
+  v.N = x->ndim;
+  v.G = v.N - 2;
+  int64_t rows = 1;
+  for (int n = 0; n < v.N; ++n) v.dims[n] = (int)x->dims[n];
+  for (int m = 0; m < v.G; ++m) {
+    v.grp_p[m] = (v.dims[m] + kGrpPad - 1) / kGrpPad * kGrpPad;
+    rows *= x->dims[m];
+  }
+  v.xv.ndim = 3;
+  v.xv.dims[0] = rows;
+  v.xv.dims[1] = x->dims[v.N - 2];
+  v.xv.dims[2] = x->dims[v.N - 1];
+  v.xv.X = x->X;
+  v.w = cp_layout(&v.xv, base, cache);
+  Carve cv;
+  cv.base = base;
+  cv.off = v.w.bytes;
+  for (int m = 0; m < v.G; ++m) {
+    const size_t n = (size_t)v.grp_p[m] * kRP;
+    for (float** p : {&v.gref[m], &v.gcur[m], &v.gx1[m], &v.gx2[m], &v.fnum[m], &v.fden[m], &v.gc[m]})
+      *p = cv.take<float>(n);
+    v.gstats[m] = cv.take<float>((size_t)((v.grp_p[m] + kSlotRows - 1) / kSlotRows) * 96);
+  }
+  v.bytes = cv.off + 256;
+  return v;
+}
+
+size_t cp_ws_bytes(const comm_dense* x, bool cache) {
+  return x->ndim == 3 ? cp_layout(x, nullptr, cache).bytes : cpn_layout(x, nullptr, cache).bytes;
+}
+
+// Super factor(s) of the view from G grouped views each: out0 = KR(src0), and
+// out1 = KR(src1) if src1 is given.
+int cpn_kr(const CpnWs& v, const FView* src0, float* out0, const FView* src1, float* out1, hipStream_t st) {
+  KrArgs k = {};
+  k.G = v.G;
+  for (int m = 0; m < v.G; ++m) {
+    k.dims[m] = v.dims[m];
+    k.f[0][m] = src0[m];
+    if (src1) k.f[1][m] = src1[m];
+  }
+  k.rows = (int)v.xv.dims[0];
+  k.rows_p = v.w.rows_p[0];
+  k.nout = src1 ? 2 : 1;
+  k.out[0] = out0;
+  k.out[1] = out1;
+  HIP_TRY(launch_kr(k, st));
+  return COMM_OK;
+}
+
+// Numerators (weights wn) and, with wd, denominators (weights wd) of the
+// grouped modes in `modes` from the super mode's partial slots of the last pass.
+int cpn_fold(const CpnWs& v, const int* modes, int count, const FView* wn, const FView* wd, hipStream_t st) {
+  FoldArgs f = {};
+  f.G = v.G;
+  for (int m = 0; m < v.G; ++m) f.dims[m] = v.dims[m];
+  auto job = [&](int n, const float* part, const FView* wts, float* out) {
+    FoldJob& J = f.job[f.njobs++];
+    J.mode = n;
+    J.part = part;
+    J.slots = v.w.g.m1_slots();
+    J.rows_total = v.w.g.Ip;
+    for (int m = 0; m < v.G; ++m) J.w[m] = wts[m];
+    J.out = out;
+    J.rows_p = v.grp_p[n];
+  };
+  for (int q = 0; q < count; ++q) {
+    job(modes[q], v.w.m1n, wn, v.fnum[modes[q]]);
+    if (wd) job(modes[q], v.w.m1d, wd, v.fden[modes[q]]);
+  }
+  HIP_TRY(launch_fold(f, st));
+  return COMM_OK;
+}
+
+// Numerator source of caller mode n: folded buffer (grouped) or the view's slots.
+void cpn_num_src(const CpnWs& v, int n, bool den, const float** part, int* slots, int* rows_total, int* rows_p) {
+  if (n < v.G) {
+    *part = den ? v.fden[n] : v.fnum[n];
+    *slots = 1;
+    *rows_total = v.grp_p[n];
+    *rows_p = v.grp_p[n];
+  } else {
+    const int q = n - v.G + 1;
+    slots_of(v.w, q, den, part, slots, rows_total);
+    *rows_p = v.w.rows_p[q];
+  }
+}
+
+// Block update of caller mode n: max(anchor * (Num/Den)^gamma, eps), into the
+// caller's factor and, if given, a padded copy.  With `closed` (beta = 1) Den
+// is the product of the column sums of the other N - 1 blocks `cur`.
+int cpn_apply(const CpnWs& v, comm_model* m, int n, const FView* closed, FView anchor, float* out_pad, float gamma,
+              float eps, hipStream_t st) {
+  SlotUpdateArgs u = {};
+  u.njobs = 1;
+  SlotJob& J = u.job[0];
+  J.mode = kSlotUpdate;
+  cpn_num_src(v, n, false, &J.num_part, &J.num_slots, &J.rows_total, &J.rows_p);
+  if (closed) {
+    FView others[kMaxModes];
+    int rows[kMaxModes], k = 0;
+    for (int q = 0; q < v.N; ++q)
+      if (q != n) {
+        others[k] = closed[q];
+        rows[k++] = v.dims[q];
+      }
+    HIP_TRY(launch_colsum_prod(others, rows, k, v.w.dprod, st));
+    J.den_closed = v.w.dprod;
+  } else {
+    int rt, rp;
+    cpn_num_src(v, n, true, &J.den_part, &J.den_slots, &rt, &rp);
+  }
+  J.rows = v.dims[n];
+  J.cols = m->rank;
+  J.anchor = anchor;
+  J.gamma = gamma;
+  J.eps = eps;
+  J.out_pad = out_pad;
+  J.out_user = m->factors[n];
+  J.ld_user = m->rank;
+  HIP_TRY(launch_slot_update(u, st));
+  return COMM_OK;
+}
+
+int cpn_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
+                  hipStream_t st) {
+  CpnWs v = cpn_layout(x, nullptr, false);
+  int rc = ensure_ws(ctx, v.bytes, st);
+  if (rc) return rc;
+  v = cpn_layout(x, ctx->ws, false);
+  FView user[kMaxModes];
+  for (int n = 0; n < v.N; ++n) user[n] = user_view(m, n);
+  if ((rc = cpn_kr(v, user, v.w.ref.pad[0], nullptr, nullptr, st))) return rc;
+  CpPassArgs a = base_pass(&v.xv, v.w, o);
+  a.r = FSet{pad_view(v.w.ref.pad[0]), user[v.N - 2], user[v.N - 1]};
+  a.n = a.r;
+  a.want_obj = 1;
+  if ((rc = run_pass(ctx, a, v.w.g, beta_class_of(o->beta), false, st))) return rc;
+  HIP_TRY(launch_sum_f64(v.w.obj_part, v.w.g.wgs(), nullptr, out, st));
+  return COMM_OK;
+}
+
+// B-CoMM: every block sees the blocks updated before it, so each block has its
+// own pass over X, from the super factor of the current grouped blocks.
+int cpn_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
+  CpnWs v = cpn_layout(x, nullptr, false);
+  int rc = ensure_ws(ctx, v.bytes, st);
+  if (rc) return rc;
+  v = cpn_layout(x, ctx->ws, false);
+  const bool kl = o->beta == 1.0;
+  const int bc = beta_class_of(o->beta);
+  const int first = block < 0 ? 0 : block, last = block < 0 ? v.N - 1 : block;
+  FView cur[kMaxModes];
+  for (int n = 0; n < v.N; ++n) cur[n] = user_view(m, n);
+  bool super_valid = false;
+  for (int n = first; n <= last; ++n) {
+    if (!super_valid && (rc = cpn_kr(v, cur, v.w.ref.pad[0], nullptr, nullptr, st))) return rc;
+    super_valid = true;
+    const int q = n < v.G ? 0 : n - v.G + 1;
+    CpPassArgs a = base_pass(&v.xv, v.w, o);
+    a.r = FSet{pad_view(v.w.ref.pad[0]), cur[v.N - 2], cur[v.N - 1]};
+    a.n = a.r;
+    a.d = a.r;
+    a.want_v = q < 2;
+    a.want_m3 = q == 2;
+    if ((rc = run_pass(ctx, a, v.w.g, bc, !kl, st))) return rc;
+    if (n < v.G && (rc = cpn_fold(v, &n, 1, cur, kl ? nullptr : cur, st))) return rc;
+    if ((rc = cpn_apply(v, m, n, kl ? cur : nullptr, cur[n], nullptr, gamma_of(o->beta), (float)o->eps, st)))
+      return rc;
+    if (n < v.G) super_valid = false;  // a grouped block changed
+  }
+  return COMM_OK;
+}
+
+int cpn_chi(const CpnWs& v, float beta, const int* modes, int count, hipStream_t st) {
+  ChiArgs ca = {};
+  ca.beta = beta;
+  for (int q = 0; q < count; ++q) {
+    const int n = modes[q];
+    const int f = ca.nf++;
+    if (n < v.G) {
+      ca.cur[f] = v.gcur[n];
+      ca.ref[f] = v.gref[n];
+      ca.rows_p[f] = v.grp_p[n];
+      ca.x1[f] = v.gx1[n];
+      ca.x2[f] = v.gx2[n];
+    } else {
+      const int p = n - v.G + 1;
+      ca.cur[f] = v.w.cur.pad[p];
+      ca.ref[f] = v.w.ref.pad[p];
+      ca.rows_p[f] = v.w.rows_p[p];
+      ca.x1[f] = v.w.num.pad[p];
+      ca.x2[f] = v.w.den.pad[p];
+    }
+  }
+  HIP_TRY(launch_chi(ca, st));
+  return COMM_OK;
+}
+
+int cpn_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+  const bool kl = o->beta == 1.0;
+  const bool cache = !kl && o->cache_pq;
+  CpnWs v = cpn_layout(x, nullptr, cache);
+  int rc = ensure_ws(ctx, v.bytes, st);
+  if (rc) return rc;
+  v = cpn_layout(x, ctx->ws, cache);
+  const CpWs& w = v.w;
+  const int N = v.N, G = v.G;
+  const int bc = beta_class_of(o->beta);
+  const float eps = (float)o->eps;
+
+  if (kl) {
+    // One reference pass gives the super mode's numerator and those of the
+    // last two modes; the folds give the grouped modes'.  Then the closed-form
+    // inner loop of the 3-way path, over all N blocks.
+    FView ref[kMaxModes];
+    for (int n = 0; n < N; ++n) ref[n] = user_view(m, n);
+    if ((rc = cpn_kr(v, ref, w.ref.pad[0], nullptr, nullptr, st))) return rc;
+    CpPassArgs a = base_pass(&v.xv, w, o);
+    a.r = FSet{pad_view(w.ref.pad[0]), ref[N - 2], ref[N - 1]};
+    a.n = a.r;
+    a.want_v = 1;
+    a.want_m3 = 1;
+    a.want_obj = obj != nullptr;
+    if ((rc = run_pass(ctx, a, w.g, bc, false, st))) return rc;
+    int modes[kMaxGroup];
+    for (int n = 0; n < G; ++n) modes[n] = n;
+    if ((rc = cpn_fold(v, modes, G, ref, nullptr, st))) return rc;
+    SlotUpdateArgs su = {};
+    su.njobs = N;
+    KlLoopArgs k = {};
+    k.N = N;
+    k.R = m->rank;
+    k.L = o->inner_sweeps;
+    k.eps = eps;
+    for (int n = 0; n < N; ++n) {
+      SlotJob& J = su.job[n];
+      J.mode = kSlotScale;
+      cpn_num_src(v, n, false, &J.num_part, &J.num_slots, &J.rows_total, &J.rows_p);
+      J.rows = v.dims[n];
+      J.cols = m->rank;
+      J.anchor = ref[n];
+      J.out_pad = n < G ? v.gc[n] : w.c[n - G + 1];
+      J.stats = n < G ? v.gstats[n] : w.stats[n - G + 1];
+      k.c[n] = J.out_pad;
+      k.stats[n] = J.stats;
+      k.nblk[n] = (J.rows_p + kSlotRows - 1) / kSlotRows;
+      k.rows[n] = v.dims[n];
+      k.user[n] = m->factors[n];
+    }
+    if (obj) {
+      k.obj_part = w.obj_part;
+      k.obj_n = w.g.wgs();
+      k.obj_out = obj;
+    }
+    HIP_TRY(launch_slot_update(su, st));
+    HIP_TRY(launch_kl_apply(k, st));
+    return COMM_OK;
+  }
+
+  // beta != 1: padded reference and inner-iterate copies of every block; the
+  // reference super factor from the reference grouped blocks.
+  {
+    PadArgs p = {};
+    p.nf = N;
+    for (int n = 0; n < N; ++n) {
+      p.cols[n] = m->rank;
+      p.ld[n] = m->rank;
+      p.src[n] = m->factors[n];
+      p.rows[n] = v.dims[n];
+      if (n < G) {
+        p.rows_p[n] = v.grp_p[n];
+        p.dst[n] = v.gref[n];
+        p.dst2[n] = v.gcur[n];
+      } else {
+        p.rows_p[n] = w.rows_p[n - G + 1];
+        p.dst[n] = w.ref.pad[n - G + 1];
+        p.dst2[n] = w.cur.pad[n - G + 1];
+      }
+    }
+    HIP_TRY(launch_pad_factors(p, st));
+  }
+  FView gref[kMaxGroup], gx1[kMaxGroup], gx2[kMaxGroup];
+  for (int n = 0; n < G; ++n) {
+    gref[n] = pad_view(v.gref[n]);
+    gx1[n] = pad_view(v.gx1[n]);
+    gx2[n] = pad_view(v.gx2[n]);
+  }
+  if ((rc = cpn_kr(v, gref, w.ref.pad[0], nullptr, nullptr, st))) return rc;
+  const FSet ref = pad_set(w.ref);
+  bool obj_pending = obj != nullptr;
+  if (cache) {
+    CpPassArgs a = base_pass(&v.xv, w, o);
+    a.r = ref;
+    a.n = ref;
+    a.cache_mode = 1;
+    a.Pw = w.Pc;
+    a.Qw = w.Qc;
+    a.want_obj = obj_pending;
+    if ((rc = run_pass(ctx, a, w.g, bc, false, st))) return rc;
+    if (obj_pending) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+    obj_pending = false;
+  }
+  auto pass = [&](CpPassArgs& a) -> int {
+    if (cache) {
+      a.cache_mode = 2;
+      a.Pc = w.Pc;
+      a.Qc = w.Qc;
+    } else {
+      a.want_obj = obj_pending;
+    }
+    int r = run_pass(ctx, a, w.g, bc, true, st);
+    if (r) return r;
+    if (obj_pending) {
+      HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+      obj_pending = false;
+    }
+    return COMM_OK;
+  };
+  const int last2[2] = {N - 2, N - 1};
+  for (int l = 0; l < o->inner_sweeps; ++l) {
+    // grouped blocks: one pass contracts P~ and Q~ with chi of the last two
+    // blocks (unchanged while the grouped blocks are updated), then a fold per block
+    if ((rc = cpn_chi(v, (float)o->beta, last2, 2, st))) return rc;
+    {
+      CpPassArgs a = base_pass(&v.xv, w, o);
+      a.r = ref;
+      a.n = FSet{ref.A, pad_view(w.num.pad[1]), pad_view(w.num.pad[2])};
+      a.d = FSet{ref.A, pad_view(w.den.pad[1]), pad_view(w.den.pad[2])};
+      a.want_v = 1;
+      if ((rc = pass(a))) return rc;
+    }
+    for (int n = 0; n < G; ++n) {
+      int others[kMaxGroup], k = 0;
+      for (int q = 0; q < G; ++q)
+        if (q != n) others[k++] = q;
+      if ((rc = cpn_chi(v, (float)o->beta, others, k, st))) return rc;
+      if ((rc = cpn_fold(v, &n, 1, gx1, gx2, st))) return rc;
+      if ((rc = cpn_apply(v, m, n, nullptr, gref[n], v.gcur[n], gamma_of(o->beta), eps, st))) return rc;
+    }
+    // the last two blocks: the super factors of chi_1 and chi_2 of the grouped blocks
+    int all[kMaxGroup];
+    for (int q = 0; q < G; ++q) all[q] = q;
+    if ((rc = cpn_chi(v, (float)o->beta, all, G, st))) return rc;
+    if ((rc = cpn_kr(v, gx1, w.num.pad[0], gx2, w.den.pad[0], st))) return rc;
+    for (int q = 1; q <= 2; ++q) {
+      if (q == 2 && (rc = cpn_chi(v, (float)o->beta, &last2[0], 1, st))) return rc;  // block N-2 just changed
+      CpPassArgs a = base_pass(&v.xv, w, o);
+      a.r = ref;
+      a.n = pad_set(w.num);
+      a.d = pad_set(w.den);
+      if (q == 1) { a.n.B = ref.B; a.d.B = ref.B; }
+      else { a.n.C = ref.C; a.d.C = ref.C; }
+      a.want_v = q == 1;
+      a.want_m3 = q == 2;
+      if ((rc = pass(a))) return rc;
+      const int n = G - 1 + q;
+      if ((rc = cpn_apply(v, m, n, nullptr, q == 1 ? ref.B : ref.C, w.cur.pad[q], gamma_of(o->beta), eps, st)))
+        return rc;
+    }
+  }
+  return COMM_OK;
+}
+
+int cp_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
+  return x->ndim == 3 ? cp3_bcomm(ctx, x, m, block, o, st) : cpn_bcomm(ctx, x, m, block, o, st);
+}
+
+int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+  return x->ndim == 3 ? cp3_jcomm(ctx, x, m, o, obj, st) : cpn_jcomm(ctx, x, m, o, obj, st);
+}
+
+int cp_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
+                 hipStream_t st) {
+  return x->ndim == 3 ? cp3_objective(ctx, x, m, o, out, st) : cpn_objective(ctx, x, m, o, out, st);
 }
 
 template <class F>
@@ -502,7 +913,7 @@ int jcomm_check(const comm_dense* x, const comm_model* model, const comm_opts* o
 }
 
 size_t jcomm_ws_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts) {
-  if (model->kind == COMM_CP) return cp_layout(x, nullptr, opts->beta != 1.0 && opts->cache_pq).bytes;
+  if (model->kind == COMM_CP) return cp_ws_bytes(x, opts->beta != 1.0 && opts->cache_pq);
   return tucker_workspace_bytes(x, model, opts, 1);
 }
 
@@ -587,12 +998,12 @@ std::vector<int64_t> batch_key(const std::vector<BatchItem>& items, const char* 
   word((int64_t)(intptr_t)ws);
   for (const BatchItem& it : items) {
     word(it.x.ndim);
-    for (int n = 0; n < 4; ++n) word(it.x.dims[n]);
+    for (int n = 0; n < COMM_MAX_NDIM; ++n) word(it.x.dims[n]);
     word((int64_t)(intptr_t)it.x.X);
     word(it.m.kind);
     word(it.m.rank);
-    for (int n = 0; n < 4; ++n) word(it.m.core_dims[n]);
-    for (int n = 0; n < 4; ++n) word((int64_t)(intptr_t)it.m.factors[n]);
+    for (int n = 0; n < COMM_MAX_NDIM; ++n) word(it.m.core_dims[n]);
+    for (int n = 0; n < COMM_MAX_NDIM; ++n) word((int64_t)(intptr_t)it.m.factors[n]);
     word((int64_t)(intptr_t)it.m.core);
     dbl(it.o.beta);
     dbl(it.o.eps);
@@ -767,10 +1178,8 @@ int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
 
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op) {
   if (check_dense_shape(x) || !model || !opts) return 0;
-  if (model->kind == COMM_CP) {
-    const bool cache = op == 1 && opts->beta != 1.0 && opts->cache_pq;
-    return cp_layout(x, nullptr, cache).bytes;
-  }
+  if (model->kind == COMM_CP) return cp_ws_bytes(x, op == 1 && opts->beta != 1.0 && opts->cache_pq);
+  if (x->ndim != 3) return 0;
   return tucker_workspace_bytes(x, model, opts, op);
 }
 

@@ -12,6 +12,10 @@ namespace comm {
 // workspace are [rows_padded][32] row-major with zero padding.
 constexpr int kRP = 32;
 
+// Largest tensor order of the dense CP path (orders 4 and 5 run through a
+// 3-way view, see KrArgs below).
+constexpr int kMaxModes = 5;
+
 // ----------------------------------------------------------------------------------------
 // Dense 3-way CP pass
 // ----------------------------------------------------------------------------------------
@@ -83,14 +87,14 @@ hipError_t launch_cp_pass(const CpPassArgs& a, const CpGrid& g, int beta_class, 
 // in [rows_p][32]; optional transposed copy dstT[f][c][row] and second copies.
 struct PadArgs {
   int nf;
-  int cols[4], ld[4];      // valid columns and row stride of each source
-  const float* src[4];
-  int rows[4];
-  int rows_p[4];
-  float* dst[4];
-  float* dstT[4];
-  float* dst2[4];
-  float* dst2T[4];
+  int cols[kMaxModes], ld[kMaxModes];      // valid columns and row stride of each source
+  const float* src[kMaxModes];
+  int rows[kMaxModes];
+  int rows_p[kMaxModes];
+  float* dst[kMaxModes];
+  float* dstT[kMaxModes];
+  float* dst2[kMaxModes];
+  float* dst2T[kMaxModes];
 };
 hipError_t launch_pad_factors(const PadArgs& a, hipStream_t s);
 
@@ -103,13 +107,13 @@ hipError_t launch_colsum_prod(const FView* F, const int* rows, int nf, float* pr
 struct ChiArgs {
   int nf;
   float beta;
-  const float* cur[4];
-  const float* ref[4];
-  int rows_p[4];
-  float* x1[4];
-  float* x2[4];
-  float* x1T[4];   // optional transposed copies [32][rows_p]
-  float* x2T[4];
+  const float* cur[kMaxModes];
+  const float* ref[kMaxModes];
+  int rows_p[kMaxModes];
+  float* x1[kMaxModes];
+  float* x2[kMaxModes];
+  float* x1T[kMaxModes];   // optional transposed copies [32][rows_p]
+  float* x2T[kMaxModes];
 };
 hipError_t launch_chi(const ChiArgs& a, hipStream_t s);
 
@@ -125,12 +129,12 @@ hipError_t launch_chi(const ChiArgs& a, hipStream_t s);
 struct KlLoopArgs {
   int N, R, L;
   float eps;
-  const float* c[4];       // [rows_p][32]
-  const float* stats[4];   // [nblk][3][32]
-  int nblk[4];
-  int rows[4];
-  float* cur_pad[4];       // optional padded outputs [rows_p][32]
-  float* user[4];          // caller buffers (row stride R)
+  const float* c[kMaxModes];       // [rows_p][32]
+  const float* stats[kMaxModes];   // [nblk][3][32]
+  int nblk[kMaxModes];
+  int rows[kMaxModes];
+  float* cur_pad[kMaxModes];       // optional padded outputs [rows_p][32]
+  float* user[kMaxModes];          // caller buffers (row stride R)
   const double* obj_part;  // optional: objective partials to sum into *obj_out
   int64_t obj_n;
   double* obj_out;         // written if not NULL
@@ -165,9 +169,50 @@ struct SlotJob {
 };
 struct SlotUpdateArgs {
   int njobs;
-  SlotJob job[4];
+  SlotJob job[kMaxModes];
 };
 hipError_t launch_slot_update(const SlotUpdateArgs& a, hipStream_t s);
+
+// Order-N CP (N = 4, 5) through a 3-way view.  Modes 1..G (G = N - 2) are
+// fused into one super mode s = (i_1, ..., i_G), row-major (i_1 slowest), so
+// that the caller's tensor, unchanged in memory, is the 3-way tensor
+// (I_1 ... I_G) x I_{N-1} x I_N, and the CP model with factors
+// (KR, A^(N-1), A^(N)) rebuilds it exactly, KR the row-wise (Khatri-Rao)
+// product KR[s, r] = prod_{m < G} A^(m)[i_m, r] (Sec. 3.3).
+constexpr int kMaxGroup = kMaxModes - 2;
+
+// KR of G factors into [rows_p][32] (zero rows and columns beyond the valid
+// extent); up to two products per launch.
+struct KrArgs {
+  int G;
+  int dims[kMaxGroup];
+  int rows, rows_p;        // prod dims, padded rows written
+  int nout;
+  FView f[2][kMaxGroup];
+  float* out[2];
+};
+hipError_t launch_kr(const KrArgs& a, hipStream_t s);
+
+// Numerator (or denominator) of a grouped mode from the super mode's partial
+// slots: out[i, r] = sum_{s : s_mode = i} (sum_slot part[slot][s][r])
+// * prod_{m != mode} W^(m)[s_m, r] (CPContr^(n) of Sec. 6.1 taken in two
+// steps: over modes N-1 and N in the pass, over the other grouped modes here).
+// Rows dims[mode]..rows_p-1 are written as zero.  Fixed order: deterministic.
+struct FoldJob {
+  int mode;
+  const float* part;
+  int slots, rows_total;   // part is [slots][rows_total][32]
+  FView w[kMaxGroup];      // entry `mode` unused
+  float* out;              // [rows_p][32]
+  int rows_p;
+};
+struct FoldArgs {
+  int G;
+  int dims[kMaxGroup];
+  int njobs;
+  FoldJob job[2 * kMaxGroup];
+};
+hipError_t launch_fold(const FoldArgs& a, hipStream_t s);
 
 // Extrapolation of the parameter blocks (contiguous caller buffers, `count`
 // entries each).  launch_extrap_alpha writes alpha_t to alpha[0]; launch_

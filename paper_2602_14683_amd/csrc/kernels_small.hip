@@ -40,15 +40,15 @@ hipError_t launch_pad_factors(const PadArgs& a, hipStream_t s) {
 // Column sums: one workgroup, 8 row groups x 32 columns, fixed order.
 
 struct ColsumArgs {
-  FView F[4];
-  int rows[4];
+  FView F[kMaxModes];
+  int rows[kMaxModes];
   int nf;
   float* prod;       // prod[c] = product over the nf factors of the column sums
 };
 
 __global__ void __launch_bounds__(256) colsum_prod_kernel(ColsumArgs a) {
   __shared__ float part[8 * 32];
-  __shared__ float res[4][32];
+  __shared__ float res[kMaxModes][32];
   const int t = threadIdx.x;
   const int c = t & 31, g = t >> 5;
   for (int f = 0; f < a.nf; ++f) {
@@ -166,18 +166,18 @@ hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, d
 // den_last.  Every workgroup of kl_apply runs it on the same data in the same
 // order, so all of them agree bitwise without synchronising.
 __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
-  __shared__ float red[12][32][33];
-  __shared__ float S[4][32], T[4][32], Cmin[4][32];
+  __shared__ float red[3 * kMaxModes][32][33];
+  __shared__ float S[kMaxModes][32], T[kMaxModes][32], Cmin[kMaxModes][32];
   __shared__ double lds64[1024];
   const int t = threadIdx.x;
   const int c = t & 31, g = t >> 5;
   int nblk_max = 0;
 #pragma unroll
-  for (int n = 0; n < 4; ++n)
+  for (int n = 0; n < kMaxModes; ++n)
     if (n < a.N) nblk_max = max(nblk_max, a.nblk[n]);
-  float acc[4][3];
+  float acc[kMaxModes][3];
 #pragma unroll
-  for (int n = 0; n < 4; ++n) {
+  for (int n = 0; n < kMaxModes; ++n) {
     acc[n][0] = 0.0f;
     acc[n][1] = 3.402823e38f;
     acc[n][2] = 0.0f;
@@ -186,11 +186,11 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
   if (a.obj_part)
     for (int64_t e = t; e < a.obj_n; e += 1024) objs += a.obj_part[e];
   for (int b0 = g; b0 < nblk_max; b0 += 4 * 32) {
-    float v[4][4][3];
+    float v[4][kMaxModes][3];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int n = 0; n < 4; ++n)
+      for (int n = 0; n < kMaxModes; ++n)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const int b = b0 + 32 * u;
@@ -200,7 +200,7 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
+      for (int n = 0; n < kMaxModes; ++n) {
         acc[n][0] += v[u][n][0];
         acc[n][1] = fminf(acc[n][1], v[u][n][1]);
         acc[n][2] += v[u][n][2];
@@ -208,11 +208,11 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
   }
   lds64[t] = objs;
 #pragma unroll
-  for (int n = 0; n < 4; ++n)
+  for (int n = 0; n < kMaxModes; ++n)
 #pragma unroll
     for (int k = 0; k < 3; ++k) red[3 * n + k][g][c] = acc[n][k];
   __syncthreads();
-  if (t < 12 * 32) {
+  if (t < 3 * kMaxModes * 32) {
     const int q = t >> 5;
     const int n = q / 3, k = q % 3;
     float s = red[q][0][c];
@@ -246,9 +246,9 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
   if (t < 64) {
     const int col = t & 31;
     const bool real = col < a.R;
-    float Sr[4], Tr[4], Cr[4], Dl[4];
+    float Sr[kMaxModes], Tr[kMaxModes], Cr[kMaxModes], Dl[kMaxModes];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int n = 0; n < kMaxModes; ++n) {
       Sr[n] = n < a.N ? S[n][col] : 1.0f;
       Tr[n] = n < a.N ? T[n][col] : 0.0f;
       Cr[n] = n < a.N ? Cmin[n][col] : 0.0f;
@@ -256,11 +256,11 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
     }
     for (int l = 0; l < a.L; ++l) {
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
+      for (int n = 0; n < kMaxModes; ++n) {
         if (n >= a.N) break;
         float d = 1.0f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < kMaxModes; ++m)
           if (m != n && m < a.N) d *= Sr[m];
         const bool clip = real && (Cr[n] < a.eps * d);
         float snew = real ? Tr[n] / d : 0.0f;
@@ -280,7 +280,7 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
     }
     if (t < 32) {
 #pragma unroll
-      for (int n = 0; n < 4; ++n)
+      for (int n = 0; n < kMaxModes; ++n)
         if (n < a.N) den_last[n][col] = Dl[n];
     }
   }
@@ -289,7 +289,7 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
 // A^(n) = max(c^(n) / Den_last^(n), eps) for all modes; each workgroup first
 // runs the recurrence itself.
 __global__ void __launch_bounds__(1024) kl_apply_kernel(KlLoopArgs a) {
-  __shared__ float den_last[4][32];
+  __shared__ float den_last[kMaxModes][32];
   kl_recurrence(a, den_last);
   __syncthreads();
   int64_t total = 0;

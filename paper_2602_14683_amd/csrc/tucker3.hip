@@ -603,6 +603,7 @@ int tucker_check_model(const comm_model* m, const comm_dense* x) {
   if (!m) return fail(COMM_EINVAL, "model is NULL");
   if (m->kind != COMM_TUCKER) return fail(COMM_EINVAL, "model kind is not Tucker");
   if (!m->core) return fail(COMM_EINVAL, "core is NULL");
+  if (x->ndim != 3) return fail(COMM_EUNSUPPORTED, "dense Tucker of order %d is not supported (3 only)", x->ndim);
   for (int n = 0; n < x->ndim; ++n) {
     if (!m->factors[n]) return fail(COMM_EINVAL, "factors[%d] is NULL", n);
     if (m->core_dims[n] < 1) return fail(COMM_EINVAL, "core_dims[%d] = %lld", n, (long long)m->core_dims[n]);

@@ -36,3 +36,45 @@ def test_binding_lists_every_declared_symbol():
     import paper_2602_14683_amd as pkg
     assert sorted(pkg.EXPORTED) == declared_functions()
     assert pkg.load_library() is not None
+
+
+def test_binding_structs_follow_the_header():
+    import paper_2602_14683_amd as pkg
+    text = open(HEADER).read()
+    assert int(re.search(r"#define COMM_MAX_NDIM (\d+)", text).group(1)) == pkg.MAX_NDIM
+    # int + pad + int64[5] + pointer
+    assert ctypes.sizeof(pkg.Dense) == 8 + 8 * pkg.MAX_NDIM + 8
+    assert ctypes.sizeof(pkg.Model) == 8 + 8 * pkg.MAX_NDIM + 8 * pkg.MAX_NDIM + 8
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcomm.so not built")
+def test_workspace_query_by_order():
+    """comm_workspace_bytes is host arithmetic only: orders 3 to 5 of dense CP
+    are accepted, Tucker stays order 3, and an order-N tensor whose first N - 2
+    extents multiply past 2^24 is refused (0)."""
+    import paper_2602_14683_amd as pkg
+    lib = pkg.load_library()
+
+    def ws(dims, rank=0, core=None, beta=1.0, op=1):
+        d = pkg.Dense()
+        d.ndim = len(dims)
+        for n, v in enumerate(dims):
+            d.dims[n] = v
+        m = pkg.Model()
+        if core is None:
+            m.kind, m.rank = pkg.COMM_CP, rank
+        else:
+            m.kind = pkg.COMM_TUCKER
+            for n, v in enumerate(core):
+                m.core_dims[n] = v
+        o = pkg._opts(beta, 1e-12, None, 1, False)
+        return lib.comm_workspace_bytes(ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), op)
+
+    three = ws((5600, 60, 50), rank=10)
+    four = ws((80, 70, 60, 50), rank=10)
+    assert three > 0 and four > three  # the view's buffers plus the grouped modes'
+    assert ws((6, 5, 7, 30, 40), rank=4, beta=1.5) > 0
+    assert ws((80, 70, 60, 50), core=(10, 9, 8, 7)) == 0
+    assert ws((80, 70, 60), core=(10, 9, 8)) > 0
+    assert ws((4096, 4097, 2, 2), rank=4) == 0
+    assert ws((40, 50), rank=4) == 0
