@@ -288,3 +288,57 @@ def test_order4_cp_updates_decrease_objective(beta):
     for method in ("bcomm", "jcomm"):
         _, trace = cp.run(X, fac, beta, 5, method=method, L=2)
         assert all(b <= a * (1 + 1e-13) for a, b in zip(trace, trace[1:]))
+
+
+# ------------------------------------------------------- order-4 Tucker
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3])
+def test_order4_tucker_contractions_vs_unfolding(n):
+    """The einsum contractions of the order-4 Tucker oracle equal the
+    unfolding / Kronecker identities (Kolda-Bader), a route that shares no code
+    with them."""
+    rng = np.random.default_rng(21)
+    dims, J = (4, 3, 5, 3), (2, 3, 2, 2)
+    T = rng.uniform(0.0, 2.0, size=dims)
+    core = rng.uniform(0.1, 1.0, size=J)
+    fac = [rng.uniform(0.1, 1.0, size=(d, j)) for d, j in zip(dims, J)]
+    others = [fac[m] for m in range(4) if m != n]
+    np.testing.assert_allclose(tucker.factor_contr(T, core, others, n),
+                               unfolding.tucker_factor(T, core, fac, n), rtol=1e-13)
+    np.testing.assert_allclose(tucker.core_contr(T, fac), unfolding.tucker_core(T, fac), rtol=1e-13)
+    np.testing.assert_allclose(tucker.rebuild(core, fac), unfolding.tucker_rebuild(core, fac), rtol=1e-13)
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_planted_order4_tucker_is_fixed_point(beta):
+    d = workloads.planted_exact_tucker(22, (5, 4, 3, 6), (2, 3, 2, 2))
+    for G, fac in (tucker.bcomm_sweep(d.X, d.init_core, d.init_factors, beta),
+                   tucker.jcomm_outer(d.X, d.init_core, d.init_factors, beta, L=2)):
+        np.testing.assert_allclose(G, d.init_core, rtol=1e-12)
+        for a, b in zip(fac, d.init_factors):
+            np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_order4_tucker_updates_decrease_objective(beta):
+    rng = np.random.default_rng(23)
+    dims, J = (5, 4, 3, 6), (2, 3, 2, 2)
+    X = rng.poisson(tucker.rebuild(rng.uniform(0, 1, J), [rng.uniform(0, 1, (d, j)) for d, j in zip(dims, J)])
+                    * 4) + 0.5
+    core = rng.uniform(0.1, 1.0, J)
+    fac = [rng.uniform(0.1, 1.0, (d, j)) for d, j in zip(dims, J)]
+    for method in ("bcomm", "jcomm"):
+        _, _, trace = tucker.run(X, core, fac, beta, 5, method=method, L=2)
+        assert all(b <= a * (1 + 1e-13) for a, b in zip(trace, trace[1:]))
+
+
+def test_kl_mass_conservation_order4_tucker():
+    rng = np.random.default_rng(24)
+    dims, J = (5, 4, 3, 6), (2, 3, 2, 2)
+    X = rng.poisson(3.0, size=dims) + 0.5
+    core = rng.uniform(0.1, 1.0, J)
+    fac = [rng.uniform(0.1, 1.0, (d, j)) for d, j in zip(dims, J)]
+    G, cur = tucker.bcomm_sweep(X, core, fac, 1.0)
+    np.testing.assert_allclose(tucker.rebuild(G, cur).sum(), X.sum(), rtol=1e-13)
+    G, cur = tucker.jcomm_outer(X, core, fac, 1.0, L=2)
+    np.testing.assert_allclose(tucker.rebuild(G, cur).sum(), X.sum(), rtol=1e-13)
