@@ -793,7 +793,9 @@ int model_blocks(const comm_dense* x, const comm_model* m, float** ptr, int64_t*
   int nb = 0;
   if (m->kind == COMM_TUCKER) {
     ptr[nb] = m->core;
-    count[nb++] = m->core_dims[0] * m->core_dims[1] * m->core_dims[2];
+    int64_t entries = 1;
+    for (int n = 0; n < x->ndim; ++n) entries *= m->core_dims[n];
+    count[nb++] = entries;
   }
   for (int n = 0; n < x->ndim; ++n) {
     ptr[nb] = m->factors[n];
@@ -1179,7 +1181,10 @@ int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op) {
   if (check_dense_shape(x) || !model || !opts) return 0;
   if (model->kind == COMM_CP) return cp_ws_bytes(x, op == 1 && opts->beta != 1.0 && opts->cache_pq);
-  if (x->ndim != 3) return 0;
+  if (x->ndim != 3 && x->ndim != 4) return 0;
+  if (x->ndim == 4 && x->dims[0] * x->dims[1] * x->dims[2] > (1 << 24)) return 0;
+  for (int n = 0; n < x->ndim; ++n)
+    if (model->core_dims[n] < 1 || model->core_dims[n] > kRP) return 0;
   return tucker_workspace_bytes(x, model, opts, op);
 }
 
