@@ -342,3 +342,41 @@ def test_kl_mass_conservation_order4_tucker():
     np.testing.assert_allclose(tucker.rebuild(G, cur).sum(), X.sum(), rtol=1e-13)
     G, cur = tucker.jcomm_outer(X, core, fac, 1.0, L=2)
     np.testing.assert_allclose(tucker.rebuild(G, cur).sum(), X.sum(), rtol=1e-13)
+
+
+# ------------------------------------------------------- order-5 Tucker
+
+@pytest.mark.parametrize("n", [0, 2, 4])
+def test_order5_tucker_contractions_vs_unfolding(n):
+    rng = np.random.default_rng(31)
+    dims, J = (3, 4, 2, 3, 4), (2, 2, 1, 2, 3)
+    T = rng.uniform(0.0, 2.0, size=dims)
+    core = rng.uniform(0.1, 1.0, size=J)
+    fac = [rng.uniform(0.1, 1.0, size=(d, j)) for d, j in zip(dims, J)]
+    others = [fac[m] for m in range(5) if m != n]
+    np.testing.assert_allclose(tucker.factor_contr(T, core, others, n),
+                               unfolding.tucker_factor(T, core, fac, n), rtol=1e-13)
+    np.testing.assert_allclose(tucker.core_contr(T, fac), unfolding.tucker_core(T, fac), rtol=1e-13)
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_planted_order5_tucker_is_fixed_point(beta):
+    d = workloads.planted_exact_tucker(32, (4, 3, 2, 3, 5), (2, 2, 1, 2, 2))
+    for G, fac in (tucker.bcomm_sweep(d.X, d.init_core, d.init_factors, beta),
+                   tucker.jcomm_outer(d.X, d.init_core, d.init_factors, beta, L=2)):
+        np.testing.assert_allclose(G, d.init_core, rtol=1e-12)
+        for a, b in zip(fac, d.init_factors):
+            np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 1.5])
+def test_order5_tucker_updates_decrease_objective(beta):
+    rng = np.random.default_rng(33)
+    dims, J = (4, 3, 2, 3, 5), (2, 2, 1, 2, 2)
+    X = rng.poisson(tucker.rebuild(rng.uniform(0, 1, J), [rng.uniform(0, 1, (d, j)) for d, j in zip(dims, J)])
+                    * 4) + 0.5
+    core = rng.uniform(0.1, 1.0, J)
+    fac = [rng.uniform(0.1, 1.0, (d, j)) for d, j in zip(dims, J)]
+    for method in ("bcomm", "jcomm"):
+        _, _, trace = tucker.run(X, core, fac, beta, 4, method=method, L=2)
+        assert all(b <= a * (1 + 1e-13) for a, b in zip(trace, trace[1:]))
