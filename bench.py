@@ -17,6 +17,8 @@ stream), and the FP64 oracle timed on the host cores on a bounded sample.
   python bench.py --workload tucker [--beta 0|1.5]   # 200^3 Tucker, 16^3 core, J-CoMM L = 1
   python bench.py --workload coo                     # 3.3M-nonzero 4-way COO counts, beta = 1
   python bench.py --workload serving                 # Poisson stream of mixed requests, solves/s, p50/p99
+  python bench.py --workload cp4 [--beta B]          # order-4 CP 80x70x60x50, R = 10 (the paper's synthetic shape)
+  python bench.py --workload tucker4 [--beta B]      # order-4 Tucker 80x70x60x50, core 10x9x8x7
   python bench.py --calibrate-copy   # plain device copy of known size, for counter scaling
 """
 from __future__ import annotations
@@ -341,6 +343,137 @@ def run_tucker(args, ctx):
     return out
 
 
+def oracle_rate(run, iters, sample):
+    """The FP64 oracle, as it stands: run(n) performs n outer iterations;
+    timed with the BLAS threads the host gives it and with one thread."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threadpool_limits = None
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    run(iters)
+    dt = time.perf_counter() - t0
+    out = {"value": iters / dt, "unit": "outer it/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{iters} {sample}, {dt:.1f} s"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            run(1)
+            d1 = time.perf_counter() - t0
+        out["one_thread"] = {"value": 1 / d1, "unit": "outer it/s", "cores": 1, "sample": f"1 iteration, {d1:.1f} s"}
+    return out
+
+
+def run_cp4(args, ctx):
+    """The paper's synthetic CP shape: order 4, 80 x 70 x 60 x 50, R = 10,
+    J-CoMM (L = 1, objective every iteration).  Runs through the 3-way view
+    5600 x 60 x 50 with the Khatri-Rao super factor of modes 1-2."""
+    import numpy as np
+    import torch
+    import workloads
+    from oracle import cp as ocp
+
+    beta = args.beta if args.beta is not None else 1.0
+    dims, R, L = (80, 70, 60, 50), 10, 1
+    d = workloads.cp_dense(0, dims=dims, rank=R)
+    X32 = d.X.astype(np.float32)
+    init32 = [a.astype(np.float32) for a in d.init]
+    X = torch.from_numpy(X32).cuda()
+    fac = [torch.from_numpy(a).cuda() for a in init32]
+    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+
+    def step(t):
+        ctx.jcomm_outer(X, fac, beta=beta, L=L, obj_out=trace[t:t + 1])
+
+    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
+    entries = int(np.prod(dims))
+    avg_ms = kernel_ms / max(launches, 1)
+    # per entry and pass: rebuild 2R plus two contraction chains of 2R (at
+    # beta = 1 the reference pass's mode-3 chain and the chain shared by view
+    # modes 1-2; otherwise one mode's numerator and denominator), counted at
+    # the model's R = 10 although the tile pads R to 32
+    flops = 6.0 * R * entries
+    tfl = flops / (avg_ms * 1e-3) / 1e12
+    out = base_line(args, elapsed)
+    out.update({"metric": "J-CoMM outer iters/s (CP order 4, 80x70x60x50, R10)",
+                "data": "synthetic (seeded Poisson around a planted Gamma(1,1) rank-10 CP model)",
+                "config": {"workload": f"jcomm_cp_dense_80x70x60x50_r10_beta{beta}_L{L}_obj", "dims": list(dims),
+                           "rank": R, "beta": beta, "inner_sweeps": L, "parallelism": "single GPU"},
+                "roofline": {"bound": "mfma", "achieved": round(tfl, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(tfl / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                             "kernel": "cp3_pass_kernel on the 5600 x 60 x 50 view",
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 4 * entries,
+                             "hbm_gbs_algorithmic": round(4 * entries / (avg_ms * 1e-3) / 1e9, 1)},
+                "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    if not args.no_cpu_baseline:
+        X64 = X32.astype(np.float64)
+
+        def run(n):
+            cur = [a.astype(np.float64) for a in init32]
+            for _ in range(n):
+                cur, _ = ocp.jcomm_outer(X64, cur, beta, L=L, return_ref_obj=True)
+
+        out["cpu_baseline"] = oracle_rate(run, 4, f"J-CoMM outer iterations (L={L}, beta={beta}, objective "
+                                                  "included) on the full 80x70x60x50 tensor, NumPy float64")
+    return out
+
+
+def run_tucker4(args, ctx):
+    """The paper's synthetic Tucker shape: order 4, 80 x 70 x 60 x 50, core
+    10 x 9 x 8 x 7, J-CoMM (L = 1, objective every iteration)."""
+    import numpy as np
+    import torch
+    import workloads
+    from oracle import tucker as otk
+
+    beta = args.beta if args.beta is not None else 1.0
+    dims, J, L = (80, 70, 60, 50), (10, 9, 8, 7), 1
+    d = workloads.tucker_dense(0, dims=dims, core_dims=J)
+    X32 = d.X.astype(np.float32)
+    X = torch.from_numpy(X32).cuda()
+    G = torch.from_numpy(d.init_core.astype(np.float32)).cuda()
+    F = [torch.from_numpy(a.astype(np.float32)).cuda() for a in d.init_factors]
+    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+
+    def step(t):
+        ctx.jcomm_outer(X, F, core=G, beta=beta, L=L, obj_out=trace[t:t + 1])
+
+    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
+    entries = int(np.prod(dims))
+    avg_ms = kernel_ms / max(launches, 1)
+    bytes_ = 4 * entries
+    gbs = bytes_ / (avg_ms * 1e-3) / 1e9
+    out = base_line(args, elapsed)
+    out.update({"metric": "J-CoMM outer iters/s (Tucker order 4, 80x70x60x50, core 10x9x8x7)",
+                "data": "synthetic (Gamma(shape 10) around a planted Tucker model, U(0,1) core and factors)",
+                "config": {"workload": f"jcomm_tucker_dense_80x70x60x50_core10x9x8x7_beta{beta}_L{L}_obj",
+                           "dims": list(dims), "core": list(J), "beta": beta, "inner_sweeps": L,
+                           "parallelism": "single GPU"},
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                             "kernel": "tk_v_kernel / tk_m3_kernel on the 336000 x 50 view",
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "algorithmic_bytes_per_launch": bytes_},
+                "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    if not args.no_cpu_baseline:
+        X64 = X32.astype(np.float64)
+
+        def run(n):
+            g, f = d.init_core.astype(np.float32).astype(np.float64), [a.astype(np.float32).astype(np.float64)
+                                                                       for a in d.init_factors]
+            for _ in range(n):
+                g, f, _ = otk.jcomm_outer(X64, g, f, beta, L=L, return_ref_obj=True)
+
+        out["cpu_baseline"] = oracle_rate(run, 4, f"J-CoMM outer iterations (L={L}, beta={beta}, objective "
+                                                  "included) on the full 80x70x60x50 tensor, NumPy float64")
+    return out
+
+
 def run_coo(args, ctx):
     """Sparse 183x24x1140x1717 counts, 3.3M nonzeros, CP rank 32, beta = 1, L = 1."""
     import numpy as np
@@ -442,9 +575,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving"], default="cp",
+    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving", "cp4", "tucker4"], default="cp",
                     help="cp: the headline 256^3 rank-32 CP workload; tucker / coo: the other pass kernels")
-    ap.add_argument("--beta", type=float, default=None, help="beta for --workload tucker (default 0)")
+    ap.add_argument("--beta", type=float, default=None,
+                    help="beta for --workload tucker (default 0), cp4 and tucker4 (default 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -469,7 +603,8 @@ def main() -> int:
 
     import paper_2602_14683_amd as comm
     ctx = comm.Context(0)
-    out = {"cp": run_cp, "tucker": run_tucker, "coo": run_coo, "serving": run_serving}[args.workload](args, ctx)
+    out = {"cp": run_cp, "tucker": run_tucker, "coo": run_coo, "serving": run_serving, "cp4": run_cp4,
+           "tucker4": run_tucker4}[args.workload](args, ctx)
     if args.workload == "cp" and not args.no_serving:
         out["serving"] = serving_stream(args, ctx)
     ctx.close()

@@ -836,10 +836,10 @@ int ensure_aux(comm_ctx* ctx) {
 int extrap_alpha(const comm_dense* x, comm_model* m, comm_model* prev, const comm_extrap* e, float* alpha,
                  hipStream_t st) {
   ExtrapArgs a = {};
-  int64_t cnt[5];
+  int64_t cnt[kMaxBlocks];
   a.nb = model_blocks(x, m, a.cur, cnt);
-  float* pp[5];
-  int64_t pc[5];
+  float* pp[kMaxBlocks];
+  int64_t pc[kMaxBlocks];
   model_blocks(x, prev, pp, pc);
   for (int b = 0; b < a.nb; ++b) {
     a.prev[b] = pp[b];
@@ -856,9 +856,9 @@ int extrap_alpha(const comm_dense* x, comm_model* m, comm_model* prev, const com
 // Move block b (index in update order; -1 = all blocks).
 int extrap_apply(const comm_dense* x, comm_model* m, comm_model* prev, int b, float* alpha, float eps,
                  hipStream_t st) {
-  float* cur[5];
-  float* pp[5];
-  int64_t cnt[5], pc[5];
+  float* cur[kMaxBlocks];
+  float* pp[kMaxBlocks];
+  int64_t cnt[kMaxBlocks], pc[kMaxBlocks];
   const int nb = model_blocks(x, m, cur, cnt);
   model_blocks(x, prev, pp, pc);
   ExtrapArgs a = {};
@@ -1181,8 +1181,11 @@ int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op) {
   if (check_dense_shape(x) || !model || !opts) return 0;
   if (model->kind == COMM_CP) return cp_ws_bytes(x, op == 1 && opts->beta != 1.0 && opts->cache_pq);
-  if (x->ndim != 3 && x->ndim != 4) return 0;
-  if (x->ndim == 4 && x->dims[0] * x->dims[1] * x->dims[2] > (1 << 24)) return 0;
+  if (x->ndim > 3) {
+    int64_t rows = 1;
+    for (int n = 0; n < x->ndim - 1; ++n) rows *= x->dims[n];
+    if (rows > (1 << 24)) return 0;
+  }
   for (int n = 0; n < x->ndim; ++n)
     if (model->core_dims[n] < 1 || model->core_dims[n] > kRP) return 0;
   return tucker_workspace_bytes(x, model, opts, op);

@@ -218,11 +218,12 @@ hipError_t launch_fold(const FoldArgs& a, hipStream_t s);
 // entries each).  launch_extrap_alpha writes alpha_t to alpha[0]; launch_
 // extrap_apply reads it and moves the listed blocks, saving their old values
 // in prev.
+constexpr int kMaxBlocks = kMaxModes + 1;  // a Tucker core and its factors
 struct ExtrapArgs {
   int nb;
-  float* cur[5];
-  float* prev[5];
-  int64_t count[5];
+  float* cur[kMaxBlocks];
+  float* prev[kMaxBlocks];
+  int64_t count[kMaxBlocks];
   double alpha_nes, c, delta;
   float* alpha;
   float eps;

@@ -603,11 +603,14 @@ int tucker_check_model(const comm_model* m, const comm_dense* x) {
   if (!m) return fail(COMM_EINVAL, "model is NULL");
   if (m->kind != COMM_TUCKER) return fail(COMM_EINVAL, "model kind is not Tucker");
   if (!m->core) return fail(COMM_EINVAL, "core is NULL");
-  if (x->ndim != 3 && x->ndim != 4)
-    return fail(COMM_EUNSUPPORTED, "dense Tucker of order %d is not supported (3 or 4)", x->ndim);
-  if (x->ndim == 4 && x->dims[0] * x->dims[1] * x->dims[2] > (1 << 24))
-    return fail(COMM_EUNSUPPORTED, "I_1 I_2 I_3 = %lld exceeds 2^24",
-                (long long)(x->dims[0] * x->dims[1] * x->dims[2]));
+  if (x->ndim < 3 || x->ndim > 5)
+    return fail(COMM_EUNSUPPORTED, "dense Tucker of order %d is not supported (3 to 5)", x->ndim);
+  if (x->ndim > 3) {
+    int64_t rows = 1;
+    for (int n = 0; n < x->ndim - 1; ++n) rows *= x->dims[n];
+    if (rows > (1 << 24))
+      return fail(COMM_EUNSUPPORTED, "I_1 ... I_%d = %lld exceeds 2^24", x->ndim - 1, (long long)rows);
+  }
   for (int n = 0; n < x->ndim; ++n) {
     if (!m->factors[n]) return fail(COMM_EINVAL, "factors[%d] is NULL", n);
     if (m->core_dims[n] < 1) return fail(COMM_EINVAL, "core_dims[%d] = %lld", n, (long long)m->core_dims[n]);
@@ -617,13 +620,13 @@ int tucker_check_model(const comm_model* m, const comm_dense* x) {
 }
 
 size_t tucker_workspace_bytes(const comm_dense* x, const comm_model* m, const comm_opts* o, int op) {
-  if (x->ndim == 4) return tucker4_workspace_bytes(x, m, o, op);
+  if (x->ndim > 3) return tuckern_workspace_bytes(x, m, o, op);
   const bool cache = op == 1 && o->cache_pq && o->beta != 1.0;
   return tk_layout(x, m, nullptr, cache).bytes;
 }
 
 int tucker_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
-  if (x->ndim == 4) return tucker4_bcomm(ctx, x, m, block, o, st);
+  if (x->ndim > 3) return tuckern_bcomm(ctx, x, m, block, o, st);
   TkWs w = tk_layout(x, m, nullptr, false);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
@@ -654,7 +657,7 @@ int tucker_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, c
 }
 
 int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
-  if (x->ndim == 4) return tucker4_jcomm(ctx, x, m, o, obj, st);
+  if (x->ndim > 3) return tuckern_jcomm(ctx, x, m, o, obj, st);
   const bool kl = o->beta == 1.0;
   const bool cache = o->cache_pq && !kl;
   TkWs w = tk_layout(x, m, nullptr, cache);
@@ -722,7 +725,7 @@ int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_o
 
 int tucker_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
                      hipStream_t st) {
-  if (x->ndim == 4) return tucker4_objective(ctx, x, m, o, out, st);
+  if (x->ndim > 3) return tuckern_objective(ctx, x, m, o, out, st);
   TkWs w = tk_layout(x, m, nullptr, false);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;

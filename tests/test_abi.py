@@ -50,7 +50,7 @@ def test_binding_structs_follow_the_header():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcomm.so not built")
 def test_workspace_query_by_order():
     """comm_workspace_bytes is host arithmetic only: orders 3 to 5 of dense CP
-    and orders 3 and 4 of dense Tucker are accepted, and an order-N tensor whose
+    and orders 3 to 5 of dense Tucker are accepted, and an order-N tensor whose
     first N - 2 extents multiply past 2^24 is refused (0)."""
     import paper_2602_14683_amd as pkg
     lib = pkg.load_library()
@@ -75,7 +75,8 @@ def test_workspace_query_by_order():
     assert three > 0 and four > three  # the view's buffers plus the grouped modes'
     assert ws((6, 5, 7, 30, 40), rank=4, beta=1.5) > 0
     assert ws((80, 70, 60, 50), core=(10, 9, 8, 7)) > ws((80, 70, 60), core=(10, 9, 8))
-    assert ws((8, 7, 6, 5, 4), core=(2, 2, 2, 2, 2)) == 0
+    assert ws((27, 24, 7, 100, 100), core=(10, 10, 5, 10, 10)) > 0
+    assert ws((400, 300, 200, 2, 3), core=(2, 2, 2, 2, 2)) == 0  # I_1 ... I_4 > 2^24
     assert ws((80, 70, 60, 50), core=(10, 9, 8, 33)) == 0
     assert ws((80, 70, 60), core=(10, 9, 8)) > 0
     assert ws((4096, 4097, 2, 2), rank=4) == 0
