@@ -19,6 +19,7 @@ stream), and the FP64 oracle timed on the host cores on a bounded sample.
   python bench.py --workload serving                 # Poisson stream of mixed requests, solves/s, p50/p99
   python bench.py --workload cp4 [--beta B]          # order-4 CP 80x70x60x50, R = 10 (the paper's synthetic shape)
   python bench.py --workload tucker4 [--beta B]      # order-4 Tucker 80x70x60x50, core 10x9x8x7
+  python bench.py --workload tucker5 [--beta B]      # order-5 Tucker 27x24x7x100x100, core 10x10x5x10x10
   python bench.py --calibrate-copy   # plain device copy of known size, for counter scaling
 """
 from __future__ import annotations
@@ -425,13 +426,24 @@ def run_cp4(args, ctx):
 def run_tucker4(args, ctx):
     """The paper's synthetic Tucker shape: order 4, 80 x 70 x 60 x 50, core
     10 x 9 x 8 x 7, J-CoMM (L = 1, objective every iteration)."""
+    return run_tuckern(args, ctx, (80, 70, 60, 50), (10, 9, 8, 7))
+
+
+def run_tucker5(args, ctx):
+    """The shape and ranks of the paper's 5-way count experiment (27 x 24 x 7 x
+    100 x 100, core 10 x 10 x 5 x 10 x 10, run there with dense contractions)
+    on a synthetic dense tensor, J-CoMM (L = 1, objective every iteration)."""
+    return run_tuckern(args, ctx, (27, 24, 7, 100, 100), (10, 10, 5, 10, 10))
+
+
+def run_tuckern(args, ctx, dims, J):
     import numpy as np
     import torch
     import workloads
     from oracle import tucker as otk
 
     beta = args.beta if args.beta is not None else 1.0
-    dims, J, L = (80, 70, 60, 50), (10, 9, 8, 7), 1
+    L = 1
     d = workloads.tucker_dense(0, dims=dims, core_dims=J)
     X32 = d.X.astype(np.float32)
     X = torch.from_numpy(X32).cuda()
@@ -449,14 +461,17 @@ def run_tucker4(args, ctx):
     bytes_ = 4 * entries
     gbs = bytes_ / (avg_ms * 1e-3) / 1e9
     out = base_line(args, elapsed)
-    out.update({"metric": "J-CoMM outer iters/s (Tucker order 4, 80x70x60x50, core 10x9x8x7)",
+    shape = "x".join(map(str, dims))
+    core = "x".join(map(str, J))
+    rows = int(np.prod(dims[:-1]))
+    out.update({"metric": f"J-CoMM outer iters/s (Tucker order {len(dims)}, {shape}, core {core})",
                 "data": "synthetic (Gamma(shape 10) around a planted Tucker model, U(0,1) core and factors)",
-                "config": {"workload": f"jcomm_tucker_dense_80x70x60x50_core10x9x8x7_beta{beta}_L{L}_obj",
+                "config": {"workload": f"jcomm_tucker_dense_{shape}_core{core}_beta{beta}_L{L}_obj",
                            "dims": list(dims), "core": list(J), "beta": beta, "inner_sweeps": L,
                            "parallelism": "single GPU"},
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                             "kernel": "tk_v_kernel / tk_m3_kernel on the 336000 x 50 view",
+                             "kernel": f"tk_v_kernel / tk_m3_kernel on the {rows} x {dims[-1]} view",
                              "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
                              "algorithmic_bytes_per_launch": bytes_},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
@@ -469,8 +484,8 @@ def run_tucker4(args, ctx):
             for _ in range(n):
                 g, f, _ = otk.jcomm_outer(X64, g, f, beta, L=L, return_ref_obj=True)
 
-        out["cpu_baseline"] = oracle_rate(run, 4, f"J-CoMM outer iterations (L={L}, beta={beta}, objective "
-                                                  "included) on the full 80x70x60x50 tensor, NumPy float64")
+        out["cpu_baseline"] = oracle_rate(run, 3, f"J-CoMM outer iterations (L={L}, beta={beta}, objective "
+                                                  f"included) on the full {shape} tensor, NumPy float64")
     return out
 
 
@@ -575,10 +590,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving", "cp4", "tucker4"], default="cp",
+    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving", "cp4", "tucker4", "tucker5"], default="cp",
                     help="cp: the headline 256^3 rank-32 CP workload; tucker / coo: the other pass kernels")
     ap.add_argument("--beta", type=float, default=None,
-                    help="beta for --workload tucker (default 0), cp4 and tucker4 (default 1)")
+                    help="beta for --workload tucker (default 0), cp4, tucker4 and tucker5 (default 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -604,7 +619,7 @@ def main() -> int:
     import paper_2602_14683_amd as comm
     ctx = comm.Context(0)
     out = {"cp": run_cp, "tucker": run_tucker, "coo": run_coo, "serving": run_serving, "cp4": run_cp4,
-           "tucker4": run_tucker4}[args.workload](args, ctx)
+           "tucker4": run_tucker4, "tucker5": run_tucker5}[args.workload](args, ctx)
     if args.workload == "cp" and not args.no_serving:
         out["serving"] = serving_stream(args, ctx)
     ctx.close()

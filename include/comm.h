@@ -29,8 +29,9 @@
  *
  * Supported in this version: dense CP of order 3, 4 and 5 (rank R <= 32; at
  * orders 4 and 5 the product I_1 ... I_{N-2} must not exceed 2^24); dense
- * Tucker of order 3 and 4 (core sizes J_n <= 32; at order 4, I_1 I_2 I_3 <=
- * 2^24); sparse COO of order 2 to 4 (CP, beta = 1).  Other shapes return COMM_EUNSUPPORTED.  The sparse paths
+ * Tucker of order 3, 4 and 5 (core sizes J_n <= 32; at orders 4 and 5 the
+ * product I_1 ... I_{N-1} must not exceed 2^24); sparse COO of order 2 to 4
+ * (CP, beta = 1).  Other shapes return COMM_EUNSUPPORTED.  The sparse paths
  * accumulate with float atomics and are reproducible to rounding only; the
  * dense paths are deterministic.
  *
@@ -43,11 +44,11 @@
  * for B-CoMM, and for J-CoMM one pass at beta = 1 and three at beta != 1
  * (modes 1..N-2 share one).
  *
- * Dense Tucker of order 4 runs the fused passes of order 3 on the
- * (I_1 I_2 I_3) x I_4 matrix view: a row is rebuilt from the core multiplied
- * by the first three factors (mode products) and the fourth factor, and the
- * numerators of the core and of modes 1 to 3 are mode products of the pass's
- * output contracted with the core (App. C for N = 4).
+ * Dense Tucker of order N = 4, 5 runs the fused passes of order 3 on the
+ * (I_1 ... I_{N-1}) x I_N matrix view: a row is rebuilt from the core
+ * multiplied by the first N - 1 factors (mode products) and the last factor,
+ * and the numerators of the core and of modes 1 to N - 1 are mode products of
+ * the pass's output contracted with the core (App. C for general N).
  */
 #ifndef COMM_H_
 #define COMM_H_

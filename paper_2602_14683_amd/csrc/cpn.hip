@@ -39,12 +39,12 @@ hipError_t launch_kr(const KrArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// One workgroup per output row of one job: 8 groups of 32 lanes (one lane per
-// column) stride over the super-mode rows with s_mode = i, and the groups are
-// combined in order.
-constexpr int kFoldGroups = 8;
+// One workgroup per output row of one job: 32 groups of 32 lanes (one lane
+// per column) stride over the super-mode rows with s_mode = i, and the groups
+// are combined in order.
+constexpr int kFoldGroups = 32;
 
-__global__ void __launch_bounds__(256) fold_kernel(FoldArgs a) {
+__global__ void __launch_bounds__(1024) fold_kernel(FoldArgs a) {
   __shared__ float red[kFoldGroups][32];
   const FoldJob& J = a.job[blockIdx.y];
   const int i = blockIdx.x;
@@ -94,7 +94,7 @@ hipError_t launch_fold(const FoldArgs& a, hipStream_t s) {
   if (a.njobs < 1) return hipSuccess;
   int rows = 0;
   for (int j = 0; j < a.njobs; ++j) rows = rows > a.job[j].rows_p ? rows : a.job[j].rows_p;
-  hipLaunchKernelGGL(fold_kernel, dim3((unsigned)rows, (unsigned)a.njobs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(fold_kernel, dim3((unsigned)rows, (unsigned)a.njobs), dim3(32 * kFoldGroups), 0, s, a);
   return hipGetLastError();
 }
 

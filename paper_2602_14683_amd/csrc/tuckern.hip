@@ -13,9 +13,11 @@
 //            Num_n[i][j] = sum over the other indices of Z_n[..i..] G'[..j..]
 //            (one GEMM per leading core index, summed as partial slots),
 // and the mode-N numerator is the fibre-mode pass of the order-3 path on the
-// same view, against the table of the contraction set.  Mode products are
-// strided batched matrix-core GEMMs (launch_gemm); the partial tensor of a mode
-// is never formed, only V and the small products of it.
+// same view, against the table of the contraction set.  Mode products are a
+// streaming kernel (one side of each is at most 32 wide); the last
+// contraction of a grouped mode is a batched matrix-core GEMM (launch_gemm).
+// The partial tensor of a mode is never formed, only V and the small products
+// of it.
 
 #include <algorithm>
 
@@ -59,79 +61,83 @@ struct TkNModel {
 // Closed-form beta = 1 denominators (Q = 1) from the column sums S_m of the
 // denominator set's factors: den[n][j] = sum over the core entries with
 // j_n = j of G * prod_{m != n} S_m[j_m], and dcore[(j_1..j_{N-1})][j_N] =
-// prod_m S_m[j_m].  One workgroup: group g of 32 lanes owns j = g of the
-// current mode, its lanes stride over the other entries, combined in order.
-__global__ void __launch_bounds__(1024) tkn_den_closed_kernel(TkNModel m, float* den, float* dcore) {
-  __shared__ float red[32][33];
+// prod_m S_m[j_m].  Workgroup (j, n) for n < N forms den[n][j] (its threads
+// stride over the other core entries, combined in a fixed order); the
+// workgroups of row N write dcore.  Every workgroup first forms the column
+// sums itself (the factors are small), in the same order.
+__global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* den, float* dcore) {
+  __shared__ float red[8][33];
   __shared__ float S[kTkMaxN][32];
+  __shared__ float part[256];
   const int t = threadIdx.x;
   const int c = t & 31, g = t >> 5;
   const int N = m.N;
   for (int f = 0; f < N; ++f) {
     float s = 0.0f;
-    for (int r = g; r < m.rows[f]; r += 32) s += m.F[f].at(r, c, m.rows[f]);
+    for (int r = g; r < m.rows[f]; r += 8) s += m.F[f].at(r, c, m.rows[f]);
     red[g][c] = s;
     __syncthreads();
     if (t < 32) {
       float acc = 0.0f;
-      for (int q = 0; q < 32; ++q) acc += red[q][t];
+      for (int q = 0; q < 8; ++q) acc += red[q][t];
       S[f][t] = acc;
     }
     __syncthreads();
   }
-  for (int n = 0; n < N; ++n) {
-    int64_t others = 1;
+  const int n = blockIdx.y, j = blockIdx.x;
+  if (n == N) {
+    int rows = 1;
+    for (int q = 0; q < N - 1; ++q) rows *= m.J[q];
+    for (int e = j * 256 + t; e < rows * kRP; e += gridDim.x * 256) {
+      const int d = e & 31;
+      float v = 0.0f;
+      if (d < m.J[N - 1]) {
+        v = S[N - 1][d];
+        int rem = e >> 5;
+        for (int q = N - 2; q >= 0; --q) {
+          v *= S[q][rem % m.J[q]];
+          rem /= m.J[q];
+        }
+      }
+      dcore[e] = v;
+    }
+    return;
+  }
+  if (j >= kRP) return;
+  float acc = 0.0f;
+  if (j < m.J[n]) {
+    int others = 1;
     for (int q = 0; q < N; ++q)
       if (q != n) others *= m.J[q];
-    const int j = g;
-    float acc = 0.0f;
-    if (j < m.J[n]) {
-      for (int64_t o = c; o < others; o += 32) {
-        // indices of the other modes from o (last mode fastest), j at mode n
-        int64_t rem = o, off = 0, mul = 1;
-        float w = 1.0f;
-        for (int q = N - 1; q >= 0; --q) {
-          int iq = j;
-          if (q != n) {
-            iq = (int)(rem % m.J[q]);
-            rem /= m.J[q];
-            w *= S[q][iq];
-          }
-          if (q == N - 1) {
-            off = iq;
-            mul = kRP;
-          } else {
-            off += (int64_t)iq * mul;
-            mul *= m.J[q];
-          }
+    for (int o = t; o < others; o += 256) {
+      // indices of the other modes from o (last mode fastest), j at mode n
+      int rem = o, off = 0, mul = 1;
+      float w = 1.0f;
+      for (int q = N - 1; q >= 0; --q) {
+        int iq = j;
+        if (q != n) {
+          iq = rem % m.J[q];
+          rem /= m.J[q];
+          w *= S[q][iq];
         }
-        acc += m.G[off] * w;
+        if (q == N - 1) {
+          off = iq;
+          mul = kRP;
+        } else {
+          off += iq * mul;
+          mul *= m.J[q];
+        }
       }
+      acc += m.G[off] * w;
     }
-    red[g][c] = acc;
-    __syncthreads();
-    if (t < 32) {
-      float s = 0.0f;
-      for (int q = 0; q < 32; ++q) s += red[t][q];
-      den[n * kRP + t] = t < m.J[n] ? s : 0.0f;
-    }
+  }
+  part[t] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) part[t] += part[t + h];
     __syncthreads();
   }
-  int64_t rows = 1;
-  for (int q = 0; q < N - 1; ++q) rows *= m.J[q];
-  for (int64_t e = t; e < rows * kRP; e += 1024) {
-    const int d = (int)(e & 31);
-    float v = 0.0f;
-    if (d < m.J[N - 1]) {
-      v = S[N - 1][d];
-      int64_t rem = e >> 5;
-      for (int q = N - 2; q >= 0; --q) {
-        v *= S[q][(int)(rem % m.J[q])];
-        rem /= m.J[q];
-      }
-    }
-    dcore[e] = v;
-  }
+  if (t == 0) den[n * kRP + j] = j < m.J[n] ? part[0] : 0.0f;
 }
 
 namespace {
@@ -312,33 +318,123 @@ int tkn_pad(const comm_model* m, const TkNWs& w, const TkNCopy& dst, const TkNCo
 
 // Mode product of T viewed as L x I x R, for `sets` operand pairs at once:
 // Y[l][j][r] = sum_{i < I} M(i, j) T[l][i][r].  contract: M(i, j) = F[i][j]
-// (F a padded [I][32] factor, the sum runs over data rows: T x_n F^T);
+// (F a padded [I][32] factor, the sum runs over data rows: T x_n F^T; J <= 32);
 // expand: M(i, j) = F[j][i] (F a padded [J][32] factor, the sum runs over a
-// core index: T x_n F).
+// core index, I <= 32: T x_n F).  R is a multiple of 32.
+//
+// A streaming kernel rather than a matrix-core GEMM: one of I, J is at most
+// 32 and R is long, so each thread owns one (l, r), walks i with loads that
+// are contiguous in r across the wavefront, keeps up to 32 outputs in
+// registers and writes them contiguous in r; the factor entries are the same
+// for the whole wavefront.  Every input is read once (expand: once per 32
+// outputs), every output written once, in a fixed order.
+constexpr int kMpChunk = 32;
+
+struct ModeProductArgs {
+  const float* F[2];
+  const float* T[2];
+  float* Y[2];
+  int64_t L, R;
+  int I, J;
+};
+
+template <bool kContract>
+__global__ void __launch_bounds__(256) mode_product_kernel(ModeProductArgs a) {
+  const int set = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.L * a.R) return;
+  const int64_t l = e / a.R, r = e - l * a.R;
+  const float* __restrict__ F = a.F[set];
+  const float* __restrict__ t = a.T[set] + l * a.I * a.R + r;
+  float* __restrict__ y = a.Y[set] + l * a.J * a.R + r;
+  for (int j0 = 0; j0 < a.J; j0 += kMpChunk) {
+    float acc[kMpChunk];
+#pragma unroll
+    for (int jj = 0; jj < kMpChunk; ++jj) acc[jj] = 0.0f;
+    for (int i = 0; i < a.I; ++i) {
+      const float v = t[(int64_t)i * a.R];
+#pragma unroll
+      for (int jj = 0; jj < kMpChunk; ++jj) {
+        // contract: columns of a padded [I][32] row (zero past J); expand:
+        // rows j0 + jj < J of a padded [J][32] factor
+        float mf = 0.0f;
+        if (kContract) mf = F[(int64_t)i * kRP + jj];
+        else if (j0 + jj < a.J) mf = F[(int64_t)(j0 + jj) * kRP + i];
+        acc[jj] = fmaf(mf, v, acc[jj]);
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < kMpChunk; ++jj)
+      if (j0 + jj < a.J) y[(int64_t)(j0 + jj) * a.R] = acc[jj];
+  }
+}
+
+// Contract with a long summed index (data rows): the workgroup's four waves
+// own the same 64 positions and a quarter of i each; wave 0 adds the other
+// waves' partial sums in order 1, 2, 3.
+template <int kJC>
+__global__ void __launch_bounds__(256) mode_contract_split_kernel(ModeProductArgs a) {
+  __shared__ float red[3][kJC][64];
+  const int set = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = e < a.L * a.R;
+  const int64_t l = live ? e / a.R : 0, r = live ? e - l * a.R : 0;
+  const float* __restrict__ F = a.F[set];
+  const float* __restrict__ t = a.T[set] + l * a.I * a.R + r;
+  const int per = (a.I + 3) / 4;
+  const int i0 = min(a.I, wv * per), i1 = min(a.I, i0 + per);
+  float acc[kJC];
+#pragma unroll
+  for (int jj = 0; jj < kJC; ++jj) acc[jj] = 0.0f;
+  if (live) {
+#pragma unroll 4
+    for (int i = i0; i < i1; ++i) {
+      const float v = t[(int64_t)i * a.R];
+#pragma unroll
+      for (int jj = 0; jj < kJC; ++jj) acc[jj] = fmaf(F[(int64_t)i * kRP + jj], v, acc[jj]);
+    }
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int jj = 0; jj < kJC; ++jj) red[wv - 1][jj][lane] = acc[jj];
+  }
+  __syncthreads();
+  if (wv == 0 && live) {
+    float* __restrict__ y = a.Y[set] + l * a.J * a.R + r;
+#pragma unroll
+    for (int jj = 0; jj < kJC; ++jj) {
+      const float s = ((acc[jj] + red[0][jj][lane]) + red[1][jj][lane]) + red[2][jj][lane];
+      if (jj < a.J) y[(int64_t)jj * a.R] = s;
+    }
+  }
+}
+
 int mode_product(const float* const* F, const float* const* T, float* const* Y, int sets, int64_t L, int I, int J,
                  int64_t R, bool contract, hipStream_t st) {
-  GemmArgs g = {};
-  g.sam = contract ? 1 : kRP;
-  g.saki = contract ? kRP : 1;
-  g.akin_log2 = 30;
-  g.sbb = (int64_t)I * R;
-  g.sbki = R;
-  g.sbn = 1;
-  g.bkin_log2 = 30;
-  g.sob = (int64_t)J * R;
-  g.ldo = R;
-  g.M = J;
-  g.N = (int)R;
-  g.K = I;
-  g.batch = (int)L;
-  g.splits = 1;
-  g.sets = sets;
+  if (contract ? J > kRP : I > kRP) return fail(COMM_EHIP, "mode product with %d x %d outside the 32-wide tile", I, J);
+  ModeProductArgs a = {};
   for (int k = 0; k < sets; ++k) {
-    g.A[k] = F[k];
-    g.B[k] = T[k];
-    g.out[k] = Y[k];
+    a.F[k] = F[k];
+    a.T[k] = T[k];
+    a.Y[k] = Y[k];
   }
-  HIP_TRY(launch_gemm(g, st));
+  a.L = L;
+  a.R = R;
+  a.I = I;
+  a.J = J;
+  if (contract && I >= 16) {
+    // accumulators for the J <= 32 outputs in buckets of 8, 16 or 32
+    const dim3 grid((unsigned)((L * R + 63) / 64), (unsigned)sets);
+    if (J <= 8) hipLaunchKernelGGL(mode_contract_split_kernel<8>, grid, dim3(256), 0, st, a);
+    else if (J <= 16) hipLaunchKernelGGL(mode_contract_split_kernel<16>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(mode_contract_split_kernel<32>, grid, dim3(256), 0, st, a);
+  } else {
+    const dim3 grid((unsigned)((L * R + 255) / 256), (unsigned)sets);
+    if (contract) hipLaunchKernelGGL(mode_product_kernel<true>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(mode_product_kernel<false>, grid, dim3(256), 0, st, a);
+  }
+  HIP_TRY(hipGetLastError());
   return COMM_OK;
 }
 
@@ -552,7 +648,7 @@ int tkn_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
   const SlotsN* denp = &den;
   SlotsN dcore;
   if (kl) {
-    hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(1), dim3(1024), 0, st, ds, w.den_vec, w.dcore);
+    hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(kRP, w.N + 1), dim3(256), 0, st, ds, w.den_vec, w.dcore);
     HIP_TRY(hipGetLastError());
     if (blk == -1) {
       dcore = SlotsN{w.dcore, 1, (int)w.CR};
