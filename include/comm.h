@@ -30,8 +30,8 @@
  * Supported in this version: dense CP of order 3, 4 and 5 (rank R <= 32; at
  * orders 4 and 5 the product I_1 ... I_{N-2} must not exceed 2^24); dense
  * Tucker of order 3, 4 and 5 (core sizes J_n <= 32; at orders 4 and 5 the
- * product I_1 ... I_{N-1} must not exceed 2^24); sparse COO of order 2 to 4
- * (CP, beta = 1).  Other shapes return COMM_EUNSUPPORTED.  The sparse paths
+ * product I_1 ... I_{N-1} must not exceed 2^24); sparse COO CP of order 2 to
+ * 4 at beta = 1, of order 3 and 4 at other beta in (0, 2).  Other shapes return COMM_EUNSUPPORTED.  The sparse paths
  * accumulate with float atomics and are reproducible to rounding only; the
  * dense paths are deterministic.
  *
@@ -262,14 +262,35 @@ int comm_jcomm_outer_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* mode
 int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
                         const comm_opts* opts, double* out_dev, void* stream);
 
-/* One J-CoMM outer iteration for a CP model on sparse COO counts at beta = 1
- * (Sec. 6.4, paragraph on sparse tensors): numerators accumulated over the
- * nonzeros only; the beta = 1 denominator is the product of the other
- * factors' column sums.  opts->beta must be 1.  If obj_ref_dev is not NULL the
- * objective at the reference is written there (zero cells contribute the
- * model value, summed in closed form). */
+/* One J-CoMM outer iteration for a CP model on sparse COO counts (Sec. 6.4,
+ * paragraph on sparse tensors): numerators accumulated over the nonzeros only.
+ *   beta = 1: the denominator is the product of the other factors' column
+ *     sums; any order 2 to 4; the objective's zero cells contribute the model
+ *     value, summed in closed form.
+ *   beta in (0, 2), beta != 1: the denominators involve Q = Xhat^(beta-1) on
+ *     every cell, so they come from the dense pass run over the whole index
+ *     space (an all-zero tensor of the dims, 4 bytes per cell, allocated once
+ *     per context and counted against its limit); orders 3 and 4 (order 4:
+ *     I_1 I_2 <= 2^24).  The nonzeros' weights P~ are formed once per outer
+ *     iteration.  Results are reproducible to float rounding (atomics).
+ *   beta = 0 returns COMM_EUNSUPPORTED (d(0 | y) is infinite).
+ * If obj_ref_dev is not NULL the objective at the reference is written there. */
 int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
                             double* obj_ref_dev, void* stream);
+
+/* Block-MM (B-CoMM) update of a CP model on sparse COO data at beta in (0, 2)
+ * (Theorem "CP block multiplicative update" with the numerators over the
+ * nonzeros, Sec. 6.4): block in 0..N-1 or -1 for a sweep.  At beta = 1 the
+ * denominator is closed form; otherwise it comes from the dense pass over the
+ * index space as for comm_cp_jcomm_outer_coo at beta != 1 (orders 3 and 4). */
+int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,
+                       void* stream);
+
+/* D_beta(X, Xhat) over every cell of a sparse COO tensor, beta in (0, 2),
+ * float64: the dense pass's sum of d(0 | Xhat) over the index space plus, over
+ * the nonzeros, d(x | Xhat) - d(0 | Xhat).  Orders 3 and 4. */
+int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* model, const comm_opts* opts,
+                            double* out_dev, void* stream);
 
 /* A sparse COO tensor prepared for repeated J-CoMM iterations (CP, beta = 1):
  * two device copies of the nonzeros, sorted by the coordinates of modes 1

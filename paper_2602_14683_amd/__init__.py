@@ -32,7 +32,8 @@ EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_by
             "comm_profile_query", "comm_cp_update",
             "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo",
             "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
-            "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap"]
+            "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap",
+            "comm_cp_update_coo", "comm_beta_objective_coo"]
 
 
 class CommError(RuntimeError):
@@ -109,12 +110,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                             ctypes.c_void_p, ctypes.c_void_p]
     lib.comm_jcomm_outer_extrap.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Model), P(Opts), P(Extrap),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.comm_cp_update_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), ctypes.c_int, P(Opts), ctypes.c_void_p]
+    lib.comm_beta_objective_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
+                                            ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
                  "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched",
                  "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan",
-                 "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap"]:
+                 "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap", "comm_cp_update_coo",
+                 "comm_beta_objective_coo"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -409,13 +414,34 @@ class Context:
         return out
 
     def cp_jcomm_outer_coo(self, idx: Sequence, val, dims: Sequence[int], factors, L: int = 1,
-                           eps: float = 1e-12, obj_out=None, stream=None) -> None:
-        """One beta = 1 J-CoMM outer iteration on COO data (idx: per-mode int32 tensors)."""
+                           eps: float = 1e-12, obj_out=None, stream=None, beta: float = 1.0) -> None:
+        """One J-CoMM outer iteration on COO data (idx: per-mode int32 tensors);
+        beta in (0, 2) (beta != 1: orders 3 and 4, dense denominators)."""
         c = _coo(idx, val, dims)
-        m, o = _model(factors), _opts(1.0, eps, None, L)
+        m, o = _model(factors), _opts(beta, eps, None, L)
         optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
         _check(self._lib.comm_cp_jcomm_outer_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o), optr,
                                                  _stream(stream)))
+
+    def cp_update_coo(self, idx: Sequence, val, dims: Sequence[int], factors, block: int = -1, beta: float = 1.0,
+                      eps: float = 1e-12, stream=None) -> None:
+        """B-CoMM block update(s) of a CP model on COO data, beta in (0, 2)."""
+        c = _coo(idx, val, dims)
+        m, o = _model(factors), _opts(beta, eps, None)
+        _check(self._lib.comm_cp_update_coo(self._h, ctypes.byref(c), ctypes.byref(m), int(block), ctypes.byref(o),
+                                            _stream(stream)))
+
+    def beta_objective_coo(self, idx: Sequence, val, dims: Sequence[int], factors, beta: float = 1.0,
+                           eps: float = 1e-12, out=None, stream=None):
+        """D_beta over every cell of COO data (float64 device scalar), beta in (0, 2)."""
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=val.device)
+        c = _coo(idx, val, dims)
+        m, o = _model(factors), _opts(beta, eps, None)
+        _check(self._lib.comm_beta_objective_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o),
+                                                 _ptr(out, "out"), _stream(stream)))
+        return out
 
     def coo_plan(self, idx: Sequence, val, dims: Sequence[int], stream=None) -> "CooPlan":
         """Sorted device copies of a COO tensor for repeated beta = 1 J-CoMM iterations."""

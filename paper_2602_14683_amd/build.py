@@ -19,7 +19,7 @@ ARCH = os.environ.get("COMM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "cp3.hip", "cp3_bc_is.hip", "cp3_bc_half.hip", "cp3_bc_kl.hip", "cp3_bc_threehalf.hip",
            "cp3_bc_general.hip", "kernels_small.hip", "tucker3.hip", "tucker3_pass_a.hip",
-           "tucker3_pass_b.hip", "sparse.hip", "cpn.hip", "tuckern.hip"]
+           "tucker3_pass_b.hip", "sparse.hip", "cpn.hip", "tuckern.hip", "sparse_beta.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -150,6 +151,14 @@ CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
   return a;
 }
 
+// Numerator of block n taken from elsewhere (the nonzeros of a sparse
+// tensor): called with the contraction views of all N blocks (entry n is not
+// read) at the point where the dense path would take its numerator slots;
+// returns a [rows][32] buffer, one slot.
+struct NumHook {
+  std::function<int(int n, const FView* ct, const float** num)> run;
+};
+
 // Partial-slot view of mode n.
 void slots_of(const CpWs& w, int n, bool den, const float** part, int* slots, int* rows_total) {
   const CpGrid& g = w.g;
@@ -163,12 +172,16 @@ void slots_of(const CpWs& w, int n, bool den, const float** part, int* slots, in
 // given, to a padded copy.  Den is either its own slots or, at beta = 1, the
 // product of the column sums of the other two factors (views `others`).
 int cp_apply_update(const comm_model* m, const CpWs& w, int n, FView anchor, const FView* closed_others,
-                    float* out_pad, float gamma, float eps, hipStream_t st) {
+                    float* out_pad, float gamma, float eps, hipStream_t st, const float* num_override = nullptr) {
   SlotUpdateArgs u = {};
   u.njobs = 1;
   SlotJob& J = u.job[0];
   J.mode = kSlotUpdate;
   slots_of(w, n, false, &J.num_part, &J.num_slots, &J.rows_total);
+  if (num_override) {
+    J.num_part = num_override;
+    J.num_slots = 1;
+  }
   if (closed_others) {
     int rows[2], k = 0;
     for (int q = 0; q < 3; ++q)
@@ -192,7 +205,8 @@ int cp_apply_update(const comm_model* m, const CpWs& w, int n, FView anchor, con
   return COMM_OK;
 }
 
-int cp3_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
+int cp3_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st,
+              const NumHook* hook = nullptr) {
   CpWs w = cp_layout(x, nullptr, false);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
@@ -208,19 +222,26 @@ int cp3_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, cons
     a.d = cur;
     a.want_v = n < 2;
     a.want_m3 = n == 2;
-    if ((rc = run_pass(ctx, a, w.g, bc, !kl, st))) return rc;
+    // with a hook at beta = 1 the pass would only give the numerator
+    if (!(hook && kl) && (rc = run_pass(ctx, a, w.g, bc, !kl, st))) return rc;
+    const float* nb = nullptr;
+    if (hook) {
+      const FView ct[3] = {cur.A, cur.B, cur.C};
+      if ((rc = hook->run(n, ct, &nb))) return rc;
+    }
     FView others[2];
     int k = 0;
     for (int q = 0; q < 3; ++q)
       if (q != n) others[k++] = user_view(m, q);
     rc = cp_apply_update(m, w, n, user_view(m, n), kl ? others : nullptr, nullptr, gamma_of(o->beta),
-                         (float)o->eps, st);
+                         (float)o->eps, st, nb);
     if (rc) return rc;
   }
   return COMM_OK;
 }
 
-int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st,
+              const NumHook* hook = nullptr) {
   const bool kl = o->beta == 1.0;
   const bool cache = !kl && o->cache_pq;
   CpWs w = cp_layout(x, nullptr, cache);
@@ -344,7 +365,12 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
         obj_pending = false;
       }
       const FView anchor = n == 0 ? ref.A : n == 1 ? ref.B : ref.C;  // anchored at the reference block
-      rc = cp_apply_update(m, w, n, anchor, nullptr, w.cur.pad[n], gamma_of(o->beta), eps, st);
+      const float* nb = nullptr;
+      if (hook) {
+        const FView ct[3] = {pad_view(w.num.pad[0]), pad_view(w.num.pad[1]), pad_view(w.num.pad[2])};
+        if ((rc = hook->run(n, ct, &nb))) return rc;
+      }
+      rc = cp_apply_update(m, w, n, anchor, nullptr, w.cur.pad[n], gamma_of(o->beta), eps, st, nb);
       if (rc) return rc;
     }
   }
@@ -485,12 +511,16 @@ void cpn_num_src(const CpnWs& v, int n, bool den, const float** part, int* slots
 // caller's factor and, if given, a padded copy.  With `closed` (beta = 1) Den
 // is the product of the column sums of the other N - 1 blocks `cur`.
 int cpn_apply(const CpnWs& v, comm_model* m, int n, const FView* closed, FView anchor, float* out_pad, float gamma,
-              float eps, hipStream_t st) {
+              float eps, hipStream_t st, const float* num_override = nullptr) {
   SlotUpdateArgs u = {};
   u.njobs = 1;
   SlotJob& J = u.job[0];
   J.mode = kSlotUpdate;
   cpn_num_src(v, n, false, &J.num_part, &J.num_slots, &J.rows_total, &J.rows_p);
+  if (num_override) {
+    J.num_part = num_override;
+    J.num_slots = 1;
+  }
   if (closed) {
     FView others[kMaxModes];
     int rows[kMaxModes], k = 0;
@@ -537,7 +567,8 @@ int cpn_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const
 
 // B-CoMM: every block sees the blocks updated before it, so each block has its
 // own pass over X, from the super factor of the current grouped blocks.
-int cpn_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
+int cpn_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st,
+              const NumHook* hook = nullptr) {
   CpnWs v = cpn_layout(x, nullptr, false);
   int rc = ensure_ws(ctx, v.bytes, st);
   if (rc) return rc;
@@ -558,9 +589,14 @@ int cpn_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, cons
     a.d = a.r;
     a.want_v = q < 2;
     a.want_m3 = q == 2;
-    if ((rc = run_pass(ctx, a, v.w.g, bc, !kl, st))) return rc;
-    if (n < v.G && (rc = cpn_fold(v, &n, 1, cur, kl ? nullptr : cur, st))) return rc;
-    if ((rc = cpn_apply(v, m, n, kl ? cur : nullptr, cur[n], nullptr, gamma_of(o->beta), (float)o->eps, st)))
+    // with a hook at beta = 1 the pass would only give the numerator
+    if (!(hook && kl)) {
+      if ((rc = run_pass(ctx, a, v.w.g, bc, !kl, st))) return rc;
+      if (n < v.G && (rc = cpn_fold(v, &n, 1, cur, kl ? nullptr : cur, st))) return rc;
+    }
+    const float* nb = nullptr;
+    if (hook && (rc = hook->run(n, cur, &nb))) return rc;
+    if ((rc = cpn_apply(v, m, n, kl ? cur : nullptr, cur[n], nullptr, gamma_of(o->beta), (float)o->eps, st, nb)))
       return rc;
     if (n < v.G) super_valid = false;  // a grouped block changed
   }
@@ -592,7 +628,8 @@ int cpn_chi(const CpnWs& v, float beta, const int* modes, int count, hipStream_t
   return COMM_OK;
 }
 
-int cpn_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+int cpn_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st,
+              const NumHook* hook = nullptr) {
   const bool kl = o->beta == 1.0;
   const bool cache = !kl && o->cache_pq;
   CpnWs v = cpn_layout(x, nullptr, cache);
@@ -731,7 +768,15 @@ int cpn_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
         if (q != n) others[k++] = q;
       if ((rc = cpn_chi(v, (float)o->beta, others, k, st))) return rc;
       if ((rc = cpn_fold(v, &n, 1, gx1, gx2, st))) return rc;
-      if ((rc = cpn_apply(v, m, n, nullptr, gref[n], v.gcur[n], gamma_of(o->beta), eps, st))) return rc;
+      const float* nb = nullptr;
+      if (hook) {
+        FView ct[kMaxModes];
+        for (int q = 0; q < G; ++q) ct[q] = gx1[q];
+        ct[N - 2] = pad_view(w.num.pad[1]);
+        ct[N - 1] = pad_view(w.num.pad[2]);
+        if ((rc = hook->run(n, ct, &nb))) return rc;
+      }
+      if ((rc = cpn_apply(v, m, n, nullptr, gref[n], v.gcur[n], gamma_of(o->beta), eps, st, nb))) return rc;
     }
     // the last two blocks: the super factors of chi_1 and chi_2 of the grouped blocks
     int all[kMaxGroup];
@@ -750,19 +795,29 @@ int cpn_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
       a.want_m3 = q == 2;
       if ((rc = pass(a))) return rc;
       const int n = G - 1 + q;
-      if ((rc = cpn_apply(v, m, n, nullptr, q == 1 ? ref.B : ref.C, w.cur.pad[q], gamma_of(o->beta), eps, st)))
+      const float* nb = nullptr;
+      if (hook) {
+        FView ct[kMaxModes];
+        for (int g = 0; g < G; ++g) ct[g] = gx1[g];
+        ct[N - 2] = pad_view(w.num.pad[1]);
+        ct[N - 1] = pad_view(w.num.pad[2]);
+        if ((rc = hook->run(n, ct, &nb))) return rc;
+      }
+      if ((rc = cpn_apply(v, m, n, nullptr, q == 1 ? ref.B : ref.C, w.cur.pad[q], gamma_of(o->beta), eps, st, nb)))
         return rc;
     }
   }
   return COMM_OK;
 }
 
-int cp_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
-  return x->ndim == 3 ? cp3_bcomm(ctx, x, m, block, o, st) : cpn_bcomm(ctx, x, m, block, o, st);
+int cp_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st,
+             const NumHook* hook = nullptr) {
+  return x->ndim == 3 ? cp3_bcomm(ctx, x, m, block, o, st, hook) : cpn_bcomm(ctx, x, m, block, o, st, hook);
 }
 
-int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
-  return x->ndim == 3 ? cp3_jcomm(ctx, x, m, o, obj, st) : cpn_jcomm(ctx, x, m, o, obj, st);
+int cp_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st,
+             const NumHook* hook = nullptr) {
+  return x->ndim == 3 ? cp3_jcomm(ctx, x, m, o, obj, st, hook) : cpn_jcomm(ctx, x, m, o, obj, st, hook);
 }
 
 int cp_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
@@ -900,6 +955,183 @@ int check_coo_job(int ndim, const int64_t* dims, const comm_model* model, const 
   for (int n = 0; n < ndim; ++n)
     if (!model->factors[n]) return fail(COMM_EINVAL, "factors[%d] is NULL", n);
   return COMM_OK;
+}
+
+// ---------------------------------------------------------------------------------------- sparse, beta in (0, 2)
+
+// Sparse COO data at beta != 1 (Sec. 6.4, paragraph on sparse tensors): the
+// numerators, which involve P = X * Xhat^(beta-2), are accumulated over the
+// nonzeros (coo_beta_kernel); the denominators involve Q = Xhat^(beta-1) on
+// every cell, so the dense orchestration runs on an all-zero tensor of the
+// same shape (P = 0 there, Q and d(0 | Xhat) exact) and takes its numerators
+// from the nonzeros through a NumHook.  The objective is the dense pass's
+// sum of d(0 | Xhat) plus, over the nonzeros, d(x | Xhat) - d(0 | Xhat).
+
+int grow(comm_ctx* ctx, char** buf, size_t* have, size_t bytes, hipStream_t st, const char* what) {
+  if (bytes <= *have) return COMM_OK;
+  if (ctx->limit && bytes > ctx->limit)
+    return fail(COMM_ENOMEM, "%s of %zu bytes exceeds the context limit of %zu", what, bytes, ctx->limit);
+  if (*buf) {
+    HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+  }
+  hipError_t e = hipMalloc(buf, bytes);
+  if (e != hipSuccess) return fail(COMM_ENOMEM, "hipMalloc(%zu) for the %s: %s", bytes, what, hipGetErrorString(e));
+  *have = bytes;
+  return COMM_OK;
+}
+
+int ensure_zeros(comm_ctx* ctx, size_t bytes, hipStream_t st) {
+  if (bytes <= ctx->zeros_bytes) return COMM_OK;
+  int rc = grow(ctx, &ctx->zeros, &ctx->zeros_bytes, bytes, st, "zero tensor");
+  if (rc) return rc;
+  HIP_TRY(launch_fill_zero(reinterpret_cast<float*>(ctx->zeros), (int64_t)(bytes / 4), st));
+  return COMM_OK;
+}
+
+struct CooBetaWs {
+  float* num;    // [max dims][32] numerator of one block
+  float* w;      // per-nonzero P~ (J-CoMM)
+  double* obj;   // per-workgroup objective corrections
+  size_t bytes;
+};
+
+CooBetaWs coo_beta_layout(const comm_coo* x, char* base) {
+  CooBetaWs s = {};
+  int64_t rows = 1;
+  for (int n = 0; n < x->ndim; ++n) rows = std::max<int64_t>(rows, x->dims[n]);
+  Carve cv;
+  cv.base = base;
+  s.num = cv.take<float>((size_t)rows * kRP);
+  s.w = cv.take<float>((size_t)std::max<int64_t>(x->nnz, 1));
+  s.obj = cv.take<double>((size_t)coo_beta_blocks(x->nnz));
+  s.bytes = cv.off + 256;
+  return s;
+}
+
+int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* o, bool need_L) {
+  int rc = check_coo(x);
+  if (!rc) rc = check_opts(o, need_L);
+  if (rc) return rc;
+  if (!(o->beta > 0.0))
+    return fail(COMM_EUNSUPPORTED, "sparse data at beta = 0: d(0 | y) is infinite (floor X and use the dense path)");
+  if (x->ndim < 3) return fail(COMM_EUNSUPPORTED, "sparse data of order %d at this beta (3 or 4)", x->ndim);
+  if (x->ndim == 4 && x->dims[0] * x->dims[1] > (1 << 24))
+    return fail(COMM_EUNSUPPORTED, "I_1 I_2 = %lld exceeds 2^24", (long long)(x->dims[0] * x->dims[1]));
+  return check_cp_model(model, x->ndim);
+}
+
+// The dense twin of x (the context's zero tensor, allocated unless `no_dense`)
+// and the sparse buffers.
+int coo_beta_setup(comm_ctx* ctx, const comm_coo* x, bool no_dense, comm_dense* xd, CooBetaWs* s, hipStream_t st) {
+  *xd = comm_dense{};
+  xd->ndim = x->ndim;
+  size_t cells = 1;
+  for (int n = 0; n < x->ndim; ++n) {
+    xd->dims[n] = x->dims[n];
+    cells *= (size_t)x->dims[n];
+  }
+  int rc;
+  if (!no_dense && (rc = ensure_zeros(ctx, cells * sizeof(float), st))) return rc;
+  xd->X = no_dense ? nullptr : reinterpret_cast<const float*>(ctx->zeros);
+  const CooBetaWs probe = coo_beta_layout(x, nullptr);
+  if ((rc = grow(ctx, &ctx->sws, &ctx->sws_bytes, probe.bytes, st, "sparse workspace"))) return rc;
+  *s = coo_beta_layout(x, ctx->sws);
+  return COMM_OK;
+}
+
+CooBetaArgs coo_beta_base(const comm_coo* x, const comm_model* m, const comm_opts* o) {
+  CooBetaArgs a = {};
+  a.N = x->ndim;
+  a.R = m->rank;
+  a.nnz = x->nnz;
+  for (int n = 0; n < x->ndim; ++n) {
+    a.dims[n] = (int)x->dims[n];
+    a.idx[n] = x->idx[n];
+  }
+  a.val = x->val;
+  a.mode = -1;
+  a.bc = make_beta_const(o->beta);
+  a.eps = (float)o->eps;
+  return a;
+}
+
+// The hook: numerator of block n over the nonzeros against the contraction
+// views ct, with weights from a rebuild at ct (B-CoMM) or the stored P~ (J-CoMM).
+NumHook coo_num_hook(const comm_coo* x, const comm_model* m, const comm_opts* o, const CooBetaWs& s, bool stored,
+                     hipStream_t st) {
+  NumHook h;
+  h.run = [=](int n, const FView* ct, const float** num) -> int {
+    HIP_TRY(launch_fill_zero(s.num, (int64_t)x->dims[n] * kRP, st));
+    CooBetaArgs a = coo_beta_base(x, m, o);
+    a.mode = n;
+    a.num = s.num;
+    for (int q = 0; q < x->ndim; ++q) {
+      a.ct[q] = ct[q];
+      a.rb[q] = ct[q];
+    }
+    if (stored) a.w_in = s.w;
+    HIP_TRY(launch_coo_beta(a, beta_class_of(o->beta), st));
+    *num = s.num;
+    return COMM_OK;
+  };
+  return h;
+}
+
+int coo_beta_bcomm(comm_ctx* ctx, const comm_coo* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
+  comm_dense xd;
+  CooBetaWs s;
+  int rc = coo_beta_setup(ctx, x, o->beta == 1.0, &xd, &s, st);
+  if (rc) return rc;
+  const NumHook hook = coo_num_hook(x, m, o, s, false, st);
+  return cp_bcomm(ctx, &xd, m, block, o, st, &hook);
+}
+
+// Sum of the objective corrections over the nonzeros at the model m, added
+// to *out (which holds the dense pass's sum at X = 0).
+int coo_beta_obj_add(const comm_coo* x, const comm_model* m, const comm_opts* o, const CooBetaWs& s, bool keep_w,
+                     double* out, hipStream_t st) {
+  CooBetaArgs a = coo_beta_base(x, m, o);
+  for (int q = 0; q < x->ndim; ++q) a.rb[q] = user_view(m, q);
+  a.obj_part = out ? s.obj : nullptr;
+  if (keep_w) a.w_out = s.w;
+  HIP_TRY(launch_coo_beta(a, beta_class_of(o->beta), st));
+  if (out) HIP_TRY(launch_sum_f64(s.obj, coo_beta_blocks(x->nnz), out, out, st));
+  return COMM_OK;
+}
+
+int coo_beta_jcomm(comm_ctx* ctx, const comm_coo* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
+  comm_dense xd;
+  CooBetaWs s;
+  int rc = coo_beta_setup(ctx, x, false, &xd, &s, st);
+  if (rc) return rc;
+  // P~ at the reference (the caller's model before the iteration), kept for
+  // the inner sweeps; its objective corrections summed now into a partial
+  // that is added after the dense pass has written the zero-cell part
+  CooBetaArgs a = coo_beta_base(x, m, o);
+  for (int q = 0; q < x->ndim; ++q) a.rb[q] = user_view(m, q);
+  a.w_out = s.w;
+  a.obj_part = obj ? s.obj : nullptr;
+  HIP_TRY(launch_coo_beta(a, beta_class_of(o->beta), st));
+  comm_opts od = *o;
+  od.cache_pq = 0;  // the cache would hold P~ and Q~ of every cell
+  const NumHook hook = coo_num_hook(x, m, &od, s, true, st);
+  if ((rc = cp_jcomm(ctx, &xd, m, &od, obj, st, &hook))) return rc;
+  if (obj) HIP_TRY(launch_sum_f64(s.obj, coo_beta_blocks(x->nnz), obj, obj, st));
+  return COMM_OK;
+}
+
+int coo_beta_objective(comm_ctx* ctx, const comm_coo* x, const comm_model* m, const comm_opts* o, double* out,
+                       hipStream_t st) {
+  comm_dense xd;
+  CooBetaWs s;
+  int rc = coo_beta_setup(ctx, x, false, &xd, &s, st);
+  if (rc) return rc;
+  if ((rc = cp_objective(ctx, &xd, m, o, out, st))) return rc;
+  return coo_beta_obj_add(x, m, o, s, false, out, st);
 }
 
 // ---------------------------------------------------------------------------------------- J-CoMM, one or many
@@ -1146,6 +1378,8 @@ int comm_destroy(comm_ctx* ctx) {
     for (hipEvent_t e : ctx->bjoin) hipEventDestroy(e);
     if (ctx->bcapture) hipStreamDestroy(ctx->bcapture);
     if (ctx->aux) hipFree(ctx->aux);
+    if (ctx->zeros) hipFree(ctx->zeros);
+    if (ctx->sws) hipFree(ctx->sws);
     if (ctx->bfork) hipEventDestroy(ctx->bfork);
     delete ctx;
     return rc;
@@ -1283,12 +1517,51 @@ int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model,
                             double* obj_ref_dev, void* stream) {
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (opts && opts->beta != 1.0) {
+      int rc = check_coo_beta(x, model, opts, true);
+      if (rc) return rc;
+      if ((rc = set_device(ctx))) return rc;
+      hipStream_t st = (hipStream_t)stream;
+      rc = coo_beta_jcomm(ctx, x, model, opts, obj_ref_dev, st);
+      ctx->last_stream = st;
+      return rc;
+    }
     int rc = check_coo(x);
     if (!rc) rc = check_coo_job(x->ndim, x->dims, model, opts);
     if (rc) return rc;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
     rc = coo_jcomm_kl(ctx, x, model, opts, obj_ref_dev, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,
+                       void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_coo_beta(x, model, opts, false);
+    if (rc) return rc;
+    if (block < -1 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = coo_beta_bcomm(ctx, x, model, block, opts, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* model, const comm_opts* opts,
+                            double* out_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (!out_dev) return fail(COMM_EINVAL, "out_dev is NULL");
+    int rc = check_coo_beta(x, model, opts, false);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = coo_beta_objective(ctx, x, model, opts, out_dev, st);
     ctx->last_stream = st;
     return rc;
   });

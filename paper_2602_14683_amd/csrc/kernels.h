@@ -231,6 +231,34 @@ struct ExtrapArgs {
 hipError_t launch_extrap_alpha(const ExtrapArgs& a, hipStream_t s);
 hipError_t launch_extrap_apply(const ExtrapArgs& a, hipStream_t s);
 
+// Sparse COO at any beta in (0, 2) (Sec. 6.4, paragraph on sparse tensors):
+// per nonzero t (half a wavefront, lane = rank component), X~_t from the
+// rebuild set rb, P_t = x_t max(X~_t, eps)^(beta-2), and for `mode` >= 0
+// num[i_mode][r] += P_t prod_{m != mode} ct_m[i_m][r] (float atomics).  With
+// w_in the weights come from an earlier call instead of a rebuild; w_out
+// keeps them.  obj_part (one value per workgroup) receives the sum over the
+// nonzeros of d(x | X~) - d(0 | X~), the correction of a dense evaluation at
+// X = 0.  Nonzeros with a coordinate outside [0, dims) are skipped.
+struct CooBetaArgs {
+  int N, R;
+  int64_t nnz;
+  int dims[4];
+  const int32_t* idx[4];
+  const float* val;
+  FView rb[4];
+  FView ct[4];
+  int mode;
+  float* num;              // [dims[mode]][32], zeroed by the caller
+  const float* w_in;
+  float* w_out;
+  double* obj_part;
+  BetaConst bc;
+  float eps;
+};
+int coo_beta_blocks(int64_t nnz);
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+hipError_t launch_coo_beta(const CooBetaArgs& a, int beta_class, hipStream_t s);
+
 // Sum of n float64 partials in a fixed order; writes *out (device).  If add_to
 // is not NULL its value is added.
 hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, double* out, hipStream_t s);

@@ -66,11 +66,13 @@ def test_coo_day_hour_lat_lon_workload(ctx):
         assert max_rel(host64(a), b) < 1e-4
 
 
-def test_coo_rejects_beta_other_than_one(ctx):
+def test_coo_rejects_beta_zero(ctx):
+    """Sparse data at beta = 0: d(0 | y) is infinite, so the sparse path refuses
+    it (beta in (0, 2) is served; see tests/test_gpu_sparse_beta.py)."""
     s = workloads.sparse_small(2)
     idx, val = _dev_coo(s)
     fac = [dev(a) for a in s.init]
-    o = comm._opts(0.5, 1e-12, None, 1)
+    o = comm._opts(0.0, 1e-12, None, 1)
     c = comm.Coo()
     c.ndim = 4
     for n, d in enumerate(s.dims):
