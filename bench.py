@@ -20,6 +20,7 @@ stream), and the FP64 oracle timed on the host cores on a bounded sample.
   python bench.py --workload cp4 [--beta B]          # order-4 CP 80x70x60x50, R = 10 (the paper's synthetic shape)
   python bench.py --workload tucker4 [--beta B]      # order-4 Tucker 80x70x60x50, core 10x9x8x7
   python bench.py --workload tucker5 [--beta B]      # order-5 Tucker 27x24x7x100x100, core 10x10x5x10x10
+  python bench.py --workload coo_beta [--beta B]     # the sparse counts at beta != 1 (default 1/2)
   python bench.py --calibrate-copy   # plain device copy of known size, for counter scaling
 """
 from __future__ import annotations
@@ -344,9 +345,10 @@ def run_tucker(args, ctx):
     return out
 
 
-def oracle_rate(run, iters, sample):
+def oracle_rate(run, iters, sample, one_thread=True):
     """The FP64 oracle, as it stands: run(n) performs n outer iterations;
-    timed with the BLAS threads the host gives it and with one thread."""
+    timed with the BLAS threads the host gives it and (unless one_thread is
+    False) with one thread."""
     try:
         from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
@@ -358,7 +360,7 @@ def oracle_rate(run, iters, sample):
     dt = time.perf_counter() - t0
     out = {"value": iters / dt, "unit": "outer it/s", "cores": int(threads), "kind": "oracle",
            "sample": f"{iters} {sample}, {dt:.1f} s"}
-    if threadpool_limits is not None:
+    if one_thread and threadpool_limits is not None:
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             run(1)
@@ -531,6 +533,72 @@ def run_coo(args, ctx):
     return out
 
 
+def run_coo_beta(args, ctx):
+    """Sparse 183x24x1140x1717 counts, 3.3M nonzeros, CP rank 32, beta != 1
+    (default 1/2), J-CoMM L = 1 with the objective: numerators over the
+    nonzeros, the Q~ denominators and the zero cells' objective from the dense
+    pass over all 8.6G cells (the paper notes these are dense at beta != 1)."""
+    import numpy as np
+    import torch
+    import workloads
+    from oracle import cp as ocp
+
+    beta = args.beta if args.beta is not None else 0.5
+    s = workloads.sparse_counts(0)
+    idx = [torch.tensor(s.idx[:, n].astype(np.int32), device="cuda") for n in range(4)]
+    val = torch.from_numpy(s.val.astype(np.float32)).cuda()
+    fac = [torch.from_numpy(a.astype(np.float32)).cuda() for a in s.init]
+    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+
+    def step(t):
+        ctx.cp_jcomm_outer_coo(idx, val, s.dims, fac, L=1, obj_out=trace[t:t + 1], beta=beta)
+
+    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
+    cells = int(np.prod(s.dims))
+    R = 32
+    avg_ms = kernel_ms / max(launches, 1)
+    # per cell and pass, what the denominators need: rebuild 2R and the Q
+    # contraction chain 2R (the pass also runs its P chain on the zeros)
+    flops = 4.0 * R * cells
+    tfl = flops / (avg_ms * 1e-3) / 1e12
+    out = base_line(args, elapsed)
+    out.update({"metric": f"J-CoMM outer iters/s (sparse CP 183x24x1140x1717, 3.3M nnz, R32, beta {beta})",
+                "data": "synthetic (Zipf lat/lon, diurnal hour, Poisson(2)+1 counts)",
+                "config": {"workload": f"jcomm_cp_coo_183x24x1140x1717_nnz3.3M_r32_beta{beta}_L1_obj",
+                           "dims": list(s.dims), "nnz": int(val.numel()), "rank": R, "beta": beta,
+                           "inner_sweeps": 1, "parallelism": "single GPU"},
+                "roofline": {"bound": "mfma", "achieved": round(tfl, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(tfl / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                             "kernel": "cp3_pass_kernel over the 4392 x 1140 x 1717 view of the zero tensor",
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "algorithmic_flops_per_launch": flops},
+                "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    if not args.no_cpu_baseline:
+        # the dense oracle cannot hold this tensor (69 GB in float64): one outer
+        # iteration on the sub-tensor of the first 114 latitude and 171
+        # longitude indices (1/100 of the cells), scaled by the cell ratio
+        keep = (s.idx[:, 2] < 114) & (s.idx[:, 3] < 171)
+        sub = (183, 24, 114, 171)
+        X = np.zeros(sub)
+        X[tuple(s.idx[keep].T)] = s.val[keep]
+        init = [a.astype(np.float32).astype(np.float64) for a in s.init]
+        init = [init[0], init[1], init[2][:114], init[3][:171]]
+        ratio = cells / float(np.prod(sub))
+
+        def run(n):
+            cur = init
+            for _ in range(n):
+                cur, _ = ocp.jcomm_outer(X, cur, beta, L=1, return_ref_obj=True)
+
+        cb = oracle_rate(run, 1, f"J-CoMM outer iteration (L=1, beta={beta}, objective included) of the dense "
+                                 f"oracle on the 183x24x114x171 sub-tensor ({int(keep.sum())} nonzeros), rate "
+                                 f"divided by the cell ratio {ratio:.1f}", one_thread=False)
+        cb["value"] = cb["value"] / ratio
+        out["cpu_baseline"] = cb
+    return out
+
+
 def serving_stream(args, ctx):
     """A Poisson stream of CP / Tucker requests (dims U{16..256}, rank or core
     size in {4, 8, 16, 32}, beta in {0, 1/2, 1, 3/2}), each run to a relative
@@ -590,10 +658,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving", "cp4", "tucker4", "tucker5"], default="cp",
+    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving", "cp4", "tucker4", "tucker5", "coo_beta"], default="cp",
                     help="cp: the headline 256^3 rank-32 CP workload; tucker / coo: the other pass kernels")
     ap.add_argument("--beta", type=float, default=None,
-                    help="beta for --workload tucker (default 0), cp4, tucker4 and tucker5 (default 1)")
+                    help="beta for --workload tucker (default 0), cp4, tucker4 and tucker5 (default 1), coo_beta (default 1/2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -619,7 +687,7 @@ def main() -> int:
     import paper_2602_14683_amd as comm
     ctx = comm.Context(0)
     out = {"cp": run_cp, "tucker": run_tucker, "coo": run_coo, "serving": run_serving, "cp4": run_cp4,
-           "tucker4": run_tucker4, "tucker5": run_tucker5}[args.workload](args, ctx)
+           "tucker4": run_tucker4, "tucker5": run_tucker5, "coo_beta": run_coo_beta}[args.workload](args, ctx)
     if args.workload == "cp" and not args.no_serving:
         out["serving"] = serving_stream(args, ctx)
     ctx.close()
