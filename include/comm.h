@@ -31,7 +31,8 @@
  * orders 4 and 5 the product I_1 ... I_{N-2} must not exceed 2^24); dense
  * Tucker of order 3, 4 and 5 (core sizes J_n <= 32; at orders 4 and 5 the
  * product I_1 ... I_{N-1} must not exceed 2^24); sparse COO CP of order 2 to
- * 4 at beta = 1, of order 3 and 4 at other beta in (0, 2).  Other shapes return COMM_EUNSUPPORTED.  The sparse paths
+ * 4 at beta = 1 and of order 3 to 5 at any beta in (0, 2); sparse COO Tucker
+ * of order 3 to 5 at beta in (0, 2).  Other shapes return COMM_EUNSUPPORTED.  The sparse paths
  * accumulate with float atomics and are reproducible to rounding only; the
  * dense paths are deterministic.
  *
@@ -132,9 +133,9 @@ typedef struct {
  * nonzero t (int32, 0 <= idx < dims[n]); val[t] > 0.  Device buffers. */
 typedef struct {
   int ndim;
-  int64_t dims[4];
+  int64_t dims[COMM_MAX_NDIM];
   int64_t nnz;
-  const int32_t* idx[4];
+  const int32_t* idx[COMM_MAX_NDIM];
   const float* val;
 } comm_coo;
 
@@ -270,8 +271,8 @@ int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* mo
  *   beta in (0, 2), beta != 1: the denominators involve Q = Xhat^(beta-1) on
  *     every cell, so they come from the dense pass run over the whole index
  *     space (an all-zero tensor of the dims, 4 bytes per cell, allocated once
- *     per context and counted against its limit); orders 3 and 4 (order 4:
- *     I_1 I_2 <= 2^24).  The nonzeros' weights P~ are formed once per outer
+ *     per context and counted against its limit); orders 3 to 5 (orders 4 and
+ *     5: I_1 ... I_{N-2} <= 2^24).  The nonzeros' weights P~ are formed once per outer
  *     iteration.  Results are reproducible to float rounding (atomics).
  *   beta = 0 returns COMM_EUNSUPPORTED (d(0 | y) is infinite).
  * If obj_ref_dev is not NULL the objective at the reference is written there. */
@@ -282,15 +283,30 @@ int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model,
  * (Theorem "CP block multiplicative update" with the numerators over the
  * nonzeros, Sec. 6.4): block in 0..N-1 or -1 for a sweep.  At beta = 1 the
  * denominator is closed form; otherwise it comes from the dense pass over the
- * index space as for comm_cp_jcomm_outer_coo at beta != 1 (orders 3 and 4). */
+ * index space as for comm_cp_jcomm_outer_coo at beta != 1 (orders 3 to 5). */
 int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,
                        void* stream);
 
 /* D_beta(X, Xhat) over every cell of a sparse COO tensor, beta in (0, 2),
- * float64: the dense pass's sum of d(0 | Xhat) over the index space plus, over
- * the nonzeros, d(x | Xhat) - d(0 | Xhat).  Orders 3 and 4. */
+ * float64, for a CP or a Tucker model: the dense pass's sum of d(0 | Xhat) over
+ * the index space plus, over the nonzeros, d(x | Xhat) - d(0 | Xhat).  Orders
+ * 3 to 5. */
 int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* model, const comm_opts* opts,
                             double* out_dev, void* stream);
+
+/* Tucker on sparse COO data, orders 3 to 5, beta in (0, 2) (Sec. 4.3 and
+ * App. C with the numerators over the nonzeros, Sec. 6.4).  The numerators'
+ * contraction of P along the last mode is a scatter of the nonzeros into the
+ * rows of the (I_1 ... I_{N-1}) x I_N view, the last mode's numerator a gather
+ * of the rebuild table; the remaining contractions are those of the dense
+ * order-N path.  Denominators: closed form at beta = 1, otherwise the dense
+ * pass over the index space (all-zero tensor, as for CP).  block as in
+ * comm_tucker_update; the J-CoMM call as comm_jcomm_outer.  Results are
+ * reproducible to float rounding (atomics). */
+int comm_tucker_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,
+                           void* stream);
+int comm_tucker_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
+                                double* obj_ref_dev, void* stream);
 
 /* A sparse COO tensor prepared for repeated J-CoMM iterations (CP, beta = 1):
  * two device copies of the nonzeros, sorted by the coordinates of modes 1

@@ -33,7 +33,8 @@ EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_by
             "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo",
             "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
             "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap",
-            "comm_cp_update_coo", "comm_beta_objective_coo"]
+            "comm_cp_update_coo", "comm_beta_objective_coo", "comm_tucker_update_coo",
+            "comm_tucker_jcomm_outer_coo"]
 
 
 class CommError(RuntimeError):
@@ -60,8 +61,8 @@ class Opts(ctypes.Structure):
 
 
 class Coo(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * 4), ("nnz", ctypes.c_int64),
-                ("idx", ctypes.c_void_p * 4), ("val", ctypes.c_void_p)]
+    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * MAX_NDIM), ("nnz", ctypes.c_int64),
+                ("idx", ctypes.c_void_p * MAX_NDIM), ("val", ctypes.c_void_p)]
 
 
 class Extrap(ctypes.Structure):
@@ -113,13 +114,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.comm_cp_update_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), ctypes.c_int, P(Opts), ctypes.c_void_p]
     lib.comm_beta_objective_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
                                             ctypes.c_void_p]
+    lib.comm_tucker_update_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), ctypes.c_int, P(Opts),
+                                           ctypes.c_void_p]
+    lib.comm_tucker_jcomm_outer_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
+                                                ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
                  "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched",
                  "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan",
                  "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap", "comm_cp_update_coo",
-                 "comm_beta_objective_coo"]:
+                 "comm_beta_objective_coo", "comm_tucker_update_coo", "comm_tucker_jcomm_outer_coo"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -201,6 +206,8 @@ def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq:
 
 def _coo(idx: Sequence, val, dims: Sequence[int]) -> Coo:
     import torch
+    if len(dims) > MAX_NDIM:
+        raise ValueError(f"at most {MAX_NDIM} modes")
     c = Coo()
     c.ndim = len(dims)
     for n, dn in enumerate(dims):
@@ -431,17 +438,34 @@ class Context:
         _check(self._lib.comm_cp_update_coo(self._h, ctypes.byref(c), ctypes.byref(m), int(block), ctypes.byref(o),
                                             _stream(stream)))
 
-    def beta_objective_coo(self, idx: Sequence, val, dims: Sequence[int], factors, beta: float = 1.0,
+    def beta_objective_coo(self, idx: Sequence, val, dims: Sequence[int], factors, core=None, beta: float = 1.0,
                            eps: float = 1e-12, out=None, stream=None):
-        """D_beta over every cell of COO data (float64 device scalar), beta in (0, 2)."""
+        """D_beta over every cell of COO data (float64 device scalar), beta in (0, 2), CP or Tucker."""
         import torch
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=val.device)
         c = _coo(idx, val, dims)
-        m, o = _model(factors), _opts(beta, eps, None)
+        m, o = _model(factors, core), _opts(beta, eps, None)
         _check(self._lib.comm_beta_objective_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o),
                                                  _ptr(out, "out"), _stream(stream)))
         return out
+
+    def tucker_update_coo(self, idx: Sequence, val, dims: Sequence[int], core, factors, block: int = -2,
+                          beta: float = 1.0, eps: float = 1e-12, stream=None) -> None:
+        """B-CoMM block update(s) of a Tucker model on COO data, beta in (0, 2) (-1 core, n factor, -2 sweep)."""
+        c = _coo(idx, val, dims)
+        m, o = _model(factors, core), _opts(beta, eps, None)
+        _check(self._lib.comm_tucker_update_coo(self._h, ctypes.byref(c), ctypes.byref(m), int(block),
+                                                ctypes.byref(o), _stream(stream)))
+
+    def tucker_jcomm_outer_coo(self, idx: Sequence, val, dims: Sequence[int], core, factors, beta: float = 1.0,
+                               L: int = 1, eps: float = 1e-12, obj_out=None, stream=None) -> None:
+        """One J-CoMM outer iteration of a Tucker model on COO data, beta in (0, 2)."""
+        c = _coo(idx, val, dims)
+        m, o = _model(factors, core), _opts(beta, eps, None, L)
+        optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
+        _check(self._lib.comm_tucker_jcomm_outer_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o),
+                                                     optr, _stream(stream)))
 
     def coo_plan(self, idx: Sequence, val, dims: Sequence[int], stream=None) -> "CooPlan":
         """Sorted device copies of a COO tensor for repeated beta = 1 J-CoMM iterations."""

@@ -932,9 +932,12 @@ int extrap_apply(const comm_dense* x, comm_model* m, comm_model* prev, int b, fl
 
 // ---------------------------------------------------------------------------------------- sparse checks
 
-int check_coo(const comm_coo* x) {
+// max_ndim: 4 for the beta = 1 CP kernels, COMM_MAX_NDIM for the others.
+int check_coo(const comm_coo* x, int max_ndim = 4) {
   if (!x) return fail(COMM_EINVAL, "x is NULL");
-  if (x->ndim < 2 || x->ndim > 4) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
+  if (x->ndim < 2 || x->ndim > COMM_MAX_NDIM) return fail(COMM_EINVAL, "ndim = %d", x->ndim);
+  if (x->ndim > max_ndim) return fail(COMM_EUNSUPPORTED, "sparse data of order %d on this path (at most %d)",
+                                      x->ndim, max_ndim);
   if (x->nnz < 0) return fail(COMM_EINVAL, "nnz < 0");
   for (int n = 0; n < x->ndim; ++n) {
     if (x->dims[n] < 1 || x->dims[n] > (1 << 24)) return fail(COMM_EINVAL, "dims[%d]", n);
@@ -1003,6 +1006,7 @@ CooBetaWs coo_beta_layout(const comm_coo* x, char* base) {
   CooBetaWs s = {};
   int64_t rows = 1;
   for (int n = 0; n < x->ndim; ++n) rows = std::max<int64_t>(rows, x->dims[n]);
+  rows = (rows + 31) / 32 * 32;  // also the padded fibre mode of the Tucker path
   Carve cv;
   cv.base = base;
   s.num = cv.take<float>((size_t)rows * kRP);
@@ -1013,15 +1017,22 @@ CooBetaWs coo_beta_layout(const comm_coo* x, char* base) {
 }
 
 int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* o, bool need_L) {
-  int rc = check_coo(x);
+  int rc = check_coo(x, COMM_MAX_NDIM);
   if (!rc) rc = check_opts(o, need_L);
   if (rc) return rc;
   if (!(o->beta > 0.0))
     return fail(COMM_EUNSUPPORTED, "sparse data at beta = 0: d(0 | y) is infinite (floor X and use the dense path)");
-  if (x->ndim < 3) return fail(COMM_EUNSUPPORTED, "sparse data of order %d at this beta (3 or 4)", x->ndim);
-  if (x->ndim == 4 && x->dims[0] * x->dims[1] > (1 << 24))
-    return fail(COMM_EUNSUPPORTED, "I_1 I_2 = %lld exceeds 2^24", (long long)(x->dims[0] * x->dims[1]));
-  return check_cp_model(model, x->ndim);
+  if (x->ndim < 3) return fail(COMM_EUNSUPPORTED, "sparse data of order %d on this path (3 to 5)", x->ndim);
+  if (!model) return fail(COMM_EINVAL, "model is NULL");
+  // the dense twin's shape limits (3-way view for CP, row view for Tucker)
+  comm_dense xd = {};
+  xd.ndim = x->ndim;
+  for (int n = 0; n < x->ndim; ++n) xd.dims[n] = x->dims[n];
+  xd.X = reinterpret_cast<const float*>(x->val);  // not read: shapes only
+  if ((rc = check_dense_shape(&xd))) return rc;
+  if (model->kind == COMM_CP) return check_cp_model(model, x->ndim);
+  if (model->kind == COMM_TUCKER) return tucker_check_model(model, &xd);
+  return fail(COMM_EINVAL, "model kind %d", model->kind);
 }
 
 // The dense twin of x (the context's zero tensor, allocated unless `no_dense`)
@@ -1130,8 +1141,25 @@ int coo_beta_objective(comm_ctx* ctx, const comm_coo* x, const comm_model* m, co
   CooBetaWs s;
   int rc = coo_beta_setup(ctx, x, false, &xd, &s, st);
   if (rc) return rc;
+  if (m->kind == COMM_TUCKER) {
+    const TkSparse sp{x, s.w, s.num, s.obj};
+    return tuckern_objective(ctx, &xd, m, o, out, st, &sp);
+  }
   if ((rc = cp_objective(ctx, &xd, m, o, out, st))) return rc;
   return coo_beta_obj_add(x, m, o, s, false, out, st);
+}
+
+// Sparse Tucker (orders 3 to 5) on the order-N path; at beta = 1 no dense pass.
+int coo_tucker(comm_ctx* ctx, const comm_coo* x, comm_model* m, int block, const comm_opts* o, double* obj,
+               bool jcomm, hipStream_t st) {
+  comm_dense xd;
+  CooBetaWs s;
+  int rc = coo_beta_setup(ctx, x, o->beta == 1.0, &xd, &s, st);
+  if (rc) return rc;
+  const TkSparse sp{x, s.w, s.num, s.obj};
+  comm_opts od = *o;
+  od.cache_pq = 0;
+  return jcomm ? tuckern_jcomm(ctx, &xd, m, &od, obj, st, &sp) : tuckern_bcomm(ctx, &xd, m, block, &od, st, &sp);
 }
 
 // ---------------------------------------------------------------------------------------- J-CoMM, one or many
@@ -1520,6 +1548,7 @@ int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model,
     if (opts && opts->beta != 1.0) {
       int rc = check_coo_beta(x, model, opts, true);
       if (rc) return rc;
+      if (model->kind != COMM_CP) return fail(COMM_EINVAL, "model kind is not CP");
       if ((rc = set_device(ctx))) return rc;
       hipStream_t st = (hipStream_t)stream;
       rc = coo_beta_jcomm(ctx, x, model, opts, obj_ref_dev, st);
@@ -1543,10 +1572,42 @@ int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int 
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = check_coo_beta(x, model, opts, false);
     if (rc) return rc;
+    if (model->kind != COMM_CP) return fail(COMM_EINVAL, "model kind is not CP");
     if (block < -1 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
     rc = coo_beta_bcomm(ctx, x, model, block, opts, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_tucker_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,
+                           void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_coo_beta(x, model, opts, false);
+    if (rc) return rc;
+    if (model->kind != COMM_TUCKER) return fail(COMM_EINVAL, "model kind is not Tucker");
+    if (block < -2 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = coo_tucker(ctx, x, model, block, opts, nullptr, false, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_tucker_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
+                                double* obj_ref_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = check_coo_beta(x, model, opts, true);
+    if (rc) return rc;
+    if (model->kind != COMM_TUCKER) return fail(COMM_EINVAL, "model kind is not Tucker");
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = coo_tucker(ctx, x, model, -2, opts, obj_ref_dev, true, st);
     ctx->last_stream = st;
     return rc;
   });

@@ -242,11 +242,11 @@ hipError_t launch_extrap_apply(const ExtrapArgs& a, hipStream_t s);
 struct CooBetaArgs {
   int N, R;
   int64_t nnz;
-  int dims[4];
-  const int32_t* idx[4];
+  int dims[kMaxModes];
+  const int32_t* idx[kMaxModes];
   const float* val;
-  FView rb[4];
-  FView ct[4];
+  FView rb[kMaxModes];
+  FView ct[kMaxModes];
   int mode;
   float* num;              // [dims[mode]][32], zeroed by the caller
   const float* w_in;
@@ -258,6 +258,35 @@ struct CooBetaArgs {
 int coo_beta_blocks(int64_t nnz);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_coo_beta(const CooBetaArgs& a, int beta_class, hipStream_t s);
+
+// Sparse COO data for an order-N Tucker model (N = 3..5) on the
+// (I_1 ... I_{N-1}) x I_N view: per nonzero t (half a wavefront, lane = d)
+// X~_t = sum_d T[row_t][d] C[i_N][d] from the rebuild table T and fibre-mode
+// factor C, P_t = x_t max(X~_t, eps)^(beta-2) (or w_in[t]); then
+//   op 1: out[row_t][d] += P_t Cc[i_N][d]   (the V rows: P contracted on mode N)
+//   op 2: out[i_N][d]   += P_t Tc[row_t][d] (the fibre-mode numerator)
+// with the contraction set's fibre factor Cc / table Tc (float atomics).
+// w_out keeps the weights; obj_part receives per workgroup the sum over the
+// nonzeros of d(x | X~) - d(0 | X~).  Out-of-range coordinates are skipped.
+struct CooTkArgs {
+  int N;
+  int64_t nnz;
+  int dims[kMaxModes];
+  const int32_t* idx[kMaxModes];
+  const float* val;
+  const float* Tr;
+  FView Cr;
+  int op;
+  const float* Tc;
+  FView Cc;
+  float* out;
+  const float* w_in;
+  float* w_out;
+  double* obj_part;
+  BetaConst bc;
+  float eps;
+};
+hipError_t launch_coo_tucker(const CooTkArgs& a, int beta_class, hipStream_t s);
 
 // Sum of n float64 partials in a fixed order; writes *out (device).  If add_to
 // is not NULL its value is added.

@@ -20,10 +20,10 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
   double obj = 0.0;
   for (int64_t t = half; t < a.nnz; t += nhalf) {
     // every lane of the half reads the same nonzero
-    int ii[4] = {0, 0, 0, 0};
+    int ii[kMaxModes] = {};
     bool ok = true;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < kMaxModes; ++m) {
       if (m < a.N) {
         ii[m] = a.idx[m][t];
         ok = ok && ii[m] >= 0 && ii[m] < a.dims[m];
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
       if (rlive) {
         z = 1.0f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < kMaxModes; ++m)
           if (m < a.N) z *= a.rb[m].at(ii[m], r, a.dims[m]);
       }
       // sum over the 32 lanes of this half (partners stay inside the half)
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
     if (a.mode >= 0 && rlive) {
       float c = w;
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < kMaxModes; ++m)
         if (m < a.N && m != a.mode) c *= a.ct[m].at(ii[m], r, a.dims[m]);
       unsafeAtomicAdd(&a.num[(int64_t)ii[a.mode] * kRP + r], c);
     }
@@ -73,6 +73,76 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
       a.obj_part[blockIdx.x] = s;
     }
   }
+}
+
+template <int BC>
+__global__ void __launch_bounds__(kCooBetaThreads) coo_tucker_kernel(CooTkArgs a) {
+  __shared__ double lobj[kCooBetaThreads / 64];
+  const int lane = threadIdx.x & 63;
+  const int d = lane & 31;
+  const int64_t half = ((int64_t)blockIdx.x * kCooBetaThreads + threadIdx.x) >> 5;
+  const int64_t nhalf = ((int64_t)gridDim.x * kCooBetaThreads) >> 5;
+  const int L = a.N - 1;  // the fibre mode
+  double obj = 0.0;
+  for (int64_t t = half; t < a.nnz; t += nhalf) {
+    int ii[kMaxModes] = {};
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < kMaxModes; ++m) {
+      if (m < a.N) {
+        ii[m] = a.idx[m][t];
+        ok = ok && ii[m] >= 0 && ii[m] < a.dims[m];
+      }
+    }
+    if (!ok) continue;
+    int64_t row = 0;
+#pragma unroll
+    for (int m = 0; m < kMaxModes; ++m)
+      if (m < L) row = row * a.dims[m] + ii[m];
+    const int iL = ii[L];
+    float w;
+    if (a.w_in) {
+      w = a.w_in[t];
+    } else {
+      float z = a.Tr[row * kRP + d] * a.Cr.at(iL, d, a.dims[L]);
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) z += __shfl_xor(z, off);
+      const float x = a.val[t];
+      const float y = fmaxf(z, a.eps);
+      float p, q;
+      weights<BC>(x, y, a.bc.beta, p, q);
+      w = p;
+      if (d == 0) {
+        if (a.w_out) a.w_out[t] = p;
+        if (a.obj_part) obj += (double)dbeta_term<BC>(x, y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc);
+      }
+    }
+    if (a.op == 1) unsafeAtomicAdd(&a.out[row * kRP + d], w * a.Cc.at(iL, d, a.dims[L]));
+    else if (a.op == 2) unsafeAtomicAdd(&a.out[(int64_t)iL * kRP + d], w * a.Tc[row * kRP + d]);
+  }
+  if (a.obj_part) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
+    if (lane == 0) lobj[threadIdx.x >> 6] = obj;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int q = 0; q < kCooBetaThreads / 64; ++q) s += lobj[q];
+      a.obj_part[blockIdx.x] = s;
+    }
+  }
+}
+
+hipError_t launch_coo_tucker(const CooTkArgs& a, int bc, hipStream_t s) {
+  const dim3 grid((unsigned)coo_beta_blocks(a.nnz)), block(kCooBetaThreads);
+  switch (bc) {
+    case kHalf: hipLaunchKernelGGL(coo_tucker_kernel<kHalf>, grid, block, 0, s, a); break;
+    case kKL: hipLaunchKernelGGL(coo_tucker_kernel<kKL>, grid, block, 0, s, a); break;
+    case kThreeHalf: hipLaunchKernelGGL(coo_tucker_kernel<kThreeHalf>, grid, block, 0, s, a); break;
+    case kGeneral: hipLaunchKernelGGL(coo_tucker_kernel<kGeneral>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 __global__ void clear_f32_kernel(float* p, int64_t n) {

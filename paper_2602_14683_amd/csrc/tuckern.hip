@@ -140,6 +140,22 @@ __global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* 
   if (t == 0) den[n * kRP + j] = j < m.J[n] ? part[0] : 0.0f;
 }
 
+// Total mass of the model, sum over the cells of Xhat = sum_j G[j] prod_m
+// S_m[j_m] = <G, dcore> over the padded core, in float64, fixed order.
+__global__ void __launch_bounds__(256) tkn_mass_kernel(const float* G, const float* dcore, int64_t n, double* out) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int64_t e = t; e < n; e += 256) s += (double)G[e] * (double)dcore[e];
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = red[0];
+}
+
 namespace {
 
 struct TkNCopy {
@@ -606,12 +622,34 @@ int tkn_apply(const comm_model* m, const TkNWs& w, int blk, const SlotsN& num, c
   return COMM_OK;
 }
 
+CooTkArgs coo_tk_args(const TkSparse* sp, const TkNWs& w, const comm_opts* o, const float* Tr, FView Cr) {
+  CooTkArgs a = {};
+  const comm_coo* x = sp->coo;
+  a.N = x->ndim;
+  a.nnz = x->nnz;
+  for (int n = 0; n < x->ndim; ++n) {
+    a.dims[n] = (int)x->dims[n];
+    a.idx[n] = x->idx[n];
+  }
+  a.val = x->val;
+  a.Tr = Tr;
+  a.Cr = Cr;
+  a.bc = make_beta_const(o->beta);
+  a.eps = (float)o->eps;
+  (void)w;
+  return a;
+}
+
 // Update of block blk with X rebuilt from w.Tr and the fibre-mode factor cl
 // (or read from the cached P~ / Q~), contraction sets ns / ds (their fibre-mode
 // factors transposed in cnT / cdT; for the fibre block their tables in w.TT).
+// With sp (sparse data) the numerator comes from the nonzeros: weights
+// rebuilt from (w.Tr, cl) or, when stored, taken from sp->w; tnum is the
+// contraction set's table in row layout (fibre block).
 int tkn_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, const TkNWs& w, int blk,
               FView cl, const TkNModel& ns, const TkNModel& ds, const float* cnT, const float* cdT, bool cached,
-              bool want_obj, FView anchor, const TkNCopy& pad, double* obj, hipStream_t st) {
+              bool want_obj, FView anchor, const TkNCopy& pad, double* obj, hipStream_t st,
+              const TkSparse* sp = nullptr, const float* tnum = nullptr, bool stored = false) {
   const bool kl = o->beta == 1.0;
   const int sets = kl ? 1 : 2;
   const int bc = beta_class_of(o->beta);
@@ -625,19 +663,46 @@ int tkn_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
   }
   SlotsN num, den;
   int rc;
+  // sparse data at beta = 1: the dense passes would only give numerators
+  const bool dense_pass = !(sp && kl);
+  CooTkArgs sa = {};
+  if (sp) {
+    sa = coo_tk_args(sp, w, o, w.Tr, cl);
+    if (stored) sa.w_in = sp->w;
+  }
   if (blk == w.N - 1) {
     a.T2nT = w.TT[0];
     a.T2dT = w.TT[1];
-    rc = profiled(ctx, st, [&] { return launch_tk_m3(a, bc, mode, sets, st); });
-    if (rc) return rc;
+    if (dense_pass) {
+      rc = profiled(ctx, st, [&] { return launch_tk_m3(a, bc, mode, sets, st); });
+      if (rc) return rc;
+    }
     num = SlotsN{w.m3[0], w.npg, w.Kp};
     den = SlotsN{w.m3[1], w.npg, w.Kp};
+    if (sp) {
+      HIP_TRY(launch_fill_zero(sp->buf, (int64_t)w.Kp * kRP, st));
+      sa.op = 2;
+      sa.Tc = tnum;
+      sa.out = sp->buf;
+      HIP_TRY(launch_coo_tucker(sa, bc, st));
+      num = SlotsN{sp->buf, 1, w.Kp};
+    }
   } else {
     a.CnT = cnT;
     a.CdT = cdT;
-    rc = profiled(ctx, st, [&] { return launch_tk_v(a, bc, mode, want_obj, sets, st); });
-    if (rc) return rc;
-    if (want_obj && obj) HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, obj, st));
+    if (dense_pass) {
+      rc = profiled(ctx, st, [&] { return launch_tk_v(a, bc, mode, want_obj, sets, st); });
+      if (rc) return rc;
+      if (want_obj && obj) HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, obj, st));
+    }
+    if (sp) {
+      // V of the numerator from the nonzeros (the dense pass left it zero)
+      HIP_TRY(launch_fill_zero(w.V[0], w.np * kRP, st));
+      sa.op = 1;
+      sa.Cc = ns.F[w.N - 1];
+      sa.out = w.V[0];
+      HIP_TRY(launch_coo_tucker(sa, bc, st));
+    }
     const TkNModel cs[2] = {ns, ds};
     SlotsN nd[2];
     if ((rc = tkn_numerators(w, blk, cs, sets, nd, st))) return rc;
@@ -671,8 +736,8 @@ size_t tuckern_workspace_bytes(const comm_dense* x, const comm_model* m, const c
   return tkn_layout(x, m, nullptr, cache).bytes;
 }
 
-int tuckern_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o,
-                  hipStream_t st) {
+int tuckern_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st,
+                  const TkSparse* sp) {
   TkNWs w = tkn_layout(x, m, nullptr, false);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
@@ -691,20 +756,20 @@ int tuckern_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, 
       TkNWs w2 = w;
       w2.TT[1] = w.TT[0];
       rc = tkn_block(ctx, x, m, o, w2, blk, cur.F[last], cur, cur, nullptr, nullptr, false, false,
-                     block_viewn(cur, blk), w.cur, nullptr, st);
+                     block_viewn(cur, blk), w.cur, nullptr, st, sp, w.Tr);
     } else {
       rc = tkn_block(ctx, x, m, o, w, blk, cur.F[last], cur, cur, w.cur.facTL, w.cur.facTL, false, false,
-                     block_viewn(cur, blk), w.cur, nullptr, st);
+                     block_viewn(cur, blk), w.cur, nullptr, st, sp, w.Tr);
     }
     if (rc) return rc;
   }
   return COMM_OK;
 }
 
-int tuckern_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj,
-                  hipStream_t st) {
+int tuckern_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st,
+                  const TkSparse* sp) {
   const bool kl = o->beta == 1.0;
-  const bool cache = o->cache_pq && !kl;
+  const bool cache = o->cache_pq && !kl && !sp;
   TkNWs w = tkn_layout(x, m, nullptr, cache);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
@@ -715,6 +780,23 @@ int tuckern_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_
   // the reference, and so its table, is fixed for the whole outer iteration
   if ((rc = tkn_table(w, &ref, 1, &w.Tr, st))) return rc;
   bool obj_pending = obj != nullptr;
+  if (sp) {
+    // the nonzeros' weights at the reference, kept for the inner sweeps, and
+    // their objective corrections (added once the zero cells' part is written)
+    CooTkArgs sa = coo_tk_args(sp, w, o, w.Tr, ref.F[last]);
+    sa.w_out = sp->w;
+    sa.obj_part = obj ? sp->obj : nullptr;
+    HIP_TRY(launch_coo_tucker(sa, beta_class_of(o->beta), st));
+    if (kl && obj) {
+      // no dense pass at beta = 1: the zero cells contribute sum Xhat, the
+      // model's total mass, from the closed-form denominators' column sums
+      hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(kRP, w.N + 1), dim3(256), 0, st, ref, w.den_vec, w.dcore);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(tkn_mass_kernel, dim3(1), dim3(256), 0, st, ref.G, w.dcore, w.CR * kRP, obj);
+      HIP_TRY(hipGetLastError());
+      obj_pending = false;
+    }
+  }
   if (cache) {
     TkPassArgs a = passn_args(x, o, w);
     a.T2r = w.Tr;
@@ -766,16 +848,17 @@ int tuckern_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_
           if ((rc = tkn_transpose(w, w.V[k], w.TT[k], st))) return rc;
       }
       rc = tkn_block(ctx, x, m, o, w, blk, ref.F[last], ns, ds, w.num.facTL, w.den.facTL, cache, obj_pending,
-                     block_viewn(ref, blk), w.cur, obj, st);
+                     block_viewn(ref, blk), w.cur, obj, st, sp, w.V[0], true);
       if (rc) return rc;
       obj_pending = false;
     }
   }
+  if (sp && obj) HIP_TRY(launch_sum_f64(sp->obj, coo_beta_blocks(sp->coo->nnz), obj, obj, st));
   return COMM_OK;
 }
 
 int tuckern_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,
-                      hipStream_t st) {
+                      hipStream_t st, const TkSparse* sp) {
   TkNWs w = tkn_layout(x, m, nullptr, false);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
@@ -789,5 +872,11 @@ int tuckern_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, c
   rc = profiled(ctx, st, [&] { return launch_tk_v(a, beta_class_of(o->beta), kTkFromX, true, 0, st); });
   if (rc) return rc;
   HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, out, st));
+  if (sp) {
+    CooTkArgs sa = coo_tk_args(sp, w, o, w.Tr, cur.F[w.N - 1]);
+    sa.obj_part = sp->obj;
+    HIP_TRY(launch_coo_tucker(sa, beta_class_of(o->beta), st));
+    HIP_TRY(launch_sum_f64(sp->obj, coo_beta_blocks(sp->coo->nnz), out, out, st));
+  }
   return COMM_OK;
 }
