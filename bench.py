@@ -21,6 +21,7 @@ stream), and the FP64 oracle timed on the host cores on a bounded sample.
   python bench.py --workload tucker4 [--beta B]      # order-4 Tucker 80x70x60x50, core 10x9x8x7
   python bench.py --workload tucker5 [--beta B]      # order-5 Tucker 27x24x7x100x100, core 10x10x5x10x10
   python bench.py --workload coo_beta [--beta B]     # the sparse counts at beta != 1 (default 1/2)
+  python bench.py --workload tucker5_coo [--beta B]  # sparse 27x24x7x100x100 counts, Tucker (10,10,5,10,10)
   python bench.py --calibrate-copy   # plain device copy of known size, for counter scaling
 """
 from __future__ import annotations
@@ -599,6 +600,58 @@ def run_coo_beta(args, ctx):
     return out
 
 
+def run_tucker5_coo(args, ctx):
+    """Sparse counts with the shape, ranks and sparsity of the paper's 5-way
+    experiment: 27 x 24 x 7 x 100 x 100, 0.6% nonzeros (Poisson(2) + 1),
+    Tucker core 10 x 10 x 5 x 10 x 10, J-CoMM (L = 1, objective every
+    iteration), beta = 1 by default (closed-form denominators, no dense pass)."""
+    import numpy as np
+    import torch
+    import workloads
+    from oracle import tucker as otk
+
+    beta = args.beta if args.beta is not None else 1.0
+    dims, J = (27, 24, 7, 100, 100), (10, 10, 5, 10, 10)
+    s = workloads.sparse_small(0, dims=dims, density=0.006, rank=2)
+    rng = np.random.default_rng(1)
+    core0 = rng.uniform(0.1, 1.0, J).astype(np.float32)
+    fac0 = [rng.uniform(0.1, 1.0, (d, j)).astype(np.float32) for d, j in zip(dims, J)]
+    idx = [torch.tensor(s.idx[:, n].astype(np.int32), device="cuda") for n in range(5)]
+    val = torch.from_numpy(s.val.astype(np.float32)).cuda()
+    G = torch.from_numpy(core0).cuda()
+    F = [torch.from_numpy(a).cuda() for a in fac0]
+    trace = torch.zeros(args.warmup + args.steps + 1, dtype=torch.float64, device="cuda")
+
+    def step(t):
+        ctx.tucker_jcomm_outer_coo(idx, val, dims, G, F, beta=beta, L=1, obj_out=trace[t:t + 1])
+
+    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
+    nnz = int(val.numel())
+    out = base_line(args, elapsed)
+    out.update({"metric": f"J-CoMM outer iters/s (sparse Tucker 27x24x7x100x100, {nnz} nnz, core 10x10x5x10x10, "
+                          f"beta {beta})",
+                "data": "synthetic (uniform 0.6% support, Poisson(2)+1 counts)",
+                "config": {"workload": f"jcomm_tucker_coo_27x24x7x100x100_nnz{nnz}_core10x10x5x10x10_beta{beta}_L1_obj",
+                           "dims": list(dims), "nnz": nnz, "core": list(J), "beta": beta, "inner_sweeps": 1,
+                           "parallelism": "single GPU"},
+                "roofline": None if launches == 0 else {
+                    "bound": "hbm", "kernel": "tk_v_kernel / tk_m3_kernel on the zero tensor (Q~ denominators)",
+                    "kernel_avg_us": round(kernel_ms / launches * 1e3, 2), "launches": launches},
+                "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
+    if not args.no_cpu_baseline:
+        X = workloads.densify(s)
+
+        def run(n):
+            g, f = core0.astype(np.float64), [a.astype(np.float64) for a in fac0]
+            for _ in range(n):
+                g, f, _ = otk.jcomm_outer(X, g, f, beta, L=1, return_ref_obj=True)
+
+        out["cpu_baseline"] = oracle_rate(run, 2, f"J-CoMM outer iterations (L=1, beta={beta}, objective included) "
+                                                  "of the dense oracle on the densified 45M-cell tensor", one_thread=False)
+    return out
+
+
 def serving_stream(args, ctx):
     """A Poisson stream of CP / Tucker requests (dims U{16..256}, rank or core
     size in {4, 8, 16, 32}, beta in {0, 1/2, 1, 3/2}), each run to a relative
@@ -658,7 +711,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving", "cp4", "tucker4", "tucker5", "coo_beta"], default="cp",
+    ap.add_argument("--workload", choices=["cp", "tucker", "coo", "serving", "cp4", "tucker4", "tucker5", "coo_beta", "tucker5_coo"], default="cp",
                     help="cp: the headline 256^3 rank-32 CP workload; tucker / coo: the other pass kernels")
     ap.add_argument("--beta", type=float, default=None,
                     help="beta for --workload tucker (default 0), cp4, tucker4 and tucker5 (default 1), coo_beta (default 1/2)")
@@ -687,7 +740,8 @@ def main() -> int:
     import paper_2602_14683_amd as comm
     ctx = comm.Context(0)
     out = {"cp": run_cp, "tucker": run_tucker, "coo": run_coo, "serving": run_serving, "cp4": run_cp4,
-           "tucker4": run_tucker4, "tucker5": run_tucker5, "coo_beta": run_coo_beta}[args.workload](args, ctx)
+           "tucker4": run_tucker4, "tucker5": run_tucker5, "coo_beta": run_coo_beta,
+           "tucker5_coo": run_tucker5_coo}[args.workload](args, ctx)
     if args.workload == "cp" and not args.no_serving:
         out["serving"] = serving_stream(args, ctx)
     ctx.close()

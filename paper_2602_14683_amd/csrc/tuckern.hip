@@ -66,24 +66,38 @@ struct TkNModel {
 // workgroups of row N write dcore.  Every workgroup first forms the column
 // sums itself (the factors are small), in the same order.
 __global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* den, float* dcore) {
-  __shared__ float red[8][33];
+  __shared__ float red[kTkMaxN][8][33];
   __shared__ float S[kTkMaxN][32];
   __shared__ float part[256];
   const int t = threadIdx.x;
   const int c = t & 31, g = t >> 5;
   const int N = m.N;
-  for (int f = 0; f < N; ++f) {
-    float s = 0.0f;
-    for (int r = g; r < m.rows[f]; r += 8) s += m.F[f].at(r, c, m.rows[f]);
-    red[g][c] = s;
+  // column sums of all factors at once: row group g of each factor, then the
+  // eight groups in order
+  {
+    float s[kTkMaxN];
+#pragma unroll
+    for (int f = 0; f < kTkMaxN; ++f) s[f] = 0.0f;
+    int rmax = 0;
+    for (int f = 0; f < N; ++f) rmax = max(rmax, m.rows[f]);
+    for (int r = g; r < rmax; r += 8) {
+#pragma unroll
+      for (int f = 0; f < kTkMaxN; ++f)
+        if (f < N) s[f] += m.F[f].at(r, c, m.rows[f]);
+    }
+#pragma unroll
+    for (int f = 0; f < kTkMaxN; ++f) red[f][g][c] = s[f];
     __syncthreads();
-    if (t < 32) {
+    if (t < N * 32) {
+      const int f = t >> 5;
       float acc = 0.0f;
-      for (int q = 0; q < 8; ++q) acc += red[q][t];
-      S[f][t] = acc;
+      for (int q = 0; q < 8; ++q) acc += red[f][q][c];
+      S[f][c] = acc;
     }
     __syncthreads();
   }
+  // the column sums go out too (after the denominators), for the model's mass
+  if (blockIdx.x == 0 && blockIdx.y == 0 && t < N * 32) den[kTkMaxN * kRP + t] = S[t >> 5][t & 31];
   const int n = blockIdx.y, j = blockIdx.x;
   if (n == N) {
     int rows = 1;
@@ -141,19 +155,15 @@ __global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* 
 }
 
 // Total mass of the model, sum over the cells of Xhat = sum_j G[j] prod_m
-// S_m[j_m] = <G, dcore> over the padded core, in float64, fixed order.
-__global__ void __launch_bounds__(256) tkn_mass_kernel(const float* G, const float* dcore, int64_t n, double* out) {
-  __shared__ double red[256];
+// S_m[j_m] = sum_a den[0][a] S_1[a], from the closed-form denominators and
+// the column sums that tkn_den_closed_kernel leaves behind them; float64,
+// fixed order (one wavefront).
+__global__ void __launch_bounds__(64) tkn_mass_kernel(const float* den, double* out) {
   const int t = threadIdx.x;
-  double s = 0.0;
-  for (int64_t e = t; e < n; e += 256) s += (double)G[e] * (double)dcore[e];
-  red[t] = s;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) red[t] += red[t + h];
-    __syncthreads();
-  }
-  if (t == 0) out[0] = red[0];
+  double s = t < 32 ? (double)den[t] * (double)den[kTkMaxN * kRP + t] : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+  if (t == 0) out[0] = s;
 }
 
 namespace {
@@ -180,7 +190,7 @@ struct TkNWs {
   float* PA[2];           // ping-pong buffers of the mode-product chains
   float* PB[2];
   float* slots[2];
-  float* den_vec;         // [N][32]
+  float* den_vec;         // [N][32] denominators, then [N][32] column sums
   float* dcore;           // [CR][32]
   TkNCopy ref, cur, num, den;
   float *Pc, *Qc;
@@ -273,7 +283,7 @@ TkNWs tkn_layout(const comm_dense* x, const comm_model* md, char* base, bool cac
     w.slots[k] = cv.take<float>(sl);
   }
   w.obj_part = cv.take<double>((size_t)w.vwgs);
-  w.den_vec = cv.take<float>((size_t)kTkMaxN * kRP);
+  w.den_vec = cv.take<float>((size_t)2 * kTkMaxN * kRP);  // denominators, then the column sums
   w.dcore = cv.take<float>(core);
   for (TkNCopy* c : {&w.ref, &w.cur, &w.num, &w.den}) {
     c->core = cv.take<float>(core);
@@ -792,7 +802,7 @@ int tuckern_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_
       // model's total mass, from the closed-form denominators' column sums
       hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(kRP, w.N + 1), dim3(256), 0, st, ref, w.den_vec, w.dcore);
       HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(tkn_mass_kernel, dim3(1), dim3(256), 0, st, ref.G, w.dcore, w.CR * kRP, obj);
+      hipLaunchKernelGGL(tkn_mass_kernel, dim3(1), dim3(64), 0, st, w.den_vec, obj);
       HIP_TRY(hipGetLastError());
       obj_pending = false;
     }
