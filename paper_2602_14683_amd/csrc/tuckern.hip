@@ -65,25 +65,30 @@ struct TkNModel {
 // stride over the other core entries, combined in a fixed order); the
 // workgroups of row N write dcore.  Every workgroup first forms the column
 // sums itself (the factors are small), in the same order.
-__global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* den, float* dcore) {
-  __shared__ float red[kTkMaxN][8][33];
+constexpr int kDenThreads = 1024;
+constexpr int kDenBatch = 4;   // independent loads in flight per thread
+
+__global__ void __launch_bounds__(kDenThreads) tkn_den_closed_kernel(TkNModel m, float* den, float* dcore) {
+  __shared__ float red[kTkMaxN][32][33];
   __shared__ float S[kTkMaxN][32];
-  __shared__ float part[256];
+  __shared__ float part[kDenThreads];
   const int t = threadIdx.x;
-  const int c = t & 31, g = t >> 5;
+  const int c = t & 31, g = t >> 5;   // 32 row groups of 32 lanes
   const int N = m.N;
-  // column sums of all factors at once: row group g of each factor, then the
-  // eight groups in order
+  // column sums of all factors at once: row group g of each factor (loads of
+  // all factors issued together), then the 32 groups in order
   {
     float s[kTkMaxN];
 #pragma unroll
     for (int f = 0; f < kTkMaxN; ++f) s[f] = 0.0f;
     int rmax = 0;
     for (int f = 0; f < N; ++f) rmax = max(rmax, m.rows[f]);
-    for (int r = g; r < rmax; r += 8) {
+    for (int r = g; r < rmax; r += 32) {
+      float v[kTkMaxN];
 #pragma unroll
-      for (int f = 0; f < kTkMaxN; ++f)
-        if (f < N) s[f] += m.F[f].at(r, c, m.rows[f]);
+      for (int f = 0; f < kTkMaxN; ++f) v[f] = f < N ? m.F[f].at(r, c, m.rows[f]) : 0.0f;
+#pragma unroll
+      for (int f = 0; f < kTkMaxN; ++f) s[f] += v[f];
     }
 #pragma unroll
     for (int f = 0; f < kTkMaxN; ++f) red[f][g][c] = s[f];
@@ -91,7 +96,7 @@ __global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* 
     if (t < N * 32) {
       const int f = t >> 5;
       float acc = 0.0f;
-      for (int q = 0; q < 8; ++q) acc += red[f][q][c];
+      for (int q = 0; q < 32; ++q) acc += red[f][q][c];
       S[f][c] = acc;
     }
     __syncthreads();
@@ -102,7 +107,7 @@ __global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* 
   if (n == N) {
     int rows = 1;
     for (int q = 0; q < N - 1; ++q) rows *= m.J[q];
-    for (int e = j * 256 + t; e < rows * kRP; e += gridDim.x * 256) {
+    for (int e = j * kDenThreads + t; e < rows * kRP; e += gridDim.x * kDenThreads) {
       const int d = e & 31;
       float v = 0.0f;
       if (d < m.J[N - 1]) {
@@ -123,31 +128,48 @@ __global__ void __launch_bounds__(256) tkn_den_closed_kernel(TkNModel m, float* 
     int others = 1;
     for (int q = 0; q < N; ++q)
       if (q != n) others *= m.J[q];
-    for (int o = t; o < others; o += 256) {
-      // indices of the other modes from o (last mode fastest), j at mode n
-      int rem = o, off = 0, mul = 1;
-      float w = 1.0f;
-      for (int q = N - 1; q >= 0; --q) {
-        int iq = j;
-        if (q != n) {
-          iq = rem % m.J[q];
-          rem /= m.J[q];
-          w *= S[q][iq];
+    for (int o0 = t; o0 < others; o0 += kDenBatch * kDenThreads) {
+      // kDenBatch entries per thread, their loads issued together
+      int offs[kDenBatch];
+      float ws[kDenBatch];
+#pragma unroll
+      for (int u = 0; u < kDenBatch; ++u) {
+        const int o = o0 + u * kDenThreads;
+        int off = 0;
+        float w = 0.0f;
+        if (o < others) {
+          // indices of the other modes from o (last mode fastest), j at mode n
+          int rem = o, mul = 1;
+          w = 1.0f;
+          for (int q = N - 1; q >= 0; --q) {
+            int iq = j;
+            if (q != n) {
+              iq = rem % m.J[q];
+              rem /= m.J[q];
+              w *= S[q][iq];
+            }
+            if (q == N - 1) {
+              off = iq;
+              mul = kRP;
+            } else {
+              off += iq * mul;
+              mul *= m.J[q];
+            }
+          }
         }
-        if (q == N - 1) {
-          off = iq;
-          mul = kRP;
-        } else {
-          off += iq * mul;
-          mul *= m.J[q];
-        }
+        offs[u] = off;
+        ws[u] = w;
       }
-      acc += m.G[off] * w;
+      float gv[kDenBatch];
+#pragma unroll
+      for (int u = 0; u < kDenBatch; ++u) gv[u] = m.G[offs[u]];
+#pragma unroll
+      for (int u = 0; u < kDenBatch; ++u) acc += gv[u] * ws[u];
     }
   }
   part[t] = acc;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = kDenThreads / 2; h > 0; h >>= 1) {
     if (t < h) part[t] += part[t + h];
     __syncthreads();
   }
@@ -723,7 +745,7 @@ int tkn_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
   const SlotsN* denp = &den;
   SlotsN dcore;
   if (kl) {
-    hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(kRP, w.N + 1), dim3(256), 0, st, ds, w.den_vec, w.dcore);
+    hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(kRP, w.N + 1), dim3(kDenThreads), 0, st, ds, w.den_vec, w.dcore);
     HIP_TRY(hipGetLastError());
     if (blk == -1) {
       dcore = SlotsN{w.dcore, 1, (int)w.CR};
@@ -800,7 +822,7 @@ int tuckern_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_
     if (kl && obj) {
       // no dense pass at beta = 1: the zero cells contribute sum Xhat, the
       // model's total mass, from the closed-form denominators' column sums
-      hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(kRP, w.N + 1), dim3(256), 0, st, ref, w.den_vec, w.dcore);
+      hipLaunchKernelGGL(tkn_den_closed_kernel, dim3(kRP, w.N + 1), dim3(kDenThreads), 0, st, ref, w.den_vec, w.dcore);
       HIP_TRY(hipGetLastError());
       hipLaunchKernelGGL(tkn_mass_kernel, dim3(1), dim3(64), 0, st, w.den_vec, obj);
       HIP_TRY(hipGetLastError());
