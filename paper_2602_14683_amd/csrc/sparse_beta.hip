@@ -18,7 +18,13 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
   const int64_t nhalf = ((int64_t)gridDim.x * kCooBetaThreads) >> 5;
   const bool rlive = r < a.R;
   double obj = 0.0;
-  for (int64_t t = half; t < a.nnz; t += nhalf) {
+  // each half owns a contiguous chunk of the stream, so that equal target
+  // rows of consecutive nonzeros are summed in a register (one atomic per run)
+  const int64_t chunk = (a.nnz + nhalf - 1) / nhalf;
+  const int64_t t0 = half * chunk, t1 = min(a.nnz, t0 + chunk);
+  int run_row = -1;
+  float run_acc = 0.0f;
+  for (int64_t t = t0; t < t1; ++t) {
     // every lane of the half reads the same nonzero
     int ii[kMaxModes] = {};
     bool ok = true;
@@ -59,9 +65,16 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
 #pragma unroll
       for (int m = 0; m < kMaxModes; ++m)
         if (m < a.N && m != a.mode) c *= a.ct[m].at(ii[m], r, a.dims[m]);
-      unsafeAtomicAdd(&a.num[(int64_t)ii[a.mode] * kRP + r], c);
+      const int row = ii[a.mode];
+      if (row != run_row) {
+        if (run_row >= 0) unsafeAtomicAdd(&a.num[(int64_t)run_row * kRP + r], run_acc);
+        run_row = row;
+        run_acc = 0.0f;
+      }
+      run_acc += c;
     }
   }
+  if (run_row >= 0 && rlive) unsafeAtomicAdd(&a.num[(int64_t)run_row * kRP + r], run_acc);
   if (a.obj_part) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
@@ -84,7 +97,13 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_tucker_kernel(CooTkArgs a
   const int64_t nhalf = ((int64_t)gridDim.x * kCooBetaThreads) >> 5;
   const int L = a.N - 1;  // the fibre mode
   double obj = 0.0;
-  for (int64_t t = half; t < a.nnz; t += nhalf) {
+  // contiguous chunk per half; equal target rows of consecutive nonzeros are
+  // summed in a register (one atomic per run)
+  const int64_t chunk = (a.nnz + nhalf - 1) / nhalf;
+  const int64_t t0 = half * chunk, t1 = min(a.nnz, t0 + chunk);
+  int64_t run_row = -1;
+  float run_acc = 0.0f;
+  for (int64_t t = t0; t < t1; ++t) {
     int ii[kMaxModes] = {};
     bool ok = true;
 #pragma unroll
@@ -117,9 +136,18 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_tucker_kernel(CooTkArgs a
         if (a.obj_part) obj += (double)dbeta_term<BC>(x, y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc);
       }
     }
-    if (a.op == 1) unsafeAtomicAdd(&a.out[row * kRP + d], w * a.Cc.at(iL, d, a.dims[L]));
-    else if (a.op == 2) unsafeAtomicAdd(&a.out[(int64_t)iL * kRP + d], w * a.Tc[row * kRP + d]);
+    if (a.op != 0) {
+      const int64_t target = a.op == 1 ? row : (int64_t)iL;
+      const float c = a.op == 1 ? w * a.Cc.at(iL, d, a.dims[L]) : w * a.Tc[row * kRP + d];
+      if (target != run_row) {
+        if (run_row >= 0) unsafeAtomicAdd(&a.out[run_row * kRP + d], run_acc);
+        run_row = target;
+        run_acc = 0.0f;
+      }
+      run_acc += c;
+    }
   }
+  if (run_row >= 0) unsafeAtomicAdd(&a.out[run_row * kRP + d], run_acc);
   if (a.obj_part) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
