@@ -1016,6 +1016,9 @@ CooBetaWs coo_beta_layout(const comm_coo* x, char* base) {
   return s;
 }
 
+// 2^36 cells = 256 GiB of zeros, beyond any single device's memory.
+constexpr uint64_t kMaxZeroCells = uint64_t(1) << 36;
+
 int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* o, bool need_L) {
   int rc = check_coo(x, COMM_MAX_NDIM);
   if (!rc) rc = check_opts(o, need_L);
@@ -1030,6 +1033,15 @@ int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* 
   for (int n = 0; n < x->ndim; ++n) xd.dims[n] = x->dims[n];
   xd.X = reinterpret_cast<const float*>(x->val);  // not read: shapes only
   if ((rc = check_dense_shape(&xd))) return rc;
+  // the dense twin (4 bytes per cell) must fit the device: cap the cell count
+  // before any product can wrap
+  uint64_t cells = 1;
+  for (int n = 0; n < x->ndim; ++n) {
+    if (cells > (kMaxZeroCells / (uint64_t)x->dims[n]))
+      return fail(COMM_ENOMEM, "the index space of this sparse tensor exceeds %llu cells (dense denominators)",
+                  (unsigned long long)kMaxZeroCells);
+    cells *= (uint64_t)x->dims[n];
+  }
   if (model->kind == COMM_CP) return check_cp_model(model, x->ndim);
   if (model->kind == COMM_TUCKER) return tucker_check_model(model, &xd);
   return fail(COMM_EINVAL, "model kind %d", model->kind);

@@ -169,3 +169,21 @@ def test_refuses_beta_zero_and_order_two(ctx):
     torch.cuda.synchronize()
     for a, b in zip(fac, s.init):
         assert np.array_equal(host64(a), f32(b))
+
+
+def test_index_space_beyond_device_is_refused(ctx):
+    """Three modes of 2^24: the dense twin would need 2^72 cells.  The call is
+    refused with COMM_ENOMEM before anything is allocated or launched (the
+    factors are not read, so small stand-ins suffice)."""
+    dims = (1 << 24, 1 << 24, 1 << 24)
+    idx = [torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda") for _ in dims]
+    val = dev(np.array([1.0, 2.0, 3.0]))
+    fac = [dev(np.ones((4, 3))) for _ in dims]
+    with pytest.raises(comm.CommError) as e:
+        ctx.cp_update_coo(idx, val, dims, fac, block=0, beta=0.5)
+    assert e.value.code == comm.COMM_ENOMEM
+    with pytest.raises(comm.CommError) as e:
+        ctx.beta_objective_coo(idx, val, dims, fac, beta=1.5)
+    assert e.value.code == comm.COMM_ENOMEM
+    torch.cuda.synchronize()
+    assert np.array_equal(host64(fac[0]), np.ones((4, 3)))
