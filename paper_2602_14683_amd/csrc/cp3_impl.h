@@ -130,7 +130,7 @@ __device__ __forceinline__ int out_row(int v, int h) { return 8 * (v >> 2) + 4 *
 // d_1 = s^2 [(x + y) - 2 x s S(s^2)],  S(z) = sum_{k>=0} z^k / (2k + 3).
 // Nine terms keep the truncation below 1e-7 relative for |s| < 1/2.  Entries
 // with |s| >= 1/2 ("far") take the direct form, which there loses at most a
-// couple of bits (kl_direct).  x = 0 gives y.  `rsum` is 1 / (x + y).
+// couple of bits.  x = 0 gives y.  `rsum` is 1 / (x + y).
 __device__ __forceinline__ float kl_series(float x, float y, float rsum, bool& far) {
   const float sum = x + y, diff = y - x;
   const float s = diff * rsum;
@@ -154,19 +154,23 @@ __device__ __forceinline__ float kl_direct(float x, float y) {
 }
 
 // Weights and (optionally) the objective term of one entry.  At beta = 1 one
-// reciprocal of y (x + y) serves both P = x / y and the objective's s; `far`
-// flags an entry whose term must be recomputed with kl_direct.
+// reciprocal of y (x + y) serves both P = x / y and the objective's s.  Both
+// forms of d_1 are evaluated and the far flag selects one: a tile of a few
+// hundred entries nearly always holds a far one, so a branch would run for
+// almost every tile.  The direct form takes log(y / x) = -log(P).
 template <int BC, bool kObj>
-__device__ __forceinline__ void entry(float x, float y, const BetaConst& bc, float& p, float& q, float& d,
-                                      bool& far) {
-  far = false;
+__device__ __forceinline__ void entry(float x, float y, const BetaConst& bc, float& p, float& q, float& d) {
   if constexpr (BC == kKL) {
     q = 1.0f;
     if constexpr (kObj) {
       const float sum = x + y;
       const float r = fast_rcp(y * sum);
       p = x * (sum * r);
-      d = kl_series(x, y, y * r, far);
+      bool far;
+      const float ds = kl_series(x, y, y * r, far);
+      // x = 0 makes the direct form NaN; far is false there
+      const float dd = fmaf(x * 0.69314718055994531f, fast_log2(p), y - x);
+      d = far ? dd : ds;
     } else {
       p = x * fast_rcp(y);
     }
@@ -404,7 +408,6 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       }
     } else {
       const f32x16& xh = xh_cur;
-      bool anyfar = false;
       // the tile's 16 nonnegative terms per lane are summed in float32 (relative
       // error <= 15 * 2^-24) before entering the float64 accumulator
       float objt = 0.0f;
@@ -414,32 +417,20 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
         if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
         const float y = fmaxf(xh[v], a.eps);
         float p, q, d = 0.0f;
-        bool far;
-        entry<BC, kObj>(x, y, a.bc, p, q, d, far);
+        entry<BC, kObj>(x, y, a.bc, p, q, d);
         pv[v] = valid[v] ? p : 0.f;
         qv[v] = valid[v] ? q : 0.f;
         if (kObj) objt += valid[v] ? d : 0.0f;
-        anyfar |= far && valid[v];
-        // the general objective is long; keep the scheduler from interleaving all
+        // the objective is long; keep the scheduler from interleaving all
         // sixteen entries (register pressure)
-        if constexpr (kObj && BC != kKL) {
+        if constexpr (kObj) {
           if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }
+      // pin the tile's objective here: left free, the compiler sinks the
+      // sixteen terms past the contraction and keeps x, y and 1 / (x + y) alive
+      if constexpr (kObj && BC == kKL) asm volatile("" : "+v"(objt));
       if constexpr (kObj) obj += (double)objt;
-      if constexpr (kObj && BC == kKL) {
-        // rare: entries with |s| >= 1/2 replace their series term by the direct form
-        if (__builtin_amdgcn_ballot_w64(anyfar)) {
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const float x = xv[v], y = fmaxf(xh[v], a.eps);
-            const float sum = x + y;
-            bool far;
-            const float ds = kl_series(x, y, fast_rcp(sum), far);
-            if (far && valid[v]) obj += (double)kl_direct(x, y) - (double)ds;
-          }
-        }
-      }
       if (kWrite) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {

@@ -130,12 +130,8 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
         if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
         const float y = fmaxf(xh[v], a.eps);
         float p, q, d = 0.0f;
-        bool far;
-        entry<BC, kObj>(x, y, a.bc, p, q, d, far);
-        if constexpr (kObj) {
-          if (BC == kKL && far) d = kl_direct(x, y);
-          objt += ok ? d : 0.0f;
-        }
+        entry<BC, kObj>(x, y, a.bc, p, q, d);
+        if constexpr (kObj) objt += ok ? d : 0.0f;
         pv[v] = ok ? p : 0.0f;
         qv[v] = ok ? q : 0.0f;
       }
@@ -280,8 +276,7 @@ __global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
         if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
         const float y = fmaxf(xh[v], a.eps);
         float p, q, d;
-        bool far;
-        entry<BC, false>(x, y, a.bc, p, q, d, far);
+        entry<BC, false>(x, y, a.bc, p, q, d);
         pv[v] = ok ? p : 0.0f;
         qv[v] = ok ? q : 0.0f;
       }
