@@ -40,33 +40,41 @@ struct T2Args {
   int64_t Pp;
 };
 
-// Workgroup (i, set): T1[b][c] = sum_a A[i][a] G[a][b][c] in LDS, then
-// T2[(i,j)][c] = sum_b B[j][b] T1[b][c] on the matrix cores, one 32-wide j tile
-// per wave at a time, computed transposed (lane = j) so that both the row
-// layout and the transposed copy are written with coalesced stores (zero for
-// c >= J3).
+// Workgroup (i, j slab, set): T1[b][c] = sum_a A[i][a] G[a][b][c] in LDS, then
+// T2[(i,j)][c] = sum_b B[j][b] T1[b][c] on the matrix cores for the slab's
+// (up to) 128 j, one 32-wide j tile per wave, computed transposed (lane = j)
+// so that both the row layout and the transposed copy are written with
+// coalesced stores (zero for c >= J3).  Each slab recomputes T1 (J1 J2 J3
+// products): cheaper than the latency of a workgroup that walks all of J.
+constexpr int kT2Slab = 32 * kWaves;
 __global__ void __launch_bounds__(256) tk_t2_kernel(T2Args t) {
   __shared__ float t1[32][33];
-  const int i = blockIdx.x % t.I, set = blockIdx.x / t.I;
+  __shared__ float sa[32];
+  const int nslab = (t.J + kT2Slab - 1) / kT2Slab;
+  const int i = blockIdx.x % t.I, slab = (blockIdx.x / t.I) % nslab, set = blockIdx.x / (t.I * nslab);
   const TkModel& m = t.m[set];
   const int I = t.I, J = t.J;
+  if (threadIdx.x < 32) sa[threadIdx.x] = (int)threadIdx.x < m.J1 ? m.A.at(i, threadIdx.x, I) : 0.0f;
+  __syncthreads();
+  // unpredicated loads over a in batches (a predicated load per a would be
+  // one dependent round trip each)
+  const int64_t ga = (int64_t)m.J2 * m.ldG;
   for (int e = threadIdx.x; e < 32 * 32; e += 256) {
     const int b = e >> 5, c = e & 31;
-    const bool live = b < m.J2 && c < m.J3;
-    float g[32];
-#pragma unroll
-    for (int a = 0; a < 32; ++a) g[a] = (live && a < m.J1) ? m.G[((int64_t)a * m.J2 + b) * m.ldG + c] : 0.0f;
     float s = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 32; ++a)
-      if (a < m.J1) s = fmaf(m.A.at(i, a, I), g[a], s);
+    if (b < m.J2 && c < m.J3) {
+      const float* gp = m.G + (int64_t)b * m.ldG + c;
+#pragma unroll 8
+      for (int a = 0; a < m.J1; ++a) s = fmaf(sa[a], gp[a * ga], s);
+    }
     t1[b][c] = s;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, w = threadIdx.x >> 6;
   float* out = t.out[set] + (int64_t)i * J * kRP;
   float* outT = t.outT[set];
-  for (int j0 = 32 * w; j0 < J; j0 += 32 * kWaves) {
+  const int j0 = slab * kT2Slab + 32 * w;
+  if (j0 < J) {
     // T2^T[c][j] = sum_b T1[b][c] B[j][b]: A operand T1 (lane: c), B operand B rows (lane: j)
     float brow[16];
     row16(m.B.p + (int64_t)(j0 + col) * kRP + 16 * h, j0 + col < J, brow);
@@ -88,7 +96,7 @@ __global__ void __launch_bounds__(256) tk_t2_kernel(T2Args t) {
     }
   }
   // the transposed copy's padding past the last pair reads as zero
-  if (outT && i == I - 1) {
+  if (outT && i == I - 1 && slab == 0) {
     const int64_t np = (int64_t)I * J;
     const int pad = (int)(t.Pp - np);
     for (int e = threadIdx.x; e < 32 * pad; e += 256) outT[(int64_t)(e / pad) * t.Pp + np + e % pad] = 0.0f;
@@ -106,7 +114,8 @@ hipError_t launch_tk_t2(const TkModel* m, float* const* T2, float* const* T2T, i
   t.I = I;
   t.J = J;
   t.Pp = Pp;
-  hipLaunchKernelGGL(tk_t2_kernel, dim3((unsigned)(I * sets)), dim3(256), 0, s, t);
+  const int nslab = (J + kT2Slab - 1) / kT2Slab;
+  hipLaunchKernelGGL(tk_t2_kernel, dim3((unsigned)(I * nslab * sets)), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
