@@ -237,6 +237,20 @@ enum PassVariant : int { kNumOnly = 0, kNumDen = 1, kCacheNumDen = 2, kCacheWrit
 
 constexpr int kSA = 36;  // row stride of the staged rebuild rows (bank spread for 16-byte reads)
 
+static_assert(kCpTI * 32 % kThreads == 0 && kCpTJ * 32 % kThreads == 0, "staging loops take whole rounds");
+
+// FView::at in two halves, for batches of loads that stay in flight
+// together: the load always reads a clamped, valid address (rows and cols are
+// at least 1), and the mask (scale by 0 outside rows x cols; a factor entry is
+// finite) is applied after the batch.  A select on the loaded value would be
+// turned back into a branch around each load.
+__device__ __forceinline__ float load_clamped(const FView& f, int row, int c, int rows) {
+  return f.p[(size_t)min(row, rows - 1) * f.ld + min(c, f.cols - 1)];
+}
+__device__ __forceinline__ float mask_of(const FView& f, int row, int c, int rows) {
+  return (row < rows && c < f.cols) ? 1.0f : 0.0f;
+}
+
 struct PassShared {
   float t[kWaves][32 * kLdsT];      // per-wave transpose buffers
   float m1[2][2][kCpTI * 32];        // [num/den][k-slice][i][r]
@@ -289,22 +303,13 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   const bool kvalid = kcol < K;
   const unsigned lane_off = (unsigned)(4 * h * K + kt * 32 + col) + (unsigned)k0;
 
-  // ---- stage the workgroup's factor rows in LDS (zero outside rows x cols)
-  for (int e = tid; e < kCpTI * 32; e += kThreads) {
-    const int r = e >> 5, c = e & 31;
-    const int i = i0 + r;
-    if (!kCache) sh.ra[r * kSA + c] = a.r.A.at(i, c, I);
-    sh.na[e] = a.n.A.at(i, c, I);
-    if (kDen) sh.da[e] = a.d.A.at(i, c, I);
-  }
-  for (int e = tid; e < kCpTJ * 32; e += kThreads) {
-    const int r = e >> 5, c = e & 31;
-    const int j = j0 + r;
-    if (!kCache) sh.rb[r * kSA + c] = a.r.B.at(j, c, J);
-    sh.nb[e] = a.n.B.at(j, c, J);
-    if (kDen) sh.db[e] = a.d.B.at(j, c, J);
-  }
-  __syncthreads();
+  // Every global load of the prologue is issued before the first wait: the
+  // wave's first pair block of X, its C operands, then the factor rows that
+  // the workgroup stages in LDS (one round trip instead of one per loop step).
+  const float* src0 = kCache ? a.Pc : a.X;
+  float xb[2][16], qb[2][16];
+  load_tile<kInterior>(src0, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, xb[0]);
+  if (kCache) load_tile<kInterior>(a.Qc, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, qb[0]);
 
   // ---- per-wave operands that do not depend on the pair block:
   // rebuild C rows (k = kcol, r = 16h + s) and contraction C columns
@@ -316,6 +321,46 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
     ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
     if (kDen) ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
   }
+
+  // ---- stage the workgroup's factor rows in LDS (zero outside rows x cols):
+  // all loads into registers first, then the stores (a store between two loads
+  // would keep the second load waiting behind the first)
+  constexpr int kQA = kCpTI * 32 / kThreads, kQB = kCpTJ * 32 / kThreads;
+  float sa[kQA][3], sb[kQB][3];
+#pragma unroll
+  for (int q = 0; q < kQA; ++q) {
+    const int e = tid + q * kThreads;
+    const int i = i0 + (e >> 5), c = e & 31;
+    sa[q][0] = kCache ? 0.0f : load_clamped(a.r.A, i, c, I);
+    sa[q][1] = load_clamped(a.n.A, i, c, I);
+    sa[q][2] = kDen ? load_clamped(a.d.A, i, c, I) : 0.0f;
+  }
+#pragma unroll
+  for (int q = 0; q < kQB; ++q) {
+    const int e = tid + q * kThreads;
+    const int j = j0 + (e >> 5), c = e & 31;
+    sb[q][0] = kCache ? 0.0f : load_clamped(a.r.B, j, c, J);
+    sb[q][1] = load_clamped(a.n.B, j, c, J);
+    sb[q][2] = kDen ? load_clamped(a.d.B, j, c, J) : 0.0f;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < kQA; ++q) {
+    const int e = tid + q * kThreads;
+    const int i = i0 + (e >> 5), c = e & 31;
+    if (!kCache) sh.ra[(e >> 5) * kSA + c] = sa[q][0] * mask_of(a.r.A, i, c, I);
+    sh.na[e] = sa[q][1] * mask_of(a.n.A, i, c, I);
+    if (kDen) sh.da[e] = sa[q][2] * mask_of(a.d.A, i, c, I);
+  }
+#pragma unroll
+  for (int q = 0; q < kQB; ++q) {
+    const int e = tid + q * kThreads;
+    const int j = j0 + (e >> 5), c = e & 31;
+    if (!kCache) sh.rb[(e >> 5) * kSA + c] = sb[q][0] * mask_of(a.r.B, j, c, J);
+    sh.nb[e] = sb[q][1] * mask_of(a.n.B, j, c, J);
+    if (kDen) sh.db[e] = sb[q][2] * mask_of(a.d.B, j, c, J);
+  }
+  __syncthreads();
   // bf16 forms of the per-wave operands (split for the rebuild)
   bf16x8 crh[2], crl[2], ctnb[2], ctdb[2];
   if constexpr (kBf) {
@@ -336,11 +381,6 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   float m1n[4] = {}, m1d[4] = {};
   double obj = 0.0;
   const bool want_m3 = !kWrite && a.want_m3, want_v = !kWrite && a.want_v;
-
-  const float* src0 = kCache ? a.Pc : a.X;
-  float xb[2][16], qb[2][16];
-  load_tile<kInterior>(src0, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, xb[0]);
-  if (kCache) load_tile<kInterior>(a.Qc, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, qb[0]);
 
   // The reconstruction of pair block t + 1 is issued on the matrix cores
   // before tile t's entries are evaluated, so that a wave's vector work
