@@ -192,3 +192,25 @@ def test_invalid_arguments_leave_buffers_untouched(ctx):
     torch.cuda.synchronize()
     for a, b in zip(fac, init):
         assert np.array_equal(host64(a), b)
+
+
+@pytest.mark.parametrize("dims,R", [((3, 5, 7), 1), ((1, 1, 1), 3), ((2, 33, 65), 2), ((17, 1, 3), 31)])
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 1.5])
+def test_tiny_and_single_row_shapes(ctx, dims, R, beta):
+    """Tensors smaller than one workgroup tile in some or every mode, rank 1 to
+    31: the staged factor rows and columns past the edge read as zero. Every
+    block update and one J-CoMM iteration with its objective match the oracle."""
+    X, init = _problem(dims, R, 11)
+    for n in range(3):
+        fac = [dev(a) for a in init]
+        ctx.cp_update(dev(X), fac, block=n, beta=beta)
+        torch.cuda.synchronize()
+        assert max_rel(host64(fac[n]), ocp.block_update(X, init, n, beta)) < TOL_UPDATE, f"mode {n}"
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(dev(X), fac, beta=beta, L=2, obj_out=obj)
+    torch.cuda.synchronize()
+    want, fref = ocp.jcomm_outer(X, init, beta, L=2, return_ref_obj=True)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < 3 * TOL_UPDATE
+    assert abs(obj.item() - fref) <= 1e-5 * abs(fref) + 1e-9
