@@ -20,7 +20,10 @@
  *     error nothing is modified and the call returns a nonzero code, with a
  *     message available from comm_last_error() (thread-local).
  *   - Outputs are clipped to >= eps.  Inputs with entries < eps violate the
- *     precondition of the paper's updates; the library does not check them.
+ *     precondition of the paper's updates; the library checks them only when
+ *     opts.check_inputs is set (a debug mode that synchronises the stream).
+ *   - Device faults surface at the caller's next synchronisation, or through
+ *     comm_check().
  *   - No C++ exception crosses this interface.
  *   - Calls sharing one context must not overlap in time (the context owns
  *     the scratch workspace); use one context per concurrent stream.
@@ -119,7 +122,14 @@ typedef struct {
  *   precision     COMM_FP32 or COMM_BF16 (see above).
  *   cache_pq      J-CoMM at beta != 1: 1 = store P~ and Q~ once per outer
  *                 iteration in the workspace and stream them in the inner
- *                 passes; 0 = recompute them from X and the reference. */
+ *                 passes; 0 = recompute them from X and the reference.
+ *   check_inputs  debug mode: 1 = before anything is launched, verify on the
+ *                 device that the data are finite and >= 0 (dense X, or the
+ *                 COO values) and every parameter is finite and >= eps
+ *                 (the precondition Theta >= eps of the updates); a violation
+ *                 returns COMM_EINVAL with nothing modified.  The check
+ *                 synchronises the stream, so it cannot run under stream
+ *                 capture.  0 = no check (default). */
 typedef struct {
   double beta;
   double eps;
@@ -127,6 +137,7 @@ typedef struct {
   int inner_sweeps;
   int precision;
   int cache_pq;
+  int check_inputs;
 } comm_opts;
 
 /* Sparse COO data (CP, beta = 1 only).  idx[n][t] is the mode-n coordinate of
@@ -157,6 +168,11 @@ int comm_create(int device, size_t workspace_limit_bytes, comm_ctx** out);
 
 /* Synchronise the context's last stream and free its workspace. */
 int comm_destroy(comm_ctx* ctx);
+
+/* Synchronise the stream of the context's last call and report an
+ * asynchronous HIP error raised since (a device fault in a kernel), as
+ * COMM_EHIP with the runtime's message; COMM_OK otherwise. */
+int comm_check(comm_ctx* ctx);
 
 /* Message of the last error raised on this thread (never NULL). */
 const char* comm_last_error(void);

@@ -34,7 +34,7 @@ EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_by
             "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
             "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap",
             "comm_cp_update_coo", "comm_beta_objective_coo", "comm_tucker_update_coo",
-            "comm_tucker_jcomm_outer_coo"]
+            "comm_tucker_jcomm_outer_coo", "comm_check"]
 
 
 class CommError(RuntimeError):
@@ -57,7 +57,8 @@ class Model(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("eps_x", ctypes.c_double),
-                ("inner_sweeps", ctypes.c_int), ("precision", ctypes.c_int), ("cache_pq", ctypes.c_int)]
+                ("inner_sweeps", ctypes.c_int), ("precision", ctypes.c_int), ("cache_pq", ctypes.c_int),
+                ("check_inputs", ctypes.c_int)]
 
 
 class Coo(ctypes.Structure):
@@ -118,13 +119,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                            ctypes.c_void_p]
     lib.comm_tucker_jcomm_outer_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
                                                 ctypes.c_void_p]
+    lib.comm_check.argtypes = [ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
                  "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched",
                  "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan",
                  "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap", "comm_cp_update_coo",
-                 "comm_beta_objective_coo", "comm_tucker_update_coo", "comm_tucker_jcomm_outer_coo"]:
+                 "comm_beta_objective_coo", "comm_tucker_update_coo", "comm_tucker_jcomm_outer_coo", "comm_check"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -191,8 +193,9 @@ def _model(factors: Sequence, core=None) -> Model:
 
 
 def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq: bool = False,
-          precision: str = "fp32") -> Opts:
+          precision: str = "fp32", check_inputs: bool = False) -> Opts:
     o = Opts()
+    o.check_inputs = 1 if check_inputs else 0
     o.beta = float(beta)
     o.eps = float(eps)
     o.eps_x = float(eps if eps_x is None else eps_x)
@@ -251,7 +254,7 @@ class Batch:
 
     Each item is a dict with the arguments of :meth:`Context.jcomm_outer`:
     ``X``, ``factors`` and optionally ``core``, ``beta``, ``L``, ``eps``,
-    ``eps_x``, ``cache_pq``, ``precision`` and ``obj_out`` (a float64 device view of one
+    ``eps_x``, ``cache_pq``, ``precision``, ``check_inputs`` and ``obj_out`` (a float64 device view of one
     element).  The structures keep the tensors' device pointers, so the
     tensors must stay alive and in place while the batch is in use."""
 
@@ -267,7 +270,7 @@ class Batch:
             d = _dense(it["X"])
             m = _model(it["factors"], it.get("core"))
             o = _opts(it.get("beta", 1.0), it.get("eps", 1e-12), it.get("eps_x"), it.get("L", 1),
-                      it.get("cache_pq", False), it.get("precision", "fp32"))
+                      it.get("cache_pq", False), it.get("precision", "fp32"), it.get("check_inputs", False))
             self._dense[k], self._model[k], self._opts[k] = d, m, o
             pr = self.array[k]
             pr.x = ctypes.pointer(d)
@@ -286,9 +289,13 @@ class Batch:
 
 
 class Context:
-    """A library context on one device; owns the scratch workspace."""
+    """A library context on one device; owns the scratch workspace.
 
-    def __init__(self, device: int = 0, workspace_limit: int = 0):
+    check_inputs=True sets comm_opts.check_inputs on every call: the data and
+    parameters are verified on the device first (a synchronising debug mode)."""
+
+    def __init__(self, device: int = 0, workspace_limit: int = 0, check_inputs: bool = False):
+        self.check_inputs = bool(check_inputs)
         self._lib = load_library()
         h = ctypes.c_void_p()
         _check(self._lib.comm_create(int(device), int(workspace_limit), ctypes.byref(h)))
@@ -310,6 +317,15 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+    def check(self) -> None:
+        """comm_check: synchronise and raise CommError on an asynchronous device error."""
+        _check(self._lib.comm_check(self._h))
+
+    def _o(self, *args, **kw) -> Opts:
+        o = _opts(*args, **kw)
+        o.check_inputs = 1 if self.check_inputs else 0
+        return o
 
     # ---------------------------------------------------------------- measurement
 
@@ -341,7 +357,7 @@ class Context:
             m.kind = COMM_TUCKER
             for n, v in enumerate(core_dims):
                 m.core_dims[n] = int(v)
-        o = _opts(beta, 1e-12, None, L, cache_pq)
+        o = self._o(beta, 1e-12, None, L, cache_pq)
         return int(self._lib.comm_workspace_bytes(ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), int(op)))
 
     # ---------------------------------------------------------------- entry points
@@ -349,14 +365,14 @@ class Context:
     def cp_update(self, X, factors, block: int = -1, beta: float = 1.0, eps: float = 1e-12,
                   eps_x: Optional[float] = None, stream=None, precision: str = "fp32") -> None:
         """B-CoMM block update(s) of a CP model in place (block -1: full sweep)."""
-        d, m, o = _dense(X), _model(factors), _opts(beta, eps, eps_x, precision=precision)
+        d, m, o = _dense(X), _model(factors), self._o(beta, eps, eps_x, precision=precision)
         _check(self._lib.comm_cp_update(self._h, ctypes.byref(d), ctypes.byref(m), int(block), ctypes.byref(o),
                                         _stream(stream)))
 
     def tucker_update(self, X, core, factors, block: int = -2, beta: float = 1.0, eps: float = 1e-12,
                       eps_x: Optional[float] = None, stream=None, precision: str = "fp32") -> None:
         """B-CoMM block update(s) of a Tucker model in place (-1 core, n factor, -2 sweep)."""
-        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, precision=precision)
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, precision=precision)
         _check(self._lib.comm_tucker_update(self._h, ctypes.byref(d), ctypes.byref(m), int(block),
                                             ctypes.byref(o), _stream(stream)))
 
@@ -364,7 +380,7 @@ class Context:
                     eps_x: Optional[float] = None, cache_pq: bool = False, obj_out=None, stream=None,
                     precision: str = "fp32") -> None:
         """One J-CoMM outer iteration in place; F(reference) into obj_out[0] (float64) if given."""
-        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, L, cache_pq, precision)
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, cache_pq, precision)
         optr = None
         if obj_out is not None:
             import torch
@@ -388,7 +404,7 @@ class Context:
                            eps_x: Optional[float] = None, alpha_out=None, stream=None, precision: str = "fp32"):
         """Extrapolated B-CoMM sweep in place; ``prev`` (and ``prev_core``) hold the
         previous iterate and receive the one for the next call."""
-        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, precision=precision)
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, precision=precision)
         pm = _model(prev, prev_core)
         e = Extrap(float(alpha_nes), float(c), float(delta))
         aptr = _f32(alpha_out, "alpha_out") if alpha_out is not None else None
@@ -401,7 +417,7 @@ class Context:
                            stream=None, precision: str = "fp32"):
         """J-CoMM outer iteration from the extrapolated reference, in place."""
         d, m = _dense(X), _model(factors, core)
-        o = _opts(beta, eps, eps_x, L, cache_pq, precision)
+        o = self._o(beta, eps, eps_x, L, cache_pq, precision)
         pm = _model(prev, prev_core)
         e = Extrap(float(alpha_nes), float(c), float(delta))
         optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
@@ -415,7 +431,7 @@ class Context:
         import torch
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=X.device)
-        d, m, o = _dense(X), _model(factors, core), _opts(beta, eps, eps_x, precision=precision)
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, precision=precision)
         _check(self._lib.comm_beta_objective(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o),
                                              _ptr(out, "out"), _stream(stream)))
         return out
@@ -425,7 +441,7 @@ class Context:
         """One J-CoMM outer iteration on COO data (idx: per-mode int32 tensors);
         beta in (0, 2) (beta != 1: orders 3 and 4, dense denominators)."""
         c = _coo(idx, val, dims)
-        m, o = _model(factors), _opts(beta, eps, None, L)
+        m, o = _model(factors), self._o(beta, eps, None, L)
         optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
         _check(self._lib.comm_cp_jcomm_outer_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o), optr,
                                                  _stream(stream)))
@@ -434,7 +450,7 @@ class Context:
                       eps: float = 1e-12, stream=None) -> None:
         """B-CoMM block update(s) of a CP model on COO data, beta in (0, 2)."""
         c = _coo(idx, val, dims)
-        m, o = _model(factors), _opts(beta, eps, None)
+        m, o = _model(factors), self._o(beta, eps, None)
         _check(self._lib.comm_cp_update_coo(self._h, ctypes.byref(c), ctypes.byref(m), int(block), ctypes.byref(o),
                                             _stream(stream)))
 
@@ -445,7 +461,7 @@ class Context:
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=val.device)
         c = _coo(idx, val, dims)
-        m, o = _model(factors, core), _opts(beta, eps, None)
+        m, o = _model(factors, core), self._o(beta, eps, None)
         _check(self._lib.comm_beta_objective_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o),
                                                  _ptr(out, "out"), _stream(stream)))
         return out
@@ -454,7 +470,7 @@ class Context:
                           beta: float = 1.0, eps: float = 1e-12, stream=None) -> None:
         """B-CoMM block update(s) of a Tucker model on COO data, beta in (0, 2) (-1 core, n factor, -2 sweep)."""
         c = _coo(idx, val, dims)
-        m, o = _model(factors, core), _opts(beta, eps, None)
+        m, o = _model(factors, core), self._o(beta, eps, None)
         _check(self._lib.comm_tucker_update_coo(self._h, ctypes.byref(c), ctypes.byref(m), int(block),
                                                 ctypes.byref(o), _stream(stream)))
 
@@ -462,7 +478,7 @@ class Context:
                                L: int = 1, eps: float = 1e-12, obj_out=None, stream=None) -> None:
         """One J-CoMM outer iteration of a Tucker model on COO data, beta in (0, 2)."""
         c = _coo(idx, val, dims)
-        m, o = _model(factors, core), _opts(beta, eps, None, L)
+        m, o = _model(factors, core), self._o(beta, eps, None, L)
         optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
         _check(self._lib.comm_tucker_jcomm_outer_coo(self._h, ctypes.byref(c), ctypes.byref(m), ctypes.byref(o),
                                                      optr, _stream(stream)))
@@ -477,7 +493,7 @@ class Context:
     def cp_jcomm_outer_coo_plan(self, plan: "CooPlan", factors, L: int = 1, eps: float = 1e-12, obj_out=None,
                                 stream=None) -> None:
         """cp_jcomm_outer_coo on a planned tensor."""
-        m, o = _model(factors), _opts(1.0, eps, None, L)
+        m, o = _model(factors), self._o(1.0, eps, None, L)
         optr = _ptr(obj_out, "obj_out") if obj_out is not None else None
         _check(self._lib.comm_cp_jcomm_outer_coo_plan(self._h, plan.handle, ctypes.byref(m), ctypes.byref(o), optr,
                                                       _stream(stream)))

@@ -887,6 +887,49 @@ int ensure_aux(comm_ctx* ctx) {
   return COMM_OK;
 }
 
+// opts->check_inputs: the data (nd values at data) finite and >= 0, every
+// parameter of the model finite and >= eps; otherwise COMM_EINVAL before
+// anything is updated.  The flag is the int 128 bytes into ctx->aux (the
+// extrapolation weight uses its first float).  Synchronises the stream.
+int input_check(comm_ctx* ctx, const float* data, int64_t nd, const comm_model* m, int ndim, const int64_t* dims,
+                const comm_opts* o, hipStream_t st) {
+  if (!o || !o->check_inputs) return COMM_OK;
+  int rc = ensure_aux(ctx);
+  if (rc) return rc;
+  int* flag = reinterpret_cast<int*>(ctx->aux + 32);
+  HIP_TRY(launch_fill_zero(reinterpret_cast<float*>(flag), 1, st));
+  if (data) HIP_TRY(launch_check_range(data, nd, 0.0f, 1, flag, st));
+  const float eps = (float)o->eps;
+  int64_t core = 1;
+  for (int n = 0; n < ndim; ++n) {
+    const int64_t cols = m->kind == COMM_CP ? m->rank : m->core_dims[n];
+    core *= m->core_dims[n];
+    HIP_TRY(launch_check_range(m->factors[n], dims[n] * cols, eps, 2, flag, st));
+  }
+  if (m->kind == COMM_TUCKER) HIP_TRY(launch_check_range(m->core, core, eps, 2, flag, st));
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h & 1) return fail(COMM_EINVAL, "check_inputs: the data hold a negative or non-finite value");
+  if (h & 2) return fail(COMM_EINVAL, "check_inputs: a parameter is below eps or not finite");
+  return COMM_OK;
+}
+
+int64_t dense_numel(const comm_dense* x) {
+  int64_t n = 1;
+  for (int k = 0; k < x->ndim; ++k) n *= x->dims[k];
+  return n;
+}
+
+int input_check_dense(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o,
+                      hipStream_t st) {
+  return input_check(ctx, x->X, dense_numel(x), m, x->ndim, x->dims, o, st);
+}
+
+int input_check_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* m, const comm_opts* o, hipStream_t st) {
+  return input_check(ctx, x->val, x->nnz, m, x->ndim, x->dims, o, st);
+}
+
 // alpha_t of the whole model into alpha (device).
 int extrap_alpha(const comm_dense* x, comm_model* m, comm_model* prev, const comm_extrap* e, float* alpha,
                  hipStream_t st) {
@@ -1334,6 +1377,14 @@ int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags
     total += it.bytes;
   }
   if (count == 0) return COMM_OK;
+  // debug input checks, eagerly on the caller's stream, before any problem runs
+  for (int p = 0; p < count; ++p) {
+    const int rc = input_check_dense(ctx, probs[p].x, probs[p].model, probs[p].opts, st);
+    if (rc) {
+      std::string msg = g_last_error;
+      return fail(rc, "problem %d: %s", p, msg.c_str());
+    }
+  }
   int rc = batch_resources(ctx);
   if (rc) return rc;
   if ((rc = batch_ensure_ws(ctx, total, st))) return rc;
@@ -1426,6 +1477,18 @@ int comm_destroy(comm_ctx* ctx) {
   });
 }
 
+int comm_check(comm_ctx* ctx) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(ctx->last_stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(COMM_EHIP, "asynchronous error: %s", hipGetErrorString(e));
+    return COMM_OK;
+  });
+}
+
 int comm_profile_enable(comm_ctx* ctx, int on) {
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
@@ -1476,6 +1539,7 @@ int comm_cp_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int bl
     if (block < -1 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
     rc = cp_bcomm(ctx, x, model, block, opts, st);
     ctx->last_stream = st;
     return rc;
@@ -1490,6 +1554,7 @@ int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, cons
     if (rc) return rc;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
     rc = jcomm_run(ctx, x, model, opts, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
@@ -1524,9 +1589,11 @@ int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* mo
     hipStream_t st = (hipStream_t)stream;
     if (model->kind == COMM_CP) {
       if ((rc = check_cp_model(model, x->ndim))) return rc;
+      if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
       rc = cp_objective(ctx, x, model, opts, out_dev, st);
     } else if (model->kind == COMM_TUCKER) {
       if ((rc = tucker_check_model(model, x))) return rc;
+      if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
       rc = tucker_objective(ctx, x, model, opts, out_dev, st);
     } else {
       return fail(COMM_EINVAL, "model kind %d", model->kind);
@@ -1547,6 +1614,7 @@ int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, in
     if (block < -2 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
     rc = tucker_bcomm(ctx, x, model, block, opts, st);
     ctx->last_stream = st;
     return rc;
@@ -1563,6 +1631,7 @@ int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model,
       if (model->kind != COMM_CP) return fail(COMM_EINVAL, "model kind is not CP");
       if ((rc = set_device(ctx))) return rc;
       hipStream_t st = (hipStream_t)stream;
+      if ((rc = input_check_coo(ctx, x, model, opts, st))) return rc;
       rc = coo_beta_jcomm(ctx, x, model, opts, obj_ref_dev, st);
       ctx->last_stream = st;
       return rc;
@@ -1572,6 +1641,7 @@ int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model,
     if (rc) return rc;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_coo(ctx, x, model, opts, st))) return rc;
     rc = coo_jcomm_kl(ctx, x, model, opts, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
@@ -1588,6 +1658,7 @@ int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int 
     if (block < -1 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_coo(ctx, x, model, opts, st))) return rc;
     rc = coo_beta_bcomm(ctx, x, model, block, opts, st);
     ctx->last_stream = st;
     return rc;
@@ -1604,6 +1675,7 @@ int comm_tucker_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, 
     if (block < -2 || block >= x->ndim) return fail(COMM_EINVAL, "block = %d", block);
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_coo(ctx, x, model, opts, st))) return rc;
     rc = coo_tucker(ctx, x, model, block, opts, nullptr, false, st);
     ctx->last_stream = st;
     return rc;
@@ -1619,6 +1691,7 @@ int comm_tucker_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* mo
     if (model->kind != COMM_TUCKER) return fail(COMM_EINVAL, "model kind is not Tucker");
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_coo(ctx, x, model, opts, st))) return rc;
     rc = coo_tucker(ctx, x, model, -2, opts, obj_ref_dev, true, st);
     ctx->last_stream = st;
     return rc;
@@ -1634,6 +1707,7 @@ int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* 
     if (rc) return rc;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_coo(ctx, x, model, opts, st))) return rc;
     rc = coo_beta_objective(ctx, x, model, opts, out_dev, st);
     ctx->last_stream = st;
     return rc;
@@ -1670,6 +1744,7 @@ int comm_cp_jcomm_outer_coo_plan(comm_ctx* ctx, const comm_coo_plan* plan, comm_
     if (rc) return rc;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check(ctx, nullptr, 0, model, N, dims, opts, st))) return rc;
     rc = coo_jcomm_kl_plan(ctx, plan, model, opts, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
@@ -1692,6 +1767,7 @@ int comm_bcomm_sweep_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* mode
     if ((rc = set_device(ctx))) return rc;
     if ((rc = ensure_aux(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
     float* alpha = alpha_dev ? alpha_dev : ctx->aux;
     if ((rc = extrap_alpha(x, model, prev, extrap, alpha, st))) return rc;
     // each block is moved just before its own update (Tucker: core, then modes)
@@ -1718,6 +1794,7 @@ int comm_jcomm_outer_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* mode
     if ((rc = set_device(ctx))) return rc;
     if ((rc = ensure_aux(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
     float* alpha = alpha_dev ? alpha_dev : ctx->aux;
     if ((rc = extrap_alpha(x, model, prev, extrap, alpha, st))) return rc;
     // the outer reference is the extrapolated model; the inner iterate starts there

@@ -141,6 +141,8 @@ struct KlLoopArgs {
   int obj_add_model_mass;  // also add sum_r prod_n colsum(A~^(n))_r (sparse objective)
 };
 hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s);
+// Sets `bit` in *flag if one of the n floats at p is below lo or not finite.
+hipError_t launch_check_range(const float* p, int64_t n, float lo, int bit, int* flag, hipStream_t s);
 
 // Reduction of partial slots [slots][rows_total][32] (fixed order) fused with
 //   kSlotScale:  out = anchor * Num, plus per-block column statistics

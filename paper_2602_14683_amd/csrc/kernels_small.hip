@@ -417,6 +417,25 @@ hipError_t launch_slot_update(const SlotUpdateArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Debug check of caller inputs: sets `bit` in *flag when one of the n values
+// is below lo or is not finite (NaN fails both comparisons, +inf the second).
+__global__ void __launch_bounds__(256) check_range_kernel(const float* __restrict__ p, int64_t n, float lo, int bit,
+                                                          int* flag) {
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const float v = p[e];
+    bad |= !(v >= lo && v <= 3.402823466e38f);
+  }
+  if (bad) atomicOr(flag, bit);
+}
+
+hipError_t launch_check_range(const float* p, int64_t n, float lo, int bit, int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(check_range_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, lo, bit, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s) {
   int64_t n = 0;
   for (int q = 0; q < a.N; ++q) n += (int64_t)a.rows[q] * kRP;

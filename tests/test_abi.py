@@ -45,6 +45,11 @@ def test_binding_structs_follow_the_header():
     # int + pad + int64[5] + pointer
     assert ctypes.sizeof(pkg.Dense) == 8 + 8 * pkg.MAX_NDIM + 8
     assert ctypes.sizeof(pkg.Model) == 8 + 8 * pkg.MAX_NDIM + 8 * pkg.MAX_NDIM + 8
+    # beta, eps, eps_x; inner_sweeps, precision, cache_pq, check_inputs
+    assert ctypes.sizeof(pkg.Opts) == 3 * 8 + 4 * 4
+    assert [f[0] for f in pkg.Opts._fields_] == re.findall(
+        r"^\s+(?:double|int) (\w+);", re.search(r"typedef struct \{\n  double beta;.*?\} comm_opts;", text,
+                                                  re.S).group(0), re.M)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcomm.so not built")
