@@ -268,8 +268,20 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
           // exact column sum of max(c / Den, eps) for clipped columns; the two
           // lane halves take alternate rows, combined in order
           float s = 0.0f;
-          if (clip)
-            for (int r = t >> 5; r < a.rows[n]; r += 2) s += fmaxf(a.c[n][(int64_t)r * kRP + col] / d, a.eps);
+          if (clip) {
+            // rows in the same order as one at a time, sixteen loads in flight
+            const float* cp = a.c[n] + col;
+            const int rows = a.rows[n];
+            int r = t >> 5;
+            for (; r + 30 < rows; r += 32) {
+              float v[16];
+#pragma unroll
+              for (int u = 0; u < 16; ++u) v[u] = cp[(int64_t)(r + 2 * u) * kRP];
+#pragma unroll
+              for (int u = 0; u < 16; ++u) s += fmaxf(v[u] / d, a.eps);
+            }
+            for (; r < rows; r += 2) s += fmaxf(cp[(int64_t)r * kRP] / d, a.eps);
+          }
           const float other = __shfl_xor(s, 32);
           const float exact = (t < 32) ? s + other : other + s;
           if (clip) snew = exact;

@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
   const int64_t t1 = min(a.nnz, t0 + a.chunk);
   const int R = a.R;
   const bool rlive = r < R;
+  const int rcol = rlive ? r : R - 1;
 
   int cur[2] = {-1, -1};
   float acc[2] = {0.0f, 0.0f};
@@ -127,15 +128,24 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
         for (int m = 0; m < N; ++m) ii[u][m] = __shfl(my[m], src);
         xs[u] = __shfl(myx, src);
       }
+      // every gather of the batch is issued before the first use: lanes with
+      // nothing to gather read row 0 / column R - 1 (valid addresses) and are
+      // zeroed by a mask after the batch (a guarded load per nonzero would be
+      // a branch and a round trip each)
+      float g[kCooBatch][4];
 #pragma unroll
       for (int u = 0; u < kCooBatch; ++u) {
-        float z = 0.0f;
-        if (oks[u] && rlive) {
-          z = a.A[0][(int64_t)ii[u][0] * R + r];
+        const bool live = oks[u] && rlive;
 #pragma unroll
-          for (int m = 1; m < N; ++m) z *= a.A[m][(int64_t)ii[u][m] * R + r];
-        }
-        zs[u] = z;
+        for (int m = 0; m < N; ++m) g[u][m] = a.A[m][(int64_t)(live ? ii[u][m] : 0) * R + rcol];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kCooBatch; ++u) {
+        float z = g[u][0];
+#pragma unroll
+        for (int m = 1; m < N; ++m) z *= g[u][m];
+        zs[u] = z * ((oks[u] && rlive) ? 1.0f : 0.0f);
       }
       float y[kCooBatch];
 #pragma unroll
