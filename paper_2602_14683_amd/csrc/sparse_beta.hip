@@ -103,48 +103,91 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_tucker_kernel(CooTkArgs a
   const int64_t t0 = half * chunk, t1 = min(a.nnz, t0 + chunk);
   int64_t run_row = -1;
   float run_acc = 0.0f;
-  for (int64_t t = t0; t < t1; ++t) {
-    int ii[kMaxModes] = {};
-    bool ok = true;
+  // kG nonzeros at a time, each step's loads issued together before their
+  // first use: a nonzero past the chunk re-reads the chunk's last one, a row
+  // or column past the edge reads a valid one, and masks apply afterwards (a
+  // guarded load per nonzero would be a branch and a round trip each).  The
+  // nonzeros are then accumulated in stream order, as one at a time.
+  constexpr int kG = 4;
+  const int cr_col = min(d, a.Cr.cols - 1), cc_col = a.op == 1 ? min(d, a.Cc.cols - 1) : 0;
+  const float cr_mask = d < a.Cr.cols ? 1.0f : 0.0f;
+  const float cc_mask = a.op == 1 && d < a.Cc.cols ? 1.0f : 0.0f;
+  for (int64_t tb = t0; tb < t1; tb += kG) {
+    int ii[kG][kMaxModes];
 #pragma unroll
-    for (int m = 0; m < kMaxModes; ++m) {
-      if (m < a.N) {
-        ii[m] = a.idx[m][t];
-        ok = ok && ii[m] >= 0 && ii[m] < a.dims[m];
-      }
+    for (int u = 0; u < kG; ++u) {
+      const int64_t t = min(tb + u, t1 - 1);
+#pragma unroll
+      for (int m = 0; m < kMaxModes; ++m) ii[u][m] = a.idx[m < a.N ? m : 0][t];
     }
-    if (!ok) continue;
-    int64_t row = 0;
+    __builtin_amdgcn_sched_barrier(0);
+    bool live[kG];
+    int64_t row[kG];
+    int iL[kG];
 #pragma unroll
-    for (int m = 0; m < kMaxModes; ++m)
-      if (m < L) row = row * a.dims[m] + ii[m];
-    const int iL = ii[L];
-    float w;
+    for (int u = 0; u < kG; ++u) {
+      bool ok = tb + u < t1;
+#pragma unroll
+      for (int m = 0; m < kMaxModes; ++m)
+        if (m < a.N) ok = ok && ii[u][m] >= 0 && ii[u][m] < a.dims[m];
+      live[u] = ok;
+      int64_t rr = 0;
+      int il = 0;
+#pragma unroll
+      for (int m = 0; m < kMaxModes; ++m) {
+        const int im = ok ? ii[u][m] : 0;
+        if (m < L) rr = rr * a.dims[m] + im;
+        if (m == L) il = im;
+      }
+      row[u] = rr;
+      iL[u] = il;
+    }
+    float w[kG];
     if (a.w_in) {
-      w = a.w_in[t];
-    } else {
-      float z = a.Tr[row * kRP + d] * a.Cr.at(iL, d, a.dims[L]);
 #pragma unroll
-      for (int off = 16; off > 0; off >>= 1) z += __shfl_xor(z, off);
-      const float x = a.val[t];
-      const float y = fmaxf(z, a.eps);
-      float p, q;
-      weights<BC>(x, y, a.bc.beta, p, q);
-      w = p;
-      if (d == 0) {
-        if (a.w_out) a.w_out[t] = p;
-        if (a.obj_part) obj += (double)dbeta_term<BC>(x, y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc);
+      for (int u = 0; u < kG; ++u) w[u] = a.w_in[min(tb + u, t1 - 1)];
+    } else {
+      float tr[kG], cr[kG], xv[kG];
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        tr[u] = a.Tr[row[u] * kRP + d];
+        cr[u] = a.Cr.p[(int64_t)iL[u] * a.Cr.ld + cr_col];
+        xv[u] = a.val[min(tb + u, t1 - 1)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        float z = tr[u] * (cr[u] * cr_mask);
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) z += __shfl_xor(z, off);
+        const float y = fmaxf(z, a.eps);
+        float p, q;
+        weights<BC>(xv[u], y, a.bc.beta, p, q);
+        w[u] = p;
+        if (d == 0 && live[u]) {
+          if (a.w_out) a.w_out[tb + u] = p;
+          if (a.obj_part)
+            obj += (double)dbeta_term<BC>(xv[u], y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc);
+        }
       }
     }
     if (a.op != 0) {
-      const int64_t target = a.op == 1 ? row : (int64_t)iL;
-      const float c = a.op == 1 ? w * a.Cc.at(iL, d, a.dims[L]) : w * a.Tc[row * kRP + d];
-      if (target != run_row) {
-        if (run_row >= 0) unsafeAtomicAdd(&a.out[run_row * kRP + d], run_acc);
-        run_row = target;
-        run_acc = 0.0f;
+      float cf[kG];
+#pragma unroll
+      for (int u = 0; u < kG; ++u)
+        cf[u] = a.op == 1 ? a.Cc.p[(int64_t)iL[u] * a.Cc.ld + cc_col] * cc_mask : a.Tc[row[u] * kRP + d];
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        if (!live[u]) continue;
+        const int64_t target = a.op == 1 ? row[u] : (int64_t)iL[u];
+        const float c = w[u] * cf[u];
+        if (target != run_row) {
+          if (run_row >= 0) unsafeAtomicAdd(&a.out[run_row * kRP + d], run_acc);
+          run_row = target;
+          run_acc = 0.0f;
+        }
+        run_acc += c;
       }
-      run_acc += c;
     }
   }
   if (run_row >= 0) unsafeAtomicAdd(&a.out[run_row * kRP + d], run_acc);
