@@ -124,6 +124,10 @@ CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
 }
 
 int run_pass(comm_ctx* ctx, const CpPassArgs& a, const CpGrid& g, int bc, bool den, hipStream_t st) {
+  // without X the pass must take x = 0 itself: every class but beta = 1
+  // does, unless it reads the P~ / Q~ cache instead (which needs no X)
+  if (!a.X && a.cache_mode != 2 && (!a.x_zero || bc == kKL))
+    return fail(COMM_EHIP, "internal error: a pass without X at beta class %d", bc);
   return profiled(ctx, st, [&] { return launch_cp_pass(a, g, bc, den, st); });
 }
 
@@ -135,6 +139,7 @@ FSet pad_set(const FactorSet& s) { return FSet{pad_view(s.pad[0]), pad_view(s.pa
 CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
   CpPassArgs a = {};
   a.X = x->X;
+  a.x_zero = x->X == nullptr;  // the dense twin of sparse data at beta != 1
   a.I = w.dims[0];
   a.J = w.dims[1];
   a.K = w.dims[2];
@@ -1090,8 +1095,9 @@ int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* 
   return fail(COMM_EINVAL, "model kind %d", model->kind);
 }
 
-// The dense twin of x (the context's zero tensor, allocated unless `no_dense`)
-// and the sparse buffers.
+// The dense twin of x and the sparse buffers.  The twin's X is the context's
+// zero tensor, allocated unless `no_dense`; the CP passes need no tensor (a
+// null X tells them that x = 0 everywhere), the Tucker passes read it.
 int coo_beta_setup(comm_ctx* ctx, const comm_coo* x, bool no_dense, comm_dense* xd, CooBetaWs* s, hipStream_t st) {
   *xd = comm_dense{};
   xd->ndim = x->ndim;
@@ -1150,7 +1156,7 @@ NumHook coo_num_hook(const comm_coo* x, const comm_model* m, const comm_opts* o,
 int coo_beta_bcomm(comm_ctx* ctx, const comm_coo* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  int rc = coo_beta_setup(ctx, x, o->beta == 1.0, &xd, &s, st);
+  int rc = coo_beta_setup(ctx, x, true, &xd, &s, st);
   if (rc) return rc;
   const NumHook hook = coo_num_hook(x, m, o, s, false, st);
   return cp_bcomm(ctx, &xd, m, block, o, st, &hook);
@@ -1172,7 +1178,7 @@ int coo_beta_obj_add(const comm_coo* x, const comm_model* m, const comm_opts* o,
 int coo_beta_jcomm(comm_ctx* ctx, const comm_coo* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  int rc = coo_beta_setup(ctx, x, false, &xd, &s, st);
+  int rc = coo_beta_setup(ctx, x, true, &xd, &s, st);
   if (rc) return rc;
   // P~ at the reference (the caller's model before the iteration), kept for
   // the inner sweeps; its objective corrections summed now into a partial
@@ -1194,7 +1200,8 @@ int coo_beta_objective(comm_ctx* ctx, const comm_coo* x, const comm_model* m, co
                        hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  int rc = coo_beta_setup(ctx, x, false, &xd, &s, st);
+  // the beta = 1 pass reads its X: there the CP twin keeps the zero tensor
+  int rc = coo_beta_setup(ctx, x, m->kind == COMM_CP && o->beta != 1.0, &xd, &s, st);
   if (rc) return rc;
   if (m->kind == COMM_TUCKER) {
     const TkSparse sp{x, s.w, s.num, s.obj};

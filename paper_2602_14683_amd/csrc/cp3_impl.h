@@ -308,7 +308,15 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   // the workgroup stages in LDS (one round trip instead of one per loop step).
   const float* src0 = kCache ? a.Pc : a.X;
   float xb[2][16], qb[2][16];
-  load_tile<kInterior>(src0, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, xb[0]);
+  // X known to be all zero (the dense twin of a sparse tensor): x = 0 is not
+  // loaded, and P = 0 is not contracted (its slots stay zero)
+  const bool xz = BC != kKL && !kCache && a.x_zero;
+  if (xz) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) xb[0][v] = xb[1][v] = 0.0f;
+  } else {
+    load_tile<kInterior>(src0, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, xb[0]);
+  }
   if (kCache) load_tile<kInterior>(a.Qc, 2 * mg, 0, lane_off, i0, j0, I, J, K, kvalid, h, qb[0]);
 
   // ---- per-wave operands that do not depend on the pair block:
@@ -422,7 +430,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
     if (t + 1 < 8) {
       // prefetch the next pair block (the next i block after jb = 3)
       const int ibn = 2 * mg + ((t + 1) >> 2), jbn = (jb + 1) & 3;
-      load_tile<kInterior>(src0, ibn, jbn, lane_off, i0, j0, I, J, K, kvalid, h, xb[(jb + 1) & 1]);
+      if (!xz) load_tile<kInterior>(src0, ibn, jbn, lane_off, i0, j0, I, J, K, kvalid, h, xb[(jb + 1) & 1]);
       if (kCache) load_tile<kInterior>(a.Qc, ibn, jbn, lane_off, i0, j0, I, J, K, kvalid, h, qb[(jb + 1) & 1]);
     }
     const float(&xv)[16] = xb[jb & 1];
@@ -491,7 +499,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       for (int g = 0; g < 4; ++g) ag[g] = sh.na[(ib * 4 + g) * 32 + col];
 #pragma unroll
       for (int q = 0; q < 4; ++q) bq[q] = sh.nb[(jb * 8 + 4 * h + q) * 32 + col];
-      contract_tile<kBf>(pv, ag, bq, ctn, ctnb, want_m3, want_v, m3n, m1n, m2n[jb], sh.t[w], col, h);
+      if (!xz) contract_tile<kBf>(pv, ag, bq, ctn, ctnb, want_m3, want_v, m3n, m1n, m2n[jb], sh.t[w], col, h);
       if (kDen) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) ag[g] = sh.da[(ib * 4 + g) * 32 + col];

@@ -75,6 +75,8 @@ struct CpPassArgs {
   float* m1d;
   float* m2d;
   double* obj_part;        // one float64 partial per workgroup
+  int x_zero;              // X is all zero and not read (x = 0 everywhere); P is then
+                           // zero and its contractions are skipped (beta != 1 only)
 };
 
 hipError_t launch_cp_pass(const CpPassArgs& a, const CpGrid& g, int beta_class, bool den, hipStream_t s);
