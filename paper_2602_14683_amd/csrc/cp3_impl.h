@@ -588,7 +588,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
 }
 
 template <int BC, int kVar, bool kObj, bool kBf>
-__global__ void __launch_bounds__(kThreads, BC == kKL ? 2 : 1) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
+__global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
   __shared__ PassShared sh;
   const int wg = blockIdx.x;
   const int bk = wg % gk;
