@@ -66,7 +66,7 @@ __device__ __forceinline__ void load_fibre(const float* __restrict__ row, int64_
 }
 
 template <int BC, int kMode, bool kObj, int kSets, bool kBf>
-__global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
+__global__ void __launch_bounds__(kThreads, 4) tk_v_kernel(TkPassArgs a) {
   __shared__ float red[kWaves][kSets > 0 ? kSets : 1][32 * 33];
   __shared__ double sobj[kWaves];
   const int lane = threadIdx.x & 63;
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kThreads) tk_v_kernel(TkPassArgs a) {
 // Mode-3 pass.  Workgroup (kt, g): k tile kt, pair group g of 4 * tpw pair
 // tiles; wave w takes tiles g * 4 * tpw + w * tpw + t, t < tpw.
 template <int BC, int kMode, int kSets, bool kBf>
-__global__ void __launch_bounds__(kThreads) tk_m3_kernel(TkPassArgs a) {
+__global__ void __launch_bounds__(kThreads, 3) tk_m3_kernel(TkPassArgs a) {
   __shared__ float red[kWaves][2][32 * 33];
   const int lane = threadIdx.x & 63;
   const int col = lane & 31, h = lane >> 5;
