@@ -128,24 +128,29 @@ __device__ __forceinline__ int out_row(int v, int h) { return 8 * (v >> 2) + 4 *
 // d_1(x | y) = y - x - x log(y / x) without cancellation: with
 // s = (y - x) / (y + x), log(y / x) = 2 atanh(s), which gives
 // d_1 = s^2 [(x + y) - 2 x s S(s^2)],  S(z) = sum_{k>=0} z^k / (2k + 3).
-// Nine terms keep the truncation below 1e-7 relative for |s| < 1/2.  Entries
-// with |s| >= 1/2 ("far") take the direct form, which there loses at most a
-// couple of bits.  x = 0 gives y.  `rsum` is 1 / (x + y).
+// For z <= 1/4 (|s| <= 1/2) -2 S(z) is replaced by a degree-5 polynomial
+// fitted for least maximum relative error (Lawson's iteration on a fine grid,
+// coefficients rounded to float32): 1.1e-7 relative error including the
+// float32 Horner evaluation, five FMAs where the Taylor series needs nine
+// terms for 6e-7.  Entries with |s| >= 1/2 ("far") take the direct form, which
+// there loses at most a couple of bits.
+__device__ __forceinline__ float kl_series_core(float x, float s, float z, float sum) {
+  float T = -0.3158642351627350f;
+  T = fmaf(T, z, -0.1293550580739975f);
+  T = fmaf(T, z, -0.2295092195272446f);
+  T = fmaf(T, z, -0.2852697074413300f);
+  T = fmaf(T, z, -0.4000097811222076f);
+  T = fmaf(T, z, -0.6666666269302368f);
+  return z * fmaf(x * s, T, sum);
+}
+
+// Series form with its far flag; x = 0 gives y.  `rsum` is 1 / (x + y).
 __device__ __forceinline__ float kl_series(float x, float y, float rsum, bool& far) {
-  const float sum = x + y, diff = y - x;
-  const float s = diff * rsum;
+  const float sum = x + y;
+  const float s = (y - x) * rsum;
   const float z = s * s;
-  float S = 1.0f / 19.0f;
-  S = fmaf(S, z, 1.0f / 17.0f);
-  S = fmaf(S, z, 1.0f / 15.0f);
-  S = fmaf(S, z, 1.0f / 13.0f);
-  S = fmaf(S, z, 1.0f / 11.0f);
-  S = fmaf(S, z, 1.0f / 9.0f);
-  S = fmaf(S, z, 1.0f / 7.0f);
-  S = fmaf(S, z, 1.0f / 5.0f);
-  S = fmaf(S, z, 1.0f / 3.0f);
   far = z >= 0.25f && x > 0.0f;
-  const float d = z * fmaf(-2.0f * x * s, S, sum);
+  const float d = kl_series_core(x, s, z, sum);
   return x > 0.0f ? d : y;
 }
 
@@ -157,7 +162,9 @@ __device__ __forceinline__ float kl_direct(float x, float y) {
 // reciprocal of y (x + y) serves both P = x / y and the objective's s.  Both
 // forms of d_1 are evaluated and the far flag selects one: a tile of a few
 // hundred entries nearly always holds a far one, so a branch would run for
-// almost every tile.  The direct form takes log(y / x) = -log(P).
+// almost every tile.  The direct form takes log(y / x) = -log(P), with P
+// raised to the smallest normal float so that x = 0 gives 0 * (-126) and the
+// direct form returns y, the exact term; x = 0 always has s = 1 and so takes it.
 template <int BC, bool kObj>
 __device__ __forceinline__ void entry(float x, float y, const BetaConst& bc, float& p, float& q, float& d) {
   if constexpr (BC == kKL) {
@@ -166,11 +173,12 @@ __device__ __forceinline__ void entry(float x, float y, const BetaConst& bc, flo
       const float sum = x + y;
       const float r = fast_rcp(y * sum);
       p = x * (sum * r);
-      bool far;
-      const float ds = kl_series(x, y, y * r, far);
-      // x = 0 makes the direct form NaN; far is false there
-      const float dd = fmaf(x * 0.69314718055994531f, fast_log2(p), y - x);
-      d = far ? dd : ds;
+      const float diff = y - x;
+      const float s = diff * (y * r);
+      const float z = s * s;
+      const float ds = kl_series_core(x, s, z, sum);
+      const float dd = fmaf(x * 0.69314718055994531f, fast_log2(fmaxf(p, 1.17549435e-38f)), diff);
+      d = z >= 0.25f ? dd : ds;
     } else {
       p = x * fast_rcp(y);
     }
@@ -469,9 +477,10 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
         pv[v] = valid[v] ? p : 0.f;
         qv[v] = valid[v] ? q : 0.f;
         if (kObj) objt += valid[v] ? d : 0.0f;
-        // the objective is long; keep the scheduler from interleaving all
-        // sixteen entries (register pressure)
-        if constexpr (kObj) {
+        // the general objective terms are long: keep the scheduler from
+        // interleaving all sixteen entries (register pressure).  The KL term
+        // is short enough to leave free (two waves per SIMD, no spills).
+        if constexpr (kObj && BC != kKL) {
           if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }
