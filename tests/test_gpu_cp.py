@@ -214,3 +214,20 @@ def test_tiny_and_single_row_shapes(ctx, dims, R, beta):
     for a, b in zip(fac, want):
         assert max_rel(host64(a), b) < 3 * TOL_UPDATE
     assert abs(obj.item() - fref) <= 1e-5 * abs(fref) + 1e-9
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_objective_at_exact_fit(ctx, beta):
+    """Data equal to the model (rounded to float32): every term is of the order
+    of x^beta u^2 with u the rounding-level relative gap between x and the
+    rebuilt model, about 1e-14 of x^beta.  Taken in a form that cancels
+    (differences of O(x^beta) quantities), the terms keep errors of about 1e-7
+    of x^beta, so the sum would sit near 1e-10 of sum(x^beta) or above."""
+    rng = np.random.default_rng(21)
+    dims, R = (37, 70, 90), 32
+    init = [f32(rng.uniform(0.1, 1.0, size=(d, R))) for d in dims]
+    X = f32(ocp.rebuild(init))
+    out = ctx.beta_objective(dev(X), [dev(a) for a in init], beta=beta)
+    torch.cuda.synchronize()
+    scale = float(np.sum(X.astype(np.float64) ** beta))
+    assert 0.0 <= out.item() < 1e-11 * scale

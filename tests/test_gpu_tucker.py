@@ -168,3 +168,20 @@ def test_tucker_unaligned_tensor(ctx):
     for a, b in zip(F, wf):
         assert max_rel(host64(a), b) < 1e-4
     assert abs(obj.item() - fref) / fref < 1e-5
+
+
+@pytest.mark.parametrize("beta", BETAS)
+def test_tucker_objective_at_exact_fit(ctx, beta):
+    """Data equal to the Tucker model (rounded to float32): the objective is
+    of the order of 1e-14 of sum(x^beta) when every term is evaluated without
+    cancellation (about 1e-10 or more otherwise)."""
+    rng = np.random.default_rng(22)
+    dims, J = (37, 45, 70), (8, 6, 5)
+    core = f32(rng.uniform(0.1, 1.0, size=J))
+    fac = [f32(rng.uniform(0.1, 1.0, size=(d, j))) for d, j in zip(dims, J)]
+    X = f32(otk.rebuild(core, fac))
+    G, F = _dev_model(core, fac)
+    out = ctx.beta_objective(dev(X), F, core=G, beta=beta)
+    torch.cuda.synchronize()
+    scale = float(np.sum(X.astype(np.float64) ** beta))
+    assert 0.0 <= out.item() < 1e-11 * scale
