@@ -146,7 +146,8 @@ def control_512(ctx, steps):
 
 
 def comparisons(ctx, X, init32, steps):
-    """Config-2 companions on the same tensor and GPU: J-CoMM at beta = 0.5 and
+    """Config-2 companions on the same tensor and GPU: J-CoMM at beta = 0.5 (P~/Q~
+    recomputed, and with the autotune table's choice) and
     the plain block-MM (B-CoMM) sweep at beta = 1 and 0.5, each from the same
     initial factors, in iterations per second (wall clock around `steps`)."""
     import torch
@@ -167,6 +168,14 @@ def comparisons(ctx, X, init32, steps):
         fac = [torch.from_numpy(a).cuda() for a in init32]
         res[f"jcomm_beta{beta}_L5_obj_it_s"] = rate(
             lambda: ctx.jcomm_outer(X, fac, beta=beta, L=5, obj_out=obj))
+        # the autotune table's choice between streaming the cached P~/Q~ and
+        # recomputing them, then the rate with that choice
+        fac = [torch.from_numpy(a).cuda() for a in init32]
+        tuned = ctx.tune_jcomm(X, fac, beta=beta, L=5, reps=3)
+        res[f"jcomm_beta{beta}_L5_tune"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                            for k, v in tuned.items()}
+        res[f"jcomm_beta{beta}_L5_obj_auto_it_s"] = rate(
+            lambda: ctx.jcomm_outer(X, fac, beta=beta, L=5, obj_out=obj, cache_pq="auto"))
     # the headline iteration with bf16 matrix-core tiles, and its objective
     # against the float32 path after the same number of iterations
     fac = [torch.from_numpy(a).cuda() for a in init32]

@@ -89,6 +89,9 @@ extern "C" {
 #define COMM_FP32 0
 #define COMM_BF16 1
 
+/* comm_opts.cache_pq: take the choice recorded by comm_tune_jcomm. */
+#define COMM_CACHE_AUTO (-1)
+
 typedef struct comm_ctx comm_ctx;
 
 /* Largest order of comm_dense and comm_model. */
@@ -122,7 +125,11 @@ typedef struct {
  *   precision     COMM_FP32 or COMM_BF16 (see above).
  *   cache_pq      J-CoMM at beta != 1: 1 = store P~ and Q~ once per outer
  *                 iteration in the workspace and stream them in the inner
- *                 passes; 0 = recompute them from X and the reference.
+ *                 passes; 0 = recompute them from X and the reference;
+ *                 COMM_CACHE_AUTO = the choice comm_tune_jcomm recorded for
+ *                 this problem in the context, else 1.  Both give the same
+ *                 results; only time and workspace differ.  Other values are
+ *                 refused (COMM_EINVAL).
  *   check_inputs  debug mode: 1 = before anything is launched, verify on the
  *                 device that the data are finite and >= 0 (dense X, or the
  *                 COO values) and every parameter is finite and >= eps
@@ -173,6 +180,27 @@ int comm_destroy(comm_ctx* ctx);
  * asynchronous HIP error raised since (a device fault in a kernel), as
  * COMM_EHIP with the runtime's message; COMM_OK otherwise. */
 int comm_check(comm_ctx* ctx);
+
+/* Autotuning of J-CoMM (not a passage of the paper: a choice between two
+ * evaluations of the same update).  For the problem given (shapes, rank or
+ * core sizes, beta, precision and L of x, model and opts; opts->cache_pq is
+ * ignored), runs one untimed and then `reps` timed outer iterations with
+ * cache_pq = 1 and with cache_pq = 0, each from a device copy of the model's
+ * parameters, so the caller's model is left as it was.  The faster choice is
+ * stored in the context's autotune table, where calls with cache_pq =
+ * COMM_CACHE_AUTO on a problem with the same key find it.  When the cache
+ * variant cannot run (workspace limit), 0 is recorded.  At beta = 1 no P~ / Q~
+ * is kept, so 0 is recorded without timing.
+ *   reps     1 to 1000.
+ *   choice   if not NULL, receives the recorded choice (0 or 1).
+ *   ms       if not NULL, receives ms[0] (recompute) and ms[1] (cache), the
+ *            mean time of one outer iteration in milliseconds, NaN when not
+ *            run.
+ * The call allocates a copy of the parameters, may grow the workspace to hold
+ * the cache, synchronises `stream`, and drops the cached graph of the batched
+ * entry point.  Errors as for comm_jcomm_outer. */
+int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts, int reps,
+                    int* choice, double* ms, void* stream);
 
 /* Message of the last error raised on this thread (never NULL). */
 const char* comm_last_error(void);

@@ -27,6 +27,7 @@ COMM_FP32 = 0
 COMM_BF16 = 1
 PRECISIONS = {"fp32": COMM_FP32, "bf16": COMM_BF16}
 COMM_BATCH_GRAPH = 1
+COMM_CACHE_AUTO = -1
 
 EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_profile_enable",
             "comm_profile_query", "comm_cp_update",
@@ -34,7 +35,7 @@ EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_by
             "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
             "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap",
             "comm_cp_update_coo", "comm_beta_objective_coo", "comm_tucker_update_coo",
-            "comm_tucker_jcomm_outer_coo", "comm_check"]
+            "comm_tucker_jcomm_outer_coo", "comm_check", "comm_tune_jcomm"]
 
 
 class CommError(RuntimeError):
@@ -120,13 +121,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.comm_tucker_jcomm_outer_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
                                                 ctypes.c_void_p]
     lib.comm_check.argtypes = [ctypes.c_void_p]
+    lib.comm_tune_jcomm.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), ctypes.c_int, P(ctypes.c_int),
+                                    P(ctypes.c_double), ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
                  "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched",
                  "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan",
                  "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap", "comm_cp_update_coo",
-                 "comm_beta_objective_coo", "comm_tucker_update_coo", "comm_tucker_jcomm_outer_coo", "comm_check"]:
+                 "comm_beta_objective_coo", "comm_tucker_update_coo", "comm_tucker_jcomm_outer_coo", "comm_check",
+                 "comm_tune_jcomm"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -192,7 +196,7 @@ def _model(factors: Sequence, core=None) -> Model:
     return m
 
 
-def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq: bool = False,
+def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq: "bool | str" = False,
           precision: str = "fp32", check_inputs: bool = False) -> Opts:
     o = Opts()
     o.check_inputs = 1 if check_inputs else 0
@@ -203,7 +207,12 @@ def _opts(beta: float, eps: float, eps_x: Optional[float], L: int = 1, cache_pq:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
     o.precision = PRECISIONS[precision]
-    o.cache_pq = 1 if cache_pq else 0
+    if isinstance(cache_pq, str):
+        if cache_pq != "auto":
+            raise ValueError("cache_pq must be True, False or 'auto'")
+        o.cache_pq = COMM_CACHE_AUTO
+    else:
+        o.cache_pq = 1 if cache_pq else 0
     return o
 
 
@@ -340,7 +349,7 @@ class Context:
         return ms.value, n.value
 
     def workspace_bytes(self, dims: Sequence[int], rank: int = 0, core_dims: Optional[Sequence[int]] = None,
-                        beta: float = 1.0, L: int = 1, cache_pq: bool = False, op: int = 1) -> int:
+                        beta: float = 1.0, L: int = 1, cache_pq: "bool | str" = False, op: int = 1) -> int:
         """Workspace bytes of one call on a tensor of shape `dims` (op 0 update,
         1 jcomm_outer, 2 objective): CP of `rank`, or Tucker with `core_dims`.
         Needs no buffers; 0 if the arguments are invalid."""
@@ -377,7 +386,7 @@ class Context:
                                             ctypes.byref(o), _stream(stream)))
 
     def jcomm_outer(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
-                    eps_x: Optional[float] = None, cache_pq: bool = False, obj_out=None, stream=None,
+                    eps_x: Optional[float] = None, cache_pq: "bool | str" = False, obj_out=None, stream=None,
                     precision: str = "fp32") -> None:
         """One J-CoMM outer iteration in place; F(reference) into obj_out[0] (float64) if given."""
         d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, cache_pq, precision)
@@ -389,6 +398,20 @@ class Context:
             optr = _ptr(obj_out, "obj_out")
         _check(self._lib.comm_jcomm_outer(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), optr,
                                           _stream(stream)))
+
+    def tune_jcomm(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
+                   eps_x: Optional[float] = None, precision: str = "fp32", reps: int = 3, stream=None) -> dict:
+        """Time a J-CoMM outer iteration with and without the P~/Q~ cache on copies
+        of the parameters and record the faster in the context's autotune table,
+        which ``cache_pq="auto"`` calls on the same problem use.  Returns
+        ``{"cache_pq": 0 or 1, "ms_recompute": t0, "ms_cache": t1}`` (NaN when a
+        variant was not run)."""
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, False, precision)
+        choice = ctypes.c_int(-1)
+        ms = (ctypes.c_double * 2)()
+        _check(self._lib.comm_tune_jcomm(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), int(reps),
+                                         ctypes.byref(choice), ms, _stream(stream)))
+        return {"cache_pq": choice.value, "ms_recompute": ms[0], "ms_cache": ms[1]}
 
     def jcomm_outer_batched(self, batch: "Batch", graph: bool = False, stream=None) -> None:
         """One J-CoMM outer iteration for every problem of `batch`, each with the
@@ -413,7 +436,7 @@ class Context:
 
     def jcomm_outer_extrap(self, X, factors, prev, core=None, prev_core=None, beta: float = 1.0, L: int = 1,
                            alpha_nes: float = 0.0, c: float = 1.0, delta: float = 1e-12, eps: float = 1e-12,
-                           eps_x: Optional[float] = None, cache_pq: bool = False, obj_out=None, alpha_out=None,
+                           eps_x: Optional[float] = None, cache_pq: "bool | str" = False, obj_out=None, alpha_out=None,
                            stream=None, precision: str = "fp32"):
         """J-CoMM outer iteration from the extrapolated reference, in place."""
         d, m = _dense(X), _model(factors, core)

@@ -30,6 +30,8 @@ int check_opts(const comm_opts* o, bool need_L) {
   if (need_L && o->inner_sweeps < 1) return fail(COMM_EINVAL, "inner_sweeps must be >= 1");
   if (o->precision != COMM_FP32 && o->precision != COMM_BF16)
     return fail(COMM_EINVAL, "precision %d is neither COMM_FP32 nor COMM_BF16", o->precision);
+  if (o->cache_pq != 0 && o->cache_pq != 1 && o->cache_pq != COMM_CACHE_AUTO)
+    return fail(COMM_EINVAL, "cache_pq %d is not 0, 1 or COMM_CACHE_AUTO", o->cache_pq);
   return COMM_OK;
 }
 
@@ -1241,10 +1243,51 @@ size_t jcomm_ws_bytes(const comm_dense* x, const comm_model* model, const comm_o
   return tucker_workspace_bytes(x, model, opts, 1);
 }
 
+// Key of the autotune table: what fixes a J-CoMM outer iteration's launch
+// sequence and sizes (model kind, shape, rank or core, beta, precision, L).
+std::vector<int64_t> tune_key(const comm_dense* x, const comm_model* m, const comm_opts* o) {
+  std::vector<int64_t> k = {m->kind, x->ndim};
+  for (int n = 0; n < x->ndim; ++n) k.push_back(x->dims[n]);
+  if (m->kind == COMM_CP) {
+    k.push_back(m->rank);
+  } else {
+    for (int n = 0; n < x->ndim; ++n) k.push_back(m->core_dims[n]);
+  }
+  int64_t beta_bits;
+  std::memcpy(&beta_bits, &o->beta, sizeof beta_bits);
+  k.push_back(beta_bits);
+  k.push_back(o->precision);
+  k.push_back(o->inner_sweeps);
+  return k;
+}
+
+int jcomm_variant(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* o, double* obj,
+                  hipStream_t st) {
+  return model->kind == COMM_CP ? cp_jcomm(ctx, x, model, o, obj, st) : tucker_jcomm(ctx, x, model, o, obj, st);
+}
+
+// cache_pq = COMM_CACHE_AUTO takes the choice the table holds for the problem,
+// and the cache when it holds none.
 int jcomm_run(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts, double* obj,
               hipStream_t st) {
-  return model->kind == COMM_CP ? cp_jcomm(ctx, x, model, opts, obj, st) : tucker_jcomm(ctx, x, model, opts, obj, st);
+  comm_opts o = *opts;
+  if (o.cache_pq == COMM_CACHE_AUTO) {
+    const auto it = ctx->tune.find(tune_key(x, model, opts));
+    o.cache_pq = it == ctx->tune.end() ? 1 : it->second;
+  }
+  return jcomm_variant(ctx, x, model, &o, obj, st);
 }
+
+// Device copy of a model's parameters for the tuner (freed on scope exit).
+struct TuneScratch {
+  float* buf = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~TuneScratch() {
+    if (buf) hipFree(buf);
+    for (hipEvent_t e : ev)
+      if (e) hipEventDestroy(e);
+  }
+};
 
 // A batch runs every problem with the kernels and launch shapes of a single
 // call, on a private slice of the batch workspace, so its result does not
@@ -1565,6 +1608,86 @@ int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, cons
     rc = jcomm_run(ctx, x, model, opts, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
+  });
+}
+
+int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts, int reps,
+                    int* choice, double* ms, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = jcomm_check(x, model, opts);
+    if (rc) return rc;
+    if (reps < 1 || reps > 1000) return fail(COMM_EINVAL, "reps = %d (1 to 1000)", reps);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
+    double t[2] = {NAN, NAN};  // per outer iteration: [0] recompute, [1] cache
+    int best = 0;
+    if (opts->beta != 1.0) {
+      // the variants run on a copy of the parameters; the caller's are not touched
+      comm_model sm = *model;
+      size_t count[COMM_MAX_NDIM + 1] = {};
+      size_t total = 0;
+      for (int n = 0; n < x->ndim; ++n) {
+        const int64_t cols = model->kind == COMM_CP ? model->rank : model->core_dims[n];
+        count[n] = (size_t)x->dims[n] * (size_t)cols;
+        total += count[n];
+      }
+      if (model->kind == COMM_TUCKER) {
+        count[COMM_MAX_NDIM] = 1;
+        for (int n = 0; n < x->ndim; ++n) count[COMM_MAX_NDIM] *= (size_t)model->core_dims[n];
+        total += count[COMM_MAX_NDIM];
+      }
+      TuneScratch sc;
+      HIP_TRY(hipMalloc(&sc.buf, total * sizeof(float)));
+      HIP_TRY(hipEventCreate(&sc.ev[0]));
+      HIP_TRY(hipEventCreate(&sc.ev[1]));
+      size_t off = 0;
+      for (int n = 0; n < x->ndim; ++n) {
+        sm.factors[n] = sc.buf + off;
+        off += count[n];
+      }
+      if (model->kind == COMM_TUCKER) sm.core = sc.buf + off;
+      auto reset = [&]() -> int {
+        for (int n = 0; n < x->ndim; ++n)
+          HIP_TRY(hipMemcpyAsync(sm.factors[n], model->factors[n], count[n] * sizeof(float),
+                                 hipMemcpyDeviceToDevice, st));
+        if (model->kind == COMM_TUCKER)
+          HIP_TRY(hipMemcpyAsync(sm.core, model->core, count[COMM_MAX_NDIM] * sizeof(float),
+                                 hipMemcpyDeviceToDevice, st));
+        return COMM_OK;
+      };
+      for (int v = 1; v >= 0; --v) {
+        comm_opts o = *opts;
+        o.cache_pq = v;
+        if ((rc = reset())) return rc;
+        // one untimed iteration (workspace growth, first touch), then reps timed
+        rc = jcomm_variant(ctx, x, &sm, &o, nullptr, st);
+        if (rc && v == 1) continue;  // no room for the cache: recompute wins
+        if (rc) return rc;
+        if ((rc = reset())) return rc;
+        HIP_TRY(hipEventRecord(sc.ev[0], st));
+        for (int r = 0; r < reps; ++r)
+          if ((rc = jcomm_variant(ctx, x, &sm, &o, nullptr, st))) return rc;
+        HIP_TRY(hipEventRecord(sc.ev[1], st));
+        HIP_TRY(hipEventSynchronize(sc.ev[1]));
+        float el = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&el, sc.ev[0], sc.ev[1]));
+        t[v] = (double)el / reps;
+      }
+      HIP_TRY(hipStreamSynchronize(st));
+      best = !std::isnan(t[1]) && t[1] <= t[0] ? 1 : 0;
+    }
+    ctx->tune[tune_key(x, model, opts)] = best;
+    // a captured batch may have resolved COMM_CACHE_AUTO with the old table
+    if ((rc = batch_drop_graph(ctx))) return rc;
+    if (choice) *choice = best;
+    if (ms) {
+      ms[0] = t[0];
+      ms[1] = t[1];
+    }
+    ctx->last_stream = st;
+    return COMM_OK;
   });
 }
 

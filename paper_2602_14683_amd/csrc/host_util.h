@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -21,6 +22,8 @@ struct comm_ctx {
   size_t ws_bytes = 0;
   hipStream_t last_stream = nullptr;
   float* aux = nullptr;     // small device scratch that outlives workspace growth (extrapolation weight)
+  // autotune table: J-CoMM problem key -> measured faster cache_pq (0 or 1)
+  std::map<std::vector<int64_t>, int> tune;
   // measurement: event pairs around every fused dense pass launch
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

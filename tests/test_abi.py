@@ -86,3 +86,14 @@ def test_workspace_query_by_order():
     assert ws((80, 70, 60), core=(10, 9, 8)) > 0
     assert ws((4096, 4097, 2, 2), rank=4) == 0
     assert ws((40, 50), rank=4) == 0
+
+
+def test_cache_option_values():
+    import paper_2602_14683_amd as pkg
+    header = open(HEADER).read()
+    assert int(re.search(r"#define COMM_CACHE_AUTO \((-?\d+)\)", header).group(1)) == pkg.COMM_CACHE_AUTO
+    assert pkg._opts(0.5, 1e-12, None, cache_pq="auto").cache_pq == pkg.COMM_CACHE_AUTO
+    assert pkg._opts(0.5, 1e-12, None, cache_pq=True).cache_pq == 1
+    assert pkg._opts(0.5, 1e-12, None, cache_pq=False).cache_pq == 0
+    with pytest.raises(ValueError):
+        pkg._opts(0.5, 1e-12, None, cache_pq="always")

@@ -1,0 +1,112 @@
+"""GPU tests of the J-CoMM autotune table (comm_tune_jcomm and
+cache_pq = COMM_CACHE_AUTO), through the C ABI.
+
+The two variants it chooses between evaluate the same update, so a call with
+cache_pq="auto" must give bitwise the result of a call with the recorded
+choice, and the tuner must leave the caller's parameters as they were."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2602_14683_amd as comm  # noqa: E402
+from oracle import cp as ocp  # noqa: E402
+from oracle import tucker as otk  # noqa: E402
+from tests.gpu_util import dev, f32  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = comm.Context(0)
+    yield c
+    c.close()
+
+
+def _cp(seed, dims=(37, 70, 90), R=8):
+    rng = np.random.default_rng(seed)
+    planted = [rng.uniform(0.0, 1.0, size=(d, R)) for d in dims]
+    X = rng.poisson(ocp.rebuild(planted) * 4.0).astype(np.float64)
+    init = [f32(rng.uniform(0.1, 1.0, size=(d, R))) for d in dims]
+    return X, init, None
+
+
+def _tucker(seed, dims=(30, 36, 40), J=(6, 5, 4)):
+    rng = np.random.default_rng(seed)
+    core = rng.uniform(0.0, 1.0, size=J)
+    fac = [rng.uniform(0.0, 1.0, size=(d, j)) for d, j in zip(dims, J)]
+    X = rng.poisson(otk.rebuild(core, fac) * 2.0).astype(np.float64)
+    icore = f32(rng.uniform(0.1, 1.0, size=J))
+    ifac = [f32(rng.uniform(0.1, 1.0, size=(d, j))) for d, j in zip(dims, J)]
+    return X, ifac, icore
+
+
+def _run(ctx, X, init, core, beta, cache_pq, L=2):
+    F = [dev(a) for a in init]
+    G = dev(core) if core is not None else None
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer(dev(X), F, core=G, beta=beta, L=L, cache_pq=cache_pq, obj_out=obj)
+    torch.cuda.synchronize()
+    return [f.cpu().numpy() for f in F], (G.cpu().numpy() if G is not None else None), obj.item()
+
+
+@pytest.mark.parametrize("make,beta", [(_cp, 0.5), (_cp, 1.5), (_cp, 0.0), (_tucker, 0.5), (_tucker, 1.5)])
+def test_auto_takes_the_tuned_choice_bitwise(ctx, make, beta):
+    X, init, core = make(3)
+    Xd = dev(X)
+    F = [dev(a) for a in init]
+    G = dev(core) if core is not None else None
+    before = [f.clone() for f in F] + ([G.clone()] if G is not None else [])
+    res = ctx.tune_jcomm(Xd, F, core=G, beta=beta, L=2, reps=2)
+    torch.cuda.synchronize()
+    assert res["cache_pq"] in (0, 1)
+    assert res["ms_recompute"] > 0.0 and res["ms_cache"] > 0.0
+    want = 1 if res["ms_cache"] <= res["ms_recompute"] else 0
+    assert res["cache_pq"] == want
+    after = F + ([G] if G is not None else [])
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)  # the tuner ran on copies
+    got = _run(ctx, X, init, core, beta, "auto")
+    ref = _run(ctx, X, init, core, beta, bool(res["cache_pq"]))
+    other = _run(ctx, X, init, core, beta, not bool(res["cache_pq"]))
+    for a, b in zip(got[0], ref[0]):
+        assert np.array_equal(a, b)
+    if core is not None:
+        assert np.array_equal(got[1], ref[1])
+    assert got[2] == ref[2]
+    # the two variants evaluate the same update
+    for a, b in zip(ref[0], other[0]):
+        assert np.max(np.abs(a - b) / np.abs(b)) < 1e-5
+
+
+def test_auto_without_an_entry_is_the_cache(ctx):
+    X, init, core = _cp(5, dims=(21, 33, 45), R=4)
+    got = _run(ctx, X, init, core, 0.5, "auto")
+    ref = _run(ctx, X, init, core, 0.5, True)
+    for a, b in zip(got[0], ref[0]):
+        assert np.array_equal(a, b)
+    assert got[2] == ref[2]
+
+
+def test_beta_one_records_recompute_without_timing(ctx):
+    X, init, core = _cp(6, dims=(20, 24, 28), R=4)
+    res = ctx.tune_jcomm(dev(X), [dev(a) for a in init], beta=1.0, L=2)
+    assert res["cache_pq"] == 0
+    assert math.isnan(res["ms_recompute"]) and math.isnan(res["ms_cache"])
+
+
+def test_bad_reps_and_cache_value_refused(ctx):
+    X, init, core = _cp(7, dims=(20, 24, 28), R=4)
+    with pytest.raises(comm.CommError):
+        ctx.tune_jcomm(dev(X), [dev(a) for a in init], beta=0.5, reps=0)
+    o = comm._opts(0.5, 1e-12, None, L=1)
+    o.cache_pq = 7
+    d, m = comm._dense(dev(X)), comm._model([dev(a) for a in init], None)
+    import ctypes
+    rc = ctx._lib.comm_jcomm_outer(ctx._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), None, None)
+    assert rc == comm.COMM_EINVAL
