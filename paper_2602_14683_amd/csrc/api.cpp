@@ -1268,13 +1268,18 @@ int jcomm_variant(comm_ctx* ctx, const comm_dense* x, comm_model* model, const c
 
 // cache_pq = COMM_CACHE_AUTO takes the choice the table holds for the problem,
 // and the cache when it holds none.
-int jcomm_run(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts, double* obj,
-              hipStream_t st) {
+comm_opts resolve_cache(const comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts) {
   comm_opts o = *opts;
   if (o.cache_pq == COMM_CACHE_AUTO) {
     const auto it = ctx->tune.find(tune_key(x, model, opts));
     o.cache_pq = it == ctx->tune.end() ? 1 : it->second;
   }
+  return o;
+}
+
+int jcomm_run(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts, double* obj,
+              hipStream_t st) {
+  const comm_opts o = resolve_cache(ctx, x, model, opts);
   return jcomm_variant(ctx, x, model, &o, obj, st);
 }
 
@@ -1396,7 +1401,9 @@ int batch_issue(comm_ctx* ctx, std::vector<BatchItem>& items, hipStream_t origin
     sub.ws = ctx->bws + it.off;
     sub.ws_bytes = it.bytes;
     sub.limit = it.bytes;  // a slice never grows: a larger need is an error, not an allocation
-    int rc = jcomm_run(&sub, &it.x, &it.m, &it.o, it.obj, ctx->bstreams[p % S]);
+    // the autotune table is the parent context's (the slice was sized for the cache)
+    const comm_opts o = resolve_cache(ctx, &it.x, &it.m, &it.o);
+    int rc = jcomm_run(&sub, &it.x, &it.m, &o, it.obj, ctx->bstreams[p % S]);
     if (rc) return rc;
   }
   for (int q = 0; q < S; ++q) {

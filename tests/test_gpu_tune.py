@@ -110,3 +110,40 @@ def test_bad_reps_and_cache_value_refused(ctx):
     import ctypes
     rc = ctx._lib.comm_jcomm_outer(ctx._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), None, None)
     assert rc == comm.COMM_EINVAL
+
+
+def _launches(ctx, X, init, core, beta, cache_pq, L=2):
+    ctx.profile_query()  # reset
+    ctx.profile_enable(True)
+    _run(ctx, X, init, core, beta, cache_pq, L)
+    n = ctx.profile_query()[1]
+    ctx.profile_enable(False)
+    return n
+
+
+@pytest.mark.parametrize("make", [_cp, _tucker])
+def test_auto_runs_the_recorded_variant(ctx, make):
+    # the cached variant writes P~ / Q~ in a pass of its own, so the two differ
+    # in their count of fused pass launches: auto must match the recorded one
+    X, init, core = make(8)
+    F = [dev(a) for a in init]
+    G = dev(core) if core is not None else None
+    choice = ctx.tune_jcomm(dev(X), F, core=G, beta=0.5, L=2, reps=1)["cache_pq"]
+    n = {v: _launches(ctx, X, init, core, 0.5, bool(v)) for v in (0, 1)}
+    assert n[0] != n[1]
+    assert _launches(ctx, X, init, core, 0.5, "auto") == n[choice]
+
+
+def test_batched_auto_takes_the_table_of_its_context(ctx):
+    X, init, core = _cp(9, dims=(24, 30, 36), R=8)
+    Xd = dev(X)
+    ctx.tune_jcomm(Xd, [dev(a) for a in init], beta=0.5, L=2, reps=1)
+    single = _run(ctx, X, init, core, 0.5, "auto")
+    F = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.jcomm_outer_batched(comm.Batch([{"X": Xd, "factors": F, "beta": 0.5, "L": 2, "cache_pq": "auto",
+                                         "obj_out": obj}]))
+    torch.cuda.synchronize()
+    for a, b in zip(single[0], [f.cpu().numpy() for f in F]):
+        assert np.array_equal(a, b)
+    assert obj.item() == single[2]
