@@ -176,6 +176,11 @@ def comparisons(ctx, X, init32, steps):
                                             for k, v in tuned.items()}
         res[f"jcomm_beta{beta}_L5_obj_auto_it_s"] = rate(
             lambda: ctx.jcomm_outer(X, fac, beta=beta, L=5, obj_out=obj, cache_pq="auto"))
+    # beta = 0.5 with bf16 tiles: P~/Q~ recomputed, and cached (as bf16)
+    for cache in (False, True):
+        fac = [torch.from_numpy(a).cuda() for a in init32]
+        res[f"jcomm_beta0.5_L5_obj_bf16_{'cache' if cache else 'recompute'}_it_s"] = rate(
+            lambda: ctx.jcomm_outer(X, fac, beta=0.5, L=5, obj_out=obj, cache_pq=cache, precision="bf16"))
     # the headline iteration with bf16 matrix-core tiles, and its objective
     # against the float32 path after the same number of iterations
     fac = [torch.from_numpy(a).cuda() for a in init32]

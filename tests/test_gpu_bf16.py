@@ -196,3 +196,25 @@ def test_bf16_tucker_objective(ctx, beta):
     torch.cuda.synchronize()
     want = oobjective(X, otk.rebuild(core, fac), beta)
     assert abs(out.item() - want) / want < 2e-4
+
+
+@pytest.mark.parametrize("dims,R,beta", [((37, 70, 90), 32, 0.5), ((30, 40, 50), 5, 1.5), ((21, 33, 45), 8, 0.0),
+                                          ((16, 20, 24, 28), 8, 0.5)])
+def test_bf16_cache_matches_recompute_bitwise(ctx, dims, R, beta):
+    """With bf16 tiles, cached P~ and Q~ enter the contractions through the same
+    bf16 conversion as recomputed ones, and the cache is written by the same
+    rebuild: J-CoMM with and without the cache must agree bit for bit."""
+    rng = np.random.default_rng(17)
+    planted = [rng.uniform(0.0, 1.0, size=(d, R)) for d in dims]
+    X = dev(rng.poisson(ocp.rebuild(planted) * 4.0).astype(np.float64))
+    init = [f32(rng.uniform(0.1, 1.0, size=(d, R))) for d in dims]
+    out = {}
+    for cache in (True, False):
+        F = [dev(a) for a in init]
+        obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.jcomm_outer(X, F, beta=beta, L=2, cache_pq=cache, obj_out=obj, precision="bf16")
+        torch.cuda.synchronize()
+        out[cache] = ([f.cpu().numpy() for f in F], obj.item())
+    for a, b in zip(out[True][0], out[False][0]):
+        assert np.array_equal(a, b)
+    assert out[True][1] == out[False][1]
