@@ -1686,7 +1686,9 @@ int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
       best = !std::isnan(t[1]) && t[1] <= t[0] ? 1 : 0;
     }
     ctx->tune[tune_key(x, model, opts)] = best;
-    // a captured batch may have resolved COMM_CACHE_AUTO with the old table
+    // a captured batch may have resolved COMM_CACHE_AUTO with the old table;
+    // its last replay ends before the graph goes
+    if ((rc = batch_sync_all(ctx, st))) return rc;
     if ((rc = batch_drop_graph(ctx))) return rc;
     if (choice) *choice = best;
     if (ms) {

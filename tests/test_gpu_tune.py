@@ -147,3 +147,22 @@ def test_batched_auto_takes_the_table_of_its_context(ctx):
     for a, b in zip(single[0], [f.cpu().numpy() for f in F]):
         assert np.array_equal(a, b)
     assert obj.item() == single[2]
+
+
+def test_tuning_between_graph_replays(ctx):
+    # tuning drops the captured graph of the batched entry point (its replays
+    # resolved the option with the old table); the next graph call recaptures
+    X, init, core = _cp(10, dims=(24, 30, 36), R=8)
+    Xd = dev(X)
+    F = [dev(a) for a in init]
+    batch = comm.Batch([{"X": Xd, "factors": F, "beta": 0.5, "L": 2, "cache_pq": "auto"}])
+    ctx.jcomm_outer_batched(batch, graph=True)
+    choice = ctx.tune_jcomm(Xd, [dev(a) for a in init], beta=0.5, L=2, reps=1)["cache_pq"]
+    ctx.jcomm_outer_batched(batch, graph=True)
+    torch.cuda.synchronize()
+    G = [dev(a) for a in init]
+    for _ in range(2):
+        ctx.jcomm_outer(Xd, G, beta=0.5, L=2, cache_pq=bool(choice))
+    torch.cuda.synchronize()
+    for a, b in zip(F, G):
+        assert torch.equal(a, b)
