@@ -1098,8 +1098,8 @@ int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* 
 }
 
 // The dense twin of x and the sparse buffers.  The twin's X is the context's
-// zero tensor, allocated unless `no_dense`; the CP passes need no tensor (a
-// null X tells them that x = 0 everywhere), the Tucker passes read it.
+// zero tensor, allocated unless `no_dense`: a null X tells the CP passes
+// (except at beta = 1) and the Tucker passes that x = 0 everywhere.
 int coo_beta_setup(comm_ctx* ctx, const comm_coo* x, bool no_dense, comm_dense* xd, CooBetaWs* s, hipStream_t st) {
   *xd = comm_dense{};
   xd->ndim = x->ndim;
@@ -1202,8 +1202,9 @@ int coo_beta_objective(comm_ctx* ctx, const comm_coo* x, const comm_model* m, co
                        hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  // the beta = 1 pass reads its X: there the CP twin keeps the zero tensor
-  int rc = coo_beta_setup(ctx, x, m->kind == COMM_CP && o->beta != 1.0, &xd, &s, st);
+  // the CP pass at beta = 1 reads its X: there the CP twin keeps the zero
+  // tensor; the Tucker passes take a missing X as x = 0 in every class
+  int rc = coo_beta_setup(ctx, x, m->kind == COMM_TUCKER || o->beta != 1.0, &xd, &s, st);
   if (rc) return rc;
   if (m->kind == COMM_TUCKER) {
     const TkSparse sp{x, s.w, s.num, s.obj};
@@ -1218,7 +1219,7 @@ int coo_tucker(comm_ctx* ctx, const comm_coo* x, comm_model* m, int block, const
                bool jcomm, hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  int rc = coo_beta_setup(ctx, x, o->beta == 1.0, &xd, &s, st);
+  int rc = coo_beta_setup(ctx, x, true, &xd, &s, st);  // the Tucker passes need no zero tensor
   if (rc) return rc;
   const TkSparse sp{x, s.w, s.num, s.obj};
   comm_opts od = *o;

@@ -108,8 +108,15 @@ __global__ void __launch_bounds__(kThreads, 4) tk_v_kernel(TkPassArgs a) {
       }
     } else {
       float xv[16];
-      if (vec && full) load_fibre<true>(xrow, k0, K, h, pvalid, xv);
-      else load_fibre<false>(xrow, k0, K, h, pvalid, xv);
+      if (!a.X) {
+        // no tensor: the all-zero dense twin of sparse data (x = 0 everywhere)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) xv[v] = 0.0f;
+      } else if (vec && full) {
+        load_fibre<true>(xrow, k0, K, h, pvalid, xv);
+      } else {
+        load_fibre<false>(xrow, k0, K, h, pvalid, xv);
+      }
       // rebuild: A = C rows (lane: k = k0 + col), B = T2 rows (lane: pair)
       float crow[16];
       row16(a.C.p + (int64_t)(k0 + col) * kRP + 16 * h, k0 + col < K, crow);
@@ -236,6 +243,12 @@ __global__ void __launch_bounds__(kThreads, 3) tk_m3_kernel(TkPassArgs a) {
   const int64_t pbase = (int64_t)(g * kWaves + w) * a.tpw * 32;
   // the fibre entries of the next pair tile are loaded while the current one is processed
   auto fetch = [&](int64_t p0, float (&dst)[16], const float* src) {
+    if (!src) {
+      // no tensor: the all-zero dense twin of sparse data (x = 0 everywhere)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) dst[v] = 0.0f;
+      return;
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t m = p0 + out_row(v, h);
