@@ -127,9 +127,10 @@ typedef struct {
  *                 iteration in the workspace and stream them in the inner
  *                 passes; 0 = recompute them from X and the reference;
  *                 COMM_CACHE_AUTO = the choice comm_tune_jcomm recorded for
- *                 this problem in the context, else 1.  Both give the same
- *                 results; only time and workspace differ.  Other values are
- *                 refused (COMM_EINVAL).
+ *                 this problem in the context, else 1 if the workspace the
+ *                 cache needs is within the context's limit, else 0.  Both
+ *                 give the same results; only time and workspace differ.
+ *                 Other values are refused (COMM_EINVAL).
  *   check_inputs  debug mode: 1 = before anything is launched, verify on the
  *                 device that the data are finite and >= 0 (dense X, or the
  *                 COO values) and every parameter is finite and >= eps

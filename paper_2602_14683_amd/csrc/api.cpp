@@ -1267,13 +1267,19 @@ int jcomm_variant(comm_ctx* ctx, const comm_dense* x, comm_model* model, const c
   return model->kind == COMM_CP ? cp_jcomm(ctx, x, model, o, obj, st) : tucker_jcomm(ctx, x, model, o, obj, st);
 }
 
-// cache_pq = COMM_CACHE_AUTO takes the choice the table holds for the problem,
-// and the cache when it holds none.
+// cache_pq = COMM_CACHE_AUTO takes the choice the table holds for the problem;
+// when it holds none, the cache if the workspace it needs is within the
+// context's limit, else recomputation.
 comm_opts resolve_cache(const comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts) {
   comm_opts o = *opts;
   if (o.cache_pq == COMM_CACHE_AUTO) {
     const auto it = ctx->tune.find(tune_key(x, model, opts));
-    o.cache_pq = it == ctx->tune.end() ? 1 : it->second;
+    if (it != ctx->tune.end()) {
+      o.cache_pq = it->second;
+    } else {
+      o.cache_pq = 1;
+      o.cache_pq = !ctx->limit || jcomm_ws_bytes(x, model, &o) <= ctx->limit ? 1 : 0;
+    }
   }
   return o;
 }
@@ -1430,7 +1436,8 @@ int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags
     it.m = *q.model;
     it.o = *q.opts;
     it.obj = q.obj_ref_dev;
-    it.bytes = (jcomm_ws_bytes(q.x, q.model, q.opts) + 255) & ~size_t(255);
+    const comm_opts ro = resolve_cache(ctx, q.x, q.model, q.opts);
+    it.bytes = (jcomm_ws_bytes(q.x, q.model, &ro) + 255) & ~size_t(255);
     it.off = total;
     total += it.bytes;
   }

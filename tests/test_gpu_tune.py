@@ -166,3 +166,31 @@ def test_tuning_between_graph_replays(ctx):
     torch.cuda.synchronize()
     for a, b in zip(F, G):
         assert torch.equal(a, b)
+
+
+def test_auto_without_an_entry_recomputes_when_the_cache_exceeds_the_limit():
+    dims, R = (37, 70, 90), 8
+    X, init, core = _cp(11, dims=dims, R=R)
+    probe = comm.Context(0)
+    try:
+        need = {c: probe.workspace_bytes(dims, rank=R, beta=0.5, L=2, cache_pq=c) for c in (False, True)}
+    finally:
+        probe.close()
+    assert need[False] < need[True]
+    small = comm.Context(0, workspace_limit=(need[False] + need[True]) // 2)
+    try:
+        with pytest.raises(comm.CommError):
+            _run(small, X, init, core, 0.5, True)
+        got = _run(small, X, init, core, 0.5, "auto")
+        ref = _run(small, X, init, core, 0.5, False)
+        for a, b in zip(got[0], ref[0]):
+            assert np.array_equal(a, b)
+        assert got[2] == ref[2]
+        F = [dev(a) for a in init]
+        small.jcomm_outer_batched(comm.Batch([{"X": dev(X), "factors": F, "beta": 0.5, "L": 2,
+                                               "cache_pq": "auto"}]))
+        torch.cuda.synchronize()
+        for a, b in zip(ref[0], [f.cpu().numpy() for f in F]):
+            assert np.array_equal(a, b)
+    finally:
+        small.close()
