@@ -210,7 +210,8 @@ const char* comm_last_error(void);
  * arguments).  `op` is 0 = cp_update / tucker_update, 1 = jcomm_outer,
  * 2 = beta_objective.  Only shapes, model kind, rank / core sizes and options
  * are read; buffer pointers may be NULL (a server sizes requests before
- * loading them). */
+ * loading them).  cache_pq = COMM_CACHE_AUTO is counted as 1, the larger need
+ * (there is no context, hence no autotune table, to resolve it). */
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op);
 
 /* Measurement hooks.  While enabled, the context records a pair of HIP events
