@@ -34,11 +34,11 @@ reconstruction is clipped, 0 log 0, gamma at the boundary cases, Tucker block
 order, where eps is enforced in the inner loop) are fixed by keyword defaults
 documented on each function.
 """
-from .divergence import (beta_divergence, objective, objective_from_model, gamma, powers,
+from .divergence import (beta_divergence, objective, gamma, powers,
                          chi1, chi2, EPS_DEFAULT)
 from . import cp, tucker, sparse, surrogate, unfolding, loops
 
 __all__ = [
-    "beta_divergence", "objective", "objective_from_model", "gamma", "powers", "chi1", "chi2",
+    "beta_divergence", "objective", "gamma", "powers", "chi1", "chi2",
     "EPS_DEFAULT", "cp", "tucker", "sparse", "surrogate", "unfolding", "loops",
 ]

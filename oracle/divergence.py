@@ -58,17 +58,6 @@ def objective(X: np.ndarray, Xhat: np.ndarray, beta: float, eps: float = EPS_DEF
     return math.fsum(beta_divergence(Xf, Xc, beta).ravel())
 
 
-def objective_from_model(X, model, beta: float, eps: float = EPS_DEFAULT,
-                         eps_x: float | None = None) -> float:
-    """Objective at a model given as ('cp', factors) or ('tucker', core, factors)."""
-    from . import cp, tucker
-    if model[0] == "cp":
-        Xhat = cp.rebuild(model[1])
-    else:
-        Xhat = tucker.rebuild(model[1], model[2])
-    return objective(X, Xhat, beta, eps, eps_x)
-
-
 def gamma(beta: float) -> float:
     """Multiplicative exponent (Remark on gamma(beta)): 1/(2-beta) for beta < 1,
     1 for 1 <= beta < 2.  beta = 0 gives 1/2, beta = 1 gives 1."""

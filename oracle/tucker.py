@@ -94,16 +94,40 @@ def bcomm_sweep(X, core, factors, beta, eps=EPS_DEFAULT, eps_x=None) -> Tuple[np
     return G, cur
 
 
+def jcomm_inner_update_core(Pt, Qt, cur, ref, Gref, beta, eps=EPS_DEFAULT) -> np.ndarray:
+    """Tucker core inner update of J-CoMM (Sec. 5.3; App. C.3, eqs. jmm_core_num,
+    jmm_core_den): P~ contracted against chi_1(A^(n), A~^(n)) and Q~ against
+    chi_2(A^(n), A~^(n)) for every n, with the current inner factors; anchored at
+    the reference core: max(G~ (Num_J / Den_J)^gamma, eps)."""
+    N = len(cur)
+    a1 = [chi1(cur[m], ref[m], beta) for m in range(N)]
+    a2 = [chi2(cur[m], ref[m], beta) for m in range(N)]
+    num = core_contr(Pt, a1)
+    den = core_contr(Qt, a2)
+    return np.maximum(Gref * np.power(num / den, gamma(beta)), eps)
+
+
+def jcomm_inner_update_factor(Pt, Qt, G, Gref, cur, ref, n, beta, eps=EPS_DEFAULT) -> np.ndarray:
+    """Tucker factor inner update of J-CoMM for mode n (App. C.3, eqs.
+    jmm_factor_num, jmm_factor_den): Num_J / Den_J contract P~ / Q~ with
+    chi_1 / chi_2 of the current core against G~ and of the other current
+    factors against their references; anchored at A~^(n)."""
+    N = len(cur)
+    g1 = chi1(G, Gref, beta)
+    g2 = chi2(G, Gref, beta)
+    o1 = [chi1(cur[m], ref[m], beta) for m in range(N) if m != n]
+    o2 = [chi2(cur[m], ref[m], beta) for m in range(N) if m != n]
+    num = factor_contr(Pt, g1, o1, n)
+    den = factor_contr(Qt, g2, o2, n)
+    return np.maximum(ref[n] * np.power(num / den, gamma(beta)), eps)
+
+
 def jcomm_outer(X, core, factors, beta, L=1, eps=EPS_DEFAULT, eps_x=None, return_ref_obj=False):
     """One outer iteration of J-CoMM for Tucker (Algorithm J-CoMM with the Tucker
-    inner updates of Sec. 5.3 and App. C.3).
-
-    Core: G = max(G~ (P~_core,J / Q~_core,J)^gamma, eps) with P~ contracted against
-    chi_1(A^(n), A~^(n)) and Q~ against chi_2(A^(n), A~^(n)) for every n
-    (eqs. jmm_core_num, jmm_core_den).  Factor n: Num_J / Den_J contract P~ / Q~
-    with G_(1) / G_(2) and the other transformed factors (eqs. jmm_factor_num,
-    jmm_factor_den), anchored at A~^(n).  The transforms always use the current
-    inner values, so the factor updates see the new core."""
+    inner updates of Sec. 5.3 and App. C.3): the reference Theta~ = (G~, A~),
+    P~ and Q~ formed once from X~ = rebuild(Theta~), then L sweeps of the core
+    update followed by the factor updates of modes 1..N.  The transforms always
+    use the current inner values, so the factor updates see the new core."""
     if L < 1:
         raise ValueError("L must be >= 1")
     Gref = np.array(core, dtype=np.float64, copy=True)
@@ -112,22 +136,10 @@ def jcomm_outer(X, core, factors, beta, L=1, eps=EPS_DEFAULT, eps_x=None, return
     Pt, Qt = powers(X, Xt, beta, eps, eps_x)
     G = Gref.copy()
     cur = [a.copy() for a in ref]
-    g = gamma(beta)
-    N = len(cur)
     for _ in range(L):
-        a1 = [chi1(cur[m], ref[m], beta) for m in range(N)]
-        a2 = [chi2(cur[m], ref[m], beta) for m in range(N)]
-        num = core_contr(Pt, a1)
-        den = core_contr(Qt, a2)
-        G = np.maximum(Gref * np.power(num / den, g), eps)
-        for n in range(N):
-            g1 = chi1(G, Gref, beta)
-            g2 = chi2(G, Gref, beta)
-            o1 = [chi1(cur[m], ref[m], beta) for m in range(N) if m != n]
-            o2 = [chi2(cur[m], ref[m], beta) for m in range(N) if m != n]
-            num = factor_contr(Pt, g1, o1, n)
-            den = factor_contr(Qt, g2, o2, n)
-            cur[n] = np.maximum(ref[n] * np.power(num / den, g), eps)
+        G = jcomm_inner_update_core(Pt, Qt, cur, ref, Gref, beta, eps)
+        for n in range(len(cur)):
+            cur[n] = jcomm_inner_update_factor(Pt, Qt, G, Gref, cur, ref, n, beta, eps)
     if return_ref_obj:
         return G, cur, objective(X, Xt, beta, eps, eps_x)
     return G, cur

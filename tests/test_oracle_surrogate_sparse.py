@@ -83,6 +83,52 @@ def test_tucker_inner_updates_decrease_G(beta):
 
 
 @pytest.mark.parametrize("beta", BETAS)
+@pytest.mark.parametrize("L", [1, 2])
+def test_tucker_every_inner_block_is_block_minimiser(beta, L):
+    """Each block of a Tucker J-CoMM sweep (the core, then every factor, in
+    every inner sweep) is the minimiser of G(. | ref) over that block with the
+    other blocks at their current inner values (Sec. 5.3; App. C.3): random
+    log-perturbations of the freshly updated block never lower G, and G does
+    not increase from one block to the next."""
+    rng = np.random.default_rng(6)
+    dims, J = (4, 3, 5), (2, 3, 2)
+    Gref = rng.uniform(0.3, 1.2, size=J)
+    ref = [rng.uniform(0.3, 1.2, size=(d, j)) for d, j in zip(dims, J)]
+    X = rng.poisson(2.0, size=dims).astype(float) + 0.1
+    Pt, Qt = powers(X, tucker.rebuild(Gref, ref), beta)
+    G, cur = Gref.copy(), [a.copy() for a in ref]
+    g_prev = surrogate.surrogate_tucker(X, G, cur, Gref, ref, beta)
+
+    def check_minimal(G, cur, g_new, block):
+        for _ in range(6):
+            if block < 0:
+                Gp, cp_ = G * np.exp(rng.normal(0, 0.05, size=G.shape)), cur
+            else:
+                Gp = G
+                cp_ = [a * np.exp(rng.normal(0, 0.05, size=a.shape)) if m == block else a
+                       for m, a in enumerate(cur)]
+            assert surrogate.surrogate_tucker(X, Gp, cp_, Gref, ref, beta) >= g_new * (1 - 1e-13), block
+
+    for _ in range(L):
+        G = tucker.jcomm_inner_update_core(Pt, Qt, cur, ref, Gref, beta)
+        g_new = surrogate.surrogate_tucker(X, G, cur, Gref, ref, beta)
+        assert g_new <= g_prev * (1 + 1e-13)
+        check_minimal(G, cur, g_new, -1)
+        g_prev = g_new
+        for n in range(3):
+            cur[n] = tucker.jcomm_inner_update_factor(Pt, Qt, G, Gref, cur, ref, n, beta)
+            g_new = surrogate.surrogate_tucker(X, G, cur, Gref, ref, beta)
+            assert g_new <= g_prev * (1 + 1e-13), n
+            check_minimal(G, cur, g_new, n)
+            g_prev = g_new
+    # the step-by-step sweep is the oracle's outer iteration
+    G2, cur2 = tucker.jcomm_outer(X, Gref, ref, beta, L=L)
+    np.testing.assert_array_equal(G, G2)
+    for a, b in zip(cur, cur2):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("beta", BETAS)
 def test_scalar_minimiser_brute_force(beta):
     rng = np.random.default_rng(5)
     for _ in range(5):
