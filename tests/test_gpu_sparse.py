@@ -1,8 +1,9 @@
 """GPU parity of the sparse COO beta = 1 J-CoMM path against the FP64 oracle.
 
-The COO path scatters with hardware float atomics, so the bar is the FP32 one
-(1e-5 relative per factor entry after one outer iteration) rather than bitwise
-reproducibility."""
+The COO path scatters with hardware float atomics, so results are reproducible
+to rounding, not bitwise.  The bars are the dense path's: 1e-5 relative per
+factor entry after one outer iteration with one inner sweep, 3e-5 after two or
+three inner sweeps (each sweep compounds the rounding of the last)."""
 import numpy as np
 import pytest
 
@@ -17,6 +18,8 @@ if not torch.cuda.is_available():
 
 import paper_2602_14683_amd as comm  # noqa: E402
 from tests.gpu_util import dev, f32, host64, max_rel  # noqa: E402
+
+TOL = 1e-5  # relative, per factor entry, after one outer iteration with L = 1
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +47,7 @@ def test_coo_jcomm_matches_oracle(ctx, dims, density, rank, L):
     torch.cuda.synchronize()
     want, fref = osp.jcomm_outer_kl(s.idx, s.val, init, L=L, return_ref_obj=True)
     for a, b in zip(fac, want):
-        assert max_rel(host64(a), b) < 3e-5
+        assert max_rel(host64(a), b) < TOL * (1 if L == 1 else 3)
     assert abs(obj.item() - fref) / fref < 1e-5
 
 
@@ -112,7 +115,7 @@ def test_coo_plan_matches_oracle(ctx, dims, density, rank, L):
     torch.cuda.synchronize()
     want, fref = osp.jcomm_outer_kl(s.idx, s.val, init, L=L, return_ref_obj=True)
     for a, b in zip(fac, want):
-        assert max_rel(host64(a), b) < 3e-5
+        assert max_rel(host64(a), b) < TOL * (1 if L == 1 else 3)
     assert abs(obj.item() - fref) / fref < 1e-5
     plan.close()
 
@@ -136,7 +139,7 @@ def test_coo_plan_skips_out_of_range_coordinates(ctx):
             ctx.cp_jcomm_outer_coo(idx, val, s.dims, fac, L=2)
         torch.cuda.synchronize()
         for a, b in zip(fac, want):
-            assert max_rel(host64(a), b) < 3e-5
+            assert max_rel(host64(a), b) < 3 * TOL
 
 
 def test_coo_plan_empty_tensor(ctx):
@@ -198,4 +201,4 @@ def test_coo_unaligned_factors(ctx):
     torch.cuda.synchronize()
     want = osp.jcomm_outer_kl(s.idx, s.val, init, L=2)
     for a, b in zip(fac, want):
-        assert max_rel(host64(a), b) < 3e-5
+        assert max_rel(host64(a), b) < 3 * TOL

@@ -5,9 +5,10 @@ The updates of a sparse tensor are those of its dense form by definition; the
 library accumulates the P-numerators over the nonzeros only and takes the
 Q-denominators and the zero cells' objective from the dense pass over an
 all-zero tensor of the same shape.  Float atomics make the nonzero sums
-reproducible to rounding only, so the bars are the FP32 ones: 3e-5 relative
-per factor entry after one block update or sweep, 1e-4 after a J-CoMM outer
-iteration with two inner sweeps, 1e-5 on the objective."""
+reproducible to rounding only (not bitwise); the bars are the dense path's:
+1e-5 relative per factor entry after one block update, 3e-5 after a sweep or a
+J-CoMM outer iteration with two inner sweeps, 1e-5 on the objective, 1e-4 on
+an objective trace."""
 
 import numpy as np
 import pytest
@@ -52,7 +53,7 @@ def test_block_update_every_mode(ctx, dims, density, rank, beta):
         fac = [dev(a) for a in init]
         ctx.cp_update_coo(idx, val, dims, fac, block=n, beta=beta)
         torch.cuda.synchronize()
-        assert max_rel(host64(fac[n]), ocp.block_update(X, init, n, beta)) < 3e-5, f"mode {n}"
+        assert max_rel(host64(fac[n]), ocp.block_update(X, init, n, beta)) < 1e-5, f"mode {n}"
         for m in range(len(dims)):
             if m != n:
                 assert np.array_equal(host64(fac[m]), init[m])
@@ -69,7 +70,7 @@ def test_bcomm_sweep(ctx, dims, density, rank, beta):
     ctx.cp_update_coo(idx, val, dims, fac, block=-1, beta=beta)
     torch.cuda.synchronize()
     for a, b in zip(fac, ocp.bcomm_sweep(X, init, beta)):
-        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), b) < 3e-5
 
 
 @pytest.mark.parametrize("dims,density,rank", CASES)
@@ -85,7 +86,7 @@ def test_jcomm_outer(ctx, dims, density, rank, beta):
     torch.cuda.synchronize()
     want, fref = ocp.jcomm_outer(X, init, beta, L=2, return_ref_obj=True)
     for a, b in zip(fac, want):
-        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), b) < 3e-5
     assert abs(obj.item() - fref) / fref < 1e-5
 
 
@@ -133,7 +134,7 @@ def test_out_of_range_coordinates_are_skipped(ctx):
     out = ctx.beta_objective_coo(idx, val, dims, [dev(a) for a in init], beta=0.5)
     torch.cuda.synchronize()
     for a, b in zip(fac, ocp.bcomm_sweep(X, init, 0.5)):
-        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), b) < 3e-5
     want = oobjective(X, ocp.rebuild(init), 0.5)
     assert abs(out.item() - want) / want < 1e-5
 

@@ -5,9 +5,10 @@ tensor.
 The sparse Tucker path scatters the nonzeros into the rows of the
 (I_1 ... I_{N-1}) x I_N view (the numerators' contraction along the last mode)
 and gathers the rebuild table for the last mode's numerator; the other
-contractions are the dense order-N path's.  Float atomics: bars as for the
-sparse CP path (3e-5 per entry after one block update, 1e-4 after a sweep or
-a J-CoMM outer iteration, 1e-5 on the objective)."""
+contractions are the dense order-N path's.  Float atomics: reproducible to
+rounding only; the bars are the dense path's (1e-5 per entry after one block
+update or a J-CoMM outer iteration with L = 1, 3e-5 after a sweep or L = 2,
+1e-5 on the objective)."""
 import numpy as np
 import pytest
 
@@ -54,9 +55,9 @@ def test_block_update_every_block(ctx, dims, density, J, beta):
         ctx.tucker_update_coo(idx, val, dims, G, F, block=blk, beta=beta)
         torch.cuda.synchronize()
         if blk == -1:
-            assert max_rel(host64(G), otk.block_update_core(X, core, fac, beta)) < 3e-5, "core"
+            assert max_rel(host64(G), otk.block_update_core(X, core, fac, beta)) < 1e-5, "core"
         else:
-            assert max_rel(host64(F[blk]), otk.block_update_factor(X, core, fac, blk, beta)) < 3e-5, f"mode {blk}"
+            assert max_rel(host64(F[blk]), otk.block_update_factor(X, core, fac, blk, beta)) < 1e-5, f"mode {blk}"
 
 
 @pytest.mark.parametrize("dims,density,J", CASES[:3])
@@ -67,9 +68,9 @@ def test_bcomm_sweep(ctx, dims, density, J, beta):
     ctx.tucker_update_coo(idx, val, dims, G, F, block=-2, beta=beta)
     torch.cuda.synchronize()
     wg, wf = otk.bcomm_sweep(X, core, fac, beta)
-    assert max_rel(host64(G), wg) < 1e-4
+    assert max_rel(host64(G), wg) < 3e-5
     for a, b in zip(F, wf):
-        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), b) < 3e-5
 
 
 @pytest.mark.parametrize("dims,density,J", CASES)
@@ -81,9 +82,9 @@ def test_jcomm_outer(ctx, dims, density, J, beta):
     ctx.tucker_jcomm_outer_coo(idx, val, dims, G, F, beta=beta, L=2, obj_out=obj)
     torch.cuda.synchronize()
     wg, wf, fref = otk.jcomm_outer(X, core, fac, beta, L=2, return_ref_obj=True)
-    assert max_rel(host64(G), wg) < 1e-4
+    assert max_rel(host64(G), wg) < 3e-5
     for a, b in zip(F, wf):
-        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), b) < 3e-5
     assert abs(obj.item() - fref) / fref < 1e-5
 
 
@@ -108,9 +109,9 @@ def test_uber_shaped_counts_27x24x7x100x100(ctx, beta):
     ctx.tucker_jcomm_outer_coo(idx, val, dims, G, F, beta=beta, L=1, obj_out=obj)
     torch.cuda.synchronize()
     wg, wf, fref = otk.jcomm_outer(X, core, fac, beta, L=1, return_ref_obj=True)
-    assert max_rel(host64(G), wg) < 1e-4
+    assert max_rel(host64(G), wg) < 1e-5
     for a, b in zip(F, wf):
-        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), b) < 1e-5
     assert abs(obj.item() - fref) / fref < 1e-5
 
 
@@ -128,7 +129,7 @@ def test_order5_cp_on_sparse_data(ctx, beta):
     torch.cuda.synchronize()
     want, fref = ocp.jcomm_outer(X, init, beta, L=2, return_ref_obj=True)
     for a, b in zip(fac, want):
-        assert max_rel(host64(a), b) < 1e-4
+        assert max_rel(host64(a), b) < 3e-5
     assert abs(obj.item() - fref) / fref < 1e-5
 
 
