@@ -148,8 +148,10 @@ typedef struct {
   int check_inputs;
 } comm_opts;
 
-/* Sparse COO data (CP, beta = 1 only).  idx[n][t] is the mode-n coordinate of
- * nonzero t (int32, 0 <= idx < dims[n]); val[t] > 0.  Device buffers. */
+/* Sparse COO data, for the CP and Tucker entry points that take it (each
+ * states its orders and its range of beta).  idx[n][t] is the mode-n
+ * coordinate of nonzero t (int32, 0 <= idx < dims[n]); val[t] > 0.  Device
+ * buffers, read only. */
 typedef struct {
   int ndim;
   int64_t dims[COMM_MAX_NDIM];
@@ -316,9 +318,9 @@ int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* mo
  *     value, summed in closed form.
  *   beta in (0, 2), beta != 1: the denominators involve Q = Xhat^(beta-1) on
  *     every cell, so they come from the dense pass run over the whole index
- *     space (an all-zero tensor of the dims, 4 bytes per cell, allocated once
- *     per context and counted against its limit); orders 3 to 5 (orders 4 and
- *     5: I_1 ... I_{N-2} <= 2^24).  The nonzeros' weights P~ are formed once per outer
+ *     space at x = 0 (the pass reads no tensor there, so the index space
+ *     needs no memory; at most 2^36 cells); orders 3 to 5 (orders 4 and 5:
+ *     I_1 ... I_{N-2} <= 2^24).  The nonzeros' weights P~ are formed once per outer
  *     iteration.  Results are reproducible to float rounding (atomics).
  *   beta = 0 returns COMM_EUNSUPPORTED (d(0 | y) is infinite).
  * If obj_ref_dev is not NULL the objective at the reference is written there. */
@@ -334,9 +336,12 @@ int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int 
                        void* stream);
 
 /* D_beta(X, Xhat) over every cell of a sparse COO tensor, beta in (0, 2),
- * float64, for a CP or a Tucker model: the dense pass's sum of d(0 | Xhat) over
- * the index space plus, over the nonzeros, d(x | Xhat) - d(0 | Xhat).  Orders
- * 3 to 5. */
+ * float64, for a CP or a Tucker model (Sec. 3.2 over the cells of Sec. 6.4):
+ * the dense pass's sum of d(0 | Xhat) over the index space plus, over the
+ * nonzeros, d(x | Xhat) - d(0 | Xhat).  Orders 3 to 5.  CP at beta = 1 needs
+ * no dense pass: a zero cell contributes Xhat, so the zero cells sum in closed
+ * form as the model's mass sum_r prod_n colsum(A^(n))_r minus the nonzeros'
+ * Xhat (orders 2 to 5, any index space, workspace independent of it). */
 int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* model, const comm_opts* opts,
                             double* out_dev, void* stream);
 
@@ -346,7 +351,7 @@ int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* 
  * rows of the (I_1 ... I_{N-1}) x I_N view, the last mode's numerator a gather
  * of the rebuild table; the remaining contractions are those of the dense
  * order-N path.  Denominators: closed form at beta = 1, otherwise the dense
- * pass over the index space (all-zero tensor, as for CP).  block as in
+ * pass over the index space at x = 0 (no memory, as for CP).  block as in
  * comm_tucker_update; the J-CoMM call as comm_jcomm_outer.  Results are
  * reproducible to float rounding (atomics). */
 int comm_tucker_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,

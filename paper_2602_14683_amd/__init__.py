@@ -462,7 +462,8 @@ class Context:
     def cp_jcomm_outer_coo(self, idx: Sequence, val, dims: Sequence[int], factors, L: int = 1,
                            eps: float = 1e-12, obj_out=None, stream=None, beta: float = 1.0) -> None:
         """One J-CoMM outer iteration on COO data (idx: per-mode int32 tensors);
-        beta in (0, 2) (beta != 1: orders 3 and 4, dense denominators)."""
+        beta in (0, 2) (beta = 1: orders 2 to 4, closed-form denominators;
+        beta != 1: orders 3 to 5, dense denominators)."""
         c = _coo(idx, val, dims)
         m, o = _model(factors), self._o(beta, eps, None, L)
         optr = _ptr(obj_out, "obj_out") if obj_out is not None else None

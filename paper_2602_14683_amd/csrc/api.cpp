@@ -1015,10 +1015,11 @@ int check_coo_job(int ndim, const int64_t* dims, const comm_model* model, const 
 // Sparse COO data at beta != 1 (Sec. 6.4, paragraph on sparse tensors): the
 // numerators, which involve P = X * Xhat^(beta-2), are accumulated over the
 // nonzeros (coo_beta_kernel); the denominators involve Q = Xhat^(beta-1) on
-// every cell, so the dense orchestration runs on an all-zero tensor of the
-// same shape (P = 0 there, Q and d(0 | Xhat) exact) and takes its numerators
-// from the nonzeros through a NumHook.  The objective is the dense pass's
-// sum of d(0 | Xhat) plus, over the nonzeros, d(x | Xhat) - d(0 | Xhat).
+// every cell, so the dense orchestration runs on the all-zero twin of the
+// tensor (P = 0 there, Q and d(0 | Xhat) exact; the twin is a null X, which
+// the passes read as x = 0 without loading anything) and takes its
+// numerators from the nonzeros through a NumHook.  The objective is the dense
+// pass's sum of d(0 | Xhat) plus, over the nonzeros, d(x | Xhat) - d(0 | Xhat).
 
 int grow(comm_ctx* ctx, char** buf, size_t* have, size_t bytes, hipStream_t st, const char* what) {
   if (bytes <= *have) return COMM_OK;
@@ -1034,14 +1035,6 @@ int grow(comm_ctx* ctx, char** buf, size_t* have, size_t bytes, hipStream_t st, 
   hipError_t e = hipMalloc(buf, bytes);
   if (e != hipSuccess) return fail(COMM_ENOMEM, "hipMalloc(%zu) for the %s: %s", bytes, what, hipGetErrorString(e));
   *have = bytes;
-  return COMM_OK;
-}
-
-int ensure_zeros(comm_ctx* ctx, size_t bytes, hipStream_t st) {
-  if (bytes <= ctx->zeros_bytes) return COMM_OK;
-  int rc = grow(ctx, &ctx->zeros, &ctx->zeros_bytes, bytes, st, "zero tensor");
-  if (rc) return rc;
-  HIP_TRY(launch_fill_zero(reinterpret_cast<float*>(ctx->zeros), (int64_t)(bytes / 4), st));
   return COMM_OK;
 }
 
@@ -1066,8 +1059,9 @@ CooBetaWs coo_beta_layout(const comm_coo* x, char* base) {
   return s;
 }
 
-// 2^36 cells = 256 GiB of zeros, beyond any single device's memory.
-constexpr uint64_t kMaxZeroCells = uint64_t(1) << 36;
+// The dense passes over the index space run a grid over every cell: 2^36
+// cells bounds their index arithmetic (and their time).
+constexpr uint64_t kMaxTwinCells = uint64_t(1) << 36;
 
 int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* o, bool need_L) {
   int rc = check_coo(x, COMM_MAX_NDIM);
@@ -1083,13 +1077,12 @@ int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* 
   for (int n = 0; n < x->ndim; ++n) xd.dims[n] = x->dims[n];
   xd.X = reinterpret_cast<const float*>(x->val);  // not read: shapes only
   if ((rc = check_dense_shape(&xd))) return rc;
-  // the dense twin (4 bytes per cell) must fit the device: cap the cell count
-  // before any product can wrap
+  // cap the cell count of the index space before any product can wrap
   uint64_t cells = 1;
   for (int n = 0; n < x->ndim; ++n) {
-    if (cells > (kMaxZeroCells / (uint64_t)x->dims[n]))
+    if (cells > (kMaxTwinCells / (uint64_t)x->dims[n]))
       return fail(COMM_ENOMEM, "the index space of this sparse tensor exceeds %llu cells (dense denominators)",
-                  (unsigned long long)kMaxZeroCells);
+                  (unsigned long long)kMaxTwinCells);
     cells *= (uint64_t)x->dims[n];
   }
   if (model->kind == COMM_CP) return check_cp_model(model, x->ndim);
@@ -1097,22 +1090,17 @@ int check_coo_beta(const comm_coo* x, const comm_model* model, const comm_opts* 
   return fail(COMM_EINVAL, "model kind %d", model->kind);
 }
 
-// The dense twin of x and the sparse buffers.  The twin's X is the context's
-// zero tensor, allocated unless `no_dense`: a null X tells the CP passes
-// (except at beta = 1) and the Tucker passes that x = 0 everywhere.
-int coo_beta_setup(comm_ctx* ctx, const comm_coo* x, bool no_dense, comm_dense* xd, CooBetaWs* s, hipStream_t st) {
+// The dense twin of x and the sparse buffers.  The twin has no memory: its
+// null X tells the CP passes (every class but beta = 1, which never runs a
+// dense pass on sparse data) and the Tucker passes that x = 0 everywhere.
+int coo_beta_setup(comm_ctx* ctx, const comm_coo* x, comm_dense* xd, CooBetaWs* s, hipStream_t st) {
   *xd = comm_dense{};
   xd->ndim = x->ndim;
-  size_t cells = 1;
-  for (int n = 0; n < x->ndim; ++n) {
-    xd->dims[n] = x->dims[n];
-    cells *= (size_t)x->dims[n];
-  }
-  int rc;
-  if (!no_dense && (rc = ensure_zeros(ctx, cells * sizeof(float), st))) return rc;
-  xd->X = no_dense ? nullptr : reinterpret_cast<const float*>(ctx->zeros);
+  for (int n = 0; n < x->ndim; ++n) xd->dims[n] = x->dims[n];
+  xd->X = nullptr;
   const CooBetaWs probe = coo_beta_layout(x, nullptr);
-  if ((rc = grow(ctx, &ctx->sws, &ctx->sws_bytes, probe.bytes, st, "sparse workspace"))) return rc;
+  int rc = grow(ctx, &ctx->sws, &ctx->sws_bytes, probe.bytes, st, "sparse workspace");
+  if (rc) return rc;
   *s = coo_beta_layout(x, ctx->sws);
   return COMM_OK;
 }
@@ -1158,7 +1146,7 @@ NumHook coo_num_hook(const comm_coo* x, const comm_model* m, const comm_opts* o,
 int coo_beta_bcomm(comm_ctx* ctx, const comm_coo* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  int rc = coo_beta_setup(ctx, x, true, &xd, &s, st);
+  int rc = coo_beta_setup(ctx, x, &xd, &s, st);
   if (rc) return rc;
   const NumHook hook = coo_num_hook(x, m, o, s, false, st);
   return cp_bcomm(ctx, &xd, m, block, o, st, &hook);
@@ -1180,7 +1168,7 @@ int coo_beta_obj_add(const comm_coo* x, const comm_model* m, const comm_opts* o,
 int coo_beta_jcomm(comm_ctx* ctx, const comm_coo* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  int rc = coo_beta_setup(ctx, x, true, &xd, &s, st);
+  int rc = coo_beta_setup(ctx, x, &xd, &s, st);
   if (rc) return rc;
   // P~ at the reference (the caller's model before the iteration), kept for
   // the inner sweeps; its objective corrections summed now into a partial
@@ -1202,9 +1190,9 @@ int coo_beta_objective(comm_ctx* ctx, const comm_coo* x, const comm_model* m, co
                        hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  // the CP pass at beta = 1 reads its X: there the CP twin keeps the zero
-  // tensor; the Tucker passes take a missing X as x = 0 in every class
-  int rc = coo_beta_setup(ctx, x, m->kind == COMM_TUCKER || o->beta != 1.0, &xd, &s, st);
+  // (CP at beta = 1 never comes here: its zero cells sum in closed form,
+  // coo_objective_kl); no zero tensor is needed
+  int rc = coo_beta_setup(ctx, x, &xd, &s, st);
   if (rc) return rc;
   if (m->kind == COMM_TUCKER) {
     const TkSparse sp{x, s.w, s.num, s.obj};
@@ -1219,7 +1207,7 @@ int coo_tucker(comm_ctx* ctx, const comm_coo* x, comm_model* m, int block, const
                bool jcomm, hipStream_t st) {
   comm_dense xd;
   CooBetaWs s;
-  int rc = coo_beta_setup(ctx, x, true, &xd, &s, st);  // the Tucker passes need no zero tensor
+  int rc = coo_beta_setup(ctx, x, &xd, &s, st);
   if (rc) return rc;
   const TkSparse sp{x, s.w, s.num, s.obj};
   comm_opts od = *o;
@@ -1408,9 +1396,8 @@ int batch_issue(comm_ctx* ctx, std::vector<BatchItem>& items, hipStream_t origin
     sub.ws = ctx->bws + it.off;
     sub.ws_bytes = it.bytes;
     sub.limit = it.bytes;  // a slice never grows: a larger need is an error, not an allocation
-    // the autotune table is the parent context's (the slice was sized for the cache)
-    const comm_opts o = resolve_cache(ctx, &it.x, &it.m, &it.o);
-    int rc = jcomm_run(&sub, &it.x, &it.m, &o, it.obj, ctx->bstreams[p % S]);
+    // it.o holds the resolved cache choice the slice was sized for
+    int rc = jcomm_variant(&sub, &it.x, &it.m, &it.o, it.obj, ctx->bstreams[p % S]);
     if (rc) return rc;
   }
   for (int q = 0; q < S; ++q) {
@@ -1434,14 +1421,37 @@ int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags
     BatchItem& it = items[(size_t)p];
     it.x = *q.x;
     it.m = *q.model;
-    it.o = *q.opts;
+    // the cache choice is resolved once here: the slices are sized for it
+    it.o = resolve_cache(ctx, q.x, q.model, q.opts);
     it.obj = q.obj_ref_dev;
-    const comm_opts ro = resolve_cache(ctx, q.x, q.model, q.opts);
-    it.bytes = (jcomm_ws_bytes(q.x, q.model, &ro) + 255) & ~size_t(255);
-    it.off = total;
+    it.bytes = (jcomm_ws_bytes(q.x, q.model, &it.o) + 255) & ~size_t(255);
     total += it.bytes;
   }
   if (count == 0) return COMM_OK;
+  // Automatic choices without a table entry took the cache whenever each
+  // problem's own workspace fits the limit; if the batch together does not,
+  // they fall back to recomputation, largest slice first, until it fits.
+  while (ctx->limit && total > ctx->limit) {
+    int pick = -1;
+    for (int p = 0; p < count; ++p) {
+      const BatchItem& it = items[(size_t)p];
+      if (probs[p].opts->cache_pq != COMM_CACHE_AUTO || !it.o.cache_pq ||
+          ctx->tune.count(tune_key(&it.x, &it.m, probs[p].opts)))
+        continue;
+      if (pick < 0 || it.bytes > items[(size_t)pick].bytes) pick = p;
+    }
+    if (pick < 0) break;
+    BatchItem& it = items[(size_t)pick];
+    it.o.cache_pq = 0;
+    const size_t nb = (jcomm_ws_bytes(&it.x, &it.m, &it.o) + 255) & ~size_t(255);
+    total -= it.bytes - nb;
+    it.bytes = nb;
+  }
+  total = 0;
+  for (BatchItem& it : items) {
+    it.off = total;
+    total += it.bytes;
+  }
   // debug input checks, eagerly on the caller's stream, before any problem runs
   for (int p = 0; p < count; ++p) {
     const int rc = input_check_dense(ctx, probs[p].x, probs[p].model, probs[p].opts, st);
@@ -1534,7 +1544,6 @@ int comm_destroy(comm_ctx* ctx) {
     for (hipEvent_t e : ctx->bjoin) hipEventDestroy(e);
     if (ctx->bcapture) hipStreamDestroy(ctx->bcapture);
     if (ctx->aux) hipFree(ctx->aux);
-    if (ctx->zeros) hipFree(ctx->zeros);
     if (ctx->sws) hipFree(ctx->sws);
     if (ctx->bfork) hipEventDestroy(ctx->bfork);
     delete ctx;
@@ -1678,7 +1687,7 @@ int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
         if ((rc = reset())) return rc;
         // one untimed iteration (workspace growth, first touch), then reps timed
         rc = jcomm_variant(ctx, x, &sm, &o, nullptr, st);
-        if (rc && v == 1) continue;  // no room for the cache: recompute wins
+        if (rc == COMM_ENOMEM && v == 1) continue;  // no room for the cache: recompute wins
         if (rc) return rc;
         if ((rc = reset())) return rc;
         HIP_TRY(hipEventRecord(sc.ev[0], st));
@@ -1850,7 +1859,21 @@ int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* 
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (!out_dev) return fail(COMM_EINVAL, "out_dev is NULL");
-    int rc = check_coo_beta(x, model, opts, false);
+    int rc;
+    if (opts && opts->beta == 1.0 && model && model->kind == COMM_CP) {
+      // closed form over the zero cells: no dense twin, orders 2 to 5
+      rc = check_coo(x, COMM_MAX_NDIM);
+      if (!rc) rc = check_opts(opts, false);
+      if (!rc) rc = check_cp_model(model, x->ndim);
+      if (rc) return rc;
+      if ((rc = set_device(ctx))) return rc;
+      hipStream_t st = (hipStream_t)stream;
+      if ((rc = input_check_coo(ctx, x, model, opts, st))) return rc;
+      rc = coo_objective_kl(ctx, x, model, opts, out_dev, st);
+      ctx->last_stream = st;
+      return rc;
+    }
+    rc = check_coo_beta(x, model, opts, false);
     if (rc) return rc;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;

@@ -41,11 +41,8 @@ struct comm_ctx {
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gkey;
   hipStream_t glast = nullptr;
-  // sparse data at beta != 1: an all-zero dense tensor of the index space
-  // (never written after it is cleared) that the dense pass runs on for the
-  // Q~ denominators, and the sparse steps' own buffers
-  char* zeros = nullptr;
-  size_t zeros_bytes = 0;
+  // sparse data at beta != 1 and sparse Tucker: the sparse steps' own
+  // buffers (per-nonzero weights, one numerator, objective partials)
   char* sws = nullptr;
   size_t sws_bytes = 0;
 };

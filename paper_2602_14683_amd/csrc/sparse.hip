@@ -56,11 +56,11 @@ namespace comm {
 struct CooPassArgs {
   int N, R;
   int64_t nnz;
-  int dims[4];            // in the stream's slot order
-  const int32_t* idx[4];
+  int dims[kMaxModes];            // in the stream's slot order
+  const int32_t* idx[kMaxModes];
   const float* val;
-  const float* A[4];      // factors, slot order, row stride R
-  float* M[4];            // [dims][32] accumulators, slot order
+  const float* A[kMaxModes];      // factors, slot order, row stride R
+  float* M[kMaxModes];            // [dims][32] accumulators, slot order (no accumulation: unused)
   int run_modes;          // slots [0, run_modes) accumulated by runs
   int atom_modes;         // slots [run_modes, run_modes + atom_modes) per nonzero
   float eps;
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
     const int cnt = (int)min((int64_t)64, t1 - tb);
     // 64 nonzeros, one per lane, coalesced; validity once per nonzero; the
     // coordinates travel as row offsets
-    int my[4] = {0, 0, 0, 0};
+    int my[kMaxModes] = {0, 0, 0, 0, 0};
     float myx = 0.0f;
     bool valid = lane < cnt;
     if (valid) {
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
     float myy = 1.0f;   // X~ of this lane's own nonzero, for the objective
     for (int j0 = 0; j0 < 32; j0 += kCooBatch) {
       if (2 * j0 >= cnt) break;
-      int ii[kCooBatch][4];
+      int ii[kCooBatch][kMaxModes];
       float xs[kCooBatch], zs[kCooBatch];
       bool oks[kCooBatch];
 #pragma unroll
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
       // nothing to gather read row 0 / column R - 1 (valid addresses) and are
       // zeroed by a mask after the batch (a guarded load per nonzero would be
       // a branch and a round trip each)
-      float g[kCooBatch][4];
+      float g[kCooBatch][kMaxModes];
 #pragma unroll
       for (int u = 0; u < kCooBatch; ++u) {
         const bool live = oks[u] && rlive;
@@ -203,19 +203,66 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
 template <int N>
 hipError_t launch_coo_n(const CooPassArgs& a, int blocks, hipStream_t st) {
   const dim3 grid((unsigned)blocks), block(kCooThreads);
-  if (a.run_modes == 2 && a.atom_modes == N - 2) hipLaunchKernelGGL((coo_pass_kernel<N, 2, N - 2>), grid, block, 0, st, a);
-  else if (a.run_modes == 2 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 2, 0>), grid, block, 0, st, a);
-  else if (a.run_modes == 1 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 1, 0>), grid, block, 0, st, a);
-  else return hipErrorInvalidValue;
+  if (a.run_modes == 0 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 0, 0>), grid, block, 0, st, a);
+  else if constexpr (N <= 4) {
+    if (a.run_modes == 2 && a.atom_modes == N - 2) hipLaunchKernelGGL((coo_pass_kernel<N, 2, N - 2>), grid, block, 0, st, a);
+    else if (a.run_modes == 2 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 2, 0>), grid, block, 0, st, a);
+    else if (a.run_modes == 1 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 1, 0>), grid, block, 0, st, a);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
+// (order 5 only without accumulation: the objective)
 hipError_t launch_coo(const CooPassArgs& a, int blocks, hipStream_t st) {
   switch (a.N) {
     case 2: return launch_coo_n<2>(a, blocks, st);
     case 3: return launch_coo_n<3>(a, blocks, st);
     case 4: return launch_coo_n<4>(a, blocks, st);
+    case 5: return launch_coo_n<5>(a, blocks, st);
     default: return hipErrorInvalidValue;
+  }
+}
+
+// The model's mass over every cell, sum_r prod_n colsum(A^(n))_r, in float64
+// (the column sums too), written to out[0].  One workgroup: thread t sums
+// rows t / 32, t / 32 + 32, ... of column t % 32; the 32 row groups are
+// combined in order.
+struct MassArgs {
+  int N, R;
+  int rows[kMaxModes];
+  const float* A[kMaxModes];   // row stride R
+  double* out;
+};
+
+__global__ void __launch_bounds__(1024) model_mass_kernel(MassArgs a) {
+  __shared__ double part[1024];
+  __shared__ double cs[kMaxModes][32];
+  const int t = threadIdx.x;
+  const int c = t & 31, g = t >> 5;
+  for (int n = 0; n < a.N; ++n) {
+    double s = 0.0;
+    if (c < a.R)
+      for (int i = g; i < a.rows[n]; i += 32) s += (double)a.A[n][(int64_t)i * a.R + c];
+    part[t] = s;
+    __syncthreads();
+    if (t < 32) {
+      double v = 0.0;
+      for (int gg = 0; gg < 32; ++gg) v += part[gg * 32 + t];
+      cs[n][t] = v;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double mass = 0.0;
+    for (int r = 0; r < a.R; ++r) {
+      double p = 1.0;
+      for (int n = 0; n < a.N; ++n) p *= cs[n][r];
+      mass += p;
+    }
+    a.out[0] = mass;
   }
 }
 
@@ -268,8 +315,8 @@ int bits_for(uint64_t n) {
 }
 
 struct CooWs {
-  float* M[4];
-  float* stats[4];
+  float* M[kMaxModes];
+  float* stats[kMaxModes];
   double* obj_part;
   size_t bytes;
 };
@@ -399,6 +446,38 @@ int coo_jcomm_kl_plan(comm_ctx* ctx, const comm_coo_plan* p, comm_model* m, cons
                     c == 0 && obj != nullptr, (float)o->eps, st);
     return rc;
   });
+}
+
+// D_1(X, Xhat) over every cell without touching the zero cells (Sec. 3.2 at
+// beta = 1, Sec. 6.4): a zero cell contributes d_1(0 | Xhat) = Xhat, so the
+// sum over all cells is the model's mass sum_r prod_n colsum(A^(n))_r plus,
+// over the nonzeros, d_1(x | X~) - X~ (the pass without accumulation).
+int coo_objective_kl(comm_ctx* ctx, const comm_coo* x, const comm_model* m, const comm_opts* o, double* out,
+                     hipStream_t st) {
+  const int N = x->ndim;
+  int dims[kMaxModes] = {0, 0, 0, 0, 0};
+  for (int n = 0; n < N; ++n) dims[n] = (int)x->dims[n];
+  const int blocks = coo_blocks(x->nnz);
+  CooWs w = coo_layout(N, dims, blocks, nullptr);
+  int rc = ensure_ws(ctx, w.bytes, st);
+  if (rc) return rc;
+  w = coo_layout(N, dims, blocks, ctx->ws);
+  MassArgs ma = {};
+  ma.N = N;
+  ma.R = m->rank;
+  for (int n = 0; n < N; ++n) {
+    ma.rows[n] = dims[n];
+    ma.A[n] = m->factors[n];
+  }
+  ma.out = out;
+  hipLaunchKernelGGL(model_mass_kernel, dim3(1), dim3(1024), 0, st, ma);
+  HIP_TRY(hipGetLastError());
+  if (x->nnz <= 0) return COMM_OK;
+  const int order[kMaxModes] = {0, 1, 2, 3, 4};
+  if ((rc = coo_pass(ctx, N, order, x->idx, x->val, x->nnz, dims, m, w, 0, 0, true, (float)o->eps, st)))
+    return rc;
+  HIP_TRY(launch_sum_f64(w.obj_part, blocks, out, out, st));
+  return COMM_OK;
 }
 
 // Two device copies of the COO: copy 0 sorted by (i1, i2) with the modes in

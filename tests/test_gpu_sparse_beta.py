@@ -172,6 +172,29 @@ def test_refuses_beta_zero_and_order_two(ctx):
         assert np.array_equal(host64(a), f32(b))
 
 
+@pytest.mark.parametrize("dims,density,rank", [((40, 50), 0.05, 6), ((60, 70, 80), 0.004, 32),
+                                               ((9, 10, 11, 12, 30), 0.005, 5)])
+def test_kl_objective_needs_no_dense_twin(dims, density, rank):
+    """CP at beta = 1: zero cells contribute Xhat, so they sum in closed form
+    (the model's mass minus the nonzeros' Xhat) and no dense pass runs.  The
+    context's workspace limit is far below the 4 bytes per cell a dense twin
+    would take; orders 2 and 5 are served too (Sec. 3.2 at beta = 1, Sec. 6.4)."""
+    s = workloads.sparse_small(7, dims=dims, density=density, rank=rank)
+    cells = int(np.prod(dims))
+    limit = 1 << 20
+    assert 4 * cells > limit or len(dims) == 2
+    small = comm.Context(0, workspace_limit=limit)
+    try:
+        init = [f32(a) for a in s.init]
+        idx, val = _dev_coo(s)
+        out = small.beta_objective_coo(idx, val, dims, [dev(a) for a in init], beta=1.0)
+        X = workloads.densify(s)
+        want = oobjective(X, ocp.rebuild(init), 1.0)
+        assert abs(out.item() - want) / want < 1e-5
+    finally:
+        small.close()
+
+
 def test_index_space_beyond_device_is_refused(ctx):
     """Three modes of 2^24: the dense twin would need 2^72 cells.  The call is
     refused with COMM_ENOMEM before anything is allocated or launched (the

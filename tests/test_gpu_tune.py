@@ -194,3 +194,37 @@ def test_auto_without_an_entry_recomputes_when_the_cache_exceeds_the_limit():
             assert np.array_equal(a, b)
     finally:
         small.close()
+
+
+def test_batched_auto_fits_the_limit_by_recomputing_the_largest():
+    """Two automatic problems without a table entry whose caches fit the limit
+    one at a time but not together: the batch recomputes P~/Q~ for the larger
+    one and keeps the cache for the other, and each result is bitwise that of
+    the single call with that choice."""
+    shapes = [(37, 70, 90), (30, 40, 50)]
+    R = 8
+    probe = comm.Context(0)
+    try:
+        need = [{c: (probe.workspace_bytes(d, rank=R, beta=0.5, L=2, cache_pq=c) + 255) // 256 * 256
+                 for c in (False, True)} for d in shapes]
+    finally:
+        probe.close()
+    limit = need[0][False] + need[1][True]
+    assert need[0][True] + need[1][True] > limit >= need[0][True]
+    probs = [_cp(21 + q, dims=d, R=R) for q, d in enumerate(shapes)]
+    small = comm.Context(0, workspace_limit=limit)
+    try:
+        want = [_run(small, probs[0][0], probs[0][1], None, 0.5, False),
+                _run(small, probs[1][0], probs[1][1], None, 0.5, True)]
+        F = [[dev(a) for a in p[1]] for p in probs]
+        objs = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in probs]
+        small.jcomm_outer_batched(comm.Batch([{"X": dev(p[0]), "factors": f, "beta": 0.5, "L": 2,
+                                               "cache_pq": "auto", "obj_out": o}
+                                              for p, f, o in zip(probs, F, objs)]))
+        torch.cuda.synchronize()
+        for q in range(2):
+            for a, b in zip(want[q][0], [f.cpu().numpy() for f in F[q]]):
+                assert np.array_equal(a, b)
+            assert objs[q].item() == want[q][2]
+    finally:
+        small.close()
