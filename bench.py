@@ -336,6 +336,7 @@ def run_tucker(args, ctx):
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
                              "kernel": "tk_v_kernel / tk_m3_kernel (fused rebuild + P~, Q~ + numerator and denominator contractions)",
                              "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "passes_per_outer_iteration": round(launches / max(args.steps, 1), 3),
                              "algorithmic_bytes_per_launch": bytes_, "algorithmic_flops_per_launch": flops,
                              "tflops_algorithmic": round(flops / (avg_ms * 1e-3) / 1e12, 2)},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})

@@ -280,6 +280,7 @@ struct TkWs {
   float* H[2];
   float* slots[2];   // numerator / denominator split-K outputs
   size_t slot_floats;
+  float* kslots[3];  // beta = 1: the core, mode-1 and mode-2 numerators, kept for the outer iteration
   float* den_vec;    // [3][32]
   float* dcore;      // [J1 J2][32]
   TkCopy ref, cur, num, den, user_pad;
@@ -324,6 +325,9 @@ TkWs tk_layout(const comm_dense* x, const comm_model* m, char* base, bool cache)
   w.slot_floats = s;
   w.slots[0] = cv.take<float>(s);
   w.slots[1] = cv.take<float>(s);
+  w.kslots[0] = cv.take<float>((size_t)kSplitCore * J1 * J2 * kRP);
+  w.kslots[1] = cv.take<float>((size_t)kSplit1 * I * kRP);
+  w.kslots[2] = cv.take<float>((size_t)kSplit2 * J * kRP);
   w.den_vec = cv.take<float>(3 * kRP);
   w.dcore = cv.take<float>((size_t)J1 * J2 * kRP);
   for (TkCopy* c : {&w.ref, &w.cur, &w.num, &w.den, &w.user_pad}) {
@@ -416,7 +420,12 @@ TkPassArgs pass_args(const comm_dense* x, const comm_opts* o, const TkWs& w) {
 
 // Numerator slots of block blk (-1 core, 0, 1) from V of the contraction set
 // cs[0] (into out[0]) and, when sets = 2, the denominator from V of cs[1].
-int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hipStream_t st) {
+// reuse_u: U from the core block's GEMMs of the same sweep is still valid
+// (same V, same B'), so mode 1 starts from it.  slot_out: where the split-K
+// outputs go (default w.slots).
+int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hipStream_t st, bool reuse_u = false,
+             float* const* slot_out = nullptr) {
+  float* const* so = slot_out ? slot_out : w.slots;
   const int I = w.dims[0], J = w.dims[1];
   const int J1 = w.J[0], J2 = w.J[1];
   constexpr int kNoWrap = 30, kWrap32 = 5;
@@ -429,7 +438,7 @@ int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hi
       g.out[k] = fo(k);
     }
   };
-  if (blk == -1 || blk == 0) {
+  if (blk == -1 || (blk == 0 && !reuse_u)) {
     // U[i][b][c] = sum_j B'[j][b] V[i][j][c]
     GemmArgs g = {};
     g.sab = 0; g.sam = 1; g.akin_log2 = kNoWrap; g.sako = 0; g.saki = kRP;
@@ -447,9 +456,9 @@ int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hi
     g.sob = 0; g.sos = (int64_t)I * kRP; g.ldo = kRP;
     g.M = I; g.N = J1; g.K = J2 * kRP; g.batch = 1; g.splits = kSplit1;
     set_ptrs(g, [&](int k) { return (const float*)w.U[k]; }, [&](int k) { return cs[k].G; },
-             [&](int k) { return w.slots[k]; });
+             [&](int k) { return so[k]; });
     HIP_TRY(launch_gemm(g, st));
-    for (int k = 0; k < sets; ++k) out[k] = Slots{w.slots[k], kSplit1, I};
+    for (int k = 0; k < sets; ++k) out[k] = Slots{so[k], kSplit1, I};
   } else if (blk == -1) {
     // Ncore[a][(b,c)] = sum_i A'[i][a] U[i][(b,c)]
     GemmArgs g = {};
@@ -458,9 +467,9 @@ int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hi
     g.sob = 0; g.sos = (int64_t)J1 * J2 * kRP; g.ldo = (int64_t)J2 * kRP;
     g.M = J1; g.N = J2 * kRP; g.K = I; g.batch = 1; g.splits = kSplitCore;
     set_ptrs(g, [&](int k) { return cs[k].A.p; }, [&](int k) { return (const float*)w.U[k]; },
-             [&](int k) { return w.slots[k]; });
+             [&](int k) { return so[k]; });
     HIP_TRY(launch_gemm(g, st));
-    for (int k = 0; k < sets; ++k) out[k] = Slots{w.slots[k], kSplitCore, J1 * J2};
+    for (int k = 0; k < sets; ++k) out[k] = Slots{so[k], kSplitCore, J1 * J2};
   } else {
     // H[i][(b,c)] = sum_a A'[i][a] G'[a][(b,c)];  Num2[j][b] = sum_{(i,c)} V[i][j][c] H[i][b][c]
     GemmArgs g = {};
@@ -476,9 +485,9 @@ int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hi
     h.sob = 0; h.sos = (int64_t)J * kRP; h.ldo = kRP;
     h.M = J; h.N = J2; h.K = I * kRP; h.batch = 1; h.splits = kSplit2;
     set_ptrs(h, [&](int k) { return V[k]; }, [&](int k) { return (const float*)w.H[k]; },
-             [&](int k) { return w.slots[k]; });
+             [&](int k) { return so[k]; });
     HIP_TRY(launch_gemm(h, st));
-    for (int k = 0; k < sets; ++k) out[k] = Slots{w.slots[k], kSplit2, J};
+    for (int k = 0; k < sets; ++k) out[k] = Slots{so[k], kSplit2, J};
   }
   return COMM_OK;
 }
@@ -542,14 +551,33 @@ int tk_closed_den(const TkWs& w, int blk, const TkModel& ds, Slots* core_den, co
   return COMM_OK;
 }
 
-// Update of block blk: numerator (and, unless beta = 1, denominator) against
-// the sets ns / ds with X rebuilt from rb (its T2 in w.T2r) or read from the
-// cached P~ / Q~; t2n / t2d are the sets' T2 for the mode-3 block.
-int tk_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, const TkWs& w, int blk,
-             const TkModel& rb, const TkModel& ns, const TkModel& ds, const float* cnT, const float* cdT,
-             bool cached, bool want_obj, FView anchor, float* out_pad, double* obj, hipStream_t st) {
+// Numerator (and, unless beta = 1, denominator) slots of block blk against the
+// sets ns / ds from the V of the last V pass (blk -1, 0, 1; reuse_u: the core
+// block's U of this sweep serves mode 1), then the block update.
+int tk_from_v(comm_model* m, const comm_opts* o, const TkWs& w, int blk, const TkModel& ns, const TkModel& ds,
+              bool reuse_u, FView anchor, float* out_pad, hipStream_t st) {
   const bool kl = o->beta == 1.0;
   const int sets = kl ? 1 : 2;
+  const TkModel cs[2] = {ns, ds};
+  Slots nd[2];
+  int rc = tk_gemms(w, blk, cs, sets, nd, st, reuse_u);
+  if (rc) return rc;
+  Slots den = nd[1];
+  const float* vec = nullptr;
+  Slots* denp = &den;
+  if (kl) {
+    if ((rc = tk_closed_den(w, blk, ds, &den, &vec, st))) return rc;
+    if (blk != -1) denp = nullptr;
+  }
+  return tk_apply(m, w, blk, nd[0], denp, vec, anchor, out_pad, w.cur.facT2, gamma_of(o->beta), (float)o->eps, st);
+}
+
+// The V pass (blocks -1, 0, 1) or the mode-3 pass (block 2) over X rebuilt
+// from rb (its T2 in w.T2r) or over the cached P~ / Q~, with the sets whose
+// mode-3 factors (transposed) are cnT / cdT and whose T2 are in w.T2nT / T2dT.
+int tk_pass(comm_ctx* ctx, const comm_dense* x, const comm_opts* o, const TkWs& w, int blk, const TkModel& rb,
+            const float* cnT, const float* cdT, bool cached, bool want_obj, double* obj, hipStream_t st) {
+  const int sets = o->beta == 1.0 ? 1 : 2;
   const int bc = beta_class_of(o->beta);
   const int mode = cached ? kTkCacheRead : kTkFromX;
   TkPassArgs a = pass_args(x, o, w);
@@ -559,32 +587,34 @@ int tk_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts*
     a.Pc = w.Pc;
     a.Qc = w.Qc;
   }
-  Slots num, den;
-  int rc;
   if (blk == 2) {
     a.T2nT = w.T2nT;
     a.T2dT = w.T2dT;
-    rc = profiled(ctx, st, [&] { return launch_tk_m3(a, bc, mode, sets, st); });
-    if (rc) return rc;
-    num = Slots{w.m3[0], w.npg, w.Kp};
-    den = Slots{w.m3[1], w.npg, w.Kp};
-  } else {
-    a.CnT = cnT;
-    a.CdT = cdT;
-    rc = profiled(ctx, st, [&] { return launch_tk_v(a, bc, mode, want_obj, sets, st); });
-    if (rc) return rc;
-    if (want_obj && obj) HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, obj, st));
-    const TkModel cs[2] = {ns, ds};
-    Slots nd[2];
-    if ((rc = tk_gemms(w, blk, cs, sets, nd, st))) return rc;
-    num = nd[0];
-    den = nd[1];
+    return profiled(ctx, st, [&] { return launch_tk_m3(a, bc, mode, sets, st); });
   }
+  a.CnT = cnT;
+  a.CdT = cdT;
+  int rc = profiled(ctx, st, [&] { return launch_tk_v(a, bc, mode, want_obj, sets, st); });
+  if (rc) return rc;
+  if (want_obj && obj) HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, obj, st));
+  return COMM_OK;
+}
+
+// Update of block blk: its pass, then its numerator / denominator and the update.
+int tk_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, const TkWs& w, int blk,
+             const TkModel& rb, const TkModel& ns, const TkModel& ds, const float* cnT, const float* cdT,
+             bool cached, bool want_obj, FView anchor, float* out_pad, double* obj, hipStream_t st) {
+  int rc = tk_pass(ctx, x, o, w, blk, rb, cnT, cdT, cached, want_obj, obj, st);
+  if (rc) return rc;
+  if (blk != 2) return tk_from_v(m, o, w, blk, ns, ds, false, anchor, out_pad, st);
+  const bool kl = o->beta == 1.0;
+  const Slots num{w.m3[0], w.npg, w.Kp};
+  Slots den{w.m3[1], w.npg, w.Kp};
   const float* vec = nullptr;
   Slots* denp = &den;
   if (kl) {
     if ((rc = tk_closed_den(w, blk, ds, &den, &vec, st))) return rc;
-    if (blk != -1) denp = nullptr;
+    denp = nullptr;
   }
   return tk_apply(m, w, blk, num, denp, vec, anchor, out_pad, w.cur.facT2, gamma_of(o->beta), (float)o->eps, st);
 }
@@ -676,7 +706,8 @@ int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_o
   if ((rc = tk_pad(m, w, w.ref, &w.cur, st))) return rc;
   const TkModel ref = model_of(w, w.ref);
   // the reference model, and so its T2, is fixed for the whole outer iteration
-  if ((rc = tk_t2(w, ref, w.T2r, nullptr, st))) return rc;
+  // (at beta = 1 it is also the mode-3 block's contraction set, transposed)
+  if ((rc = tk_t2(w, ref, w.T2r, kl ? w.T2nT : nullptr, st))) return rc;
   bool obj_pending = obj != nullptr;
   if (cache) {
     TkPassArgs a = pass_args(x, o, w);
@@ -690,44 +721,94 @@ int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_o
     obj_pending = false;
   }
   const float beta = (float)o->beta;
-  for (int l = 0; l < o->inner_sweeps; ++l) {
-    for (int blk : {-1, 0, 1, 2}) {
-      // transformed blocks from the current inner iterate (Sec. 5.3, App. C.3)
-      ChiArgs ca = {};
-      ca.beta = beta;
-      auto add = [&](const float* curp, const float* refp, int rows, float* x1, float* x2) {
-        const int f = ca.nf++;
-        ca.cur[f] = curp;
-        ca.ref[f] = refp;
-        ca.rows_p[f] = rows;
-        ca.x1[f] = x1;
-        ca.x2[f] = x2;
-      };
-      if (blk != -1) add(w.cur.core, w.ref.core, w.J[0] * w.J[1], w.num.core, w.den.core);
-      for (int q = 0; q < 3; ++q)
-        if (q != blk) {
-          add(w.cur.fac[q], w.ref.fac[q], q == 2 ? w.Kp : w.dims[q], w.num.fac[q], w.den.fac[q]);
-          if (q == 2) {
-            ca.x1T[ca.nf - 1] = w.num.facT2;
-            ca.x2T[ca.nf - 1] = w.den.facT2;
-          }
-        }
-      HIP_TRY(launch_chi(ca, st));
-      TkModel ns = model_of(w, w.num), ds = model_of(w, w.den);
-      // the active block does not enter its own contraction
-      if (blk == -1) { ns.G = ref.G; ds.G = ref.G; }
-      else if (blk == 0) { ns.A = ref.A; ds.A = ref.A; }
-      else if (blk == 1) { ns.B = ref.B; ds.B = ref.B; }
-      else { ns.C = ref.C; ds.C = ref.C; }
-      if (blk == 2) {
-        rc = kl ? tk_t2(w, ns, w.T2n, w.T2nT, st) : tk_t2_pair(w, ns, ds, st);
+  // transformed blocks of the current inner iterate (Sec. 5.3, App. C.3) for
+  // the listed blocks (-1 core, 0..2 factors) into the num / den sets
+  auto chi = [&](std::initializer_list<int> blocks) -> int {
+    ChiArgs ca = {};
+    ca.beta = beta;
+    for (int q : blocks) {
+      const int f = ca.nf++;
+      ca.cur[f] = copy_block(w.cur, q);
+      ca.ref[f] = copy_block(w.ref, q);
+      ca.rows_p[f] = q == -1 ? w.J[0] * w.J[1] : q == 2 ? w.Kp : w.dims[q];
+      ca.x1[f] = copy_block(w.num, q);
+      ca.x2[f] = copy_block(w.den, q);
+      if (q == 2) {
+        ca.x1T[f] = w.num.facT2;
+        ca.x2T[f] = w.den.facT2;
+      }
+    }
+    HIP_TRY(launch_chi(ca, st));
+    return COMM_OK;
+  };
+
+  if (kl) {
+    // beta = 1: chi_1 is the reference block, so every numerator depends on
+    // the reference alone and serves all L sweeps: one V pass (core, modes 1
+    // and 2, and the objective) and one mode-3 pass against the reference's
+    // own T2.  The sweeps then need only the closed-form denominators of the
+    // current blocks and the updates.
+    if ((rc = chi({2}))) return rc;  // the reference mode-3 factor, transposed, for the V pass
+    if ((rc = tk_pass(ctx, x, o, w, -1, ref, w.num.facT2, nullptr, false, obj_pending, obj, st))) return rc;
+    Slots num[4], unused[2];
+    if ((rc = tk_gemms(w, -1, &ref, 1, unused, st, false, &w.kslots[0]))) return rc;
+    num[0] = unused[0];
+    if ((rc = tk_gemms(w, 0, &ref, 1, unused, st, true, &w.kslots[1]))) return rc;
+    num[1] = unused[0];
+    if ((rc = tk_gemms(w, 1, &ref, 1, unused, st, false, &w.kslots[2]))) return rc;
+    num[2] = unused[0];
+    if ((rc = tk_pass(ctx, x, o, w, 2, ref, nullptr, nullptr, false, false, nullptr, st))) return rc;
+    num[3] = Slots{w.m3[0], w.npg, w.Kp};
+    const TkModel cur = model_of(w, w.cur);
+    for (int l = 0; l < o->inner_sweeps; ++l) {
+      for (int blk : {-1, 0, 1, 2}) {
+        Slots den;
+        const float* vec = nullptr;
+        if ((rc = tk_closed_den(w, blk, cur, &den, &vec, st))) return rc;
+        rc = tk_apply(m, w, blk, num[blk + 1], blk == -1 ? &den : nullptr, vec, block_view(ref, blk),
+                      copy_block(w.cur, blk), w.cur.facT2, 1.0f, (float)o->eps, st);
         if (rc) return rc;
       }
-      rc = tk_block(ctx, x, m, o, w, blk, ref, ns, ds, w.num.facT2, w.den.facT2, cache, obj_pending,
-                    block_view(ref, blk), copy_block(w.cur, blk), obj, st);
-      if (rc) return rc;
-      obj_pending = false;
     }
+    return COMM_OK;
+  }
+
+  // beta != 1, per sweep: one V pass serves the core and modes 1 and 2 (the
+  // mode-3 sets do not change until the mode-3 block), then the mode-3 pass.
+  for (int l = 0; l < o->inner_sweeps; ++l) {
+    // core block: sets of the three factors, the V pass, U and the core numerators
+    if ((rc = chi({0, 1, 2}))) return rc;
+    TkModel ns = model_of(w, w.num), ds = model_of(w, w.den);
+    ns.G = ref.G;  // the active block does not enter its own contraction
+    ds.G = ref.G;
+    const bool want_obj = obj_pending && !cache;
+    if ((rc = tk_pass(ctx, x, o, w, -1, ref, w.num.facT2, w.den.facT2, cache, want_obj, obj, st))) return rc;
+    obj_pending = false;
+    if ((rc = tk_from_v(m, o, w, -1, ns, ds, false, block_view(ref, -1), copy_block(w.cur, -1), st))) return rc;
+    // mode 1 from the same V and U: only the core's sets changed
+    if ((rc = chi({-1}))) return rc;
+    ns = model_of(w, w.num);
+    ds = model_of(w, w.den);
+    ns.A = ref.A;
+    ds.A = ref.A;
+    if ((rc = tk_from_v(m, o, w, 0, ns, ds, true, block_view(ref, 0), copy_block(w.cur, 0), st))) return rc;
+    // mode 2 from the same V: only mode 1's sets changed
+    if ((rc = chi({0}))) return rc;
+    ns = model_of(w, w.num);
+    ds = model_of(w, w.den);
+    ns.B = ref.B;
+    ds.B = ref.B;
+    if ((rc = tk_from_v(m, o, w, 1, ns, ds, false, block_view(ref, 1), copy_block(w.cur, 1), st))) return rc;
+    // mode 3: mode 2's sets, both sets' T2, the mode-3 pass
+    if ((rc = chi({1}))) return rc;
+    ns = model_of(w, w.num);
+    ds = model_of(w, w.den);
+    ns.C = ref.C;
+    ds.C = ref.C;
+    if ((rc = tk_t2_pair(w, ns, ds, st))) return rc;
+    rc = tk_block(ctx, x, m, o, w, 2, ref, ns, ds, nullptr, nullptr, cache, false, block_view(ref, 2),
+                  copy_block(w.cur, 2), nullptr, st);
+    if (rc) return rc;
   }
   return COMM_OK;
 }

@@ -681,7 +681,8 @@ CooTkArgs coo_tk_args(const TkSparse* sp, const TkNWs& w, const comm_opts* o, co
 int tkn_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, const TkNWs& w, int blk,
               FView cl, const TkNModel& ns, const TkNModel& ds, const float* cnT, const float* cdT, bool cached,
               bool want_obj, FView anchor, const TkNCopy& pad, double* obj, hipStream_t st,
-              const TkSparse* sp = nullptr, const float* tnum = nullptr, bool stored = false) {
+              const TkSparse* sp = nullptr, const float* tnum = nullptr, bool stored = false,
+              bool reuse_v = false) {
   const bool kl = o->beta == 1.0;
   const int sets = kl ? 1 : 2;
   const int bc = beta_class_of(o->beta);
@@ -722,12 +723,14 @@ int tkn_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
   } else {
     a.CnT = cnT;
     a.CdT = cdT;
-    if (dense_pass) {
+    // reuse_v: V of this sweep's core block still holds (its last-mode sets
+    // have not changed since)
+    if (dense_pass && !reuse_v) {
       rc = profiled(ctx, st, [&] { return launch_tk_v(a, bc, mode, want_obj, sets, st); });
       if (rc) return rc;
       if (want_obj && obj) HIP_TRY(launch_sum_f64(w.obj_part, w.vwgs, nullptr, obj, st));
     }
-    if (sp) {
+    if (sp && !reuse_v) {
       // V of the numerator from the nonzeros (the dense pass left it zero)
       HIP_TRY(launch_fill_zero(w.V[0], w.np * kRP, st));
       sa.op = 1;
@@ -879,8 +882,10 @@ int tuckern_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_
         for (int k = 0; k < (kl ? 1 : 2); ++k)
           if ((rc = tkn_transpose(w, w.V[k], w.TT[k], st))) return rc;
       }
+      // one V pass per sweep: the core block's V serves every block but the
+      // last mode (whose sets enter V and change only at the last block)
       rc = tkn_block(ctx, x, m, o, w, blk, ref.F[last], ns, ds, w.num.facTL, w.den.facTL, cache, obj_pending,
-                     block_viewn(ref, blk), w.cur, obj, st, sp, w.V[0], true);
+                     block_viewn(ref, blk), w.cur, obj, st, sp, w.V[0], true, blk >= 0 && blk < last);
       if (rc) return rc;
       obj_pending = false;
     }

@@ -209,8 +209,8 @@ def test_batched_auto_fits_the_limit_by_recomputing_the_largest():
                  for c in (False, True)} for d in shapes]
     finally:
         probe.close()
-    limit = need[0][False] + need[1][True]
-    assert need[0][True] + need[1][True] > limit >= need[0][True]
+    limit = max(need[0][True], need[0][False] + need[1][True])
+    assert need[0][True] > need[1][True] and need[0][True] + need[1][True] > limit
     probs = [_cp(21 + q, dims=d, R=R) for q, d in enumerate(shapes)]
     small = comm.Context(0, workspace_limit=limit)
     try:
