@@ -250,6 +250,27 @@ int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, in
 int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
                      double* obj_ref_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * J-CoMM outer iteration of comm_jcomm_outer (same arguments, kernels, launch
+ * shapes and results, bit for bit), with its workspace taken from a fixed
+ * device array of COMM_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * GPU it runs on until the process ends.  It calls no hipMalloc, hipFree or
+ * allocating library routine.
+ *   - A problem whose workspace (comm_workspace_bytes, op = 1) exceeds the
+ *     array returns COMM_ENOMEM before any launch.  cache_pq = 1 counts the
+ *     P~/Q~ cache; COMM_CACHE_AUTO takes the autotune table's choice, or the
+ *     cache when it fits, and recomputes when the cache does not fit.
+ *   - opts.check_inputs is refused (COMM_EINVAL): the debug check needs a
+ *     device flag of its own.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (nothing in it needs to start at zero: each call writes
+ *     what it reads).  Calls that overlap on one GPU (other streams, threads
+ *     or contexts) race: the caller orders them. */
+#define COMM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int comm_jcomm_outer_noalloc(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
+                             double* obj_ref_dev, void* stream);
+
 /* One J-CoMM outer iteration (as comm_jcomm_outer) for each of `count`
  * independent problems of any mix of shapes, ranks, core sizes, beta and L:
  * the batched step of a decomposition server (not a passage of the paper; the

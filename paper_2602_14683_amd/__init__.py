@@ -31,7 +31,8 @@ COMM_CACHE_AUTO = -1
 
 EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_profile_enable",
             "comm_profile_query", "comm_cp_update",
-            "comm_tucker_update", "comm_jcomm_outer", "comm_beta_objective", "comm_cp_jcomm_outer_coo",
+            "comm_tucker_update", "comm_jcomm_outer", "comm_jcomm_outer_noalloc", "comm_beta_objective",
+            "comm_cp_jcomm_outer_coo",
             "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
             "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap",
             "comm_cp_update_coo", "comm_beta_objective_coo", "comm_tucker_update_coo",
@@ -45,6 +46,7 @@ class CommError(RuntimeError):
 
 
 MAX_NDIM = 5  # COMM_MAX_NDIM
+NOALLOC_SCRATCH_BYTES = 64 << 20  # COMM_NOALLOC_SCRATCH_BYTES
 
 
 class Dense(ctypes.Structure):
@@ -99,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.comm_cp_update.argtypes = [ctypes.c_void_p, P(Dense), P(Model), ctypes.c_int, P(Opts), ctypes.c_void_p]
     lib.comm_tucker_update.argtypes = [ctypes.c_void_p, P(Dense), P(Model), ctypes.c_int, P(Opts), ctypes.c_void_p]
     lib.comm_jcomm_outer.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), ctypes.c_void_p, ctypes.c_void_p]
+    lib.comm_jcomm_outer_noalloc.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), ctypes.c_void_p,
+                                             ctypes.c_void_p]
     lib.comm_beta_objective.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), ctypes.c_void_p,
                                         ctypes.c_void_p]
     lib.comm_cp_jcomm_outer_coo.argtypes = [ctypes.c_void_p, P(Coo), P(Model), P(Opts), ctypes.c_void_p,
@@ -398,6 +402,22 @@ class Context:
             optr = _ptr(obj_out, "obj_out")
         _check(self._lib.comm_jcomm_outer(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), optr,
                                           _stream(stream)))
+
+    def jcomm_outer_noalloc(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
+                            eps_x: Optional[float] = None, cache_pq: "bool | str" = False, obj_out=None,
+                            stream=None, precision: str = "fp32") -> None:
+        """jcomm_outer with its workspace in the library's fixed per-GPU array
+        (NOALLOC_SCRATCH_BYTES): no device allocation.  Calls that overlap on one
+        GPU race; a problem that does not fit raises COMM_ENOMEM."""
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, cache_pq, precision)
+        optr = None
+        if obj_out is not None:
+            import torch
+            if obj_out.dtype != torch.float64:
+                raise TypeError("obj_out must be float64")
+            optr = _ptr(obj_out, "obj_out")
+        _check(self._lib.comm_jcomm_outer_noalloc(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), optr,
+                                                  _stream(stream)))
 
     def tune_jcomm(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
                    eps_x: Optional[float] = None, precision: str = "fp32", reps: int = 3, stream=None) -> dict:

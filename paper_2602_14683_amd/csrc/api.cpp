@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,36 @@
 using namespace comm;
 
 thread_local std::string g_last_error = "no error";
+
+// Workspace of comm_jcomm_outer_noalloc: one fixed array on every GPU the
+// library runs on, held until the process ends.  In host code the symbol
+// names a host-side stand-in, never the device memory: its device address is
+// looked up once per device (with that device current) when the first
+// context on it is created, and only that address is used.
+constexpr size_t kNoallocBytes = COMM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(COMM_EINVAL, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    HIP_TRY(hipSetDevice(prev));
+    if (e != hipSuccess || !p)
+      return fail(COMM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_addr[device] = static_cast<char*>(p);
+  }
+  *out = g_scratch_addr[device];
+  return COMM_OK;
+}
 
 int check_opts(const comm_opts* o, bool need_L) {
   if (!o) return fail(COMM_EINVAL, "opts is NULL");
@@ -1511,9 +1542,13 @@ int comm_create(int device, size_t workspace_limit_bytes, comm_ctx** out) {
     int count = 0;
     HIP_TRY(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(COMM_EINVAL, "device %d of %d", device, count);
+    char* noalloc_ws = nullptr;
+    const int rc = scratch_address(device, &noalloc_ws);
+    if (rc) return rc;
     comm_ctx* c = new comm_ctx();
     c->device = device;
     c->limit = workspace_limit_bytes;
+    c->noalloc_ws = noalloc_ws;
     *out = c;
     return COMM_OK;
   });
@@ -1630,6 +1665,40 @@ int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, cons
     hipStream_t st = (hipStream_t)stream;
     if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
     rc = jcomm_run(ctx, x, model, opts, obj_ref_dev, st);
+    ctx->last_stream = st;
+    return rc;
+  });
+}
+
+int comm_jcomm_outer_noalloc(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
+                             double* obj_ref_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    int rc = jcomm_check(x, model, opts);
+    if (rc) return rc;
+    if (opts->check_inputs)
+      return fail(COMM_EINVAL, "check_inputs needs a device flag of its own: not available without allocation");
+    if (!ctx->noalloc_ws) return fail(COMM_EHIP, "no fixed workspace on device %d", ctx->device);
+    comm_opts o = *opts;
+    if (o.cache_pq == COMM_CACHE_AUTO) {
+      const auto it = ctx->tune.find(tune_key(x, model, opts));
+      o.cache_pq = it != ctx->tune.end() ? it->second : 1;
+      if (o.cache_pq && jcomm_ws_bytes(x, model, &o) > kNoallocBytes) o.cache_pq = 0;
+    }
+    const size_t need = jcomm_ws_bytes(x, model, &o);
+    if (need > kNoallocBytes)
+      return fail(COMM_ENOMEM, "workspace of %zu bytes exceeds the %zu-byte fixed array of the allocation-free call",
+                  need, kNoallocBytes);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // the single call's orchestration on a context whose workspace is the
+    // fixed array: it never grows (a larger need is an error, checked above)
+    comm_ctx sub;
+    sub.device = ctx->device;
+    sub.ws = ctx->noalloc_ws;
+    sub.ws_bytes = kNoallocBytes;
+    sub.limit = kNoallocBytes;
+    rc = jcomm_variant(&sub, x, model, &o, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
   });

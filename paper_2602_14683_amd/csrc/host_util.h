@@ -45,6 +45,9 @@ struct comm_ctx {
   // buffers (per-nonzero weights, one numerator, objective partials)
   char* sws = nullptr;
   size_t sws_bytes = 0;
+  // device address of the fixed workspace of the allocation-free J-CoMM call
+  // on this context's device (looked up once per device)
+  char* noalloc_ws = nullptr;
 };
 
 extern thread_local std::string g_last_error;

@@ -42,6 +42,8 @@ def test_binding_structs_follow_the_header():
     import paper_2602_14683_amd as pkg
     text = open(HEADER).read()
     assert int(re.search(r"#define COMM_MAX_NDIM (\d+)", text).group(1)) == pkg.MAX_NDIM
+    m = re.search(r"#define COMM_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert int(m.group(1)) << int(m.group(2)) == pkg.NOALLOC_SCRATCH_BYTES
     # int + pad + int64[5] + pointer
     assert ctypes.sizeof(pkg.Dense) == 8 + 8 * pkg.MAX_NDIM + 8
     assert ctypes.sizeof(pkg.Model) == 8 + 8 * pkg.MAX_NDIM + 8 * pkg.MAX_NDIM + 8
