@@ -128,18 +128,18 @@ __device__ __forceinline__ int out_row(int v, int h) { return 8 * (v >> 2) + 4 *
 // d_1(x | y) = y - x - x log(y / x) without cancellation: with
 // s = (y - x) / (y + x), log(y / x) = 2 atanh(s), which gives
 // d_1 = s^2 [(x + y) - 2 x s S(s^2)],  S(z) = sum_{k>=0} z^k / (2k + 3).
-// For z <= 1/4 (|s| <= 1/2) -2 S(z) is replaced by a degree-5 polynomial
-// fitted for least maximum relative error (Lawson's iteration on a fine grid,
-// coefficients rounded to float32): 1.1e-7 relative error including the
-// float32 Horner evaluation, five FMAs where the Taylor series needs nine
-// terms for 6e-7.  Entries with |s| >= 1/2 ("far") take the direct form, which
-// there loses at most a couple of bits.
+// For z < 1/16 (|s| < 1/4) -2 S(z) is replaced by a cubic fitted for least
+// maximum relative error (Lawson's iteration on a fine grid, coefficients
+// rounded to float32): 1.0e-7 relative error including the float32 Horner
+// evaluation, three FMAs.  Entries with |s| >= 1/4 ("far") take the direct
+// form y - x - x log(y / x); there |log(y / x)| > 0.51 and d > 0.15 x, so its
+// float32 rounding costs at most about 1e-6 of the term.
+constexpr float kKlFar = 0.0625f;  // z = s^2 at |s| = 1/4
+
 __device__ __forceinline__ float kl_series_core(float x, float s, float z, float sum) {
-  float T = -0.3158642351627350f;
-  T = fmaf(T, z, -0.1293550580739975f);
-  T = fmaf(T, z, -0.2295092195272446f);
-  T = fmaf(T, z, -0.2852697074413300f);
-  T = fmaf(T, z, -0.4000097811222076f);
+  float T = -0.2467406839132309f;
+  T = fmaf(T, z, -0.28473302721977234f);
+  T = fmaf(T, z, -0.40001240372657776f);
   T = fmaf(T, z, -0.6666666269302368f);
   return z * fmaf(x * s, T, sum);
 }
@@ -149,7 +149,7 @@ __device__ __forceinline__ float kl_series(float x, float y, float rsum, bool& f
   const float sum = x + y;
   const float s = (y - x) * rsum;
   const float z = s * s;
-  far = z >= 0.25f && x > 0.0f;
+  far = z >= kKlFar && x > 0.0f;
   const float d = kl_series_core(x, s, z, sum);
   return x > 0.0f ? d : y;
 }
@@ -178,7 +178,7 @@ __device__ __forceinline__ void entry(float x, float y, const BetaConst& bc, flo
       const float z = s * s;
       const float ds = kl_series_core(x, s, z, sum);
       const float dd = fmaf(x * 0.69314718055994531f, fast_log2(fmaxf(p, 1.17549435e-38f)), diff);
-      d = z >= 0.25f ? dd : ds;
+      d = z >= kKlFar ? dd : ds;
     } else {
       p = x * fast_rcp(y);
     }
@@ -271,19 +271,29 @@ struct PassShared {
 };
 
 // X (or cached P/Q) values of pair block (ib, jb) in the Xhat layout.
+// Interior tiles read through a buffer resource based at the pair block: the
+// row offsets are uniform (scalar offset), the lane's offset is fixed for the
+// whole pass (vector offset), so a load needs no address arithmetic.  Only
+// shapes whose in-tile byte offsets stay below 2^31 (xbuf) have interior
+// tiles; others take the guarded path everywhere.
 template <bool kInterior>
 __device__ __forceinline__ void load_tile(const float* __restrict__ base, int ib, int jb, unsigned lane_off,
                                           int i0, int j0, int I, int J, int K, bool kvalid, int h,
                                           float (&x)[16]) {
-  // uniform part of the address in scalar registers, lane part a 32-bit offset
   const int sK = K, sJK = J * K;
   const float* blk = base + ((size_t)(i0 + ib * 4) * J + (j0 + jb * 8)) * K;
+  if constexpr (kInterior) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(blk), 0, 0x7FFFFFFF, 0x00020000);
+    const int voff = (int)(lane_off * 4u);
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const float* rowp = blk + (size_t)((v >> 2) * sJK + (v & 3) * sK);
-    if (kInterior) {
-      x[v] = rowp[lane_off];
-    } else {
+    for (int v = 0; v < 16; ++v)
+      x[v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                           rs, voff, ((v >> 2) * sJK + (v & 3) * sK) * 4, 0));
+  } else {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float* rowp = blk + (size_t)((v >> 2) * sJK + (v & 3) * sK);
       const int i = i0 + ib * 4 + (v >> 2);
       const int j = j0 + jb * 8 + 4 * h + (v & 3);
       x[v] = (kvalid && i < I && j < J) ? rowp[lane_off] : 0.0f;
@@ -605,7 +615,7 @@ __global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pa
   const int bj = bij % gj;
   const int bi = bij / gj;
   const bool interior =
-      (bi + 1) * kCpTI <= a.I && (bj + 1) * kCpTJ <= a.J && (bk + 1) * kCpTK <= a.K;
+      a.xbuf && (bi + 1) * kCpTI <= a.I && (bj + 1) * kCpTJ <= a.J && (bk + 1) * kCpTK <= a.K;
   if (interior)
     pass_body<BC, kVar, kObj, true, kBf>(a, sh, wg, bi, bj, bk, gj, gk);
   else

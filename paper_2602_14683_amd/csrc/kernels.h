@@ -77,6 +77,8 @@ struct CpPassArgs {
   double* obj_part;        // one float64 partial per workgroup
   int x_zero;              // X is all zero and not read (x = 0 everywhere); P is then
                            // zero and its contractions are skipped (beta != 1 only)
+  int xbuf;                // interior tiles may read X (or the cache) through a buffer
+                           // resource: 16 J K + 32 K < 2^31 (every in-tile byte offset fits)
 };
 
 hipError_t launch_cp_pass(const CpPassArgs& a, const CpGrid& g, int beta_class, bool den, hipStream_t s);

@@ -144,6 +144,30 @@ def test_deterministic_bitwise(ctx):
         assert np.array_equal(np.asarray(a), np.asarray(b))
 
 
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 1.3, 1.5])
+@pytest.mark.parametrize("dims", [(37, 70, 90), (17, 33, 65), (16, 32, 129)])
+def test_objective_bitwise_across_runs_on_boundary_tiles(ctx, beta, dims):
+    """Every beta class's objective on shapes whose tiles are ragged in one or
+    all modes (the pass tiles 16 x 32 x 64): three evaluations and three J-CoMM
+    reference objectives must agree bit for bit, and with the oracle."""
+    X, init = _problem(dims, 7, 13)
+    Xd = dev(X)
+    fac = [dev(a) for a in init]
+    vals = [ctx.beta_objective(Xd, fac, beta=beta).item() for _ in range(3)]
+    refs = []
+    for _ in range(3):
+        f = [dev(a) for a in init]
+        obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.jcomm_outer(Xd, f, beta=beta, L=1, obj_out=obj)
+        torch.cuda.synchronize()
+        refs.append(obj.item())
+    assert vals[0] == vals[1] == vals[2]
+    assert refs[0] == refs[1] == refs[2]
+    want = oobjective(_xf(X, beta), ocp.rebuild(init), beta)
+    assert abs(vals[0] - want) / want < 1e-5
+    assert abs(refs[0] - want) / want < 1e-5
+
+
 def test_full_size_headline_jcomm_kl(ctx):
     """256^3, rank 32, beta = 1, L = 5 (the measured workload): one outer
     iteration, every factor entry against the oracle."""
