@@ -186,6 +186,7 @@ CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
   a.m3d = w.m3d; a.m1d = w.m1d; a.m2d = w.m2d;
   a.obj_part = w.obj_part;
   a.bf16 = o->precision == COMM_BF16;
+  a.xbuf = 16.0 * a.J * a.K + 32.0 * a.K < 2147483648.0;
   return a;
 }
 
@@ -1792,6 +1793,16 @@ int comm_jcomm_outer_batched(comm_ctx* ctx, const comm_problem* problems, int co
     if (count < 0 || (count > 0 && !problems)) return fail(COMM_EINVAL, "count = %d with problems = %p", count,
                                                            (const void*)problems);
     if (flags & ~COMM_BATCH_GRAPH) return fail(COMM_EINVAL, "unknown flags 0x%x", flags);
+    // every problem's arguments before anything touches the device
+    for (int p = 0; p < count; ++p) {
+      const comm_problem& q = problems[p];
+      if (!q.x || !q.model || !q.opts) return fail(COMM_EINVAL, "problem %d: x, model and opts must not be NULL", p);
+      const int vrc = jcomm_check(q.x, q.model, q.opts);
+      if (vrc) {
+        std::string msg = g_last_error;
+        return fail(vrc, "problem %d: %s", p, msg.c_str());
+      }
+    }
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
