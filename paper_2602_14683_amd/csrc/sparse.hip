@@ -8,13 +8,15 @@
 // the product c^(n) = A~^(n) * Num_J^(n) that drives the beta = 1 inner loop
 // (kernels_small.hip) is M^(n) itself.
 //
-// Mapping: one nonzero per half wavefront, lane = rank component.  A wave
-// loads 64 nonzeros' coordinates and values with coalesced loads (validity
-// checked once, kept as a ballot mask) and hands them to its halves by lane
-// permutes, four nonzeros per half at a time so that their factor-row
-// gathers (128-byte rows that stay in L2) are in flight together; X~ is a
-// half-wave reduction (DPP, then one permute), and the objective is evaluated
-// once per 64 nonzeros with one nonzero per lane.  Modes
+// Mapping: one nonzero per half wavefront, lane = rank component.  Each half
+// wave takes one contiguous half of its wave's chunk (a run of equal
+// coordinates is split only at a half's ends), loads 32 nonzeros'
+// coordinates and values with coalesced loads (validity checked once, kept as
+// a ballot mask) and hands them out by lane permutes, four nonzeros at a time
+// so that their factor-row gathers (128-byte rows that stay in L2, 32-bit
+// offsets from the factors' bases) are in flight together; X~ is a half-wave
+// reduction (DPP, then one permute), and the objective is evaluated once per
+// nonzero by the lane that loaded it.  Modes
 // whose coordinate the stream is sorted by come in runs: each half keeps a
 // running sum per such mode and adds it to global memory when the
 // coordinate changes.  Other modes are added per nonzero.  Both use hardware
@@ -88,74 +90,83 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
   const int64_t wave = ((int64_t)blockIdx.x * kCooThreads + threadIdx.x) >> 6;
-  const int64_t t0 = wave * a.chunk;
-  const int64_t t1 = min(a.nnz, t0 + a.chunk);
   const int R = a.R;
   const bool rlive = r < R;
   const int rcol = rlive ? r : R - 1;
+  const uint32_t rcol4 = 4u * (uint32_t)rcol;
+  const uint32_t R4 = 4u * (uint32_t)R;
+  // the wave's chunk, each half wave one contiguous half of it, so that a run
+  // of equal coordinates is split only where a half's range ends
+  const int64_t w0 = min(a.nnz, wave * a.chunk);
+  const int64_t w1 = min(a.nnz, w0 + a.chunk);
+  const int64_t half0 = (w1 - w0 + 1) >> 1;
+  const int64_t hb = w0 + (h ? half0 : 0);
+  const int64_t he = h ? w1 : w0 + half0;
+  const int64_t steps = (half0 + 31) >> 5;   // batches of 32 per half (half 0 is the longer)
 
   int cur[2] = {-1, -1};
   float acc[2] = {0.0f, 0.0f};
   double obj = 0.0;
-  for (int64_t tb = t0; tb < t1; tb += 64) {
-    const int cnt = (int)min((int64_t)64, t1 - tb);
-    // 64 nonzeros, one per lane, coalesced; validity once per nonzero; the
-    // coordinates travel as row offsets
-    int my[kMaxModes] = {0, 0, 0, 0, 0};
+  for (int64_t sb = 0; sb < steps; ++sb) {
+    // 32 nonzeros per half, one per lane, coalesced; validity once per
+    // nonzero; a nonzero that is not valid reads row 0
+    const int64_t t = hb + sb * 32 + r;
+    const int cnt = (int)max((int64_t)0, min((int64_t)32, he - (hb + sb * 32)));
+    int my[N];
     float myx = 0.0f;
-    bool valid = lane < cnt;
+    bool valid = r < cnt;
+#pragma unroll
+    for (int m = 0; m < N; ++m) my[m] = 0;
     if (valid) {
 #pragma unroll
       for (int m = 0; m < N; ++m) {
-        const int i = a.idx[m][tb + lane];
+        const int i = a.idx[m][t];
         valid = valid && i >= 0 && i < a.dims[m];
         my[m] = i;
       }
-      myx = a.val[tb + lane];
+      myx = a.val[t];
+    }
+    if (!valid) {
+#pragma unroll
+      for (int m = 0; m < N; ++m) my[m] = 0;
     }
     const uint64_t okmask = __ballot(valid);
+    const int cmax = max(__shfl(cnt, 0), __shfl(cnt, 32));
     float myy = 1.0f;   // X~ of this lane's own nonzero, for the objective
-    for (int j0 = 0; j0 < 32; j0 += kCooBatch) {
-      if (2 * j0 >= cnt) break;
-      int ii[kCooBatch][kMaxModes];
+    for (int j0 = 0; j0 < cmax; j0 += kCooBatch) {
+      int ii[kCooBatch][N];
       float xs[kCooBatch], zs[kCooBatch];
       bool oks[kCooBatch];
 #pragma unroll
       for (int u = 0; u < kCooBatch; ++u) {
-        const int src = 2 * (j0 + u) + h;
+        const int src = (h << 5) + j0 + u;
         oks[u] = (okmask >> src) & 1;
 #pragma unroll
         for (int m = 0; m < N; ++m) ii[u][m] = __shfl(my[m], src);
         xs[u] = __shfl(myx, src);
       }
-      // every gather of the batch is issued before the first use: lanes with
-      // nothing to gather read row 0 / column R - 1 (valid addresses) and are
-      // zeroed by a mask after the batch (a guarded load per nonzero would be
-      // a branch and a round trip each)
-      float g[kCooBatch][kMaxModes];
+      // every gather of the batch is issued before the first use, each a
+      // 32-bit offset from the factor's (uniform) base
+      float g[kCooBatch][N];
 #pragma unroll
-      for (int u = 0; u < kCooBatch; ++u) {
-        const bool live = oks[u] && rlive;
+      for (int u = 0; u < kCooBatch; ++u)
 #pragma unroll
-        for (int m = 0; m < N; ++m) g[u][m] = a.A[m][(int64_t)(live ? ii[u][m] : 0) * R + rcol];
-      }
-      __builtin_amdgcn_sched_barrier(0);
+        for (int m = 0; m < N; ++m)
+          g[u][m] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(a.A[m]) +
+                                                     ((uint32_t)ii[u][m] * R4 + rcol4));
 #pragma unroll
       for (int u = 0; u < kCooBatch; ++u) {
         float z = g[u][0];
 #pragma unroll
         for (int m = 1; m < N; ++m) z *= g[u][m];
-        zs[u] = z * ((oks[u] && rlive) ? 1.0f : 0.0f);
+        zs[u] = (oks[u] && rlive) ? z : 0.0f;
       }
       float y[kCooBatch];
 #pragma unroll
       for (int u = 0; u < kCooBatch; ++u) y[u] = fmaxf(half_sum(zs[u]), a.eps);
 #pragma unroll
-      for (int u = 0; u < kCooBatch; ++u) {
-        // lane 2 j + hh owns the nonzero that half hh handled at step j
-        const float yg = __shfl(y[u], 32 * (lane & 1));
-        if ((lane >> 1) == j0 + u) myy = yg;
-      }
+      for (int u = 0; u < kCooBatch; ++u)
+        if (r == j0 + u) myy = y[u];
 #pragma unroll
       for (int u = 0; u < kCooBatch; ++u) {
         if (!oks[u]) continue;
