@@ -120,10 +120,12 @@ struct CpWs {
   float* stats[3];
   float* dprod;
   float *Pc, *Qc;
+  float *Vn, *Vd;    // J-CoMM at beta != 1: V kept by the mode-1 pass for mode 2
+  float *f2n, *f2d;  // ... and mode 2's numerator / denominator chunks folded from it
   size_t bytes;
 };
 
-CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
+CpWs cp_layout(const comm_dense* x, char* base, bool cache, bool vkeep = false) {
   CpWs w = {};
   for (int n = 0; n < 3; ++n) w.dims[n] = (int)x->dims[n];
   w.g = cp_grid(w.dims[0], w.dims[1], w.dims[2]);
@@ -141,7 +143,7 @@ CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
   w.m3d = cv.take<float>((size_t)g.m3_slots() * g.Kp * kRP);
   w.m1d = cv.take<float>((size_t)g.m1_slots() * g.Ip * kRP);
   w.m2d = cv.take<float>((size_t)g.m2_slots() * g.Jp * kRP);
-  w.obj_part = cv.take<double>((size_t)g.wgs());
+  w.obj_part = cv.take<double>((size_t)std::max<int64_t>(g.wgs(), vkeep ? cp_vpass_wgs(w.dims[0], w.dims[1]) : 0));
   for (int n = 0; n < 3; ++n) {
     w.c[n] = cv.take<float>((size_t)w.rows_p[n] * kRP);
     w.stats[n] = cv.take<float>((size_t)((w.rows_p[n] + kSlotRows - 1) / kSlotRows) * 96);
@@ -151,6 +153,13 @@ CpWs cp_layout(const comm_dense* x, char* base, bool cache) {
     const size_t total = (size_t)w.dims[0] * w.dims[1] * w.dims[2];
     w.Pc = cv.take<float>(total);
     w.Qc = cv.take<float>(total);
+  }
+  if (vkeep) {
+    const size_t pairs = (size_t)w.dims[0] * w.dims[1];
+    w.Vn = cv.take<float>(pairs * kRP);
+    w.Vd = cv.take<float>(pairs * kRP);
+    w.f2n = cv.take<float>((size_t)kVFoldChunks * g.Jp * kRP);
+    w.f2d = cv.take<float>((size_t)kVFoldChunks * g.Jp * kRP);
   }
   w.bytes = cv.off + 256;
   return w;
@@ -283,10 +292,12 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
               const NumHook* hook = nullptr) {
   const bool kl = o->beta == 1.0;
   const bool cache = !kl && o->cache_pq;
-  CpWs w = cp_layout(x, nullptr, cache);
+  // the mode-1 pass keeps V for mode 2 (float32 tiles; see own_pass below)
+  const bool vkeep = !kl && o->precision != COMM_BF16;
+  CpWs w = cp_layout(x, nullptr, cache, vkeep);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
-  w = cp_layout(x, ctx->ws, cache);
+  w = cp_layout(x, ctx->ws, cache, vkeep);
   const int bc = beta_class_of(o->beta);
   const float eps = (float)o->eps;
 
@@ -366,31 +377,100 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
     if (obj_pending) HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
     obj_pending = false;
   }
+  // Per sweep (Sec. 5.3, CP inner updates in the order of modes 1, 2, 3):
+  // mode 1 from the V pass, which keeps V = P~ x3 C' (numerator and
+  // denominator sets) since C does not change before mode 3; mode 2 folds V
+  // with the new mode-1 transforms; mode 3 from a pass of its own.
+  auto chi_of = [&](std::initializer_list<int> modes) -> int {
+    ChiArgs ca = {};
+    ca.beta = (float)o->beta;
+    for (int q : modes) {
+      const int f = ca.nf++;
+      ca.cur[f] = w.cur.pad[q];
+      ca.ref[f] = w.ref.pad[q];
+      ca.rows_p[f] = w.rows_p[q];
+      ca.x1[f] = w.num.pad[q];
+      ca.x2[f] = w.den.pad[q];
+    }
+    HIP_TRY(launch_chi(ca, st));
+    return COMM_OK;
+  };
+  // block update of mode n from explicit slots (num_override: the hook's one slot)
+  auto apply = [&](int n, const float* np, int ns, const float* dp, int ds, int rows_total,
+                   const float* num_override) -> int {
+    SlotUpdateArgs u = {};
+    u.njobs = 1;
+    SlotJob& J = u.job[0];
+    J.mode = kSlotUpdate;
+    J.num_part = num_override ? num_override : np;
+    J.num_slots = num_override ? 1 : ns;
+    J.den_part = dp;
+    J.den_slots = ds;
+    J.rows_total = rows_total;
+    J.rows = w.dims[n];
+    J.cols = m->rank;
+    J.rows_p = w.rows_p[n];
+    J.anchor = n == 0 ? ref.A : n == 1 ? ref.B : ref.C;  // anchored at the reference block
+    J.gamma = gamma_of(o->beta);
+    J.eps = eps;
+    J.out_pad = w.cur.pad[n];
+    J.out_user = m->factors[n];
+    J.ld_user = m->rank;
+    HIP_TRY(launch_slot_update(u, st));
+    return COMM_OK;
+  };
+  const FView numv[3] = {pad_view(w.num.pad[0]), pad_view(w.num.pad[1]), pad_view(w.num.pad[2])};
+  // modes 1 and 2 through their own passes (the V pass with the fold measured
+  // slower with bf16 tiles, where the contractions are cheap and the V pass's
+  // per-slice operand loads are not)
+  auto own_pass = [&](int n) -> int {
+    CpPassArgs a = base_pass(x, w, o);
+    a.r = ref;
+    a.n = pad_set(w.num);
+    a.d = pad_set(w.den);
+    if (n == 0) { a.n.A = ref.A; a.d.A = ref.A; }
+    if (n == 1) { a.n.B = ref.B; a.d.B = ref.B; }
+    a.want_v = 1;
+    if (cache) {
+      a.cache_mode = 2;
+      a.Pc = w.Pc;
+      a.Qc = w.Qc;
+    } else {
+      a.want_obj = obj_pending;
+    }
+    int rc2 = run_pass(ctx, a, w.g, bc, true, st);
+    if (rc2) return rc2;
+    if (a.want_obj) {
+      HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+      obj_pending = false;
+    }
+    const float* nb = nullptr;
+    if (hook && (rc2 = hook->run(n, numv, &nb))) return rc2;
+    const float *np, *dp;
+    int ns, ds, rt;
+    slots_of(w, n, false, &np, &ns, &rt);
+    slots_of(w, n, true, &dp, &ds, &rt);
+    return apply(n, np, ns, dp, ds, rt, nb);
+  };
+  const bool wshare = vkeep;
   for (int l = 0; l < o->inner_sweeps; ++l) {
-    for (int n = 0; n < 3; ++n) {
-      ChiArgs ca = {};
-      ca.beta = (float)o->beta;
-      for (int q = 0; q < 3; ++q) {
-        if (q == n) continue;
-        const int f = ca.nf++;
-        ca.cur[f] = w.cur.pad[q];
-        ca.ref[f] = w.ref.pad[q];
-        ca.rows_p[f] = w.rows_p[q];
-        ca.x1[f] = w.num.pad[q];
-        ca.x2[f] = w.den.pad[q];
-      }
-      HIP_TRY(launch_chi(ca, st));
+    if (!wshare) {
+      if ((rc = chi_of({1, 2}))) return rc;
+      if ((rc = own_pass(0))) return rc;
+      if ((rc = chi_of({0}))) return rc;
+      if ((rc = own_pass(1))) return rc;
+    }
+    // mode 1: the V pass against the sets of modes 2 and 3
+    if (wshare && (rc = chi_of({1, 2}))) return rc;
+    if (wshare) {
       CpPassArgs a = base_pass(x, w, o);
       a.r = ref;
       a.n = pad_set(w.num);
       a.d = pad_set(w.den);
-      // the active mode's own block does not enter its contraction; point it at
-      // the reference so that no stale buffer is read
-      if (n == 0) { a.n.A = ref.A; a.d.A = ref.A; }
-      if (n == 1) { a.n.B = ref.B; a.d.B = ref.B; }
-      if (n == 2) { a.n.C = ref.C; a.d.C = ref.C; }
-      a.want_v = n < 2;
-      a.want_m3 = n == 2;
+      a.n.A = ref.A;  // the active block does not enter its own contraction
+      a.d.A = ref.A;
+      a.Vn = w.Vn;
+      a.Vd = w.Vd;
       if (cache) {
         a.cache_mode = 2;
         a.Pc = w.Pc;
@@ -398,19 +478,57 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
       } else {
         a.want_obj = obj_pending;
       }
-      if ((rc = run_pass(ctx, a, w.g, bc, true, st))) return rc;
-      if (obj_pending) {
-        HIP_TRY(launch_sum_f64(w.obj_part, w.g.wgs(), nullptr, obj, st));
+      if ((rc = profiled(ctx, st, [&] { return launch_cp_vpass(a, bc, st); }))) return rc;
+      if (a.want_obj) {
+        HIP_TRY(launch_sum_f64(w.obj_part, cp_vpass_wgs(w.dims[0], w.dims[1]), nullptr, obj, st));
         obj_pending = false;
       }
-      const FView anchor = n == 0 ? ref.A : n == 1 ? ref.B : ref.C;  // anchored at the reference block
       const float* nb = nullptr;
-      if (hook) {
-        const FView ct[3] = {pad_view(w.num.pad[0]), pad_view(w.num.pad[1]), pad_view(w.num.pad[2])};
-        if ((rc = hook->run(n, ct, &nb))) return rc;
+      if (hook && (rc = hook->run(0, numv, &nb))) return rc;
+      const int slots = cp_vpass_m1_slots(w.dims[1]);
+      if ((rc = apply(0, w.m1n, slots, w.m1d, slots, w.g.Ip, nb))) return rc;
+    }
+    // mode 2: fold the kept V with the new mode-1 transforms
+    if (wshare && (rc = chi_of({0}))) return rc;
+    if (wshare) {
+      VFoldArgs f = {};
+      f.I = w.dims[0];
+      f.J = w.dims[1];
+      f.Jp = w.g.Jp;
+      f.Vn = w.Vn;
+      f.Vd = w.Vd;
+      f.An = pad_view(w.num.pad[0]);
+      f.Ad = pad_view(w.den.pad[0]);
+      f.outn = w.f2n;
+      f.outd = w.f2d;
+      HIP_TRY(launch_vfold(f, st));
+      const float* nb = nullptr;
+      if (hook && (rc = hook->run(1, numv, &nb))) return rc;
+      if ((rc = apply(1, w.f2n, kVFoldChunks, w.f2d, kVFoldChunks, w.g.Jp, nb))) return rc;
+    }
+    // mode 3: its own pass against the sets of modes 1 and 2
+    if ((rc = chi_of({1}))) return rc;
+    {
+      CpPassArgs a = base_pass(x, w, o);
+      a.r = ref;
+      a.n = pad_set(w.num);
+      a.d = pad_set(w.den);
+      a.n.C = ref.C;
+      a.d.C = ref.C;
+      a.want_m3 = 1;
+      if (cache) {
+        a.cache_mode = 2;
+        a.Pc = w.Pc;
+        a.Qc = w.Qc;
       }
-      rc = cp_apply_update(m, w, n, anchor, nullptr, w.cur.pad[n], gamma_of(o->beta), eps, st, nb);
-      if (rc) return rc;
+      if ((rc = run_pass(ctx, a, w.g, bc, true, st))) return rc;
+      const float* nb = nullptr;
+      if (hook && (rc = hook->run(2, numv, &nb))) return rc;
+      const float *np, *dp;
+      int ns, ds, rt;
+      slots_of(w, 2, false, &np, &ns, &rt);
+      slots_of(w, 2, true, &dp, &ds, &rt);
+      if ((rc = apply(2, np, ns, dp, ds, rt, nb))) return rc;
     }
   }
   return COMM_OK;
@@ -485,8 +603,8 @@ CpnWs cpn_layout(const comm_dense* x, char* base, bool cache) {
   return v;
 }
 
-size_t cp_ws_bytes(const comm_dense* x, bool cache) {
-  return x->ndim == 3 ? cp_layout(x, nullptr, cache).bytes : cpn_layout(x, nullptr, cache).bytes;
+size_t cp_ws_bytes(const comm_dense* x, bool cache, bool vkeep = false) {
+  return x->ndim == 3 ? cp_layout(x, nullptr, cache, vkeep).bytes : cpn_layout(x, nullptr, cache).bytes;
 }
 
 // Super factor(s) of the view from G grouped views each: out0 = KR(src0), and
@@ -1260,7 +1378,8 @@ int jcomm_check(const comm_dense* x, const comm_model* model, const comm_opts* o
 }
 
 size_t jcomm_ws_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts) {
-  if (model->kind == COMM_CP) return cp_ws_bytes(x, opts->beta != 1.0 && opts->cache_pq);
+  if (model->kind == COMM_CP)
+    return cp_ws_bytes(x, opts->beta != 1.0 && opts->cache_pq, opts->beta != 1.0 && opts->precision != COMM_BF16);
   return tucker_workspace_bytes(x, model, opts, 1);
 }
 
@@ -1627,7 +1746,9 @@ int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
 
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op) {
   if (check_dense_shape(x) || !model || !opts) return 0;
-  if (model->kind == COMM_CP) return cp_ws_bytes(x, op == 1 && opts->beta != 1.0 && opts->cache_pq);
+  if (model->kind == COMM_CP)
+    return cp_ws_bytes(x, op == 1 && opts->beta != 1.0 && opts->cache_pq,
+                       op == 1 && opts->beta != 1.0 && opts->precision != COMM_BF16);
   if (x->ndim > 3) {
     int64_t rows = 1;
     for (int n = 0; n < x->ndim - 1; ++n) rows *= x->dims[n];

@@ -7,4 +7,6 @@ hipError_t launch_bc_half(const CpPassArgs& a, const CpGrid& g, bool den, hipStr
   return launch_bc<kHalf>(a, g, den, s);
 }
 
+hipError_t launch_vpass_half(const CpPassArgs& a, hipStream_t s) { return launch_vpass_bc<kHalf>(a, s); }
+
 }  // namespace comm

@@ -7,4 +7,6 @@ hipError_t launch_bc_is(const CpPassArgs& a, const CpGrid& g, bool den, hipStrea
   return launch_bc<kIS>(a, g, den, s);
 }
 
+hipError_t launch_vpass_is(const CpPassArgs& a, hipStream_t s) { return launch_vpass_bc<kIS>(a, s); }
+
 }  // namespace comm

@@ -7,4 +7,6 @@ hipError_t launch_bc_threehalf(const CpPassArgs& a, const CpGrid& g, bool den, h
   return launch_bc<kThreeHalf>(a, g, den, s);
 }
 
+hipError_t launch_vpass_threehalf(const CpPassArgs& a, hipStream_t s) { return launch_vpass_bc<kThreeHalf>(a, s); }
+
 }  // namespace comm

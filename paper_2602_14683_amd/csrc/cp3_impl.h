@@ -622,6 +622,251 @@ __global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pa
     pass_body<BC, kVar, kObj, false, kBf>(a, sh, wg, bi, bj, bk, gj, gk);
 }
 
+// ---------------------------------------------------------------------------------------- V pass
+//
+// The mode-1 pass of a J-CoMM sweep at beta != 1 with the shared
+// intermediate kept: V[(i,j)][r] = sum_k P~[i,j,k] C'[k][r] (and the same of
+// Q~ with the denominator set) summed over all of K, written to memory, with
+// the mode-1 numerators M1 = sum_j V B' folded from it.  Mode 2's numerators
+// are then M2 = sum_i V A'_new with the mode-1 block's new transforms (C is
+// unchanged until mode 3), a fold over V instead of a second pass over X.
+//
+// Workgroup = 4 i x 32 j pairs over all of K: wave w takes the pair block of
+// the 4 i and j0 + 8w .. j0 + 8w + 7 and walks the 32-wide k slices,
+// accumulating V in registers; rebuild rows and the B' rows of the fold are
+// staged in LDS, the per-slice C operands are read from memory (they stay in
+// the caches).  Slots: M1 one per j block (bj), rows i; V [I*J][32] per set.
+
+constexpr int kVTI = 4;
+constexpr int kVTJ = 32;
+
+struct VPassShared {
+  float t[kWaves][32 * kLdsT];          // per-wave transpose buffers
+  float m1[2][kWaves][kVTI * 32];       // [num/den][wave][i][r]
+  float ra[kVTI * kSA];                 // rebuild rows of A
+  float rb[kVTJ * kSA];                 // rebuild rows of B
+  float nb[kVTJ * 32], db[kVTJ * 32];   // B' rows of the numerator / denominator sets
+  double obj[kWaves];
+};
+
+template <int BC, bool kCache, bool kObj, bool kBf, bool kInterior>
+__device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh, int bi, int bj) {
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int col = lane & 31;
+  const int h = lane >> 5;
+  const int I = a.I, J = a.J, K = a.K;
+  const int i0 = bi * kVTI, j0 = bj * kVTJ;
+  const int jb = w;  // this wave's 8 j
+
+  // stage the rebuild rows (A: 4 i, B: 32 j) and the fold's B' rows
+  for (int e = tid; e < kVTI * 32; e += kThreads) {
+    const int i = i0 + (e >> 5), c = e & 31;
+    if (!kCache) sh.ra[(e >> 5) * kSA + c] = load_clamped(a.r.A, i, c, I) * mask_of(a.r.A, i, c, I);
+  }
+  for (int e = tid; e < kVTJ * 32; e += kThreads) {
+    const int j = j0 + (e >> 5), c = e & 31;
+    if (!kCache) sh.rb[(e >> 5) * kSA + c] = load_clamped(a.r.B, j, c, J) * mask_of(a.r.B, j, c, J);
+    sh.nb[e] = load_clamped(a.n.B, j, c, J) * mask_of(a.n.B, j, c, J);
+    sh.db[e] = load_clamped(a.d.B, j, c, J) * mask_of(a.d.B, j, c, J);
+  }
+  __syncthreads();
+
+  // the rebuild operand of this wave's pair block: lane = pair m = col, r = 16h + s
+  float wr[16];
+  if (!kCache) {
+    float arow[16], brow[16];
+    load16(sh.ra + (col >> 3) * kSA + 16 * h, arow);
+    load16(sh.rb + (jb * 8 + (col & 7)) * kSA + 16 * h, brow);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) wr[s] = arow[s] * brow[s];
+  }
+  bf16x8 wrh[2], wrl[2];
+  if constexpr (kBf) {
+    if (!kCache) {
+      split_bf16(wr, wrh[0], wrl[0]);
+      split_bf16(wr + 8, wrh[1], wrl[1]);
+    }
+  }
+
+  bool pvalid[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = i0 + (v >> 2);
+    const int j = j0 + jb * 8 + 4 * h + (v & 3);
+    pvalid[v] = i < I && j < J;
+  }
+
+  f32x16 vn = {}, vd = {};
+  double obj = 0.0;
+  const float* src0 = kCache ? a.Pc : a.X;
+  const bool xz = !kCache && a.x_zero;
+  const int nk = (K + 31) / 32;
+  for (int ks = 0; ks < nk; ++ks) {
+    const int kslice = ks * 32;
+    const int kcol = kslice + col;
+    const bool kvalid = kcol < K;
+    const unsigned lane_off = (unsigned)(4 * h * K + kslice + col);
+    float xv[16], qv_in[16];
+    const bool full = kInterior && kslice + 32 <= K;
+    if (xz) {
+      // the all-zero twin of sparse data: nothing to load
+#pragma unroll
+      for (int v = 0; v < 16; ++v) xv[v] = 0.0f;
+    } else if (full) {
+      load_tile<true>(src0, 0, jb, lane_off, i0, j0, I, J, K, true, h, xv);
+      if (kCache) load_tile<true>(a.Qc, 0, jb, lane_off, i0, j0, I, J, K, true, h, qv_in);
+    } else {
+      load_tile<false>(src0, 0, jb, lane_off, i0, j0, I, J, K, kvalid, h, xv);
+      if (kCache) load_tile<false>(a.Qc, 0, jb, lane_off, i0, j0, I, J, K, kvalid, h, qv_in);
+    }
+    // per-slice C operands: rebuild rows (k = kcol, r = 16h + s) and the
+    // contraction columns (r = col, k = kslice + 16h + s)
+    float crow[16], ctn[16], ctd[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (!kCache) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
+      ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
+      ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
+    }
+    float pv[16], qv[16];
+    if (kCache) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        pv[v] = xv[v];
+        qv[v] = qv_in[v];
+      }
+    } else {
+      f32x16 xh = {};
+      if constexpr (kBf) {
+        bf16x8 crh[2], crl[2];
+        split_bf16(crow, crh[0], crl[0]);
+        split_bf16(crow + 8, crh[1], crl[1]);
+        xh = mfma_bf16(wrl[0], crh[0], xh);
+        xh = mfma_bf16(wrl[1], crh[1], xh);
+        xh = mfma_bf16(wrh[0], crl[0], xh);
+        xh = mfma_bf16(wrh[1], crl[1], xh);
+        xh = mfma_bf16(wrh[0], crh[0], xh);
+        xh = mfma_bf16(wrh[1], crh[1], xh);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) xh = mfma32(wr[s], crow[s], xh);
+      }
+      float objt = 0.0f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        float x = xv[v];
+        if constexpr (BC == kIS) x = fmaxf(x, a.eps_x);
+        const float y = fmaxf(xh[v], a.eps);
+        float p, q, d = 0.0f;
+        entry<BC, kObj>(x, y, a.bc, p, q, d);
+        const bool ok = kvalid && pvalid[v];
+        pv[v] = ok ? p : 0.0f;
+        qv[v] = ok ? q : 0.0f;
+        if (kObj) objt += ok ? d : 0.0f;
+        if constexpr (kObj) {
+          if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if constexpr (kObj) obj += (double)objt;
+    }
+    // V += P C' and Vd += Q C'd through the per-wave LDS transpose
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const float(&wv)[16] = side == 0 ? pv : qv;
+      const float(&ct)[16] = side == 0 ? ctn : ctd;
+      float* ldsT = sh.t[w];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) ldsT[out_row(v, h) * kLdsT + col] = wv[v];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      float pr[16];
+      load16(ldsT + col * kLdsT + 16 * h, pr);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      f32x16& acc = side == 0 ? vn : vd;
+      if constexpr (kBf) {
+        const bf16x8 ctb[2] = {pack_bf16(ct), pack_bf16(ct + 8)};
+        acc = chain_bf16(pr, ctb, acc);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc = mfma32(pr[s], ct[s], acc);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+
+  // acc[4g+q] = V[(i0 + g, j0 + 8 jb + 4h + q)][r = col]: store V, fold M1
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const f32x16& acc = side == 0 ? vn : vd;
+    float* Vout = side == 0 ? a.Vn : a.Vd;
+    const float* bset = side == 0 ? sh.nb : sh.db;
+    float m1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int jl = jb * 8 + 4 * h + q;
+        const int i = i0 + g, j = j0 + jl;
+        if (i < I && j < J) Vout[((size_t)i * J + j) * kRP + col] = acc[4 * g + q];
+        m1[g] = fmaf(acc[4 * g + q], bset[jl * 32 + col], m1[g]);
+      }
+      const float o = __shfl_xor(m1[g], 32);
+      if (h == 0) sh.m1[side][w][g * 32 + col] = m1[g] + o;
+    }
+  }
+  if (kObj) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
+    if (lane == 0) sh.obj[w] = obj;
+  }
+  __syncthreads();
+  const int wg = blockIdx.x;
+  if (kObj && tid == 0) {
+    double sum = sh.obj[0];
+    for (int q = 1; q < kWaves; ++q) sum += sh.obj[q];
+    a.obj_part[wg] = sum;
+  }
+  // M1 rows i0 .. i0 + 3 of slot bj: the four waves' j blocks in order
+  for (int e = tid; e < 2 * kVTI * 32; e += kThreads) {
+    const int side = e / (kVTI * 32), il = (e >> 5) & (kVTI - 1), r = e & 31;
+    const int idx = il * 32 + r;
+    const float sum = ((sh.m1[side][0][idx] + sh.m1[side][1][idx]) + sh.m1[side][2][idx]) + sh.m1[side][3][idx];
+    float* d1 = side == 0 ? a.m1n : a.m1d;
+    if (i0 + il < I) d1[((size_t)bj * a.Ip + i0 + il) * kRP + r] = sum;
+  }
+}
+
+template <int BC, bool kCache, bool kObj, bool kBf>
+__global__ void __launch_bounds__(kThreads, kObj ? 1 : 2) cp3_vpass_kernel(CpPassArgs a, int gj) {
+  __shared__ VPassShared sh;
+  const int bi = blockIdx.x / gj, bj = blockIdx.x % gj;
+  const bool interior = a.xbuf && (bi + 1) * kVTI <= a.I && (bj + 1) * kVTJ <= a.J;
+  if (interior)
+    vpass_body<BC, kCache, kObj, kBf, true>(a, sh, bi, bj);
+  else
+    vpass_body<BC, kCache, kObj, kBf, false>(a, sh, bi, bj);
+}
+
+inline int64_t vpass_wgs(int I, int J) { return (int64_t)((I + kVTI - 1) / kVTI) * ((J + kVTJ - 1) / kVTJ); }
+
+template <int BC, bool kCache, bool kObj>
+hipError_t launch_vpass_t(const CpPassArgs& a, hipStream_t s) {
+  const int gj = (a.J + kVTJ - 1) / kVTJ;
+  const dim3 grid((unsigned)vpass_wgs(a.I, a.J));
+  if (a.bf16)
+    hipLaunchKernelGGL((cp3_vpass_kernel<BC, kCache, kObj, true>), grid, dim3(kThreads), 0, s, a, gj);
+  else
+    hipLaunchKernelGGL((cp3_vpass_kernel<BC, kCache, kObj, false>), grid, dim3(kThreads), 0, s, a, gj);
+  return hipGetLastError();
+}
+
+template <int BC>
+hipError_t launch_vpass_bc(const CpPassArgs& a, hipStream_t s) {
+  return a.want_obj ? launch_vpass_t<BC, false, true>(a, s) : launch_vpass_t<BC, false, false>(a, s);
+}
+
 template <int BC, int kVar, bool kObj>
 hipError_t launch_v(const CpPassArgs& a, const CpGrid& g, hipStream_t s) {
   if (a.bf16)
@@ -653,5 +898,10 @@ hipError_t launch_bc_kl(const CpPassArgs& a, const CpGrid& g, bool den, hipStrea
 hipError_t launch_bc_threehalf(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
 hipError_t launch_bc_general(const CpPassArgs& a, const CpGrid& g, bool den, hipStream_t s);
 hipError_t launch_cache_read(const CpPassArgs& a, const CpGrid& g, hipStream_t s);
+hipError_t launch_vpass_is(const CpPassArgs& a, hipStream_t s);
+hipError_t launch_vpass_half(const CpPassArgs& a, hipStream_t s);
+hipError_t launch_vpass_threehalf(const CpPassArgs& a, hipStream_t s);
+hipError_t launch_vpass_general(const CpPassArgs& a, hipStream_t s);
+hipError_t launch_vpass_cache(const CpPassArgs& a, hipStream_t s);
 
 }  // namespace comm

@@ -79,9 +79,30 @@ struct CpPassArgs {
                            // zero and its contractions are skipped (beta != 1 only)
   int xbuf;                // interior tiles may read X (or the cache) through a buffer
                            // resource: 16 J K + 32 K < 2^31 (every in-tile byte offset fits)
+  float* Vn;               // V pass (launch_cp_vpass): V of the numerator / denominator set, [I*J][32]
+  float* Vd;
 };
 
 hipError_t launch_cp_pass(const CpPassArgs& a, const CpGrid& g, int beta_class, bool den, hipStream_t s);
+// The mode-1 pass of a beta != 1 J-CoMM sweep that keeps V (numerator and
+// denominator sets) for mode 2; M1 slots one per 32-wide j block (into m1n /
+// m1d, rows Ip), the objective partials (want_obj, not with the cache) one
+// per workgroup of cp_vpass_wgs.
+hipError_t launch_cp_vpass(const CpPassArgs& a, int beta_class, hipStream_t s);
+int64_t cp_vpass_wgs(int I, int J);
+int cp_vpass_m1_slots(int J);
+// M2 from the kept V: slots[c][j][r] = sum over i in chunk c of V[i][j][r] A'[i][r]
+// (kVFoldChunks chunks, rows Jp), numerator and denominator sets.
+constexpr int kVFoldChunks = 8;
+struct VFoldArgs {
+  int I, J, Jp;
+  const float* Vn;
+  const float* Vd;
+  FView An, Ad;            // the mode-1 block's transforms
+  float* outn;
+  float* outd;
+};
+hipError_t launch_vfold(const VFoldArgs& a, hipStream_t s);
 
 // ----------------------------------------------------------------------------------------
 // Small factor-side kernels (kernels_small.hip)
