@@ -667,57 +667,138 @@ def run_tucker5_coo(args, ctx):
     return out
 
 
-def serving_stream(args, ctx):
-    """A Poisson stream of CP / Tucker requests (dims U{16..256}, rank or core
-    size in {4, 8, 16, 32}, beta in {0, 1/2, 1, 3/2}), each run to a relative
-    objective change <= 1e-4 (or max_iters), served three ways on the same GPU:
-    continuous batching with bf16 tiles, continuous batching in float32 (both
-    replaying a captured graph of the batched step), and the plain per-request
-    float32 loop.  Request tensors are drawn on the host before the clock
-    starts; copying them to the device is part of each request's service.
-    Each bf16-served request's final objective is compared with the same
-    request's float32 per-request result."""
+def _serving_pool(args):
+    """The distinct requests a stream draws from: the first serve_pool specs of
+    the seeded generator (dims U{16..256}, rank or core size in {4, 8, 16, 32},
+    beta in {0, 1/2, 1, 3/2}, CP or Tucker), materialized once on the host, with
+    one float32 payload per precision shared by every request that draws it."""
     import workloads
     from paper_2602_14683_amd import serving
-
-    specs = workloads.serving_specs(seed=0, count=args.serve_requests, rate=args.serve_rate)
+    specs = workloads.serving_specs(seed=0, count=args.serve_pool, rate=1.0)
     mats = [workloads.materialize(s) for s in specs]
+    payloads = {prec: [serving.from_workload(m, prec) for m in mats] for prec in ("bf16", "fp32")}
+    for prec in payloads:
+        for k, d in enumerate(payloads[prec]):
+            d.tag = k
+    return specs, mats, payloads
+
+
+def _stream(n, rate, pool_size, seed):
+    """n arrivals of a Poisson process of the given rate (per second), each
+    drawing one of the pool's requests uniformly (seeded)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n)) if rate > 0 else np.zeros(n)
+    return [(k, float(t[k]), int(rng.integers(0, pool_size))) for k in range(n)]
+
+
+def _serve(ctx, stream, payloads, prec, batched, slots, budget, max_iters):
+    from paper_2602_14683_amd import serving
+    print(f"serving: {len(stream)} requests, {prec}, {'batched' if batched else 'per-request'}", file=sys.stderr,
+          flush=True)
+    ex = serving.BatchedExecutor(ctx, slots, graph=True) if batched else serving.SingleExecutor(ctx, 1)
+    reqs = [serving.ServeRequest(rid, t, payloads[prec][k]) for rid, t, k in stream]
+    srv = serving.Server(ex, budget, slots if batched else 1, tol=1e-4, max_iters=max_iters)
+    done = srv.run(reqs)
+    st = serving.summarize(done)
+    st.update({"peak_slots": srv.peak_slots, "peak_bytes": srv.peak_bytes, "steps": srv.steps,
+               "mem_waits": srv.mem_waits})
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}, done
+
+
+def serving_stream(args, ctx):
+    """A Poisson stream of CP / Tucker requests drawn from a pool of distinct
+    requests (dims U{16..256}, rank or core size in {4, 8, 16, 32}, beta in {0,
+    1/2, 1, 3/2}), each run to a relative objective change <= 1e-4 (or
+    max_iters), served three ways on the same GPU: continuous batching with
+    bf16 tiles, continuous batching in float32 (both replaying a captured graph
+    of the batched step), and the plain per-request float32 loop.  Request
+    tensors are drawn on the host before the clock starts; copying them to the
+    device is part of each request's service.  Each bf16-served request's final
+    objective is compared with the same request's float32 per-request result."""
+    specs, mats, payloads = _serving_pool(args)
+    stream = _stream(args.serve_requests, args.serve_rate, len(specs), 1)
     budget = int(args.serve_hbm_gib * (1 << 30))
-    res = {}
-    finals = {}
-    runs = (("batched_bf16", "bf16", lambda: serving.BatchedExecutor(ctx, args.serve_slots, graph=True), args.serve_slots),
-            ("batched_fp32", "fp32", lambda: serving.BatchedExecutor(ctx, args.serve_slots, graph=True), args.serve_slots),
-            ("per_request_fp32", "fp32", lambda: serving.SingleExecutor(ctx, 1), 1))
-    for name, prec, make, slots in runs:
-        reqs = [serving.ServeRequest(s.rid, s.arrival, serving.from_workload(m, prec)) for s, m in zip(specs, mats)]
-        srv = serving.Server(make(), budget, slots, tol=1e-4, max_iters=args.serve_max_iters)
-        done = srv.run(reqs)
+    res, finals = {}, {}
+    for name, prec, batched in (("batched_bf16", "bf16", True), ("batched_fp32", "fp32", True),
+                                ("per_request_fp32", "fp32", False)):
+        res[name], done = _serve(ctx, stream, payloads, prec, batched, args.serve_slots, budget, args.serve_max_iters)
         finals[name] = {c.rid: c.objective for c in done}
-        st = serving.summarize(done)
-        st.update({"peak_slots": srv.peak_slots, "peak_bytes": srv.peak_bytes, "steps": srv.steps})
-        res[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
     base = res["per_request_fp32"]["solves_per_s"]
     res["speedup_solves_per_s"] = {k: round(res[k]["solves_per_s"] / base, 3) for k in ("batched_bf16", "batched_fp32")}
     rel = [abs(finals["batched_bf16"][r] - finals["per_request_fp32"][r]) / abs(finals["per_request_fp32"][r])
            for r in finals["per_request_fp32"]]
     res["bf16_final_objective_rel_diff_vs_fp32"] = {"max": max(rel), "median": float(sorted(rel)[len(rel) // 2])}
-    res["stream"] = {"requests": len(specs), "rate_per_s": args.serve_rate, "tol": 1e-4,
+    res["stream"] = {"requests": len(stream), "distinct": len(specs), "rate_per_s": args.serve_rate, "tol": 1e-4,
                      "max_iters": args.serve_max_iters, "slots": args.serve_slots,
                      "hbm_budget_gib": args.serve_hbm_gib,
-                     "cp": sum(s.model == "cp" for s in specs), "tucker": sum(s.model == "tucker" for s in specs)}
+                     "cp": sum(specs[k].model == "cp" for _, _, k in stream),
+                     "tucker": sum(specs[k].model == "tucker" for _, _, k in stream)}
     return res
 
 
 def run_serving(args, ctx):
-    res = serving_stream(args, ctx)
-    b = res["batched_bf16"]
+    """The serving workload: first the per-request float32 loop's capacity
+    (solves/s with every request waiting at t = 0), then Poisson streams of
+    serve_requests arrivals at 0.5, 1 and 2 times that capacity, each served by
+    batched bf16, batched float32 and the per-request float32 loop, then one
+    batched bf16 stream at capacity under a 1 GiB device-memory budget (a fresh
+    context, so admission sees all the memory the library takes)."""
+    import paper_2602_14683_amd as comm
+    import torch
+    specs, mats, payloads = _serving_pool(args)
+    budget = int(args.serve_hbm_gib * (1 << 30))
+    cap_stream = _stream(args.serve_capacity_requests, 0.0, len(specs), 2)
+    cap, _ = _serve(ctx, cap_stream, payloads, "fp32", False, 1, budget, args.serve_max_iters)
+    capacity = cap["solves_per_s"]
+    runs = {}
+    for mult in (0.5, 1.0, 2.0):
+        stream = _stream(args.serve_requests, mult * capacity, len(specs), 3)
+        per = {}
+        for name, prec, batched in (("batched_bf16", "bf16", True), ("batched_fp32", "fp32", True),
+                                    ("per_request_fp32", "fp32", False)):
+            per[name], done = _serve(ctx, stream, payloads, prec, batched, args.serve_slots, budget,
+                                     args.serve_max_iters)
+            if name == "batched_bf16" and mult == 1.0:
+                bf16_done = done
+        base = per["per_request_fp32"]["solves_per_s"]
+        per["speedup_solves_per_s"] = {k: round(per[k]["solves_per_s"] / base, 3)
+                                       for k in ("batched_bf16", "batched_fp32")}
+        runs[f"{mult:g}x_capacity"] = per
+    # the reported bf16 objectives, re-evaluated in float64 by the library at
+    # the returned factors (first served occurrence of each distinct request)
+    first = {}
+    for c in bf16_done:
+        if c.status != "rejected" and c.result is not None:
+            k = c.result.get("tag")
+            if k is not None and k not in first:
+                first[k] = c
+    gaps = []
+    for k, c in first.items():
+        d = payloads["bf16"][k]
+        X = torch.from_numpy(d.X).cuda()
+        F = [torch.from_numpy(a).cuda() for a in c.result["factors"]]
+        G = torch.from_numpy(c.result["core"]).cuda() if c.result["core"] is not None else None
+        f64 = ctx.beta_objective(X, F, core=G, beta=d.beta).item()
+        gaps.append(abs(c.objective - f64) / abs(f64))
+    # admission under a 1 GiB budget, fresh context
+    small = comm.Context(0)
+    try:
+        stream = _stream(args.serve_requests, capacity, len(specs), 4)
+        tight, _ = _serve(small, stream, payloads, "bf16", True, args.serve_slots, 1 << 30, args.serve_max_iters)
+    finally:
+        small.close()
+    b = runs["1x_capacity"]["batched_bf16"]
     out = {"metric": METRIC, "value": b["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
            "steps": b["steps"], "warmup": 0, "ms_per_step": round(b["span_s"] / max(b["steps"], 1) * 1e3, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
            "data": "synthetic (planted U(0,1) CP / Tucker models plus Poisson noise, Poisson arrivals)",
-           "config": {"workload": f"serving_stream_{res['stream']['requests']}req_rate{args.serve_rate:g}",
-                      "parallelism": "single GPU"},
-           "serving": res}
+           "config": {"workload": f"serving_stream_{args.serve_requests}req_at_capacity_multiples",
+                      "distinct_requests": len(specs), "slots": args.serve_slots, "parallelism": "single GPU"},
+           "serving": {"per_request_fp32_capacity_solves_per_s": round(capacity, 3), "capacity_run": cap,
+                       "runs": runs, "budget_1gib_batched_bf16_at_capacity": tight,
+                       "bf16_reported_vs_fp64_reevaluated": {"requests": len(gaps), "max": max(gaps) if gaps else None,
+                                                             "median": sorted(gaps)[len(gaps) // 2] if gaps else None}}}
     return out
 
 
@@ -737,12 +818,18 @@ def main() -> int:
                     help="skip the beta = 0.5 and block-MM rates on the same tensor")
     ap.add_argument("--comparison-steps", type=int, default=40)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream in the default run")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=None,
+                    help="arrivals per stream (default 64 beside the headline run, 2000 for --workload serving)")
+    ap.add_argument("--serve-pool", type=int, default=48, help="distinct requests the streams draw from")
+    ap.add_argument("--serve-capacity-requests", type=int, default=150,
+                    help="requests of the per-request loop's capacity run (--workload serving)")
     ap.add_argument("--serve-rate", type=float, default=400.0, help="arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-max-iters", type=int, default=500)
     ap.add_argument("--serve-hbm-gib", type=float, default=64.0, help="device memory budget for admission")
     args = ap.parse_args()
+    if args.serve_requests is None:
+        args.serve_requests = 2000 if args.workload == "serving" else 64
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",

@@ -15,7 +15,11 @@ alone or in the mix.
 
 The scheduler (:class:`Server`) is host logic and talks to an *executor*:
 
-* ``footprint(payload) -> int``   device bytes while resident
+* ``footprint(payload) -> int``   device bytes of its own data while resident
+* ``workspace(payload) -> int``   (optional) library workspace bytes it needs; the
+                                   executor's ``ws_growth`` says how the library
+                                   sizes the shared workspace (a factor over the
+                                   active requests' sum, never shrunk)
 * ``load(payload) -> handle``     put the request on the device
 * ``step(handles) -> [float]``    one outer iteration for each handle, returns
                                    the objective at each reference point
@@ -29,6 +33,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import time
 from typing import Any, Callable, List, Optional, Sequence
 
@@ -63,6 +68,7 @@ class _Active:
     req: ServeRequest
     handle: Any
     footprint: int
+    workspace: int
     admitted: float
     iters: int = 0
     prev: Optional[float] = None
@@ -85,12 +91,18 @@ class Server:
         self.peak_bytes = 0
         self.peak_slots = 0
         self.steps = 0
+        self.mem_waits = 0        # admissions held back for memory (head of the queue)
+        self.ws_reserved = 0      # workspace the library keeps (it grows, never shrinks)
+        self._ws = getattr(executor, "workspace", None)
+        self._growth = float(getattr(executor, "ws_growth", 1.0))
 
     def run(self, requests: Sequence[ServeRequest]) -> List[Completion]:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         active: List[_Active] = []
         done: List[Completion] = []
-        used = 0
+        used = 0       # the active requests' own data
+        ws_active = 0  # the active requests' workspace needs
+        held = None    # rid of the head last held back for memory
         t0 = self.clock()
         while pending or active:
             now = self.clock() - t0
@@ -98,16 +110,26 @@ class Server:
             while pending and pending[0].arrival <= now and len(active) < self.max_slots:
                 r = pending[0]
                 fp = int(self.ex.footprint(r.payload))
-                if fp > self.budget:
+                ws = int(self._ws(r.payload)) if self._ws else 0
+                reserve = max(self.ws_reserved, math.ceil(self._growth * (ws_active + ws)))
+                alone = max(self.ws_reserved, math.ceil(self._growth * ws))
+                if fp + math.ceil(self._growth * ws) > self.budget or (not active and fp + alone > self.budget):
+                    # can never fit (or cannot fit even alone, next to the workspace
+                    # the library already holds)
                     pending.popleft()
                     done.append(Completion(r.rid, r.arrival, now, now, 0, float("nan"), "rejected"))
                     continue
-                if used + fp > self.budget:
+                if used + fp + reserve > self.budget:
+                    if held != r.rid:
+                        self.mem_waits += 1
+                        held = r.rid
                     break
                 pending.popleft()
-                active.append(_Active(r, self.ex.load(r.payload), fp, now))
+                active.append(_Active(r, self.ex.load(r.payload), fp, ws, now))
                 used += fp
-                self.peak_bytes = max(self.peak_bytes, used)
+                ws_active += ws
+                self.ws_reserved = reserve
+                self.peak_bytes = max(self.peak_bytes, used + self.ws_reserved)
             self.peak_slots = max(self.peak_slots, len(active))
             if not active:
                 if pending:
@@ -125,6 +147,7 @@ class Server:
                 if converged or a.iters >= self.max_iters:
                     res = self.ex.unload(a.handle)
                     used -= a.footprint
+                    ws_active -= a.workspace
                     done.append(Completion(a.req.rid, a.req.arrival, a.admitted, now, a.iters, f,
                                            "converged" if converged else "max_iters", res))
                 else:
@@ -140,11 +163,13 @@ def summarize(done: Sequence[Completion]) -> dict:
     if not served:
         return {"served": 0, "rejected": len(done), "solves_per_s": 0.0}
     lat = np.array([c.latency for c in served]) * 1e3
+    queue = np.array([c.admitted - c.arrival for c in served]) * 1e3
     span = max(c.finished for c in served) - min(c.arrival for c in served)
     return {"served": len(served), "rejected": len(done) - len(served),
             "converged": sum(c.status == "converged" for c in served),
             "solves_per_s": len(served) / span if span > 0 else float("inf"),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "queue_p50_ms": float(np.percentile(queue, 50)), "queue_p99_ms": float(np.percentile(queue, 99)),
             "mean_iters": float(np.mean([c.iters for c in served])), "span_s": span}
 
 
@@ -160,6 +185,7 @@ class Decomposition:
     L: int = 1
     eps: float = 1e-12
     precision: str = "fp32"
+    tag: Any = None       # the caller's label, returned with the result
 
 
 def from_workload(req, precision: str = "fp32") -> Decomposition:
@@ -173,6 +199,9 @@ def from_workload(req, precision: str = "fp32") -> Decomposition:
 
 
 class _DeviceBase:
+    # the library sizes a grown workspace at 1.25 x the need and keeps it
+    ws_growth = 1.25
+
     def __init__(self, ctx, max_slots: int):
         import torch
         self.torch = torch
@@ -182,9 +211,12 @@ class _DeviceBase:
 
     def footprint(self, d: Decomposition) -> int:
         params = sum(a.size for a in d.factors) + (d.core.size if d.core is not None else 0)
+        return 4 * (d.X.size + params)
+
+    def workspace(self, d: Decomposition) -> int:
         ws = self.ctx.workspace_bytes(d.X.shape, rank=d.factors[0].shape[1],
                                       core_dims=None if d.core is None else d.core.shape, beta=d.beta, L=d.L)
-        return 4 * (d.X.size + params) + ((ws + 255) // 256) * 256
+        return ((ws + 255) // 256) * 256
 
     def load(self, d: Decomposition) -> dict:
         torch = self.torch
@@ -193,12 +225,12 @@ class _DeviceBase:
              "factors": [torch.from_numpy(a).cuda() for a in d.factors],
              "core": torch.from_numpy(d.core).cuda() if d.core is not None else None,
              "beta": d.beta, "L": d.L, "eps": d.eps, "precision": d.precision,
-             "obj_out": self.objs[slot:slot + 1]}
+             "obj_out": self.objs[slot:slot + 1], "tag": d.tag}
         return h
 
     def unload(self, h: dict) -> dict:
         out = {"factors": [a.cpu().numpy() for a in h["factors"]],
-               "core": h["core"].cpu().numpy() if h["core"] is not None else None}
+               "core": h["core"].cpu().numpy() if h["core"] is not None else None, "tag": h["tag"]}
         self.free.append(h["slot"])
         return out
 

@@ -172,3 +172,65 @@ def test_summary_statistics():
 def test_server_rejects_bad_slot_count():
     with pytest.raises(ValueError):
         Server(None, 10, 0)
+
+
+class WorkspaceExecutor(FakeExecutor):
+    """A fake library whose shared workspace grows to ws_growth x the active
+    requests' sum and never shrinks (as the batched path sizes it); every load
+    checks data + that workspace against the budget."""
+    ws_growth = 1.25
+
+    def __init__(self, clock, budget, max_slots):
+        super().__init__(clock, budget, max_slots)
+        self.ws_held = 0
+        self.ws_need = {}
+
+    def footprint(self, p):
+        return p["fp"]
+
+    def workspace(self, p):
+        return p["ws"]
+
+    def load(self, p):
+        h = {"p": p, "t": 0}
+        self.resident[id(h)] = p["fp"]
+        self.ws_need[id(h)] = p["ws"]
+        self.ws_held = max(self.ws_held, math.ceil(1.25 * sum(self.ws_need.values())))
+        assert len(self.resident) <= self.max_slots
+        assert sum(self.resident.values()) + self.ws_held <= self.budget
+        self.log.append(("load", p["name"], self.clock()))
+        return h
+
+    def unload(self, h):
+        del self.ws_need[id(h)]
+        return super().unload(h)
+
+
+def wreq(rid, arrival, fp, ws, n_big):
+    return ServeRequest(rid, arrival, {"fp": fp, "ws": ws, "objs": geometric(n_big), "name": f"r{rid}"})
+
+
+def test_admission_counts_the_library_workspace_it_keeps():
+    # data 10 + workspace 20 each: two together need 20 + 1.25 * 40 = 70; a
+    # third would need 30 + 75 = 105 > 100, so it waits; after both leave the
+    # library still holds 50 bytes of workspace, which later admissions count
+    clk = Clock()
+    ex = WorkspaceExecutor(clk, 100, 8)
+    srv = Server(ex, 100, 8, clock=clk, wait=clk.wait)
+    reqs = [wreq(0, 0.0, 10, 20, 4), wreq(1, 0.0, 10, 20, 4), wreq(2, 0.0, 10, 20, 2), wreq(3, 20.0, 45, 8, 2)]
+    done = {c.rid: c for c in srv.run(reqs)}
+    assert all(c.status == "converged" for c in done.values())
+    assert done[2].admitted >= min(done[0].finished, done[1].finished)
+    assert srv.mem_waits >= 1
+    assert srv.ws_reserved == 50 and srv.peak_bytes <= 100
+
+
+def test_request_that_cannot_fit_beside_the_held_workspace_is_rejected():
+    # the first request leaves 1.25 * 60 = 75 bytes of workspace behind; a later
+    # one with 30 bytes of data can never fit beside it and must not wait forever
+    clk = Clock()
+    ex = WorkspaceExecutor(clk, 100, 4)
+    srv = Server(ex, 100, 4, clock=clk, wait=clk.wait)
+    done = {c.rid: c for c in srv.run([wreq(0, 0.0, 10, 60, 2), wreq(1, 10.0, 30, 4, 2)])}
+    assert done[0].status == "converged"
+    assert done[1].status == "rejected"
