@@ -184,26 +184,63 @@ int comm_destroy(comm_ctx* ctx);
  * COMM_EHIP with the runtime's message; COMM_OK otherwise. */
 int comm_check(comm_ctx* ctx);
 
-/* Autotuning of J-CoMM (not a passage of the paper: a choice between two
- * evaluations of the same update).  For the problem given (shapes, rank or
- * core sizes, beta, precision and L of x, model and opts; opts->cache_pq is
- * ignored), runs one untimed and then `reps` timed outer iterations with
- * cache_pq = 1 and with cache_pq = 0, each from a device copy of the model's
- * parameters, so the caller's model is left as it was.  The faster choice is
- * stored in the context's autotune table, where calls with cache_pq =
- * COMM_CACHE_AUTO on a problem with the same key find it.  When the cache
- * variant cannot run (workspace limit), 0 is recorded.  At beta = 1 no P~ / Q~
- * is kept, so 0 is recorded without timing.
+/* Autotuning of J-CoMM (not a passage of the paper: a choice between
+ * equivalent evaluations of the same update).  For the problem given (shapes,
+ * rank or core sizes, beta, precision and L of x, model and opts;
+ * opts->cache_pq is ignored), runs one untimed and then `reps` timed outer
+ * iterations of each variant, each from a device copy of the model's
+ * parameters, so the caller's model is left as it was.  The variants:
+ *   - beta != 1: P~ / Q~ cached (cache_pq = 1) or recomputed (0);
+ *   - dense CP of order 3 at beta != 1: modes 1 and 2 of a sweep from one V
+ *     pass (V = P~ x3 chi(C), kept for mode 2) or from a pass each;
+ *   - dense Tucker of order 3: at most 128, 64 or 256 pair groups (partial
+ *     slots) in the mode-3 pass.
+ * The fastest is stored in the context's autotune table.  An entry fixes the
+ * launch shapes (the last two choices) of every J-CoMM call on a problem with
+ * the same key in this context, single, batched or allocation-free, and its
+ * cache choice for calls with cache_pq = COMM_CACHE_AUTO; a call with an
+ * explicit cache_pq and the entry's cache choice gives bitwise the AUTO
+ * result.  Different choices change only the order of float32 sums.  Cache
+ * variants that cannot run (workspace limit) are skipped.  A problem with a
+ * single variant (CP at beta = 1, orders 4 and 5 at beta = 1) records the
+ * defaults without timing.
  *   reps     1 to 1000.
- *   choice   if not NULL, receives the recorded choice (0 or 1).
- *   ms       if not NULL, receives ms[0] (recompute) and ms[1] (cache), the
- *            mean time of one outer iteration in milliseconds, NaN when not
- *            run.
- * The call allocates a copy of the parameters, may grow the workspace to hold
- * the cache, synchronises `stream`, and drops the cached graph of the batched
- * entry point.  Errors as for comm_jcomm_outer. */
+ *   choice   if not NULL, receives the recorded cache choice (0 or 1).
+ *   ms       if not NULL, receives ms[0] and ms[1], the mean time of one outer
+ *            iteration in milliseconds of the fastest variant that recomputes
+ *            (0) and that caches (1), NaN when none ran.
+ * The call allocates a copy of the parameters, may grow the workspace to the
+ * largest variant's, synchronises `stream`, and drops the cached graph of the
+ * batched entry point.  Errors as for comm_jcomm_outer. */
 int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts, int reps,
                     int* choice, double* ms, void* stream);
+
+/* What the autotune table holds for a problem (the key as for
+ * comm_tune_jcomm; buffer pointers are not read).  found = 0: no entry, and
+ * the other fields give the defaults a call would run with. */
+typedef struct {
+  int found;      /* 1 if comm_tune_jcomm recorded this problem */
+  int cache_pq;   /* the recorded cache choice (0 without an entry) */
+  int wshare;     /* dense CP of order 3 at beta != 1: 1 = modes 1 and 2 from one V pass; -1 otherwise */
+  int tk_groups;  /* dense Tucker of order 3: pair-group cap of the mode-3 pass; 0 otherwise */
+  int variants;   /* variants timed for the entry (0: untimed defaults) */
+  double ms;      /* mean time of one outer iteration of the recorded variant (NaN if untimed) */
+} comm_tune_entry;
+
+int comm_tune_lookup(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts,
+                     comm_tune_entry* out);
+
+/* Record a table entry directly (a choice timed earlier, in another process,
+ * or fixed by the caller); the same effect on later calls as an entry that
+ * comm_tune_jcomm recorded.  Read from `entry`: cache_pq (0 or 1; 0 at
+ * beta = 1), wshare (-1 = by precision, or 0 / 1 for dense CP of order 3 at
+ * beta != 1; -1 otherwise) and tk_groups (0 = 128, or 1 to 1024 for dense
+ * Tucker of order 3; 0 otherwise); the other fields are ignored.  Buffer
+ * pointers are not read.  Synchronises `stream` and the batched entry
+ * point's streams, and drops its cached graph.  COMM_EINVAL on a field
+ * outside these ranges (the table is then unchanged). */
+int comm_tune_set(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts,
+                  const comm_tune_entry* entry, void* stream);
 
 /* Message of the last error raised on this thread (never NULL). */
 const char* comm_last_error(void);
@@ -212,8 +249,10 @@ const char* comm_last_error(void);
  * arguments).  `op` is 0 = cp_update / tucker_update, 1 = jcomm_outer,
  * 2 = beta_objective.  Only shapes, model kind, rank / core sizes and options
  * are read; buffer pointers may be NULL (a server sizes requests before
- * loading them).  cache_pq = COMM_CACHE_AUTO is counted as 1, the larger need
- * (there is no context, hence no autotune table, to resolve it). */
+ * loading them).  There is no context, hence no autotune table, so the
+ * largest need over its choices is returned: cache_pq = COMM_CACHE_AUTO
+ * counts as 1, CP J-CoMM at beta != 1 with the V pass kept for mode 2,
+ * Tucker J-CoMM with 256 mode-3 pair groups. */
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op);
 
 /* Measurement hooks.  While enabled, the context records a pair of HIP events

@@ -36,7 +36,7 @@ EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_by
             "comm_jcomm_outer_batched", "comm_coo_plan_create", "comm_coo_plan_destroy",
             "comm_cp_jcomm_outer_coo_plan", "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap",
             "comm_cp_update_coo", "comm_beta_objective_coo", "comm_tucker_update_coo",
-            "comm_tucker_jcomm_outer_coo", "comm_check", "comm_tune_jcomm"]
+            "comm_tucker_jcomm_outer_coo", "comm_check", "comm_tune_jcomm", "comm_tune_lookup", "comm_tune_set"]
 
 
 class CommError(RuntimeError):
@@ -71,6 +71,11 @@ class Coo(ctypes.Structure):
 
 class Extrap(ctypes.Structure):
     _fields_ = [("alpha_nes", ctypes.c_double), ("c", ctypes.c_double), ("delta", ctypes.c_double)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("found", ctypes.c_int), ("cache_pq", ctypes.c_int), ("wshare", ctypes.c_int),
+                ("tk_groups", ctypes.c_int), ("variants", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -127,6 +132,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.comm_check.argtypes = [ctypes.c_void_p]
     lib.comm_tune_jcomm.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), ctypes.c_int, P(ctypes.c_int),
                                     P(ctypes.c_double), ctypes.c_void_p]
+    lib.comm_tune_lookup.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), P(TuneEntry)]
+    lib.comm_tune_set.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), P(TuneEntry), ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
@@ -134,7 +141,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan",
                  "comm_bcomm_sweep_extrap", "comm_jcomm_outer_extrap", "comm_cp_update_coo",
                  "comm_beta_objective_coo", "comm_tucker_update_coo", "comm_tucker_jcomm_outer_coo", "comm_check",
-                 "comm_tune_jcomm"]:
+                 "comm_tune_jcomm", "comm_tune_lookup", "comm_tune_set"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -421,17 +428,44 @@ class Context:
 
     def tune_jcomm(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
                    eps_x: Optional[float] = None, precision: str = "fp32", reps: int = 3, stream=None) -> dict:
-        """Time a J-CoMM outer iteration with and without the P~/Q~ cache on copies
-        of the parameters and record the faster in the context's autotune table,
-        which ``cache_pq="auto"`` calls on the same problem use.  Returns
-        ``{"cache_pq": 0 or 1, "ms_recompute": t0, "ms_cache": t1}`` (NaN when a
-        variant was not run)."""
+        """Time the equivalent evaluations of a J-CoMM outer iteration (P~/Q~
+        cached or recomputed; CP: modes 1 and 2 from one V pass or a pass each;
+        Tucker: the mode-3 pair-group cap) on copies of the parameters and
+        record the fastest in the context's autotune table.  The entry fixes
+        the launch shapes of every J-CoMM call on the same problem, and the
+        cache choice of ``cache_pq="auto"`` calls.  Returns ``{"cache_pq",
+        "ms_recompute", "ms_cache"}`` (the fastest time of each cache choice,
+        NaN when none ran) merged with :meth:`tune_entry`'s fields."""
         d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, False, precision)
         choice = ctypes.c_int(-1)
         ms = (ctypes.c_double * 2)()
         _check(self._lib.comm_tune_jcomm(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), int(reps),
                                          ctypes.byref(choice), ms, _stream(stream)))
-        return {"cache_pq": choice.value, "ms_recompute": ms[0], "ms_cache": ms[1]}
+        out = self.tune_entry(X, factors, core=core, beta=beta, L=L, eps=eps, eps_x=eps_x, precision=precision)
+        out.update({"cache_pq": choice.value, "ms_recompute": ms[0], "ms_cache": ms[1]})
+        return out
+
+    def tune_entry(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
+                   eps_x: Optional[float] = None, precision: str = "fp32") -> dict:
+        """The autotune table's entry for a problem (``comm_tune_lookup``):
+        ``{"found", "cache_pq", "wshare", "tk_groups", "variants", "ms"}``;
+        without an entry, the defaults a call runs with."""
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, False, precision)
+        e = TuneEntry()
+        _check(self._lib.comm_tune_lookup(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o),
+                                          ctypes.byref(e)))
+        return {"found": bool(e.found), "cache_pq": e.cache_pq, "wshare": e.wshare, "tk_groups": e.tk_groups,
+                "variants": e.variants, "ms": e.ms}
+
+    def tune_set(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
+                 eps_x: Optional[float] = None, precision: str = "fp32", cache_pq: int = 0, wshare: int = -1,
+                 tk_groups: int = 0, stream=None) -> None:
+        """Record an autotune table entry directly (``comm_tune_set``)."""
+        d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, False, precision)
+        e = TuneEntry()
+        e.cache_pq, e.wshare, e.tk_groups = int(cache_pq), int(wshare), int(tk_groups)
+        _check(self._lib.comm_tune_set(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), ctypes.byref(e),
+                                       _stream(stream)))
 
     def jcomm_outer_batched(self, batch: "Batch", graph: bool = False, stream=None) -> None:
         """One J-CoMM outer iteration for every problem of `batch`, each with the

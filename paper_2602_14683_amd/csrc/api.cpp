@@ -125,6 +125,11 @@ struct CpWs {
   size_t bytes;
 };
 
+bool cp_wshare(const comm_opts* o, const TuneChoice& pick) {
+  if (o->beta == 1.0) return false;
+  return pick.wshare >= 0 ? pick.wshare != 0 : o->precision != COMM_BF16;
+}
+
 CpWs cp_layout(const comm_dense* x, char* base, bool cache, bool vkeep = false) {
   CpWs w = {};
   for (int n = 0; n < 3; ++n) w.dims[n] = (int)x->dims[n];
@@ -292,8 +297,9 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
               const NumHook* hook = nullptr) {
   const bool kl = o->beta == 1.0;
   const bool cache = !kl && o->cache_pq;
-  // the mode-1 pass keeps V for mode 2 (float32 tiles; see own_pass below)
-  const bool vkeep = !kl && o->precision != COMM_BF16;
+  // the mode-1 pass keeps V for mode 2 (by default with float32 tiles; see
+  // own_pass below), unless the autotune table chose otherwise
+  const bool vkeep = cp_wshare(o, ctx->pick);
   CpWs w = cp_layout(x, nullptr, cache, vkeep);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
@@ -1377,10 +1383,10 @@ int jcomm_check(const comm_dense* x, const comm_model* model, const comm_opts* o
   return fail(COMM_EINVAL, "model kind %d", model->kind);
 }
 
-size_t jcomm_ws_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts) {
-  if (model->kind == COMM_CP)
-    return cp_ws_bytes(x, opts->beta != 1.0 && opts->cache_pq, opts->beta != 1.0 && opts->precision != COMM_BF16);
-  return tucker_workspace_bytes(x, model, opts, 1);
+size_t jcomm_ws_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts,
+                      const TuneChoice& pick = TuneChoice()) {
+  if (model->kind == COMM_CP) return cp_ws_bytes(x, opts->beta != 1.0 && opts->cache_pq, cp_wshare(opts, pick));
+  return tucker_workspace_bytes(x, model, opts, 1, pick.tk_groups);
 }
 
 // Key of the autotune table: what fixes a J-CoMM outer iteration's launch
@@ -1401,32 +1407,84 @@ std::vector<int64_t> tune_key(const comm_dense* x, const comm_model* m, const co
   return k;
 }
 
+// What tune_key reads, checked without the buffers (the table calls take a
+// problem's key only).
+int tune_key_check(const comm_dense* x, const comm_model* m, const comm_opts* o) {
+  int rc = check_opts(o, true);
+  if (!rc) rc = check_dense_shape(x);
+  if (rc) return rc;
+  if (!m) return fail(COMM_EINVAL, "model is NULL");
+  if (m->kind == COMM_CP) {
+    if (m->rank < 1) return fail(COMM_EINVAL, "rank = %d", m->rank);
+  } else if (m->kind == COMM_TUCKER) {
+    for (int n = 0; n < x->ndim; ++n)
+      if (m->core_dims[n] < 1) return fail(COMM_EINVAL, "core_dims[%d] = %lld", n, (long long)m->core_dims[n]);
+  } else {
+    return fail(COMM_EINVAL, "model kind %d", m->kind);
+  }
+  return COMM_OK;
+}
+
+// The equivalent evaluations the tuner times for a problem, defaults first:
+// the P~/Q~ cache or its recomputation (beta != 1); dense CP of order 3 at
+// beta != 1: modes 1 and 2 from one V pass or a pass each; dense Tucker of
+// order 3: the mode-3 pass's pair-group cap.  One entry means nothing to time.
+std::vector<TuneChoice> tune_variants(const comm_dense* x, const comm_model* model, const comm_opts* o) {
+  std::vector<int> caches = o->beta != 1.0 ? std::vector<int>{1, 0} : std::vector<int>{0};
+  std::vector<TuneChoice> out;
+  for (int c : caches) {
+    TuneChoice t;
+    t.cache_pq = c;
+    if (model->kind == COMM_CP && x->ndim == 3 && o->beta != 1.0) {
+      const int def = o->precision != COMM_BF16;
+      for (int ws : {def, 1 - def}) {
+        t.wshare = ws;
+        out.push_back(t);
+      }
+    } else if (model->kind == COMM_TUCKER && x->ndim == 3) {
+      for (int g : {kTkGroupsDefault, 64, kTkGroupsMax}) {
+        t.tk_groups = g;
+        out.push_back(t);
+      }
+    } else {
+      out.push_back(t);
+    }
+  }
+  return out;
+}
+
 int jcomm_variant(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* o, double* obj,
                   hipStream_t st) {
   return model->kind == COMM_CP ? cp_jcomm(ctx, x, model, o, obj, st) : tucker_jcomm(ctx, x, model, o, obj, st);
 }
 
-// cache_pq = COMM_CACHE_AUTO takes the choice the table holds for the problem;
-// when it holds none, the cache if the workspace it needs is within the
-// context's limit, else recomputation.
-comm_opts resolve_cache(const comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts) {
-  comm_opts o = *opts;
-  if (o.cache_pq == COMM_CACHE_AUTO) {
-    const auto it = ctx->tune.find(tune_key(x, model, opts));
+// The options and launch shapes a call runs with: a recorded table entry
+// fixes the shapes, and the cache choice when cache_pq = COMM_CACHE_AUTO;
+// without an entry, AUTO takes the cache if its workspace is within the
+// context's limit (`limit`, 0 = none), and recomputation otherwise.
+void resolve(const comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts,
+             size_t limit, comm_opts* o, TuneChoice* pick) {
+  *o = *opts;
+  *pick = TuneChoice();
+  const auto it = ctx->tune.find(tune_key(x, model, opts));
+  if (it != ctx->tune.end()) *pick = it->second;
+  if (o->cache_pq == COMM_CACHE_AUTO) {
     if (it != ctx->tune.end()) {
-      o.cache_pq = it->second;
+      o->cache_pq = it->second.cache_pq;
     } else {
-      o.cache_pq = 1;
-      o.cache_pq = !ctx->limit || jcomm_ws_bytes(x, model, &o) <= ctx->limit ? 1 : 0;
+      o->cache_pq = 1;
+      o->cache_pq = !limit || jcomm_ws_bytes(x, model, o, *pick) <= limit ? 1 : 0;
     }
   }
-  return o;
 }
 
 int jcomm_run(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts, double* obj,
               hipStream_t st) {
-  const comm_opts o = resolve_cache(ctx, x, model, opts);
-  return jcomm_variant(ctx, x, model, &o, obj, st);
+  comm_opts o;
+  resolve(ctx, x, model, opts, ctx->limit, &o, &ctx->pick);
+  const int rc = jcomm_variant(ctx, x, model, &o, obj, st);
+  ctx->pick = TuneChoice();
+  return rc;
 }
 
 // Device copy of a model's parameters for the tuner (freed on scope exit).
@@ -1450,7 +1508,8 @@ constexpr int kBatchStreams = 4;
 struct BatchItem {
   comm_dense x;
   comm_model m;
-  comm_opts o;
+  comm_opts o;      // resolved (no COMM_CACHE_AUTO)
+  TuneChoice pick;  // resolved launch shapes
   double* obj;
   size_t off, bytes;
 };
@@ -1529,6 +1588,8 @@ std::vector<int64_t> batch_key(const std::vector<BatchItem>& items, const char* 
     word(it.o.inner_sweeps);
     word(it.o.precision);
     word(it.o.cache_pq);
+    word(it.pick.wshare);
+    word(it.pick.tk_groups);
     word((int64_t)(intptr_t)it.obj);
     word((int64_t)it.off);
   }
@@ -1547,7 +1608,8 @@ int batch_issue(comm_ctx* ctx, std::vector<BatchItem>& items, hipStream_t origin
     sub.ws = ctx->bws + it.off;
     sub.ws_bytes = it.bytes;
     sub.limit = it.bytes;  // a slice never grows: a larger need is an error, not an allocation
-    // it.o holds the resolved cache choice the slice was sized for
+    // it.o and it.pick hold the resolved choices the slice was sized for
+    sub.pick = it.pick;
     int rc = jcomm_variant(&sub, &it.x, &it.m, &it.o, it.obj, ctx->bstreams[p % S]);
     if (rc) return rc;
   }
@@ -1572,10 +1634,10 @@ int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags
     BatchItem& it = items[(size_t)p];
     it.x = *q.x;
     it.m = *q.model;
-    // the cache choice is resolved once here: the slices are sized for it
-    it.o = resolve_cache(ctx, q.x, q.model, q.opts);
+    // the choices are resolved once here: the slices are sized for them
+    resolve(ctx, q.x, q.model, q.opts, ctx->limit, &it.o, &it.pick);
     it.obj = q.obj_ref_dev;
-    it.bytes = (jcomm_ws_bytes(q.x, q.model, &it.o) + 255) & ~size_t(255);
+    it.bytes = (jcomm_ws_bytes(q.x, q.model, &it.o, it.pick) + 255) & ~size_t(255);
     total += it.bytes;
   }
   if (count == 0) return COMM_OK;
@@ -1594,7 +1656,7 @@ int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags
     if (pick < 0) break;
     BatchItem& it = items[(size_t)pick];
     it.o.cache_pq = 0;
-    const size_t nb = (jcomm_ws_bytes(&it.x, &it.m, &it.o) + 255) & ~size_t(255);
+    const size_t nb = (jcomm_ws_bytes(&it.x, &it.m, &it.o, it.pick) + 255) & ~size_t(255);
     total -= it.bytes - nb;
     it.bytes = nb;
   }
@@ -1746,9 +1808,9 @@ int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
 
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op) {
   if (check_dense_shape(x) || !model || !opts) return 0;
-  if (model->kind == COMM_CP)
-    return cp_ws_bytes(x, op == 1 && opts->beta != 1.0 && opts->cache_pq,
-                       op == 1 && opts->beta != 1.0 && opts->precision != COMM_BF16);
+  // the largest need over the choices an autotune table can make: W-sharing
+  // for CP, the most mode-3 pair groups for Tucker
+  if (model->kind == COMM_CP) return cp_ws_bytes(x, op == 1 && opts->beta != 1.0 && opts->cache_pq, op == 1 && opts->beta != 1.0);
   if (x->ndim > 3) {
     int64_t rows = 1;
     for (int n = 0; n < x->ndim - 1; ++n) rows *= x->dims[n];
@@ -1756,7 +1818,7 @@ size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const 
   }
   for (int n = 0; n < x->ndim; ++n)
     if (model->core_dims[n] < 1 || model->core_dims[n] > kRP) return 0;
-  return tucker_workspace_bytes(x, model, opts, op);
+  return tucker_workspace_bytes(x, model, opts, op, kTkGroupsMax);
 }
 
 int comm_cp_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int block, const comm_opts* opts,
@@ -1801,13 +1863,12 @@ int comm_jcomm_outer_noalloc(comm_ctx* ctx, const comm_dense* x, comm_model* mod
     if (opts->check_inputs)
       return fail(COMM_EINVAL, "check_inputs needs a device flag of its own: not available without allocation");
     if (!ctx->noalloc_ws) return fail(COMM_EHIP, "no fixed workspace on device %d", ctx->device);
-    comm_opts o = *opts;
-    if (o.cache_pq == COMM_CACHE_AUTO) {
-      const auto it = ctx->tune.find(tune_key(x, model, opts));
-      o.cache_pq = it != ctx->tune.end() ? it->second : 1;
-      if (o.cache_pq && jcomm_ws_bytes(x, model, &o) > kNoallocBytes) o.cache_pq = 0;
-    }
-    const size_t need = jcomm_ws_bytes(x, model, &o);
+    comm_opts o;
+    TuneChoice pick;
+    resolve(ctx, x, model, opts, kNoallocBytes, &o, &pick);
+    if (opts->cache_pq == COMM_CACHE_AUTO && o.cache_pq && jcomm_ws_bytes(x, model, &o, pick) > kNoallocBytes)
+      o.cache_pq = 0;
+    const size_t need = jcomm_ws_bytes(x, model, &o, pick);
     if (need > kNoallocBytes)
       return fail(COMM_ENOMEM, "workspace of %zu bytes exceeds the %zu-byte fixed array of the allocation-free call",
                   need, kNoallocBytes);
@@ -1820,6 +1881,7 @@ int comm_jcomm_outer_noalloc(comm_ctx* ctx, const comm_dense* x, comm_model* mod
     sub.ws = ctx->noalloc_ws;
     sub.ws_bytes = kNoallocBytes;
     sub.limit = kNoallocBytes;
+    sub.pick = pick;
     rc = jcomm_variant(&sub, x, model, &o, obj_ref_dev, st);
     ctx->last_stream = st;
     return rc;
@@ -1836,9 +1898,11 @@ int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = input_check_dense(ctx, x, model, opts, st))) return rc;
-    double t[2] = {NAN, NAN};  // per outer iteration: [0] recompute, [1] cache
-    int best = 0;
-    if (opts->beta != 1.0) {
+    const std::vector<TuneChoice> vars = tune_variants(x, model, opts);
+    double t[2] = {NAN, NAN};  // per outer iteration, fastest of each cache choice: [0] recompute, [1] cache
+    TuneChoice best = vars[0];
+    best.variants = 0;
+    if (vars.size() > 1) {
       // the variants run on a copy of the parameters; the caller's are not touched
       comm_model sm = *model;
       size_t count[COMM_MAX_NDIM + 1] = {};
@@ -1872,13 +1936,21 @@ int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
                                  hipMemcpyDeviceToDevice, st));
         return COMM_OK;
       };
-      for (int v = 1; v >= 0; --v) {
+      // the variants run with the context's pick set; it is cleared on every exit
+      struct PickReset {
+        comm_ctx* c;
+        ~PickReset() { c->pick = TuneChoice(); }
+      } pick_reset{ctx};
+      best.ms = INFINITY;
+      int timed = 0;
+      for (const TuneChoice& v : vars) {
         comm_opts o = *opts;
-        o.cache_pq = v;
+        o.cache_pq = v.cache_pq;
+        ctx->pick = v;
         if ((rc = reset())) return rc;
         // one untimed iteration (workspace growth, first touch), then reps timed
         rc = jcomm_variant(ctx, x, &sm, &o, nullptr, st);
-        if (rc == COMM_ENOMEM && v == 1) continue;  // no room for the cache: recompute wins
+        if (rc == COMM_ENOMEM && v.cache_pq) continue;  // no room for the cache
         if (rc) return rc;
         if ((rc = reset())) return rc;
         HIP_TRY(hipEventRecord(sc.ev[0], st));
@@ -1888,21 +1960,82 @@ int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
         HIP_TRY(hipEventSynchronize(sc.ev[1]));
         float el = 0.0f;
         HIP_TRY(hipEventElapsedTime(&el, sc.ev[0], sc.ev[1]));
-        t[v] = (double)el / reps;
+        const double per = (double)el / reps;
+        ++timed;
+        if (std::isnan(t[v.cache_pq]) || per < t[v.cache_pq]) t[v.cache_pq] = per;
+        // ties go to the earlier variant (the list starts with the defaults)
+        if (per < best.ms) {
+          best = v;
+          best.ms = per;
+        }
       }
       HIP_TRY(hipStreamSynchronize(st));
-      best = !std::isnan(t[1]) && t[1] <= t[0] ? 1 : 0;
+      best.variants = timed;
     }
     ctx->tune[tune_key(x, model, opts)] = best;
-    // a captured batch may have resolved COMM_CACHE_AUTO with the old table;
-    // its last replay ends before the graph goes
+    // a captured batch may have resolved its options with the old table; its
+    // last replay ends before the graph goes
     if ((rc = batch_sync_all(ctx, st))) return rc;
     if ((rc = batch_drop_graph(ctx))) return rc;
-    if (choice) *choice = best;
+    if (choice) *choice = best.cache_pq;
     if (ms) {
       ms[0] = t[0];
       ms[1] = t[1];
     }
+    ctx->last_stream = st;
+    return COMM_OK;
+  });
+}
+
+int comm_tune_lookup(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts,
+                     comm_tune_entry* out) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (!out) return fail(COMM_EINVAL, "out is NULL");
+    int rc = tune_key_check(x, model, opts);
+    if (rc) return rc;
+    const auto it = ctx->tune.find(tune_key(x, model, opts));
+    *out = comm_tune_entry{};
+    out->found = it != ctx->tune.end();
+    const TuneChoice c = out->found ? it->second : TuneChoice();
+    out->cache_pq = c.cache_pq;
+    out->wshare = model->kind == COMM_CP && x->ndim == 3 && opts->beta != 1.0 ? (int)cp_wshare(opts, c) : -1;
+    out->tk_groups = model->kind == COMM_TUCKER && x->ndim == 3 ? (c.tk_groups ? c.tk_groups : kTkGroupsDefault) : 0;
+    out->variants = out->found ? c.variants : 0;
+    out->ms = out->found && c.variants > 0 ? c.ms : NAN;
+    return COMM_OK;
+  });
+}
+
+int comm_tune_set(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts,
+                  const comm_tune_entry* entry, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
+    if (!entry) return fail(COMM_EINVAL, "entry is NULL");
+    int rc = tune_key_check(x, model, opts);
+    if (rc) return rc;
+    const bool cp3 = model->kind == COMM_CP && x->ndim == 3 && opts->beta != 1.0;
+    const bool tk3 = model->kind == COMM_TUCKER && x->ndim == 3;
+    if (entry->cache_pq != 0 && entry->cache_pq != 1)
+      return fail(COMM_EINVAL, "cache_pq = %d (0 or 1)", entry->cache_pq);
+    if (entry->cache_pq && opts->beta == 1.0) return fail(COMM_EINVAL, "cache_pq = 1 at beta = 1 (nothing to cache)");
+    if (entry->wshare < -1 || entry->wshare > 1 || (entry->wshare != -1 && !cp3))
+      return fail(COMM_EINVAL, "wshare = %d (-1, or 0 / 1 for dense CP of order 3 at beta != 1)", entry->wshare);
+    if (entry->tk_groups < 0 || entry->tk_groups > kTkGroupsLimit || (entry->tk_groups && !tk3))
+      return fail(COMM_EINVAL, "tk_groups = %d (0, or 1 to %d for dense Tucker of order 3)", entry->tk_groups,
+                  kTkGroupsLimit);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    TuneChoice c;
+    c.cache_pq = entry->cache_pq;
+    c.wshare = entry->wshare;
+    c.tk_groups = entry->tk_groups;
+    c.variants = 0;
+    c.ms = NAN;
+    // a captured batch may have resolved its options with the old entry
+    if ((rc = batch_sync_all(ctx, st))) return rc;
+    if ((rc = batch_drop_graph(ctx))) return rc;
+    ctx->tune[tune_key(x, model, opts)] = c;
     ctx->last_stream = st;
     return COMM_OK;
   });

@@ -15,6 +15,20 @@
 #include "../../include/comm.h"
 #include "kernels.h"
 
+// One entry of the autotune table (comm_tune_jcomm): which of the equivalent
+// evaluations of a J-CoMM outer iteration runs.  A recorded entry fixes the
+// launch shapes of every J-CoMM call on that problem in the context; the cache
+// choice applies to calls with cache_pq = COMM_CACHE_AUTO.
+constexpr int kTkGroupsDefault = 128, kTkGroupsMax = 256, kTkGroupsLimit = 1024;
+struct TuneChoice {
+  int cache_pq = 0;    // stream the P~/Q~ cache (1) or recompute it from X (0)
+  int wshare = -1;     // dense CP at beta != 1: modes 1 and 2 from one V pass (1) or a pass each (0);
+                       // -1: by the tile precision (float32 shares, bf16 does not)
+  int tk_groups = 0;   // dense order-3 Tucker mode-3 pass: at most this many pair groups (0: 128)
+  int variants = 0;    // table entries: variants timed (0: the defaults, untimed)
+  double ms = 0.0;     // table entries: mean time of one outer iteration of this variant
+};
+
 struct comm_ctx {
   int device = 0;
   size_t limit = 0;
@@ -22,8 +36,10 @@ struct comm_ctx {
   size_t ws_bytes = 0;
   hipStream_t last_stream = nullptr;
   float* aux = nullptr;     // small device scratch that outlives workspace growth (extrapolation weight)
-  // autotune table: J-CoMM problem key -> measured faster cache_pq (0 or 1)
-  std::map<std::vector<int64_t>, int> tune;
+  // autotune table: J-CoMM problem key -> the measured fastest of its
+  // equivalent evaluations; `pick` is the choice of the call in progress
+  std::map<std::vector<int64_t>, TuneChoice> tune;
+  TuneChoice pick;
   // measurement: event pairs around every fused dense pass launch
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

@@ -382,7 +382,7 @@ hipError_t launch_tk_v(const TkPassArgs& a, int beta_class, int mode, bool obj, 
 
 // Mode-3 pass: m3n[g][k][c] = sum over pair group g of P[(i,j)][k] T2n[(i,j)][c]
 // (and m3d with Q and T2d when sets = 2).
-void tk_m3_tiling(int I, int J, int* tpw, int* npg);
+void tk_m3_tiling(int I, int J, int* tpw, int* npg, int groups = 0);
 hipError_t launch_tk_m3(const TkPassArgs& a, int beta_class, int mode, int sets, hipStream_t s);
 
 // Small strided GEMMs on the matrix cores, split-K partial slots (fixed order,

@@ -7,7 +7,7 @@
 struct comm_ctx;
 
 int tucker_check_model(const comm_model* m, const comm_dense* x);
-size_t tucker_workspace_bytes(const comm_dense* x, const comm_model* m, const comm_opts* o, int op);
+size_t tucker_workspace_bytes(const comm_dense* x, const comm_model* m, const comm_opts* o, int op, int groups = 0);
 int tucker_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st);
 int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, double* obj, hipStream_t st);
 int tucker_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const comm_opts* o, double* out,

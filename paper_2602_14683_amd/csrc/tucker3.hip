@@ -21,11 +21,13 @@ namespace comm {
 
 int64_t tk_v_workgroups(int I, int J) { return ((int64_t)I * J + kTkPairsPerWg - 1) / kTkPairsPerWg; }
 
-// Mode-3 pass tiling: at most 128 pair groups (partial slots), each of 4
-// waves x tpw pair tiles of 32.
-void tk_m3_tiling(int I, int J, int* tpw, int* npg) {
+// Mode-3 pass tiling: at most `groups` pair groups (partial slots; 0 takes
+// kTkGroupsDefault), each of 4 waves x tpw pair tiles of 32.  More groups fill more of the
+// chip per k tile; fewer keep fewer partial slots to reduce.
+void tk_m3_tiling(int I, int J, int* tpw, int* npg, int groups) {
+  const int64_t cap = groups > 0 ? groups : kTkGroupsDefault;
   const int64_t tiles = ((int64_t)I * J + 31) / 32;
-  const int64_t t = std::max<int64_t>(1, (tiles + 4 * 128 - 1) / (4 * 128));
+  const int64_t t = std::max<int64_t>(1, (tiles + 4 * cap - 1) / (4 * cap));
   *tpw = (int)t;
   *npg = (int)((tiles + 4 * t - 1) / (4 * t));
 }
@@ -290,7 +292,7 @@ struct TkWs {
 
 constexpr int kSplitCore = 8, kSplit1 = 8, kSplit2 = 32;
 
-TkWs tk_layout(const comm_dense* x, const comm_model* m, char* base, bool cache) {
+TkWs tk_layout(const comm_dense* x, const comm_model* m, char* base, bool cache, int groups = 0) {
   TkWs w = {};
   for (int n = 0; n < 3; ++n) {
     w.dims[n] = (int)x->dims[n];
@@ -301,7 +303,7 @@ TkWs tk_layout(const comm_dense* x, const comm_model* m, char* base, bool cache)
   const size_t pairs = (size_t)I * J;
   w.Kp = (K + 31) / 32 * 32;
   w.Pp = ((int64_t)pairs + 31) / 32 * 32;
-  tk_m3_tiling(I, J, &w.tpw, &w.npg);
+  tk_m3_tiling(I, J, &w.tpw, &w.npg, groups);
   w.vwgs = tk_v_workgroups(I, J);
   Carve cv;
   cv.base = base;
@@ -658,10 +660,10 @@ int tucker_check_model(const comm_model* m, const comm_dense* x) {
   return COMM_OK;
 }
 
-size_t tucker_workspace_bytes(const comm_dense* x, const comm_model* m, const comm_opts* o, int op) {
+size_t tucker_workspace_bytes(const comm_dense* x, const comm_model* m, const comm_opts* o, int op, int groups) {
   if (x->ndim > 3) return tuckern_workspace_bytes(x, m, o, op);
   const bool cache = op == 1 && o->cache_pq && o->beta != 1.0;
-  return tk_layout(x, m, nullptr, cache).bytes;
+  return tk_layout(x, m, nullptr, cache, op == 1 ? groups : 0).bytes;
 }
 
 int tucker_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, const comm_opts* o, hipStream_t st) {
@@ -699,10 +701,11 @@ int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_o
   if (x->ndim > 3) return tuckern_jcomm(ctx, x, m, o, obj, st);
   const bool kl = o->beta == 1.0;
   const bool cache = o->cache_pq && !kl;
-  TkWs w = tk_layout(x, m, nullptr, cache);
+  const int groups = ctx->pick.tk_groups;
+  TkWs w = tk_layout(x, m, nullptr, cache, groups);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
-  w = tk_layout(x, m, ctx->ws, cache);
+  w = tk_layout(x, m, ctx->ws, cache, groups);
   if ((rc = tk_pad(m, w, w.ref, &w.cur, st))) return rc;
   const TkModel ref = model_of(w, w.ref);
   // the reference model, and so its T2, is fixed for the whole outer iteration

@@ -18,7 +18,7 @@ if not torch.cuda.is_available():
 import paper_2602_14683_amd as comm  # noqa: E402
 from oracle import cp as ocp  # noqa: E402
 from oracle import tucker as otk  # noqa: E402
-from tests.gpu_util import dev, f32  # noqa: E402
+from tests.gpu_util import dev, f32, host64, max_rel  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -228,3 +228,137 @@ def test_batched_auto_fits_the_limit_by_recomputing_the_largest():
             assert objs[q].item() == want[q][2]
     finally:
         small.close()
+
+
+# ------------------------------------------------------------------ variant table entries
+
+@pytest.fixture
+def fresh():
+    c = comm.Context(0)
+    yield c
+    c.close()
+
+
+def test_tuned_entry_cp(fresh):
+    X, init, core = _cp(12)
+    F = [dev(a) for a in init]
+    assert not fresh.tune_entry(dev(X), F, beta=0.5, L=2)["found"]
+    res = fresh.tune_jcomm(dev(X), F, beta=0.5, L=2, reps=2)
+    assert res["found"] and res["variants"] == 4
+    assert res["wshare"] in (0, 1) and res["tk_groups"] == 0
+    assert res["ms"] == min(res["ms_recompute"], res["ms_cache"])
+
+
+@pytest.mark.parametrize("beta,variants", [(0.5, 6), (1.0, 3)])
+def test_tuned_entry_tucker(fresh, beta, variants):
+    X, init, core = _tucker(13)
+    F, G = [dev(a) for a in init], dev(core)
+    res = fresh.tune_jcomm(dev(X), F, core=G, beta=beta, L=2, reps=1)
+    assert res["found"] and res["variants"] == variants
+    assert res["tk_groups"] in (64, 128, 256) and res["wshare"] == -1
+    if beta == 1.0:
+        assert res["cache_pq"] == 0 and math.isnan(res["ms_cache"])
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.5])
+@pytest.mark.parametrize("cache", [0, 1])
+@pytest.mark.parametrize("wshare", [0, 1])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_every_cp_variant_matches_oracle(fresh, beta, cache, wshare, precision):
+    X, init, core = _cp(14, dims=(37, 70, 90), R=32)
+    Xd = dev(X)
+    L = 2 if precision == "fp32" else 1
+    fresh.tune_set(Xd, [dev(a) for a in init], beta=beta, L=L, precision=precision, cache_pq=cache, wshare=wshare)
+    assert fresh.tune_entry(Xd, [dev(a) for a in init], beta=beta, L=L, precision=precision)["wshare"] == wshare
+    F = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fresh.jcomm_outer(Xd, F, beta=beta, L=L, cache_pq="auto", precision=precision, obj_out=obj)
+    torch.cuda.synchronize()
+    want, fref = ocp.jcomm_outer(X, init, beta, L=L, return_ref_obj=True)
+    for a, b in zip(F, want):
+        rel = np.abs(host64(a) - b) / np.abs(b)
+        if precision == "fp32":
+            assert rel.max() < 3e-5  # two sweeps of float32 updates
+        else:
+            # three chained bf16-contraction updates, each within 2 gamma 2^-8
+            # (gamma <= 1 here) of the exact one; typical errors far below
+            assert rel.max() < 3 * 8e-3 and np.median(rel) < 3 * 5e-4
+    assert abs(obj.item() - fref) / fref < (1e-5 if precision == "fp32" else 2e-4)
+
+
+@pytest.mark.parametrize("beta", [0.5, 1.0])
+@pytest.mark.parametrize("cache", [0, 1])
+@pytest.mark.parametrize("groups", [1, 7, 64, 256])
+def test_every_tucker_groups_variant_matches_oracle(fresh, beta, cache, groups):
+    if cache and beta == 1.0:
+        pytest.skip("beta = 1 never caches P~ / Q~")
+    X, init, core = _tucker(15, dims=(45, 60, 70), J=(8, 6, 5))
+    Xd = dev(X)
+    fresh.tune_set(Xd, [dev(a) for a in init], core=dev(core), beta=beta, L=2, cache_pq=cache, tk_groups=groups)
+    F, G = [dev(a) for a in init], dev(core)
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fresh.jcomm_outer(Xd, F, core=G, beta=beta, L=2, cache_pq="auto", obj_out=obj)
+    torch.cuda.synchronize()
+    wc, wf, fref = otk.jcomm_outer(X, core, init, beta, L=2, return_ref_obj=True)
+    assert max_rel(host64(G), wc) < 1e-4
+    for a, b in zip(F, wf):
+        assert max_rel(host64(a), b) < 1e-4
+    assert abs(obj.item() - fref) / fref < 1e-5
+
+
+def test_entry_fixes_shapes_of_explicit_calls(fresh):
+    # W-sharing replaces the mode-2 pass by a fold: fewer fused pass launches
+    X, init, core = _cp(16)
+    Xd = dev(X)
+    n = {}
+    for ws in (0, 1):
+        fresh.tune_set(Xd, [dev(a) for a in init], beta=0.5, L=2, cache_pq=1, wshare=ws)
+        n[ws] = _launches(fresh, X, init, core, 0.5, False)
+    assert n[1] < n[0]
+
+
+@pytest.mark.parametrize("kind", ["cp", "tucker"])
+def test_batched_and_noalloc_follow_the_entry(fresh, kind):
+    X, init, core = (_cp(17) if kind == "cp" else _tucker(17))
+    Xd = dev(X)
+    Fd = [dev(a) for a in init]
+    if kind == "cp":
+        fresh.tune_set(Xd, Fd, beta=0.5, L=2, cache_pq=0, wshare=0)
+    else:
+        fresh.tune_set(Xd, Fd, core=dev(core), beta=0.5, L=2, cache_pq=0, tk_groups=64)
+    single = _run(fresh, X, init, core, 0.5, "auto")
+    F = [dev(a) for a in init]
+    G = dev(core) if core is not None else None
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fresh.jcomm_outer_batched(comm.Batch([{"X": Xd, "factors": F, "core": G, "beta": 0.5, "L": 2,
+                                           "cache_pq": "auto", "obj_out": obj}]), graph=True)
+    torch.cuda.synchronize()
+    for a, b in zip(single[0], [f.cpu().numpy() for f in F]):
+        assert np.array_equal(a, b)
+    assert obj.item() == single[2]
+    F2 = [dev(a) for a in init]
+    G2 = dev(core) if core is not None else None
+    obj2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fresh.jcomm_outer_noalloc(Xd, F2, core=G2, beta=0.5, L=2, cache_pq="auto", obj_out=obj2)
+    torch.cuda.synchronize()
+    for a, b in zip(single[0], [f.cpu().numpy() for f in F2]):
+        assert np.array_equal(a, b)
+    if G is not None:
+        assert np.array_equal(single[1], G.cpu().numpy()) and np.array_equal(single[1], G2.cpu().numpy())
+    assert obj2.item() == single[2]
+
+
+@pytest.mark.parametrize("fields", [{"wshare": 1, "kind": "tucker"}, {"tk_groups": 64, "kind": "cp"},
+                                    {"tk_groups": 2000, "kind": "tucker"}, {"cache_pq": 2, "kind": "cp"},
+                                    {"wshare": 2, "kind": "cp"}, {"cache_pq": 1, "beta": 1.0, "kind": "cp"},
+                                    {"wshare": 1, "beta": 1.0, "kind": "cp"}])
+def test_tune_set_refuses_bad_fields(fresh, fields):
+    f = dict(fields)
+    kind = f.pop("kind")
+    beta = f.pop("beta", 0.5)
+    X, init, core = (_cp(18) if kind == "cp" else _tucker(18))
+    Xd, Fd = dev(X), [dev(a) for a in init]
+    Gd = dev(core) if core is not None else None
+    with pytest.raises(comm.CommError):
+        fresh.tune_set(Xd, Fd, core=Gd, beta=beta, L=2, **f)
+    assert not fresh.tune_entry(Xd, Fd, core=Gd, beta=beta, L=2)["found"]
