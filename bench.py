@@ -214,6 +214,43 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
 
 
+def rank16(ctx, steps):
+    """256^3 at rank 16 (beta = 1, L = 5, objective on): the 16-wide pass tiles
+    (the default at rank <= 16) against the 32-wide ones (an autotune table
+    entry on a context of its own), J-CoMM rate and pass time each."""
+    import numpy as np
+    import torch
+    import paper_2602_14683_amd as comm
+    import workloads
+
+    R = 16
+    d = workloads.cp_dense(0, dims=(256, 256, 256), rank=R)
+    X = torch.from_numpy(d.X.astype(np.float32)).cuda()
+    init = [torch.from_numpy(a.astype(np.float32)).cuda() for a in d.init]
+    flops = 6.0 * R * 256 ** 3
+    out = {"workload": "jcomm_cp_dense_256x256x256_r16_beta1_L5_obj"}
+    for tile in (0, 32):
+        c = comm.Context(0)
+        try:
+            fac = [a.clone() for a in init]
+            if tile:
+                c.tune_set(X, fac, beta=1.0, L=5, cp_tile=tile)
+            trace = torch.zeros(steps + 4, dtype=torch.float64, device="cuda")
+
+            def step(t):
+                c.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=trace[t:t + 1])
+
+            elapsed, kernel_ms, launches = timed_loop(c, step, 3, steps)
+            avg_us = kernel_ms / max(launches, 1) * 1e3
+            tfl = flops / (avg_us * 1e-6) / 1e12
+            out["tiles_16" if tile == 0 else "tiles_32"] = {
+                "outer_it_s": round(steps / elapsed, 2), "pass_avg_us": round(avg_us, 2),
+                "algorithmic_tflops": round(tfl, 2), "frac_fp32_mfma_peak": round(tfl / PEAK_FP32_MFMA_TFLOPS, 4)}
+        finally:
+            c.close()
+    return out
+
+
 def timed_loop(ctx, step, warmup, steps):
     """Warm up, then time `steps` calls of step(t) between synchronisations;
     the library records HIP events around every pass-kernel launch on the
@@ -294,6 +331,7 @@ def run_cp(args, ctx):
         out["same_gpu_comparisons"]["jcomm_beta1_L5_no_objective_it_s"] = objective_off_rate(
             ctx, X, init32, args.comparison_steps)
         out["control_512"] = control_512(ctx, 20)
+        out["rank16"] = rank16(ctx, args.comparison_steps)
     if not args.no_cpu_baseline:
         X64 = X32.astype(np.float64)
         init64 = [a.astype(np.float64) for a in init32]

@@ -191,6 +191,8 @@ int comm_check(comm_ctx* ctx);
  * iterations of each variant, each from a device copy of the model's
  * parameters, so the caller's model is left as it was.  The variants:
  *   - beta != 1: P~ / Q~ cached (cache_pq = 1) or recomputed (0);
+ *   - dense CP at rank <= 16 with float32 tiles: 16-wide (16x16x4 matrix-core
+ *     shapes) or 32-wide pass tiles (rank padded to 32);
  *   - dense CP of order 3 at beta != 1: modes 1 and 2 of a sweep from one V
  *     pass (V = P~ x3 chi(C), kept for mode 2) or from a pass each;
  *   - dense Tucker of order 3: at most 128, 64 or 256 pair groups (partial
@@ -223,6 +225,7 @@ typedef struct {
   int cache_pq;   /* the recorded cache choice (0 without an entry) */
   int wshare;     /* dense CP of order 3 at beta != 1: 1 = modes 1 and 2 from one V pass; -1 otherwise */
   int tk_groups;  /* dense Tucker of order 3: pair-group cap of the mode-3 pass; 0 otherwise */
+  int cp_tile;    /* dense CP: width of the pass tiles, 16 or 32; 0 for Tucker */
   int variants;   /* variants timed for the entry (0: untimed defaults) */
   double ms;      /* mean time of one outer iteration of the recorded variant (NaN if untimed) */
 } comm_tune_entry;
@@ -235,7 +238,9 @@ int comm_tune_lookup(comm_ctx* ctx, const comm_dense* x, const comm_model* model
  * comm_tune_jcomm recorded.  Read from `entry`: cache_pq (0 or 1; 0 at
  * beta = 1), wshare (-1 = by precision, or 0 / 1 for dense CP of order 3 at
  * beta != 1; -1 otherwise) and tk_groups (0 = 128, or 1 to 1024 for dense
- * Tucker of order 3; 0 otherwise); the other fields are ignored.  Buffer
+ * Tucker of order 3; 0 otherwise) and cp_tile (0 = by rank and precision,
+ * 32 = 32-wide, 16 = 16-wide where the rank is <= 16 with float32 tiles; 0
+ * for Tucker); the other fields are ignored.  Buffer
  * pointers are not read.  Synchronises `stream` and the batched entry
  * point's streams, and drops its cached graph.  COMM_EINVAL on a field
  * outside these ranges (the table is then unchanged). */

@@ -75,7 +75,8 @@ class Extrap(ctypes.Structure):
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("found", ctypes.c_int), ("cache_pq", ctypes.c_int), ("wshare", ctypes.c_int),
-                ("tk_groups", ctypes.c_int), ("variants", ctypes.c_int), ("ms", ctypes.c_double)]
+                ("tk_groups", ctypes.c_int), ("cp_tile", ctypes.c_int), ("variants", ctypes.c_int),
+                ("ms", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -455,15 +456,15 @@ class Context:
         _check(self._lib.comm_tune_lookup(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o),
                                           ctypes.byref(e)))
         return {"found": bool(e.found), "cache_pq": e.cache_pq, "wshare": e.wshare, "tk_groups": e.tk_groups,
-                "variants": e.variants, "ms": e.ms}
+                "cp_tile": e.cp_tile, "variants": e.variants, "ms": e.ms}
 
     def tune_set(self, X, factors, core=None, beta: float = 1.0, L: int = 1, eps: float = 1e-12,
                  eps_x: Optional[float] = None, precision: str = "fp32", cache_pq: int = 0, wshare: int = -1,
-                 tk_groups: int = 0, stream=None) -> None:
+                 tk_groups: int = 0, cp_tile: int = 0, stream=None) -> None:
         """Record an autotune table entry directly (``comm_tune_set``)."""
         d, m, o = _dense(X), _model(factors, core), self._o(beta, eps, eps_x, L, False, precision)
         e = TuneEntry()
-        e.cache_pq, e.wshare, e.tk_groups = int(cache_pq), int(wshare), int(tk_groups)
+        e.cache_pq, e.wshare, e.tk_groups, e.cp_tile = int(cache_pq), int(wshare), int(tk_groups), int(cp_tile)
         _check(self._lib.comm_tune_set(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), ctypes.byref(e),
                                        _stream(stream)))
 

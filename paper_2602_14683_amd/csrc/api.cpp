@@ -122,8 +122,15 @@ struct CpWs {
   float *Pc, *Qc;
   float *Vn, *Vd;    // J-CoMM at beta != 1: V kept by the mode-1 pass for mode 2
   float *f2n, *f2d;  // ... and mode 2's numerator / denominator chunks folded from it
+  int r16;           // the passes run the 16-wide tiles (cp_narrow)
   size_t bytes;
 };
+
+// 16-wide pass tiles: rank <= 16 with float32 tiles, unless the autotune
+// table chose the 32-wide ones.
+bool cp_narrow(int rank, const comm_opts* o, const TuneChoice& pick) {
+  return rank <= 16 && o->precision != COMM_BF16 && pick.cp_tile != 32;
+}
 
 bool cp_wshare(const comm_opts* o, const TuneChoice& pick) {
   if (o->beta == 1.0) return false;
@@ -201,6 +208,7 @@ CpPassArgs base_pass(const comm_dense* x, const CpWs& w, const comm_opts* o) {
   a.obj_part = w.obj_part;
   a.bf16 = o->precision == COMM_BF16;
   a.xbuf = 16.0 * a.J * a.K + 32.0 * a.K < 2147483648.0;
+  a.r16 = w.r16;
   return a;
 }
 
@@ -264,6 +272,7 @@ int cp3_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, cons
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
   w = cp_layout(x, ctx->ws, false);
+  w.r16 = cp_narrow(m->rank, o, ctx->pick);
   const bool kl = o->beta == 1.0;
   const int bc = beta_class_of(o->beta);
   const int first = block < 0 ? 0 : block, last = block < 0 ? 2 : block;
@@ -304,6 +313,7 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
   w = cp_layout(x, ctx->ws, cache, vkeep);
+  w.r16 = cp_narrow(m->rank, o, ctx->pick);
   const int bc = beta_class_of(o->beta);
   const float eps = (float)o->eps;
 
@@ -546,6 +556,7 @@ int cp3_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
   w = cp_layout(x, ctx->ws, false);
+  w.r16 = cp_narrow(m->rank, o, ctx->pick);
   CpPassArgs a = base_pass(x, w, o);
   a.r = user_set(m);
   a.n = a.r;
@@ -716,6 +727,7 @@ int cpn_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* m, const
   int rc = ensure_ws(ctx, v.bytes, st);
   if (rc) return rc;
   v = cpn_layout(x, ctx->ws, false);
+  v.w.r16 = cp_narrow(m->rank, o, ctx->pick);
   FView user[kMaxModes];
   for (int n = 0; n < v.N; ++n) user[n] = user_view(m, n);
   if ((rc = cpn_kr(v, user, v.w.ref.pad[0], nullptr, nullptr, st))) return rc;
@@ -736,6 +748,7 @@ int cpn_bcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, int block, cons
   int rc = ensure_ws(ctx, v.bytes, st);
   if (rc) return rc;
   v = cpn_layout(x, ctx->ws, false);
+  v.w.r16 = cp_narrow(m->rank, o, ctx->pick);
   const bool kl = o->beta == 1.0;
   const int bc = beta_class_of(o->beta);
   const int first = block < 0 ? 0 : block, last = block < 0 ? v.N - 1 : block;
@@ -799,6 +812,7 @@ int cpn_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
   int rc = ensure_ws(ctx, v.bytes, st);
   if (rc) return rc;
   v = cpn_layout(x, ctx->ws, cache);
+  v.w.r16 = cp_narrow(m->rank, o, ctx->pick);
   const CpWs& w = v.w;
   const int N = v.N, G = v.G;
   const int bc = beta_class_of(o->beta);
@@ -1426,30 +1440,34 @@ int tune_key_check(const comm_dense* x, const comm_model* m, const comm_opts* o)
 }
 
 // The equivalent evaluations the tuner times for a problem, defaults first:
-// the P~/Q~ cache or its recomputation (beta != 1); dense CP of order 3 at
+// the P~/Q~ cache or its recomputation (beta != 1); dense CP at rank <= 16
+// with float32 tiles: 16-wide or 32-wide pass tiles; dense CP of order 3 at
 // beta != 1: modes 1 and 2 from one V pass or a pass each; dense Tucker of
 // order 3: the mode-3 pass's pair-group cap.  One entry means nothing to time.
 std::vector<TuneChoice> tune_variants(const comm_dense* x, const comm_model* model, const comm_opts* o) {
-  std::vector<int> caches = o->beta != 1.0 ? std::vector<int>{1, 0} : std::vector<int>{0};
-  std::vector<TuneChoice> out;
-  for (int c : caches) {
-    TuneChoice t;
-    t.cache_pq = c;
-    if (model->kind == COMM_CP && x->ndim == 3 && o->beta != 1.0) {
-      const int def = o->precision != COMM_BF16;
-      for (int ws : {def, 1 - def}) {
-        t.wshare = ws;
-        out.push_back(t);
-      }
-    } else if (model->kind == COMM_TUCKER && x->ndim == 3) {
-      for (int g : {kTkGroupsDefault, 64, kTkGroupsMax}) {
-        t.tk_groups = g;
-        out.push_back(t);
-      }
-    } else {
-      out.push_back(t);
-    }
+  const std::vector<int> caches = o->beta != 1.0 ? std::vector<int>{1, 0} : std::vector<int>{0};
+  const bool cp = model->kind == COMM_CP;
+  std::vector<int> tiles = {0};
+  if (cp && model->rank <= 16 && o->precision != COMM_BF16) tiles.push_back(32);
+  std::vector<int> wshares = {-1};
+  if (cp && x->ndim == 3 && o->beta != 1.0) {
+    const int def = o->precision != COMM_BF16;
+    wshares = {def, 1 - def};
   }
+  std::vector<int> groups = {0};
+  if (!cp && x->ndim == 3) groups = {kTkGroupsDefault, 64, kTkGroupsMax};
+  std::vector<TuneChoice> out;
+  for (int c : caches)
+    for (int t : tiles)
+      for (int ws : wshares)
+        for (int gr : groups) {
+          TuneChoice v;
+          v.cache_pq = c;
+          v.cp_tile = t;
+          v.wshare = ws;
+          v.tk_groups = gr;
+          out.push_back(v);
+        }
   return out;
 }
 
@@ -1590,6 +1608,7 @@ std::vector<int64_t> batch_key(const std::vector<BatchItem>& items, const char* 
     word(it.o.cache_pq);
     word(it.pick.wshare);
     word(it.pick.tk_groups);
+    word(it.pick.cp_tile);
     word((int64_t)(intptr_t)it.obj);
     word((int64_t)it.off);
   }
@@ -2001,6 +2020,7 @@ int comm_tune_lookup(comm_ctx* ctx, const comm_dense* x, const comm_model* model
     out->cache_pq = c.cache_pq;
     out->wshare = model->kind == COMM_CP && x->ndim == 3 && opts->beta != 1.0 ? (int)cp_wshare(opts, c) : -1;
     out->tk_groups = model->kind == COMM_TUCKER && x->ndim == 3 ? (c.tk_groups ? c.tk_groups : kTkGroupsDefault) : 0;
+    out->cp_tile = model->kind == COMM_CP ? (cp_narrow(model->rank, opts, c) ? 16 : 32) : 0;
     out->variants = out->found ? c.variants : 0;
     out->ms = out->found && c.variants > 0 ? c.ms : NAN;
     return COMM_OK;
@@ -2024,12 +2044,18 @@ int comm_tune_set(comm_ctx* ctx, const comm_dense* x, const comm_model* model, c
     if (entry->tk_groups < 0 || entry->tk_groups > kTkGroupsLimit || (entry->tk_groups && !tk3))
       return fail(COMM_EINVAL, "tk_groups = %d (0, or 1 to %d for dense Tucker of order 3)", entry->tk_groups,
                   kTkGroupsLimit);
+    const bool narrow_ok = model->kind == COMM_CP && model->rank <= 16 && opts->precision != COMM_BF16;
+    if (!(entry->cp_tile == 0 || (entry->cp_tile == 32 && model->kind == COMM_CP) ||
+          (entry->cp_tile == 16 && narrow_ok)))
+      return fail(COMM_EINVAL, "cp_tile = %d (0; 32 for CP; 16 for CP at rank <= 16 with float32 tiles)",
+                  entry->cp_tile);
     if ((rc = set_device(ctx))) return rc;
     hipStream_t st = (hipStream_t)stream;
     TuneChoice c;
     c.cache_pq = entry->cache_pq;
     c.wshare = entry->wshare;
     c.tk_groups = entry->tk_groups;
+    c.cp_tile = entry->cp_tile == 32 ? 32 : 0;
     c.variants = 0;
     c.ms = NAN;
     // a captured batch may have resolved its options with the old entry

@@ -30,6 +30,14 @@
 // 32-wide k slice (w & 1) and 8 of the 16 (4 i x 8 j) pair blocks (w >> 1).
 // Results leave the workgroup as partial sums in fixed slots (no atomics), so
 // every reduction has a fixed order and the pass is bitwise deterministic.
+//
+// Rank <= 16 (float32 tiles) has a narrow variant (kR16): the reconstruction
+// reduces over 16 r in 8 matrix-core steps instead of 16, and the three
+// contractions run on v_mfma_f32_16x16x4f32 with 16-wide r, half the matrix
+// work of the 32-wide tiles padded with zero columns.  The weight tile reaches
+// the mode-3 contraction by lane swaps (v_permlane16_swap) that gather the
+// k < 16 and k >= 16 halves of register pairs, and the modes-1/2 contraction
+// through the same LDS transpose.
 
 #pragma once
 
@@ -120,6 +128,35 @@ __device__ __forceinline__ void load16(const float* p, float (&v)[16]) {
     v[4 * t + 2] = x[2];
     v[4 * t + 3] = x[3];
   }
+}
+
+__device__ __forceinline__ void load8(const float* p, float (&v)[8]) {
+  const f32x4* q = reinterpret_cast<const f32x4*>(p);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x4 x = q[t];
+    v[4 * t + 0] = x[0];
+    v[4 * t + 1] = x[1];
+    v[4 * t + 2] = x[2];
+    v[4 * t + 3] = x[3];
+  }
+}
+
+// v_mfma_f32_16x16x4f32: A operand lane l supplies A[l%16][l/16], B operand
+// B[l/16][l%16]; the 16x16 result sits in 4 registers per lane with
+// D[4*(l/16) + v][l%16] in register v.
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Exchange the odd 16-lane rows of x with the even rows of y: afterwards x
+// holds rows (x0, y0, x2, y2) and y rows (x1, y1, x3, y3).  In the Xhat
+// layout (lane = 32 h + k) x then carries k < 16 and y k >= 16, each for both
+// registers and both lane halves.
+__device__ __forceinline__ void swap_rows16(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
 }
 
 // Row of the 32x32 result held in register v by lane half h.
@@ -238,6 +275,67 @@ __device__ __forceinline__ void contract_tile(const float (&wv)[16], const float
   }
 }
 
+// The same for rank <= 16 with 16-wide tiles; lane l, c16 = l % 16, g = l / 16.
+// ag[t]: A' of i_local = 2t + (g & 1); bq[q]: B' of j_local = 4 (g >> 1) + q;
+// ct[s]: C'[kslice + 8g + s]; all at column r = c16.  m3acc[kb][v] =
+// M3[k = 16 kb + c16][r = 4g + v]; m1loc[t], t < 2: M1 of i_local 2t + (g & 1) over
+// this lane's j half; m2acc[q]: M2 of j_local 4 (g >> 1) + q over this lane's
+// i's.
+__device__ __forceinline__ void contract_tile16(const float (&wv)[16], const float (&ag)[2], const float (&bq)[4],
+                                                const float (&ct)[8], bool want_m3, bool want_v, f32x4 (&m3acc)[2],
+                                                float (&m1loc)[4], float (&m2acc)[4], float* ldsT, int col, int h,
+                                                int c16, int g) {
+  if (want_m3) {
+    // pair u = registers (v, v + 4), v = (u & 3) + 8 (u >> 2): after the row
+    // swap lane group g holds m = (i_local 2 (u >> 2) + (g & 1), j_local
+    // 4 (g >> 1) + (u & 3)), at k = c16 in lo and k = 16 + c16 in hi
+    float lo[8], hi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int v = (u & 3) + 8 * (u >> 2);
+      lo[u] = wv[v];
+      hi[u] = wv[v + 4];
+      swap_rows16(lo[u], hi[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float wa = ag[u >> 2] * bq[u & 3];
+      m3acc[0] = mfma16(wa, lo[u], m3acc[0]);
+      m3acc[1] = mfma16(wa, hi[u], m3acc[1]);
+    }
+  }
+  if (want_v) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) ldsT[out_row(v, h) * kLdsT + col] = wv[v];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // A operand row c16 of row block mb is m = (i_local 2 mb + ((c16 >> 2) & 1),
+    // j_local 4 (c16 >> 3) + (c16 & 3)); the reduction runs over k = 8g + s, so
+    // result row 4g + v is (i_local 2 mb + (g & 1), j_local 4 (g >> 1) + v)
+    float pr[2][8];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int m = 8 * (2 * mb + ((c16 >> 2) & 1)) + 4 * (c16 >> 3) + (c16 & 3);
+      load8(ldsT + m * kLdsT + 8 * g, pr[mb]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    f32x4 vacc[2] = {};
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) vacc[mb] = mfma16(pr[mb][t], ct[t], vacc[mb]);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        m1loc[mb] = fmaf(vacc[mb][q], bq[q], m1loc[mb]);
+        m2acc[q] = fmaf(vacc[mb][q], ag[mb], m2acc[q]);
+      }
+    }
+  }
+}
+
 // kNumOnly: contract P;  kNumDen: contract P and Q;  kCacheNumDen: P~ / Q~ read
 // from the cache instead of X + rebuild, both contracted;  kCacheWrite: rebuild,
 // write P~ / Q~ to the cache, no contraction.
@@ -301,9 +399,10 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ base, int ib
   }
 }
 
-template <int BC, int kVar, bool kObj, bool kInterior, bool kBf>
+template <int BC, int kVar, bool kObj, bool kInterior, bool kBf, bool kR16>
 __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, int wg, int bi, int bj, int bk,
                                           int gj, int gk) {
+  static_assert(!(kBf && kR16), "the narrow tiles are float32 only");
   constexpr bool kDen = kVar == kNumDen || kVar == kCacheNumDen;
   constexpr bool kCache = kVar == kCacheNumDen;
   constexpr bool kWrite = kVar == kCacheWrite;
@@ -312,6 +411,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   const int lane = tid & 63;
   const int col = lane & 31;
   const int h = lane >> 5;
+  const int c16 = lane & 15, g16 = lane >> 4;  // the 16-wide tiles' lane split
   const int kt = w & 1;
   const int mg = w >> 1;
   const int i0 = bi * kCpTI, j0 = bj * kCpTJ, k0 = bk * kCpTK;
@@ -340,12 +440,22 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   // ---- per-wave operands that do not depend on the pair block:
   // rebuild C rows (k = kcol, r = 16h + s) and contraction C columns
   // (r = col, k = kslice + 16h + s)
+  // (16-wide: rebuild r = 8h + s, contraction columns r = c16 at k = kslice + 8 g16 + s, s < 8)
   float crow[16], ctn[16], ctd[16];
+  if constexpr (kR16) {
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    if (!kCache) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
-    ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
-    if (kDen) ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
+    for (int s = 0; s < 8; ++s) {
+      if (!kCache) crow[s] = a.r.C.at(kcol, 8 * h + s, K);
+      ctn[s] = a.n.C.at(kslice + 8 * g16 + s, c16, K);
+      if (kDen) ctd[s] = a.d.C.at(kslice + 8 * g16 + s, c16, K);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (!kCache) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
+      ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
+      if (kDen) ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
+    }
   }
 
   // ---- stage the workgroup's factor rows in LDS (zero outside rows x cols):
@@ -403,6 +513,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   }
 
   f32x16 m3n = {}, m3d = {};
+  f32x4 m3n16[2] = {}, m3d16[2] = {};
   float m2n[4][4] = {}, m2d[4][4] = {};
   float m1n[4] = {}, m1d[4] = {};
   double obj = 0.0;
@@ -413,10 +524,19 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   // overlaps its own matrix-core work.
   auto rebuild = [&](int ibx, int jbx) -> f32x16 {
     // rebuild operand: lane = pair row m = col, r = 16h + s
+    f32x16 acc = {};
+    if constexpr (kR16) {
+      // r = 8h + s: the lane halves split the 16 live columns
+      float arow8[8], brow8[8];
+      load8(sh.ra + (ibx * 4 + (col >> 3)) * kSA + 8 * h, arow8);
+      load8(sh.rb + (jbx * 8 + (col & 7)) * kSA + 8 * h, brow8);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) acc = mfma32(arow8[s] * brow8[s], crow[s], acc);
+      return acc;
+    }
     float arow[16], brow[16];
     load16(sh.ra + (ibx * 4 + (col >> 3)) * kSA + 16 * h, arow);
     load16(sh.rb + (jbx * 8 + (col & 7)) * kSA + 16 * h, brow);
-    f32x16 acc = {};
     if constexpr (kBf) {
       float av[16];
 #pragma unroll
@@ -512,7 +632,26 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       }
     }
 
-    if (!kWrite && (want_m3 || want_v)) {
+    if (!kWrite && (want_m3 || want_v) && kR16) {
+      float ag2[2], bq4[4], ct8[8];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) ag2[t] = sh.na[(ib * 4 + 2 * t + (g16 & 1)) * 32 + c16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bq4[q] = sh.nb[(jb * 8 + 4 * (g16 >> 1) + q) * 32 + c16];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) ct8[t] = ctn[t];
+      if (!xz)
+        contract_tile16(pv, ag2, bq4, ct8, want_m3, want_v, m3n16, m1n, m2n[jb], sh.t[w], col, h, c16, g16);
+      if (kDen) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) ag2[t] = sh.da[(ib * 4 + 2 * t + (g16 & 1)) * 32 + c16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bq4[q] = sh.db[(jb * 8 + 4 * (g16 >> 1) + q) * 32 + c16];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) ct8[t] = ctd[t];
+        contract_tile16(qv, ag2, bq4, ct8, want_m3, want_v, m3d16, m1d, m2d[jb], sh.t[w], col, h, c16, g16);
+      }
+    } else if (!kWrite && (want_m3 || want_v)) {
       float ag[4], bq[4];
 #pragma unroll
       for (int g = 0; g < 4; ++g) ag[g] = sh.na[(ib * 4 + g) * 32 + col];
@@ -528,7 +667,21 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       }
     }
     if constexpr (kPipe) xh_cur = xh_next;
-    if (jb == 3 && want_v) {
+    if (kR16 && jb == 3 && want_v) {
+      // rows ib*4 + 2t + (g16 & 1): combine the two j halves (lanes l, l ^ 32)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int row = (ib * 4 + 2 * t + (g16 & 1)) * 32 + c16;
+        const float o = __shfl_xor(m1n[t], 32);
+        if (h == 0) sh.m1[0][kt][row] = m1n[t] + o;
+        m1n[t] = 0.0f;
+        if (kDen) {
+          const float od = __shfl_xor(m1d[t], 32);
+          if (h == 0) sh.m1[1][kt][row] = m1d[t] + od;
+          m1d[t] = 0.0f;
+        }
+      }
+    } else if (jb == 3 && want_v) {
       // this wave's M1 rows ib*4+g: combine the two lane halves (different j)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
@@ -560,6 +713,62 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
 
   // ---------------------------------------------------------------- cross-wave reductions
   constexpr int nsides = kDen ? 2 : 1;
+  if constexpr (kR16) {
+    // the same reductions over 16 live columns (the slots' columns >= 16 are
+    // not written; every reader stops at the rank)
+#pragma unroll
+    for (int side = 0; side < nsides; ++side) {
+      if (want_m3) {
+        const f32x4(&acc)[2] = side == 0 ? m3n16 : m3d16;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sh.red[w][(16 * kb + c16) * 32 + 4 * g16 + v] = acc[kb][v];
+        __syncthreads();
+        float* dst = side == 0 ? a.m3n : a.m3d;
+        const size_t slot = (size_t)(bi * gj + bj);
+        for (int e = tid; e < 2 * 32 * 16; e += kThreads) {
+          const int ks = e >> 9;
+          const int kk = (e >> 4) & 31;
+          const int r = e & 15;
+          const int k = k0 + ks * 32 + kk;
+          const float s = sh.red[ks][kk * 32 + r] + sh.red[2 + ks][kk * 32 + r];
+          if (k < K) dst[(slot * a.Kp + k) * kRP + r] = s;
+        }
+        __syncthreads();
+      }
+      if (want_v) {
+        float(&m2)[4][4] = side == 0 ? m2n : m2d;
+        // combine the two i parities (lanes l, l ^ 16)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float sv = m2[jb][q] + __shfl_xor(m2[jb][q], 16);
+            if ((g16 & 1) == 0) sh.red[w][(jb * 8 + 4 * (g16 >> 1) + q) * 32 + c16] = sv;
+          }
+        __syncthreads();
+        float* d2 = side == 0 ? a.m2n : a.m2d;
+        float* d1 = side == 0 ? a.m1n : a.m1d;
+        const size_t slot2 = (size_t)(bi * gk + bk);
+        const size_t slot1 = (size_t)(bj * gk + bk);
+        for (int e = tid; e < 32 * 16; e += kThreads) {
+          const int jl = e >> 4, r = e & 15;
+          const int o = jl * 32 + r;
+          const float sv = ((sh.red[0][o] + sh.red[1][o]) + sh.red[2][o]) + sh.red[3][o];
+          if (j0 + jl < J) d2[(slot2 * a.Jp + j0 + jl) * kRP + r] = sv;
+        }
+        for (int e = tid; e < kCpTI * 16; e += kThreads) {
+          const int il = e >> 4, r = e & 15;
+          const int o = il * 32 + r;
+          const float sv = sh.m1[side][0][o] + sh.m1[side][1][o];
+          if (i0 + il < I) d1[(slot1 * a.Ip + i0 + il) * kRP + r] = sv;
+        }
+        __syncthreads();
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int side = 0; side < nsides; ++side) {
     if (want_m3) {
@@ -606,7 +815,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   }
 }
 
-template <int BC, int kVar, bool kObj, bool kBf>
+template <int BC, int kVar, bool kObj, bool kBf, bool kR16>
 __global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
   __shared__ PassShared sh;
   const int wg = blockIdx.x;
@@ -617,9 +826,9 @@ __global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pa
   const bool interior =
       a.xbuf && (bi + 1) * kCpTI <= a.I && (bj + 1) * kCpTJ <= a.J && (bk + 1) * kCpTK <= a.K;
   if (interior)
-    pass_body<BC, kVar, kObj, true, kBf>(a, sh, wg, bi, bj, bk, gj, gk);
+    pass_body<BC, kVar, kObj, true, kBf, kR16>(a, sh, wg, bi, bj, bk, gj, gk);
   else
-    pass_body<BC, kVar, kObj, false, kBf>(a, sh, wg, bi, bj, bk, gj, gk);
+    pass_body<BC, kVar, kObj, false, kBf, kR16>(a, sh, wg, bi, bj, bk, gj, gk);
 }
 
 // ---------------------------------------------------------------------------------------- V pass
@@ -870,11 +1079,14 @@ hipError_t launch_vpass_bc(const CpPassArgs& a, hipStream_t s) {
 template <int BC, int kVar, bool kObj>
 hipError_t launch_v(const CpPassArgs& a, const CpGrid& g, hipStream_t s) {
   if (a.bf16)
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, true>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s, a,
-                       g.gj, g.gk);
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, true, false>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s,
+                       a, g.gj, g.gk);
+  else if (a.r16)
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, true>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s,
+                       a, g.gj, g.gk);
   else
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s, a,
-                       g.gj, g.gk);
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, false>), dim3((unsigned)g.wgs()), dim3(kThreads), 0,
+                       s, a, g.gj, g.gk);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct TuneChoice {
   int wshare = -1;     // dense CP at beta != 1: modes 1 and 2 from one V pass (1) or a pass each (0);
                        // -1: by the tile precision (float32 shares, bf16 does not)
   int tk_groups = 0;   // dense order-3 Tucker mode-3 pass: at most this many pair groups (0: 128)
+  int cp_tile = 0;     // dense CP passes: 0 = 16-wide tiles at rank <= 16 (float32), else 32-wide; 32 = 32-wide
   int variants = 0;    // table entries: variants timed (0: the defaults, untimed)
   double ms = 0.0;     // table entries: mean time of one outer iteration of this variant
 };

@@ -81,6 +81,8 @@ struct CpPassArgs {
                            // resource: 16 J K + 32 K < 2^31 (every in-tile byte offset fits)
   float* Vn;               // V pass (launch_cp_vpass): V of the numerator / denominator set, [I*J][32]
   float* Vd;
+  int r16;                 // every factor column >= 16 is zero (rank <= 16): 16-wide tiles
+                           // (float32 only; ignored with bf16); slot columns >= 16 are then not written
 };
 
 hipError_t launch_cp_pass(const CpPassArgs& a, const CpGrid& g, int beta_class, bool den, hipStream_t s);

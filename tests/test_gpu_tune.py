@@ -94,10 +94,18 @@ def test_auto_without_an_entry_is_the_cache(ctx):
 
 
 def test_beta_one_records_recompute_without_timing(ctx):
-    X, init, core = _cp(6, dims=(20, 24, 28), R=4)
+    # rank 20: one tile width, no cache at beta = 1, so a single variant
+    X, init, core = _cp(6, dims=(20, 24, 28), R=20)
     res = ctx.tune_jcomm(dev(X), [dev(a) for a in init], beta=1.0, L=2)
-    assert res["cache_pq"] == 0
+    assert res["cache_pq"] == 0 and res["variants"] == 0 and res["cp_tile"] == 32
     assert math.isnan(res["ms_recompute"]) and math.isnan(res["ms_cache"])
+
+
+def test_beta_one_narrow_rank_times_the_tile_widths(fresh):
+    X, init, core = _cp(6, dims=(20, 24, 28), R=4)
+    res = fresh.tune_jcomm(dev(X), [dev(a) for a in init], beta=1.0, L=2)
+    assert res["cache_pq"] == 0 and res["variants"] == 2 and res["cp_tile"] in (16, 32)
+    assert res["ms_recompute"] > 0.0 and math.isnan(res["ms_cache"])
 
 
 def test_bad_reps_and_cache_value_refused(ctx):
@@ -244,8 +252,9 @@ def test_tuned_entry_cp(fresh):
     F = [dev(a) for a in init]
     assert not fresh.tune_entry(dev(X), F, beta=0.5, L=2)["found"]
     res = fresh.tune_jcomm(dev(X), F, beta=0.5, L=2, reps=2)
-    assert res["found"] and res["variants"] == 4
-    assert res["wshare"] in (0, 1) and res["tk_groups"] == 0
+    # cache x W-sharing x tile width (rank 8: 16- or 32-wide)
+    assert res["found"] and res["variants"] == 8
+    assert res["wshare"] in (0, 1) and res["tk_groups"] == 0 and res["cp_tile"] in (16, 32)
     assert res["ms"] == min(res["ms_recompute"], res["ms_cache"])
 
 
@@ -263,12 +272,13 @@ def test_tuned_entry_tucker(fresh, beta, variants):
 @pytest.mark.parametrize("beta", [0.0, 0.5, 1.5])
 @pytest.mark.parametrize("cache", [0, 1])
 @pytest.mark.parametrize("wshare", [0, 1])
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_every_cp_variant_matches_oracle(fresh, beta, cache, wshare, precision):
-    X, init, core = _cp(14, dims=(37, 70, 90), R=32)
+@pytest.mark.parametrize("precision,R,tile", [("fp32", 32, 0), ("bf16", 32, 0), ("fp32", 12, 0), ("fp32", 12, 32)])
+def test_every_cp_variant_matches_oracle(fresh, beta, cache, wshare, precision, R, tile):
+    X, init, core = _cp(14, dims=(37, 70, 90), R=R)
     Xd = dev(X)
     L = 2 if precision == "fp32" else 1
-    fresh.tune_set(Xd, [dev(a) for a in init], beta=beta, L=L, precision=precision, cache_pq=cache, wshare=wshare)
+    fresh.tune_set(Xd, [dev(a) for a in init], beta=beta, L=L, precision=precision, cache_pq=cache, wshare=wshare,
+                   cp_tile=tile)
     assert fresh.tune_entry(Xd, [dev(a) for a in init], beta=beta, L=L, precision=precision)["wshare"] == wshare
     F = [dev(a) for a in init]
     obj = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -351,14 +361,16 @@ def test_batched_and_noalloc_follow_the_entry(fresh, kind):
 @pytest.mark.parametrize("fields", [{"wshare": 1, "kind": "tucker"}, {"tk_groups": 64, "kind": "cp"},
                                     {"tk_groups": 2000, "kind": "tucker"}, {"cache_pq": 2, "kind": "cp"},
                                     {"wshare": 2, "kind": "cp"}, {"cache_pq": 1, "beta": 1.0, "kind": "cp"},
-                                    {"wshare": 1, "beta": 1.0, "kind": "cp"}])
+                                    {"wshare": 1, "beta": 1.0, "kind": "cp"}, {"cp_tile": 16, "kind": "tucker"},
+                                    {"cp_tile": 24, "kind": "cp"}, {"cp_tile": 16, "precision": "bf16", "kind": "cp"}])
 def test_tune_set_refuses_bad_fields(fresh, fields):
     f = dict(fields)
     kind = f.pop("kind")
     beta = f.pop("beta", 0.5)
+    prec = f.pop("precision", "fp32")
     X, init, core = (_cp(18) if kind == "cp" else _tucker(18))
     Xd, Fd = dev(X), [dev(a) for a in init]
     Gd = dev(core) if core is not None else None
     with pytest.raises(comm.CommError):
-        fresh.tune_set(Xd, Fd, core=Gd, beta=beta, L=2, **f)
-    assert not fresh.tune_entry(Xd, Fd, core=Gd, beta=beta, L=2)["found"]
+        fresh.tune_set(Xd, Fd, core=Gd, beta=beta, L=2, precision=prec, **f)
+    assert not fresh.tune_entry(Xd, Fd, core=Gd, beta=beta, L=2, precision=prec)["found"]
