@@ -1842,6 +1842,7 @@ size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const 
 
 int comm_cp_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int block, const comm_opts* opts,
                    void* stream) {
+  const TraceRange trace_range("comm_cp_update");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = check_opts(opts, false);
@@ -1860,6 +1861,7 @@ int comm_cp_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int bl
 
 int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
                      double* obj_ref_dev, void* stream) {
+  const TraceRange trace_range("comm_jcomm_outer");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = jcomm_check(x, model, opts);
@@ -1875,6 +1877,7 @@ int comm_jcomm_outer(comm_ctx* ctx, const comm_dense* x, comm_model* model, cons
 
 int comm_jcomm_outer_noalloc(comm_ctx* ctx, const comm_dense* x, comm_model* model, const comm_opts* opts,
                              double* obj_ref_dev, void* stream) {
+  const TraceRange trace_range("comm_jcomm_outer_noalloc");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = jcomm_check(x, model, opts);
@@ -1909,6 +1912,7 @@ int comm_jcomm_outer_noalloc(comm_ctx* ctx, const comm_dense* x, comm_model* mod
 
 int comm_tune_jcomm(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts, int reps,
                     int* choice, double* ms, void* stream) {
+  const TraceRange trace_range("comm_tune_jcomm");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = jcomm_check(x, model, opts);
@@ -2068,6 +2072,7 @@ int comm_tune_set(comm_ctx* ctx, const comm_dense* x, const comm_model* model, c
 }
 
 int comm_jcomm_outer_batched(comm_ctx* ctx, const comm_problem* problems, int count, int flags, void* stream) {
+  const TraceRange trace_range("comm_jcomm_outer_batched");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (count < 0 || (count > 0 && !problems)) return fail(COMM_EINVAL, "count = %d with problems = %p", count,
@@ -2094,6 +2099,7 @@ int comm_jcomm_outer_batched(comm_ctx* ctx, const comm_problem* problems, int co
 
 int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* model, const comm_opts* opts,
                         double* out_dev, void* stream) {
+  const TraceRange trace_range("comm_beta_objective");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (!out_dev) return fail(COMM_EINVAL, "out_dev is NULL");
@@ -2121,6 +2127,7 @@ int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* mo
 
 int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, int block, const comm_opts* opts,
                        void* stream) {
+  const TraceRange trace_range("comm_tucker_update");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = check_opts(opts, false);
@@ -2139,6 +2146,7 @@ int comm_tucker_update(comm_ctx* ctx, const comm_dense* x, comm_model* model, in
 
 int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
                             double* obj_ref_dev, void* stream) {
+  const TraceRange trace_range("comm_cp_jcomm_outer_coo");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (opts && opts->beta != 1.0) {
@@ -2166,6 +2174,7 @@ int comm_cp_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model,
 
 int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,
                        void* stream) {
+  const TraceRange trace_range("comm_cp_update_coo");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = check_coo_beta(x, model, opts, false);
@@ -2183,6 +2192,7 @@ int comm_cp_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int 
 
 int comm_tucker_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, int block, const comm_opts* opts,
                            void* stream) {
+  const TraceRange trace_range("comm_tucker_update_coo");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = check_coo_beta(x, model, opts, false);
@@ -2200,6 +2210,7 @@ int comm_tucker_update_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, 
 
 int comm_tucker_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* model, const comm_opts* opts,
                                 double* obj_ref_dev, void* stream) {
+  const TraceRange trace_range("comm_tucker_jcomm_outer_coo");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = check_coo_beta(x, model, opts, true);
@@ -2216,6 +2227,7 @@ int comm_tucker_jcomm_outer_coo(comm_ctx* ctx, const comm_coo* x, comm_model* mo
 
 int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* model, const comm_opts* opts,
                             double* out_dev, void* stream) {
+  const TraceRange trace_range("comm_beta_objective_coo");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (!out_dev) return fail(COMM_EINVAL, "out_dev is NULL");
@@ -2245,6 +2257,7 @@ int comm_beta_objective_coo(comm_ctx* ctx, const comm_coo* x, const comm_model* 
 }
 
 int comm_coo_plan_create(comm_ctx* ctx, const comm_coo* x, comm_coo_plan** out, void* stream) {
+  const TraceRange trace_range("comm_coo_plan_create");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (!out) return fail(COMM_EINVAL, "out is NULL");
@@ -2264,6 +2277,7 @@ int comm_coo_plan_destroy(comm_coo_plan* plan) {
 
 int comm_cp_jcomm_outer_coo_plan(comm_ctx* ctx, const comm_coo_plan* plan, comm_model* model, const comm_opts* opts,
                                  double* obj_ref_dev, void* stream) {
+  const TraceRange trace_range("comm_cp_jcomm_outer_coo_plan");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (!plan) return fail(COMM_EINVAL, "plan is NULL");
@@ -2283,6 +2297,7 @@ int comm_cp_jcomm_outer_coo_plan(comm_ctx* ctx, const comm_coo_plan* plan, comm_
 
 int comm_bcomm_sweep_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* model, comm_model* prev,
                             const comm_opts* opts, const comm_extrap* extrap, float* alpha_dev, void* stream) {
+  const TraceRange trace_range("comm_bcomm_sweep_extrap");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = check_opts(opts, false);
@@ -2316,6 +2331,7 @@ int comm_bcomm_sweep_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* mode
 int comm_jcomm_outer_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* model, comm_model* prev,
                             const comm_opts* opts, const comm_extrap* extrap, double* obj_ref_dev, float* alpha_dev,
                             void* stream) {
+  const TraceRange trace_range("comm_jcomm_outer_extrap");
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     int rc = jcomm_check(x, model, opts);

@@ -12,8 +12,19 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/comm.h"
 #include "kernels.h"
+
+// A roctx range around one entry-point call (host side: the call's enqueue
+// time), named after the entry point; shown by rocprofv3 --marker-trace.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // One entry of the autotune table (comm_tune_jcomm): which of the equivalent
 // evaluations of a J-CoMM outer iteration runs.  A recorded entry fixes the

@@ -49,7 +49,8 @@ def test_host_code_under_asan_and_ubsan(tmp_path):
     assert res.returncode == 0, res.stderr[-3000:]
     exe = str(tmp_path / "harness")
     res = subprocess.run([CLANG, "-fsanitize=address,undefined", "-o", exe, hobj] + objs +
-                         ["-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")],
+                         ["-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lrocprofiler-sdk-roctx",
+                          "-Wl,-rpath," + os.path.join(ROCM, "lib")],
                          capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-3000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1",
