@@ -170,6 +170,12 @@ typedef struct {
 
 /* Flags of comm_jcomm_outer_batched. */
 #define COMM_BATCH_GRAPH 1 /* capture the batch into a HIP graph; replay it while the problem list is unchanged */
+/* Run the problems' launches grouped: each kernel that several problems run at
+ * the same point of their sequence is launched once for all of them, its
+ * workgroups reading their problem's arguments from a table in device memory
+ * (one stream; results bitwise those of separate calls).  Dense problems of
+ * order 3 only: a batch holding another order runs ungrouped. */
+#define COMM_BATCH_GROUPED 2
 
 /* Create a context on HIP device `device`.  The context owns a scratch
  * workspace that grows on demand up to `workspace_limit_bytes` (0 = no limit).
@@ -330,6 +336,11 @@ int comm_jcomm_outer_noalloc(comm_ctx* ctx, const comm_dense* x, comm_model* mod
  *     and the graph is replayed on `stream` by every later call with the same
  *     problem list (same buffers, shapes and options, compared field by field);
  *     a different list waits for earlier replays and is captured anew.
+ *   - flags |= COMM_BATCH_GROUPED: the problems' launches run grouped on
+ *     `stream` (see COMM_BATCH_GROUPED), with the same bitwise results.  The
+ *     launch tables live in device memory the context owns (one for eager
+ *     calls, one kept with the captured graph); an eager grouped call waits for
+ *     the previous one if that ran on another stream.
  *   - The batch workspace is the sum of comm_workspace_bytes(..., op = 1) over
  *     the problems (each rounded up to 256 bytes) and grows on demand within
  *     the context limit; growing it waits for earlier batched work.

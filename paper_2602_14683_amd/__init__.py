@@ -27,6 +27,7 @@ COMM_FP32 = 0
 COMM_BF16 = 1
 PRECISIONS = {"fp32": COMM_FP32, "bf16": COMM_BF16}
 COMM_BATCH_GRAPH = 1
+COMM_BATCH_GROUPED = 2
 COMM_CACHE_AUTO = -1
 
 EXPORTED = ["comm_create", "comm_destroy", "comm_last_error", "comm_workspace_bytes", "comm_profile_enable",
@@ -468,14 +469,16 @@ class Context:
         _check(self._lib.comm_tune_set(self._h, ctypes.byref(d), ctypes.byref(m), ctypes.byref(o), ctypes.byref(e),
                                        _stream(stream)))
 
-    def jcomm_outer_batched(self, batch: "Batch", graph: bool = False, stream=None) -> None:
+    def jcomm_outer_batched(self, batch: "Batch", graph: bool = False, stream=None, grouped: bool = False) -> None:
         """One J-CoMM outer iteration for every problem of `batch`, each with the
         result it would have alone; graph=True captures the batch into a HIP graph
-        once and replays it while the same Batch object's problems are passed."""
+        once and replays it while the same Batch object's problems are passed;
+        grouped=True launches each kernel once for all problems that run it at
+        the same point (dense order-3 problems)."""
         if not isinstance(batch, Batch):
             batch = Batch(batch)
-        _check(self._lib.comm_jcomm_outer_batched(self._h, batch.array, len(batch),
-                                                  COMM_BATCH_GRAPH if graph else 0, _stream(stream)))
+        flags = (COMM_BATCH_GRAPH if graph else 0) | (COMM_BATCH_GROUPED if grouped else 0)
+        _check(self._lib.comm_jcomm_outer_batched(self._h, batch.array, len(batch), flags, _stream(stream)))
 
     def bcomm_sweep_extrap(self, X, factors, prev, core=None, prev_core=None, beta: float = 1.0,
                            alpha_nes: float = 0.0, c: float = 1.0, delta: float = 1e-12, eps: float = 1e-12,
@@ -609,5 +612,5 @@ def cp_jcomm_outer_coo(idx, val, dims, factors, L=1, eps=1e-12, obj_out=None, st
     default_context().cp_jcomm_outer_coo(idx, val, dims, factors, L, eps, obj_out, stream)
 
 
-def jcomm_outer_batched(batch, graph=False, stream=None):
-    default_context().jcomm_outer_batched(batch, graph, stream)
+def jcomm_outer_batched(batch, graph=False, stream=None, grouped=False):
+    default_context().jcomm_outer_batched(batch, graph, stream, grouped)

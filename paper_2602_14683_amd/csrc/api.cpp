@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/comm.h"
+#include "group.h"
 #include "host_util.h"
 #include "kernels.h"
 #include "tucker3.h"
@@ -1639,6 +1640,225 @@ int batch_issue(comm_ctx* ctx, std::vector<BatchItem>& items, hipStream_t origin
   return COMM_OK;
 }
 
+// ---- grouped batches
+//
+// Each problem's launches are recorded (nothing runs), then issued on one
+// stream: at every step the kernel at the head of the most problems' sequences
+// runs once for all of them, through its grouped twin and a table of their
+// arguments; launches without a grouped twin run alone.  Each problem's own
+// launches keep their order, and each workgroup computes what it computes in
+// the problem's own launch, so results are bitwise those of single calls.
+struct GroupLaunch {
+  const void* kgrp;                     // null: closure `fn` of problem `p`
+  dim3 block;
+  size_t shmem;
+  uint32_t blocks;
+  size_t off_bucket, off_first, off_items;  // offsets in the table image
+  int stride;
+  const LaunchRec* rec;
+};
+
+struct GroupPlan {
+  std::vector<Recorder> recs;                      // one per problem
+  std::vector<std::vector<GroupLaunch>> shards;    // launches per internal stream
+  std::vector<char> image;                         // all tables, 256-byte aligned pieces
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int group_record(comm_ctx* ctx, std::vector<BatchItem>& items, GroupPlan& plan) {
+  plan.recs.assign(items.size(), Recorder());
+  for (size_t p = 0; p < items.size(); ++p) {
+    BatchItem& it = items[p];
+    comm_ctx sub;
+    sub.device = ctx->device;
+    sub.ws = ctx->bws + it.off;
+    sub.ws_bytes = it.bytes;
+    sub.limit = it.bytes;
+    sub.pick = it.pick;
+    struct Install {
+      explicit Install(Recorder* r) { g_recorder = r; }
+      ~Install() { g_recorder = nullptr; }
+    } install(&plan.recs[p]);
+    const int rc = jcomm_variant(&sub, &it.x, &it.m, &it.o, it.obj, nullptr);
+    if (rc) return rc;
+  }
+  return COMM_OK;
+}
+
+// Greedy grouping of the sequences of problems `ps`: at each step the kernel
+// at the head of the most sequences runs once for all of them.
+void group_shard(GroupPlan& plan, const std::vector<size_t>& ps, std::vector<GroupLaunch>& out) {
+  const size_t P = ps.size();
+  std::vector<size_t> head(P, 0);
+  auto seq = [&](size_t i) -> const std::vector<LaunchRec>& { return plan.recs[ps[i]].recs; };
+  auto take = [&](size_t bytes) {
+    const size_t off = plan.image.size();
+    plan.image.resize(align256(off + bytes), 0);
+    return off;
+  };
+  auto same = [](const LaunchRec& a, const LaunchRec& b) {
+    return a.kgrp == b.kgrp && a.block.x == b.block.x && a.shmem == b.shmem;
+  };
+  for (;;) {
+    const LaunchRec* best = nullptr;
+    int best_count = 0;
+    size_t closure_i = P;
+    for (size_t i = 0; i < P; ++i) {
+      if (head[i] >= seq(i).size()) continue;
+      const LaunchRec& r = seq(i)[head[i]];
+      if (!r.kgrp) {
+        if (closure_i == P) closure_i = i;
+        continue;
+      }
+      int c = 0;
+      for (size_t q = 0; q < P; ++q)
+        if (head[q] < seq(q).size()) c += same(seq(q)[head[q]], r);
+      if (c > best_count) {
+        best = &r;
+        best_count = c;
+      }
+    }
+    if (!best) {
+      if (closure_i == P) break;  // every sequence is done
+      GroupLaunch g{};
+      g.rec = &seq(closure_i)[head[closure_i]];
+      out.push_back(g);
+      ++head[closure_i];
+      continue;
+    }
+    GroupLaunch g{};
+    g.kgrp = best->kgrp;
+    g.block = best->block;
+    g.shmem = best->shmem;
+    g.stride = (int)best->item.size();
+    std::vector<const LaunchRec*> members;
+    const LaunchRec key = *best;
+    for (size_t q = 0; q < P; ++q) {
+      if (head[q] < seq(q).size() && same(seq(q)[head[q]], key)) {
+        members.push_back(&seq(q)[head[q]]);
+        ++head[q];
+      }
+    }
+    std::vector<uint32_t> first;
+    uint32_t total = 0;
+    for (const LaunchRec* m : members) {
+      first.push_back(total);
+      total += m->grid.x * m->grid.y * m->grid.z;
+    }
+    first.push_back(total);
+    g.blocks = total;
+    const size_t nb = (total + kGroupBucket - 1) / kGroupBucket;
+    g.off_bucket = take(nb * sizeof(uint32_t));
+    g.off_first = take(first.size() * sizeof(uint32_t));
+    g.off_items = take(members.size() * (size_t)g.stride);
+    uint32_t* bucket = reinterpret_cast<uint32_t*>(plan.image.data() + g.off_bucket);
+    for (size_t b = 0, j = 0; b < nb; ++b) {
+      const uint32_t w = (uint32_t)(b * kGroupBucket);
+      while (first[j + 1] <= w) ++j;
+      bucket[b] = (uint32_t)j;
+    }
+    std::memcpy(plan.image.data() + g.off_first, first.data(), first.size() * sizeof(uint32_t));
+    for (size_t j = 0; j < members.size(); ++j)
+      std::memcpy(plan.image.data() + g.off_items + j * g.stride, members[j]->item.data(), g.stride);
+    out.push_back(g);
+  }
+}
+
+// Problems with the same launch sequence (the same kernels in the same order)
+// share a shard, where their launches group fully; the shards, balanced by
+// their workgroup counts, run on the internal streams side by side.
+void group_plan(GroupPlan& plan, int S) {
+  std::map<std::vector<const void*>, std::vector<size_t>> by_seq;
+  std::map<std::vector<const void*>, uint64_t> weight;
+  for (size_t p = 0; p < plan.recs.size(); ++p) {
+    std::vector<const void*> sig;
+    uint64_t w = 0;
+    for (const LaunchRec& r : plan.recs[p].recs) {
+      sig.push_back(r.kgrp);
+      w += (uint64_t)r.grid.x * r.grid.y * r.grid.z;
+    }
+    by_seq[sig].push_back(p);
+    weight[sig] += w;
+  }
+  std::vector<std::pair<uint64_t, const std::vector<size_t>*>> order;
+  for (const auto& kv : by_seq) order.push_back({weight[kv.first], &kv.second});
+  std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<std::vector<size_t>> members((size_t)S);
+  std::vector<uint64_t> load((size_t)S, 0);
+  for (const auto& o : order) {
+    const size_t s = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    members[s].insert(members[s].end(), o.second->begin(), o.second->end());
+    load[s] += o.first;
+  }
+  plan.shards.assign((size_t)S, {});
+  for (int s = 0; s < S; ++s) {
+    std::sort(members[(size_t)s].begin(), members[(size_t)s].end());
+    group_shard(plan, members[(size_t)s], plan.shards[(size_t)s]);
+  }
+}
+
+// Copy the table image to `dev` (grown to fit, 256-aligned) through the
+// context's pinned buffer, on stream st.
+int group_upload(comm_ctx* ctx, const GroupPlan& plan, char** dev, size_t* dev_bytes, hipStream_t st) {
+  const size_t n = std::max<size_t>(plan.image.size(), 256);
+  if (!ctx->gtab_copied) HIP_TRY(hipEventCreateWithFlags(&ctx->gtab_copied, hipEventDisableTiming));
+  HIP_TRY(hipEventSynchronize(ctx->gtab_copied));  // the pinned image of the last copy is free again
+  if (ctx->gtab_host_bytes < n) {
+    if (ctx->gtab_host) HIP_TRY(hipHostFree(ctx->gtab_host));
+    ctx->gtab_host = nullptr;
+    ctx->gtab_host_bytes = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->gtab_host), n, hipHostMallocDefault));
+    ctx->gtab_host_bytes = n;
+  }
+  if (*dev_bytes < n) {
+    if (*dev) {
+      // earlier grouped launches may still read the old table
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(*dev));
+    }
+    *dev = nullptr;
+    *dev_bytes = 0;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(dev), n));
+    *dev_bytes = n;
+  }
+  std::memcpy(ctx->gtab_host, plan.image.data(), plan.image.size());
+  HIP_TRY(hipMemcpyAsync(*dev, ctx->gtab_host, plan.image.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(ctx->gtab_copied, st));
+  return COMM_OK;
+}
+
+int group_launch(const GroupLaunch& g, const char* dev, hipStream_t st) {
+  if (!g.kgrp) return g.rec->fn(st) == hipSuccess ? COMM_OK : fail(COMM_EHIP, "launch failed");
+  GroupTable t;
+  // (C-style casts: in the device compilation pass these members are in the
+  // constant address space)
+  t.bucket = (decltype(t.bucket))(dev + g.off_bucket);
+  t.first = (decltype(t.first))(dev + g.off_first);
+  t.items = (decltype(t.items))(dev + g.off_items);
+  t.stride = g.stride;
+  void* args[] = {&t};
+  HIP_TRY(hipLaunchKernel(g.kgrp, dim3(g.blocks), g.block, args, g.shmem, st));
+  return COMM_OK;
+}
+
+// The shards on the internal streams, forked from and joined to `origin`.
+int group_issue(comm_ctx* ctx, const GroupPlan& plan, const char* dev, hipStream_t origin) {
+  const size_t S = ctx->bstreams.size();
+  HIP_TRY(hipEventRecord(ctx->bfork, origin));
+  for (hipStream_t q : ctx->bstreams) HIP_TRY(hipStreamWaitEvent(q, ctx->bfork, 0));
+  for (size_t s = 0; s < plan.shards.size() && s < S; ++s)
+    for (const GroupLaunch& g : plan.shards[s]) {
+      const int rc = group_launch(g, dev, ctx->bstreams[s]);
+      if (rc) return rc;
+    }
+  for (size_t q = 0; q < S; ++q) {
+    HIP_TRY(hipEventRecord(ctx->bjoin[q], ctx->bstreams[q]));
+    HIP_TRY(hipStreamWaitEvent(origin, ctx->bjoin[q], 0));
+  }
+  return COMM_OK;
+}
+
 int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags, hipStream_t st) {
   std::vector<BatchItem> items((size_t)count);
   size_t total = 0;
@@ -1695,20 +1915,44 @@ int jcomm_batched(comm_ctx* ctx, const comm_problem* probs, int count, int flags
   int rc = batch_resources(ctx);
   if (rc) return rc;
   if ((rc = batch_ensure_ws(ctx, total, st))) return rc;
+  // grouped launches: dense problems of order 3 (the only ones whose launchers
+  // all have grouped twins); otherwise the problems run one by one
+  bool grouped = (flags & COMM_BATCH_GROUPED) != 0;
+  for (const BatchItem& it : items) grouped = grouped && it.x.ndim == 3;
   if (!(flags & COMM_BATCH_GRAPH)) {
-    rc = batch_issue(ctx, items, st);
+    if (grouped) {
+      GroupPlan plan;
+      if ((rc = group_record(ctx, items, plan))) return rc;
+      group_plan(plan, (int)ctx->bstreams.size());
+      // the eager table is rewritten: launches of an earlier call on another
+      // stream must be done with it
+      if (ctx->glast && ctx->glast != st) HIP_TRY(hipStreamSynchronize(ctx->glast));
+      if ((rc = group_upload(ctx, plan, &ctx->gtab, &ctx->gtab_bytes, st))) return rc;
+      rc = group_issue(ctx, plan, ctx->gtab, st);
+    } else {
+      rc = batch_issue(ctx, items, st);
+    }
     ctx->glast = st;
     return rc;
   }
   std::vector<int64_t> key = batch_key(items, ctx->bws);
+  key.push_back(grouped ? 1 : 0);
   if (!ctx->gexec || key != ctx->gkey) {
     // a different problem list: wait for the old graph's replays, then capture anew
     if (ctx->gexec) {
       if ((rc = batch_sync_all(ctx, st))) return rc;
       if ((rc = batch_drop_graph(ctx))) return rc;
     }
+    GroupPlan plan;
+    if (grouped) {
+      // the graph's table is written before the capture and kept with the graph
+      if ((rc = group_record(ctx, items, plan))) return rc;
+      group_plan(plan, (int)ctx->bstreams.size());
+      if ((rc = group_upload(ctx, plan, &ctx->gtab_graph, &ctx->gtab_graph_bytes, st))) return rc;
+      HIP_TRY(hipStreamSynchronize(st));
+    }
     HIP_TRY(hipStreamBeginCapture(ctx->bcapture, hipStreamCaptureModeThreadLocal));
-    rc = batch_issue(ctx, items, ctx->bcapture);
+    rc = grouped ? group_issue(ctx, plan, ctx->gtab_graph, ctx->bcapture) : batch_issue(ctx, items, ctx->bcapture);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->bcapture, &g);
     if (rc) {
@@ -1779,6 +2023,10 @@ int comm_destroy(comm_ctx* ctx) {
     for (hipStream_t q : ctx->bstreams) hipStreamDestroy(q);
     for (hipEvent_t e : ctx->bjoin) hipEventDestroy(e);
     if (ctx->bcapture) hipStreamDestroy(ctx->bcapture);
+    if (ctx->gtab) hipFree(ctx->gtab);
+    if (ctx->gtab_graph) hipFree(ctx->gtab_graph);
+    if (ctx->gtab_host) hipHostFree(ctx->gtab_host);
+    if (ctx->gtab_copied) hipEventDestroy(ctx->gtab_copied);
     if (ctx->aux) hipFree(ctx->aux);
     if (ctx->sws) hipFree(ctx->sws);
     if (ctx->bfork) hipEventDestroy(ctx->bfork);
@@ -2077,7 +2325,7 @@ int comm_jcomm_outer_batched(comm_ctx* ctx, const comm_problem* problems, int co
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
     if (count < 0 || (count > 0 && !problems)) return fail(COMM_EINVAL, "count = %d with problems = %p", count,
                                                            (const void*)problems);
-    if (flags & ~COMM_BATCH_GRAPH) return fail(COMM_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(COMM_BATCH_GRAPH | COMM_BATCH_GROUPED)) return fail(COMM_EINVAL, "unknown flags 0x%x", flags);
     // every problem's arguments before anything touches the device
     for (int p = 0; p < count; ++p) {
       const comm_problem& q = problems[p];

@@ -34,11 +34,11 @@ hipError_t launch_cp_vpass(const CpPassArgs& a, int beta_class, hipStream_t s) {
 
 // M2 chunks from the kept V (see launch_vfold): thread = (j, r) of an 8-j
 // block, sum over its chunk of i in order.
-__global__ void __launch_bounds__(256) vfold_kernel(VFoldArgs a) {
+__device__ __forceinline__ void vfold_body(const VFoldArgs& a, uint3 bid, uint3) {
   const int jl = threadIdx.x >> 5, r = threadIdx.x & 31;
-  const int j = blockIdx.x * 8 + jl;
-  const int c = blockIdx.y;
-  const bool den = blockIdx.z == 1;
+  const int j = bid.x * 8 + jl;
+  const int c = bid.y;
+  const bool den = bid.z == 1;
   if (j >= a.J) return;
   const int ci = (a.I + kVFoldChunks - 1) / kVFoldChunks;
   const int ib = c * ci, ie = min(a.I, ib + ci);
@@ -54,10 +54,11 @@ __global__ void __launch_bounds__(256) vfold_kernel(VFoldArgs a) {
   float* out = den ? a.outd : a.outn;
   out[((size_t)c * a.Jp + j) * kRP + r] = s0 + s1;
 }
+COMM_GROUPED_KERNELS(vfold, VFoldArgs, 256)
 
 hipError_t launch_vfold(const VFoldArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(vfold_kernel, dim3((unsigned)((a.J + 7) / 8), kVFoldChunks, 2), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return launch_or_record(vfold_kernel, vfold_grouped, dim3((unsigned)((a.J + 7) / 8), kVFoldChunks, 2), dim3(256), 0,
+                          s, a);
 }
 
 }  // namespace comm

@@ -41,6 +41,7 @@
 
 #pragma once
 
+#include "group.h"
 #include "kernels.h"
 
 namespace comm {
@@ -816,9 +817,8 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
 }
 
 template <int BC, int kVar, bool kObj, bool kBf, bool kR16>
-__global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
+__device__ __forceinline__ void cp3_pass_entry(const CpPassArgs& a, int wg, int gj, int gk) {
   __shared__ PassShared sh;
-  const int wg = blockIdx.x;
   const int bk = wg % gk;
   const int bij = wg / gk;
   const int bj = bij % gj;
@@ -829,6 +829,24 @@ __global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pa
     pass_body<BC, kVar, kObj, true, kBf, kR16>(a, sh, wg, bi, bj, bk, gj, gk);
   else
     pass_body<BC, kVar, kObj, false, kBf, kR16>(a, sh, wg, bi, bj, bk, gj, gk);
+}
+
+template <int BC, int kVar, bool kObj, bool kBf, bool kR16>
+__global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
+  cp3_pass_entry<BC, kVar, kObj, kBf, kR16>(a, blockIdx.x, gj, gk);
+}
+
+// The pass launch of one problem in a grouped launch.
+struct CpPassLaunch {
+  CpPassArgs a;
+  int gj, gk;
+};
+
+template <int BC, int kVar, bool kObj, bool kBf, bool kR16>
+__global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pass_grouped(GroupTable t) {
+  uint3 bid, gdim;
+  const CpPassLaunch& l = group_item<CpPassLaunch>(t, bid, gdim);
+  cp3_pass_entry<BC, kVar, kObj, kBf, kR16>(l.a, (int)bid.x, l.gj, l.gk);
 }
 
 // ---------------------------------------------------------------------------------------- V pass
@@ -859,7 +877,7 @@ struct VPassShared {
 };
 
 template <int BC, bool kCache, bool kObj, bool kBf, bool kInterior>
-__device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh, int bi, int bj) {
+__device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh, int bi, int bj, int wg) {
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -1031,7 +1049,6 @@ __device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh,
     if (lane == 0) sh.obj[w] = obj;
   }
   __syncthreads();
-  const int wg = blockIdx.x;
   if (kObj && tid == 0) {
     double sum = sh.obj[0];
     for (int q = 1; q < kWaves; ++q) sum += sh.obj[q];
@@ -1048,14 +1065,31 @@ __device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh,
 }
 
 template <int BC, bool kCache, bool kObj, bool kBf>
-__global__ void __launch_bounds__(kThreads, kObj ? 1 : 2) cp3_vpass_kernel(CpPassArgs a, int gj) {
+__device__ __forceinline__ void cp3_vpass_entry(const CpPassArgs& a, int wg, int gj) {
   __shared__ VPassShared sh;
-  const int bi = blockIdx.x / gj, bj = blockIdx.x % gj;
+  const int bi = wg / gj, bj = wg % gj;
   const bool interior = a.xbuf && (bi + 1) * kVTI <= a.I && (bj + 1) * kVTJ <= a.J;
   if (interior)
-    vpass_body<BC, kCache, kObj, kBf, true>(a, sh, bi, bj);
+    vpass_body<BC, kCache, kObj, kBf, true>(a, sh, bi, bj, wg);
   else
-    vpass_body<BC, kCache, kObj, kBf, false>(a, sh, bi, bj);
+    vpass_body<BC, kCache, kObj, kBf, false>(a, sh, bi, bj, wg);
+}
+
+template <int BC, bool kCache, bool kObj, bool kBf>
+__global__ void __launch_bounds__(kThreads, kObj ? 1 : 2) cp3_vpass_kernel(CpPassArgs a, int gj) {
+  cp3_vpass_entry<BC, kCache, kObj, kBf>(a, blockIdx.x, gj);
+}
+
+struct CpVPassLaunch {
+  CpPassArgs a;
+  int gj;
+};
+
+template <int BC, bool kCache, bool kObj, bool kBf>
+__global__ void __launch_bounds__(kThreads, kObj ? 1 : 2) cp3_vpass_grouped(GroupTable t) {
+  uint3 bid, gdim;
+  const CpVPassLaunch& l = group_item<CpVPassLaunch>(t, bid, gdim);
+  cp3_vpass_entry<BC, kCache, kObj, kBf>(l.a, (int)bid.x, l.gj);
 }
 
 inline int64_t vpass_wgs(int I, int J) { return (int64_t)((I + kVTI - 1) / kVTI) * ((J + kVTJ - 1) / kVTJ); }
@@ -1064,10 +1098,14 @@ template <int BC, bool kCache, bool kObj>
 hipError_t launch_vpass_t(const CpPassArgs& a, hipStream_t s) {
   const int gj = (a.J + kVTJ - 1) / kVTJ;
   const dim3 grid((unsigned)vpass_wgs(a.I, a.J));
-  if (a.bf16)
+  const CpVPassLaunch l{a, gj};
+  if (a.bf16) {
+    if (record_grouped(cp3_vpass_grouped<BC, kCache, kObj, true>, grid, dim3(kThreads), 0, l)) return hipSuccess;
     hipLaunchKernelGGL((cp3_vpass_kernel<BC, kCache, kObj, true>), grid, dim3(kThreads), 0, s, a, gj);
-  else
+  } else {
+    if (record_grouped(cp3_vpass_grouped<BC, kCache, kObj, false>, grid, dim3(kThreads), 0, l)) return hipSuccess;
     hipLaunchKernelGGL((cp3_vpass_kernel<BC, kCache, kObj, false>), grid, dim3(kThreads), 0, s, a, gj);
+  }
   return hipGetLastError();
 }
 
@@ -1078,15 +1116,18 @@ hipError_t launch_vpass_bc(const CpPassArgs& a, hipStream_t s) {
 
 template <int BC, int kVar, bool kObj>
 hipError_t launch_v(const CpPassArgs& a, const CpGrid& g, hipStream_t s) {
-  if (a.bf16)
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, true, false>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s,
-                       a, g.gj, g.gk);
-  else if (a.r16)
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, true>), dim3((unsigned)g.wgs()), dim3(kThreads), 0, s,
-                       a, g.gj, g.gk);
-  else
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, false>), dim3((unsigned)g.wgs()), dim3(kThreads), 0,
-                       s, a, g.gj, g.gk);
+  const dim3 grid((unsigned)g.wgs()), block(kThreads);
+  const CpPassLaunch l{a, g.gj, g.gk};
+  if (a.bf16) {
+    if (record_grouped(cp3_pass_grouped<BC, kVar, kObj, true, false>, grid, block, 0, l)) return hipSuccess;
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, true, false>), grid, block, 0, s, a, g.gj, g.gk);
+  } else if (a.r16) {
+    if (record_grouped(cp3_pass_grouped<BC, kVar, kObj, false, true>, grid, block, 0, l)) return hipSuccess;
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, true>), grid, block, 0, s, a, g.gj, g.gk);
+  } else {
+    if (record_grouped(cp3_pass_grouped<BC, kVar, kObj, false, false>, grid, block, 0, l)) return hipSuccess;
+    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, false>), grid, block, 0, s, a, g.gj, g.gk);
+  }
   return hipGetLastError();
 }
 

@@ -69,6 +69,15 @@ struct comm_ctx {
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gkey;
   hipStream_t glast = nullptr;
+  // grouped batches: the launch tables (device: one for eager calls, one
+  // owned by the captured graph) and the pinned host image they are copied from
+  char* gtab = nullptr;
+  size_t gtab_bytes = 0;
+  char* gtab_graph = nullptr;
+  size_t gtab_graph_bytes = 0;
+  char* gtab_host = nullptr;
+  size_t gtab_host_bytes = 0;
+  hipEvent_t gtab_copied = nullptr;
   // sparse data at beta != 1 and sparse Tucker: the sparse steps' own
   // buffers (per-nonzero weights, one numerator, objective partials)
   char* sws = nullptr;

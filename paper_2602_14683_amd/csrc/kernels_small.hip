@@ -6,6 +6,7 @@
 // CP.  Every reduction has a fixed order, so results are bitwise
 // deterministic.
 
+#include "group.h"
 #include "kernels.h"
 
 namespace comm {
@@ -13,8 +14,8 @@ namespace comm {
 // ----------------------------------------------------------------------------------------
 // Padding copies of up to 4 factors in one launch.
 
-__global__ void pad_factors_kernel(PadArgs a) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pad_factors_body(const PadArgs& a, uint3 bid, uint3) {
+  int64_t e = (int64_t)bid.x * blockDim.x + threadIdx.x;
   int f = 0;
   while (f < a.nf && e >= (int64_t)a.rows_p[f] * kRP) {
     e -= (int64_t)a.rows_p[f] * kRP;
@@ -28,12 +29,13 @@ __global__ void pad_factors_kernel(PadArgs a) {
   if (a.dst2[f]) a.dst2[f][e] = v;
   if (a.dst2T[f]) a.dst2T[f][(int64_t)c * a.rows_p[f] + row] = v;
 }
+COMM_GROUPED_KERNELS(pad_factors, PadArgs, 256)
 
 hipError_t launch_pad_factors(const PadArgs& a, hipStream_t s) {
   int64_t n = 0;
   for (int f = 0; f < a.nf; ++f) n += (int64_t)a.rows_p[f] * kRP;
-  hipLaunchKernelGGL(pad_factors_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return launch_or_record(pad_factors_kernel, pad_factors_grouped, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                          a);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -46,7 +48,7 @@ struct ColsumArgs {
   float* prod;       // prod[c] = product over the nf factors of the column sums
 };
 
-__global__ void __launch_bounds__(256) colsum_prod_kernel(ColsumArgs a) {
+__device__ __forceinline__ void colsum_prod_body(const ColsumArgs& a, uint3, uint3) {
   __shared__ float part[8 * 32];
   __shared__ float res[kMaxModes][32];
   const int t = threadIdx.x;
@@ -69,6 +71,7 @@ __global__ void __launch_bounds__(256) colsum_prod_kernel(ColsumArgs a) {
     a.prod[t] = p;
   }
 }
+COMM_GROUPED_KERNELS(colsum_prod, ColsumArgs, 256)
 
 hipError_t launch_colsum_prod(const FView* F, const int* rows, int nf, float* prod, hipStream_t s) {
   ColsumArgs a = {};
@@ -78,15 +81,14 @@ hipError_t launch_colsum_prod(const FView* F, const int* rows, int nf, float* pr
   }
   a.nf = nf;
   a.prod = prod;
-  hipLaunchKernelGGL(colsum_prod_kernel, dim3(1), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return launch_or_record(colsum_prod_kernel, colsum_prod_grouped, dim3(1), dim3(256), 0, s, a);
 }
 
 // ----------------------------------------------------------------------------------------
 // chi transforms of up to 4 factors in one launch
 
-__global__ void chi_kernel(ChiArgs a) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void chi_body(const ChiArgs& a, uint3 bid, uint3) {
+  int64_t e = (int64_t)bid.x * blockDim.x + threadIdx.x;
   int f = 0;
   while (f < a.nf && e >= (int64_t)a.rows_p[f] * kRP) {
     e -= (int64_t)a.rows_p[f] * kRP;
@@ -109,12 +111,12 @@ __global__ void chi_kernel(ChiArgs a) {
   if (a.x1T[f]) a.x1T[f][(int64_t)c * a.rows_p[f] + row] = c1;
   if (a.x2T[f]) a.x2T[f][(int64_t)c * a.rows_p[f] + row] = c2;
 }
+COMM_GROUPED_KERNELS(chi, ChiArgs, 256)
 
 hipError_t launch_chi(const ChiArgs& a, hipStream_t s) {
   int64_t n = 0;
   for (int f = 0; f < a.nf; ++f) n += (int64_t)a.rows_p[f] * kRP;
-  hipLaunchKernelGGL(chi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return launch_or_record(chi_kernel, chi_grouped, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -133,16 +135,22 @@ __device__ double block_sum_f64(const double* __restrict__ part, int64_t n, doub
   return lds[0];
 }
 
-__global__ void __launch_bounds__(1024) sum_f64_kernel(const double* __restrict__ part, int64_t n,
-                                                       const double* __restrict__ add_to, double* __restrict__ out) {
+struct SumF64Args {
+  const double* part;
+  int64_t n;
+  const double* add_to;
+  double* out;
+};
+
+__device__ __forceinline__ void sum_f64_body(const SumF64Args& a, uint3, uint3) {
   __shared__ double lds[1024];
-  const double s = block_sum_f64(part, n, lds);
-  if (threadIdx.x == 0) out[0] = s + (add_to ? add_to[0] : 0.0);
+  const double s = block_sum_f64(a.part, a.n, lds);
+  if (threadIdx.x == 0) a.out[0] = s + (a.add_to ? a.add_to[0] : 0.0);
 }
+COMM_GROUPED_KERNELS(sum_f64, SumF64Args, 1024)
 
 hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_f64_kernel, dim3(1), dim3(1024), 0, s, part, n, add_to, out);
-  return hipGetLastError();
+  return launch_or_record(sum_f64_kernel, sum_f64_grouped, dim3(1), dim3(1024), 0, s, SumF64Args{part, n, add_to, out});
 }
 
 // ----------------------------------------------------------------------------------------
@@ -165,7 +173,7 @@ hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, d
 // sweeps on 32-wide vectors in wavefront 0, and leaves the last denominators in
 // den_last.  Every workgroup of kl_apply runs it on the same data in the same
 // order, so all of them agree bitwise without synchronising.
-__device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
+__device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsigned bx) {
   __shared__ float red[3 * kMaxModes][32][33];
   __shared__ float S[kMaxModes][32], T[kMaxModes][32], Cmin[kMaxModes][32];
   __shared__ double lds64[1024];
@@ -228,7 +236,7 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
     if (t < w) lds64[t] += lds64[t + w];
   }
   __syncthreads();
-  if (a.obj_out && t == 0 && blockIdx.x == 0) {
+  if (a.obj_out && t == 0 && bx == 0) {
     double s = lds64[0];
     if (a.obj_add_model_mass) {
       // sum over all cells of the reference model: sum_r prod_n colsum(A~^(n))_r
@@ -300,14 +308,14 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32]) {
 
 // A^(n) = max(c^(n) / Den_last^(n), eps) for all modes; each workgroup first
 // runs the recurrence itself.
-__global__ void __launch_bounds__(1024) kl_apply_kernel(KlLoopArgs a) {
+__device__ __forceinline__ void kl_apply_body(const KlLoopArgs& a, uint3 bid, uint3 gdim) {
   __shared__ float den_last[kMaxModes][32];
-  kl_recurrence(a, den_last);
+  kl_recurrence(a, den_last, bid.x);
   __syncthreads();
   int64_t total = 0;
   for (int n = 0; n < a.N; ++n) total += (int64_t)a.rows[n] * kRP;
-  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < total;
-       e0 += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e0 = (int64_t)bid.x * blockDim.x + threadIdx.x; e0 < total;
+       e0 += (int64_t)gdim.x * blockDim.x) {
     int64_t e = e0;
     int n = 0;
     while (n < a.N && e >= (int64_t)a.rows[n] * kRP) {
@@ -321,6 +329,7 @@ __global__ void __launch_bounds__(1024) kl_apply_kernel(KlLoopArgs a) {
     if (a.cur_pad[n]) a.cur_pad[n][e] = v;
   }
 }
+COMM_GROUPED_KERNELS(kl_apply, KlLoopArgs, 1024)
 
 // ----------------------------------------------------------------------------------------
 // Slot reduction + update.  A workgroup covers kSlotRows rows x 32 columns of
@@ -359,11 +368,11 @@ __device__ __forceinline__ float combine_groups(const float (*l)[kSlotOut], int 
   return s;
 }
 
-__global__ void __launch_bounds__(1024) slot_update_kernel(SlotUpdateArgs a) {
+__device__ __forceinline__ void slot_update_body(const SlotUpdateArgs& a, uint3 bid, uint3) {
   __shared__ float lnum[kSlotGroups][kSlotOut];
   __shared__ float lden[kSlotGroups][kSlotOut];
   __shared__ float lc[kSlotOut], la[kSlotOut];
-  int b = blockIdx.x;
+  int b = (int)bid.x;
   int j = 0;
   while (j < a.njobs && b >= (a.job[j].rows_p + kSlotRows - 1) / kSlotRows) {
     b -= (a.job[j].rows_p + kSlotRows - 1) / kSlotRows;
@@ -422,11 +431,12 @@ __global__ void __launch_bounds__(1024) slot_update_kernel(SlotUpdateArgs a) {
   }
 }
 
+COMM_GROUPED_KERNELS(slot_update, SlotUpdateArgs, 1024)
+
 hipError_t launch_slot_update(const SlotUpdateArgs& a, hipStream_t s) {
   int blocks = 0;
   for (int j = 0; j < a.njobs; ++j) blocks += (a.job[j].rows_p + kSlotRows - 1) / kSlotRows;
-  hipLaunchKernelGGL(slot_update_kernel, dim3(blocks), dim3(1024), 0, s, a);
-  return hipGetLastError();
+  return launch_or_record(slot_update_kernel, slot_update_grouped, dim3(blocks), dim3(1024), 0, s, a);
 }
 
 // Debug check of caller inputs: sets `bit` in *flag when one of the n values
@@ -453,8 +463,7 @@ hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s) {
   for (int q = 0; q < a.N; ++q) n += (int64_t)a.rows[q] * kRP;
   int blocks = (int)((n + 1023) / 1024);
   if (blocks > 64) blocks = 64;
-  hipLaunchKernelGGL(kl_apply_kernel, dim3(blocks), dim3(1024), 0, s, a);
-  return hipGetLastError();
+return launch_or_record(kl_apply_kernel, kl_apply_grouped, dim3(blocks), dim3(1024), 0, s, a);
 }
 
 // ----------------------------------------------------------------------------------------

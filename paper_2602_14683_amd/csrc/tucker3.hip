@@ -49,11 +49,11 @@ struct T2Args {
 // coalesced stores (zero for c >= J3).  Each slab recomputes T1 (J1 J2 J3
 // products): cheaper than the latency of a workgroup that walks all of J.
 constexpr int kT2Slab = 32 * kWaves;
-__global__ void __launch_bounds__(256) tk_t2_kernel(T2Args t) {
+__device__ __forceinline__ void tk_t2_body(const T2Args& t, uint3 bid, uint3) {
   __shared__ float t1[32][33];
   __shared__ float sa[32];
   const int nslab = (t.J + kT2Slab - 1) / kT2Slab;
-  const int i = blockIdx.x % t.I, slab = (blockIdx.x / t.I) % nslab, set = blockIdx.x / (t.I * nslab);
+  const int i = bid.x % t.I, slab = (bid.x / t.I) % nslab, set = bid.x / (t.I * nslab);
   const TkModel& m = t.m[set];
   const int I = t.I, J = t.J;
   if (threadIdx.x < 32) sa[threadIdx.x] = (int)threadIdx.x < m.J1 ? m.A.at(i, threadIdx.x, I) : 0.0f;
@@ -104,6 +104,7 @@ __global__ void __launch_bounds__(256) tk_t2_kernel(T2Args t) {
     for (int e = threadIdx.x; e < 32 * pad; e += 256) outT[(int64_t)(e / pad) * t.Pp + np + e % pad] = 0.0f;
   }
 }
+COMM_GROUPED_KERNELS(tk_t2, T2Args, 256)
 
 hipError_t launch_tk_t2(const TkModel* m, float* const* T2, float* const* T2T, int sets, int I, int J, int64_t Pp,
                         hipStream_t s) {
@@ -117,8 +118,7 @@ hipError_t launch_tk_t2(const TkModel* m, float* const* T2, float* const* T2T, i
   t.J = J;
   t.Pp = Pp;
   const int nslab = (J + kT2Slab - 1) / kT2Slab;
-  hipLaunchKernelGGL(tk_t2_kernel, dim3((unsigned)(I * nslab * sets)), dim3(256), 0, s, t);
-  return hipGetLastError();
+  return launch_or_record(tk_t2_kernel, tk_t2_grouped, dim3((unsigned)(I * nslab * sets)), dim3(256), 0, s, t);
 }
 
 // ---------------------------------------------------------------------------------------- GEMM
@@ -129,10 +129,10 @@ hipError_t launch_tk_t2(const TkModel* m, float* const* T2, float* const* T2T, i
 // k = 2 s + h); operands of 16 steps are loaded before they are used.
 constexpr int kGemmBatch = 16;
 
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_body(const GemmArgs& g, uint3 bid, uint3) {
   __shared__ float red[kWaves][32 * 33];
   const int tiles_m = (g.M + 31) / 32, tiles_n = (g.N + 31) / 32;
-  int64_t id = blockIdx.x;
+  int64_t id = bid.x;
   const int tn = (int)(id % tiles_n);
   id /= tiles_n;
   const int tm = (int)(id % tiles_m);
@@ -181,16 +181,27 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   }
 }
 
+COMM_GROUPED_KERNELS(gemm, GemmArgs, 256)
+
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   const int64_t tiles = (int64_t)((g.M + 31) / 32) * ((g.N + 31) / 32) * g.batch * g.splits * g.sets;
-  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)tiles), dim3(256), 0, s, g);
-  return hipGetLastError();
+  return launch_or_record(gemm_kernel, gemm_grouped, dim3((unsigned)tiles), dim3(256), 0, s, g);
 }
 
 // ---------------------------------------------------------------------------------------- closed-form den
 
-__global__ void __launch_bounds__(1024) tk_den_closed_kernel(TkModel m, int I, int J, int K, float* den,
-                                                             float* dcore) {
+struct TkDenArgs {
+  TkModel m;
+  int I, J, K;
+  float* den;
+  float* dcore;
+};
+
+__device__ __forceinline__ void tk_den_closed_body(const TkDenArgs& args, uint3, uint3) {
+  const TkModel& m = args.m;
+  const int I = args.I, J = args.J, K = args.K;
+  float* den = args.den;
+  float* dcore = args.dcore;
   __shared__ float red[32][33];
   __shared__ float S[3][32];
   __shared__ float T1[32][33], T2[32][33];
@@ -242,9 +253,11 @@ __global__ void __launch_bounds__(1024) tk_den_closed_kernel(TkModel m, int I, i
   }
 }
 
+COMM_GROUPED_KERNELS(tk_den_closed, TkDenArgs, 1024)
+
 hipError_t launch_tk_den_closed(const TkModel& m, int I, int J, int K, float* den, float* dcore, hipStream_t s) {
-  hipLaunchKernelGGL(tk_den_closed_kernel, dim3(1), dim3(1024), 0, s, m, I, J, K, den, dcore);
-  return hipGetLastError();
+  return launch_or_record(tk_den_closed_kernel, tk_den_closed_grouped, dim3(1), dim3(1024), 0, s,
+                          TkDenArgs{m, I, J, K, den, dcore});
 }
 
 }  // namespace comm

@@ -66,14 +66,14 @@ __device__ __forceinline__ void load_fibre(const float* __restrict__ row, int64_
 }
 
 template <int BC, int kMode, bool kObj, int kSets, bool kBf>
-__global__ void __launch_bounds__(kThreads, 4) tk_v_kernel(TkPassArgs a) {
+__device__ __forceinline__ void tk_v_body(const TkPassArgs& a, unsigned bx) {
   __shared__ float red[kWaves][kSets > 0 ? kSets : 1][32 * 33];
   __shared__ double sobj[kWaves];
   const int lane = threadIdx.x & 63;
   const int col = lane & 31, h = lane >> 5;
   const int w = threadIdx.x >> 6;
   const int64_t npairs = (int64_t)a.I * a.J;
-  const int64_t p0 = (int64_t)blockIdx.x * 32;
+  const int64_t p0 = (int64_t)bx * 32;
   const int64_t pm = p0 + col;  // this lane's pair
   const bool pvalid = pm < npairs;
   const int K = a.K;
@@ -210,22 +210,34 @@ __global__ void __launch_bounds__(kThreads, 4) tk_v_kernel(TkPassArgs a) {
     if (threadIdx.x == 0) {
       double s = sobj[0];
       for (int q = 1; q < kWaves; ++q) s += sobj[q];
-      a.obj_part[blockIdx.x] = s;
+      a.obj_part[bx] = s;
     }
   }
+}
+
+template <int BC, int kMode, bool kObj, int kSets, bool kBf>
+__global__ void __launch_bounds__(kThreads, 4) tk_v_kernel(TkPassArgs a) {
+  tk_v_body<BC, kMode, kObj, kSets, kBf>(a, blockIdx.x);
+}
+
+template <int BC, int kMode, bool kObj, int kSets, bool kBf>
+__global__ void __launch_bounds__(kThreads, 4) tk_v_grouped(GroupTable t) {
+  uint3 bid, gdim;
+  const TkPassArgs& a = group_item<TkPassArgs>(t, bid, gdim);
+  tk_v_body<BC, kMode, kObj, kSets, kBf>(a, bid.x);
 }
 
 // Mode-3 pass.  Workgroup (kt, g): k tile kt, pair group g of 4 * tpw pair
 // tiles; wave w takes tiles g * 4 * tpw + w * tpw + t, t < tpw.
 template <int BC, int kMode, int kSets, bool kBf>
-__global__ void __launch_bounds__(kThreads, 3) tk_m3_kernel(TkPassArgs a) {
+__device__ __forceinline__ void tk_m3_body(const TkPassArgs& a, unsigned bx) {
   __shared__ float red[kWaves][2][32 * 33];
   const int lane = threadIdx.x & 63;
   const int col = lane & 31, h = lane >> 5;
   const int w = threadIdx.x >> 6;
   const int K = a.K;
   const int nkt = (K + 31) / 32;
-  const int kt = blockIdx.x % nkt, g = blockIdx.x / nkt;
+  const int kt = bx % nkt, g = bx / nkt;
   const int k0 = kt * 32;
   const int kcol = k0 + col;
   const bool kvalid = kcol < K;
@@ -334,21 +346,37 @@ __global__ void __launch_bounds__(kThreads, 3) tk_m3_kernel(TkPassArgs a) {
   }
 }
 
+template <int BC, int kMode, int kSets, bool kBf>
+__global__ void __launch_bounds__(kThreads, 3) tk_m3_kernel(TkPassArgs a) {
+  tk_m3_body<BC, kMode, kSets, kBf>(a, blockIdx.x);
+}
+
+template <int BC, int kMode, int kSets, bool kBf>
+__global__ void __launch_bounds__(kThreads, 3) tk_m3_grouped(GroupTable t) {
+  uint3 bid, gdim;
+  const TkPassArgs& a = group_item<TkPassArgs>(t, bid, gdim);
+  tk_m3_body<BC, kMode, kSets, kBf>(a, bid.x);
+}
+
 template <int BC, int kMode, bool kObj, int kSets>
 hipError_t launch_v(const TkPassArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)tk_v_workgroups(a.I, a.J)), block(kThreads);
-  if (a.bf16) hipLaunchKernelGGL((tk_v_kernel<BC, kMode, kObj, kSets, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((tk_v_kernel<BC, kMode, kObj, kSets, false>), grid, block, 0, s, a);
-  return hipGetLastError();
+  if (a.bf16)
+    return launch_or_record(tk_v_kernel<BC, kMode, kObj, kSets, true>, tk_v_grouped<BC, kMode, kObj, kSets, true>, grid,
+                            block, 0, s, a);
+  return launch_or_record(tk_v_kernel<BC, kMode, kObj, kSets, false>, tk_v_grouped<BC, kMode, kObj, kSets, false>, grid,
+                          block, 0, s, a);
 }
 
 template <int BC, int kMode, int kSets>
 hipError_t launch_m3(const TkPassArgs& a, hipStream_t s) {
   const int nkt = (a.K + 31) / 32;
   const dim3 grid((unsigned)(nkt * a.npg)), block(kThreads);
-  if (a.bf16) hipLaunchKernelGGL((tk_m3_kernel<BC, kMode, kSets, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((tk_m3_kernel<BC, kMode, kSets, false>), grid, block, 0, s, a);
-  return hipGetLastError();
+  if (a.bf16)
+    return launch_or_record(tk_m3_kernel<BC, kMode, kSets, true>, tk_m3_grouped<BC, kMode, kSets, true>, grid, block, 0,
+                            s, a);
+  return launch_or_record(tk_m3_kernel<BC, kMode, kSets, false>, tk_m3_grouped<BC, kMode, kSets, false>, grid, block, 0,
+                          s, a);
 }
 
 // Variants used per beta class: beta = 1 contracts P only (its denominators

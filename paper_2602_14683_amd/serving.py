@@ -238,11 +238,13 @@ class _DeviceBase:
 class BatchedExecutor(_DeviceBase):
     """All active requests advance in one ``comm_jcomm_outer_batched`` call; the
     problem list is marshalled once per change of the batch, and with
-    ``graph=True`` the library replays a captured HIP graph until it changes."""
+    ``graph=True`` the library replays a captured HIP graph until it changes;
+    ``grouped=True`` has it launch each kernel once for all requests."""
 
-    def __init__(self, ctx, max_slots: int, graph: bool = True):
+    def __init__(self, ctx, max_slots: int, graph: bool = True, grouped: bool = False):
         super().__init__(ctx, max_slots)
         self.graph = graph
+        self.grouped = grouped
         self._ids = None
         self._batch = None
 
@@ -252,7 +254,7 @@ class BatchedExecutor(_DeviceBase):
         if ids != self._ids:
             self._batch = Batch(handles)
             self._ids = ids
-        self.ctx.jcomm_outer_batched(self._batch, graph=self.graph)
+        self.ctx.jcomm_outer_batched(self._batch, graph=self.graph, grouped=self.grouped)
         host = self.objs.cpu().numpy()
         return [float(host[h["slot"]]) for h in handles]
 

@@ -90,7 +90,8 @@ def _alone_step(ctx, d):
 
 
 @pytest.mark.parametrize("graph", [False, True])
-def test_batched_equals_alone_bitwise(ctx, problems, graph):
+@pytest.mark.parametrize("grouped", [False, True])
+def test_batched_equals_alone_bitwise(ctx, problems, graph, grouped):
     n = len(problems)
     ob_batch = torch.zeros(n, dtype=torch.float64, device="cuda")
     ob_alone = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -98,7 +99,7 @@ def test_batched_equals_alone_bitwise(ctx, problems, graph):
     alo = [_device(p, ob_alone[k:k + 1]) for k, p in enumerate(problems)]
     batch = comm.Batch(bat)
     for it in range(4):
-        ctx.jcomm_outer_batched(batch, graph=graph)
+        ctx.jcomm_outer_batched(batch, graph=graph, grouped=grouped)
         for d in alo:
             _alone_step(ctx, d)
         torch.cuda.synchronize()
@@ -111,13 +112,75 @@ def test_batched_equals_alone_bitwise(ctx, problems, graph):
     sub_alone = [alo[5], alo[0], alo[3], alo[7], alo[1], alo[6]]
     batch2 = comm.Batch(sub)
     for it in range(3):
-        ctx.jcomm_outer_batched(batch2, graph=graph)
+        ctx.jcomm_outer_batched(batch2, graph=graph, grouped=grouped)
         for d in sub_alone:
             _alone_step(ctx, d)
         torch.cuda.synchronize()
         for d, e in zip(sub, sub_alone):
             for a, b in zip(_state(d), _state(e)):
                 assert np.array_equal(a, b), f"changed batch differs at iteration {it}"
+
+
+# repeats of each shape so that grouped launches hold several problems; bf16
+# tiles, ranks on both tile widths, both models, every beta class
+GROUP_MIX = [
+    ("cp", (40, 36, 50), 8, 1.0, 1, False, "fp32"),
+    ("cp", (40, 36, 50), 8, 1.0, 1, False, "fp32"),
+    ("cp", (33, 70, 41), 32, 0.5, 1, True, "fp32"),
+    ("cp", (33, 70, 41), 32, 0.5, 1, True, "fp32"),
+    ("cp", (33, 70, 41), 32, 0.5, 1, False, "bf16"),
+    ("cp", (19, 23, 90), 16, 0.0, 2, False, "fp32"),
+    ("cp", (19, 23, 90), 12, 1.5, 1, True, "fp32"),
+    ("tucker", (30, 28, 26), (6, 5, 4), 1.0, 1, False, "fp32"),
+    ("tucker", (30, 28, 26), (6, 5, 4), 1.0, 1, False, "fp32"),
+    ("tucker", (44, 20, 36), (8, 8, 8), 0.0, 1, True, "fp32"),
+    ("tucker", (44, 20, 36), (8, 8, 8), 1.5, 2, False, "bf16"),
+    ("cp", (256, 17, 33), 4, 0.7, 1, False, "fp32"),
+]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_grouped_repeats_and_precisions_bitwise(ctx, graph):
+    """Grouped launches over repeated shapes, bf16 and float32 tiles: every
+    problem bitwise equal to its single call, over several replays."""
+    probs = [_problem(200 + k, spec[:6]) for k, spec in enumerate(GROUP_MIX)]
+    n = len(probs)
+    ob_b = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ob_a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    bat = [dict(_device(p, ob_b[k:k + 1]), precision=GROUP_MIX[k][6]) for k, p in enumerate(probs)]
+    alo = [dict(_device(p, ob_a[k:k + 1]), precision=GROUP_MIX[k][6]) for k, p in enumerate(probs)]
+    batch = comm.Batch(bat)
+    for it in range(3):
+        ctx.jcomm_outer_batched(batch, graph=graph, grouped=True)
+        for d in alo:
+            ctx.jcomm_outer(d["X"], d["factors"], core=d["core"], beta=d["beta"], L=d["L"], cache_pq=d["cache_pq"],
+                            obj_out=d["obj_out"], precision=d["precision"])
+        torch.cuda.synchronize()
+        assert torch.equal(ob_b, ob_a), f"objectives differ at iteration {it}"
+        for k in range(n):
+            for a, b in zip(_state(bat[k]), _state(alo[k])):
+                assert np.array_equal(a, b), f"problem {k} differs at iteration {it}"
+
+
+def test_grouped_batch_with_order4_runs_ungrouped(ctx, problems):
+    """A batch holding an order-4 problem runs ungrouped, still exact."""
+    rng = np.random.default_rng(7)
+    dims4, R = (6, 7, 8, 9), 3
+    X4 = rng.poisson(ocp.rebuild([rng.uniform(0, 1, size=(d, R)) for d in dims4]) * 3.0).astype(np.float64)
+    init4 = [f32(rng.uniform(0.1, 1.0, size=(d, R))) for d in dims4]
+    obj = torch.zeros(2, dtype=torch.float64, device="cuda")
+    d3 = _device(problems[0], obj[0:1])
+    d4 = {"X": dev(X4), "factors": [dev(a) for a in init4], "core": None, "beta": 1.0, "L": 1, "cache_pq": False,
+          "obj_out": obj[1:2]}
+    e3 = _device(problems[0], torch.zeros(1, dtype=torch.float64, device="cuda"))
+    e4 = dict(d4, factors=[dev(a) for a in init4], obj_out=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    ctx.jcomm_outer_batched(comm.Batch([d3, d4]), grouped=True)
+    for d in (e3, e4):
+        _alone_step(ctx, d)
+    torch.cuda.synchronize()
+    for x, y in ((d3, e3), (d4, e4)):
+        for a, b in zip(_state(x), _state(y)):
+            assert np.array_equal(a, b)
 
 
 def test_batched_matches_oracle(ctx, problems):
