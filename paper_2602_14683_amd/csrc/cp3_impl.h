@@ -359,9 +359,11 @@ __device__ __forceinline__ float mask_of(const FView& f, int row, int c, int row
 }
 
 struct PassShared {
-  float t[kWaves][32 * kLdsT];      // per-wave transpose buffers
+  union {
+    float t[kWaves][32 * kLdsT];    // per-wave transpose buffers (main loop)
+    float red[kWaves][32 * 32];     // cross-wave reduction (epilogue, after a barrier)
+  };
   float m1[2][2][kCpTI * 32];        // [num/den][k-slice][i][r]
-  float red[kWaves][32 * 32];        // cross-wave reduction
   float ra[kCpTI * kSA];             // rebuild rows of A (i0 .. i0+15)
   float rb[kCpTJ * kSA];             // rebuild rows of B (j0 .. j0+31)
   float na[kCpTI * 32], nb[kCpTJ * 32];  // contraction rows for P
@@ -549,9 +551,9 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
     }
     return acc;
   };
-  // (KL only: its entries are short enough that the second accumulator still
-  // fits two waves per SIMD; the other classes rebuild at the tile itself)
-  constexpr bool kPipe = BC == kKL && !kCache;
+  // (off: the second accumulator would keep the KL pass from three waves per
+  // SIMD, which hide more latency than the overlap within one wave)
+  constexpr bool kPipe = false;
   f32x16 xh_cur = {};
   if constexpr (kPipe) xh_cur = rebuild(2 * mg, 0);
 
@@ -831,8 +833,17 @@ __device__ __forceinline__ void cp3_pass_entry(const CpPassArgs& a, int wg, int 
     pass_body<BC, kVar, kObj, false, kBf, kR16>(a, sh, wg, bi, bj, bk, gj, gk);
 }
 
+// Waves per SIMD the pass is compiled for: three for KL (its PassShared,
+// with the transpose and reduction buffers aliased, leaves room for three
+// workgroups per CU), two for the other classes without the objective, one
+// with it (their objective terms are long).
+template <int BC, bool kObj>
+constexpr int pass_waves() {
+  return BC == kKL ? 3 : (!kObj ? 2 : 1);
+}
+
 template <int BC, int kVar, bool kObj, bool kBf, bool kR16>
-__global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
+__global__ void __launch_bounds__(kThreads, (pass_waves<BC, kObj>())) cp3_pass_kernel(CpPassArgs a, int gj, int gk) {
   cp3_pass_entry<BC, kVar, kObj, kBf, kR16>(a, blockIdx.x, gj, gk);
 }
 
@@ -843,7 +854,7 @@ struct CpPassLaunch {
 };
 
 template <int BC, int kVar, bool kObj, bool kBf, bool kR16>
-__global__ void __launch_bounds__(kThreads, (BC == kKL || !kObj) ? 2 : 1) cp3_pass_grouped(GroupTable t) {
+__global__ void __launch_bounds__(kThreads, (pass_waves<BC, kObj>())) cp3_pass_grouped(GroupTable t) {
   uint3 bid, gdim;
   const CpPassLaunch& l = group_item<CpPassLaunch>(t, bid, gdim);
   cp3_pass_entry<BC, kVar, kObj, kBf, kR16>(l.a, (int)bid.x, l.gj, l.gk);
