@@ -444,6 +444,11 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   // rebuild C rows (k = kcol, r = 16h + s) and contraction C columns
   // (r = col, k = kslice + 16h + s)
   // (16-wide: rebuild r = 8h + s, contraction columns r = c16 at k = kslice + 8 g16 + s, s < 8)
+  // An interior workgroup whose factor views are all 32 wide reads every
+  // operand in bounds: plain loads, without the clamps and masks of FView::at.
+  const bool full = kInterior && !kR16 && (kCache || (a.r.A.cols == kRP && a.r.B.cols == kRP && a.r.C.cols == kRP)) &&
+                    a.n.A.cols == kRP && a.n.B.cols == kRP && a.n.C.cols == kRP &&
+                    (!kDen || (a.d.A.cols == kRP && a.d.B.cols == kRP && a.d.C.cols == kRP));
   float crow[16], ctn[16], ctd[16];
   if constexpr (kR16) {
 #pragma unroll
@@ -451,6 +456,13 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       if (!kCache) crow[s] = a.r.C.at(kcol, 8 * h + s, K);
       ctn[s] = a.n.C.at(kslice + 8 * g16 + s, c16, K);
       if (kDen) ctd[s] = a.d.C.at(kslice + 8 * g16 + s, c16, K);
+    }
+  } else if (full) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (!kCache) crow[s] = a.r.C.p[(size_t)kcol * a.r.C.ld + 16 * h + s];
+      ctn[s] = a.n.C.p[(size_t)(kslice + 16 * h + s) * a.n.C.ld + col];
+      if (kDen) ctd[s] = a.d.C.p[(size_t)(kslice + 16 * h + s) * a.d.C.ld + col];
     }
   } else {
 #pragma unroll
@@ -466,38 +478,76 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
   // would keep the second load waiting behind the first)
   constexpr int kQA = kCpTI * 32 / kThreads, kQB = kCpTJ * 32 / kThreads;
   float sa[kQA][3], sb[kQB][3];
+  if (full) {
 #pragma unroll
-  for (int q = 0; q < kQA; ++q) {
-    const int e = tid + q * kThreads;
-    const int i = i0 + (e >> 5), c = e & 31;
-    sa[q][0] = kCache ? 0.0f : load_clamped(a.r.A, i, c, I);
-    sa[q][1] = load_clamped(a.n.A, i, c, I);
-    sa[q][2] = kDen ? load_clamped(a.d.A, i, c, I) : 0.0f;
-  }
+    for (int q = 0; q < kQA; ++q) {
+      const int e = tid + q * kThreads;
+      const size_t i = (size_t)(i0 + (e >> 5));
+      const int c = e & 31;
+      sa[q][0] = kCache ? 0.0f : a.r.A.p[i * a.r.A.ld + c];
+      sa[q][1] = a.n.A.p[i * a.n.A.ld + c];
+      sa[q][2] = kDen ? a.d.A.p[i * a.d.A.ld + c] : 0.0f;
+    }
 #pragma unroll
-  for (int q = 0; q < kQB; ++q) {
-    const int e = tid + q * kThreads;
-    const int j = j0 + (e >> 5), c = e & 31;
-    sb[q][0] = kCache ? 0.0f : load_clamped(a.r.B, j, c, J);
-    sb[q][1] = load_clamped(a.n.B, j, c, J);
-    sb[q][2] = kDen ? load_clamped(a.d.B, j, c, J) : 0.0f;
+    for (int q = 0; q < kQB; ++q) {
+      const int e = tid + q * kThreads;
+      const size_t j = (size_t)(j0 + (e >> 5));
+      const int c = e & 31;
+      sb[q][0] = kCache ? 0.0f : a.r.B.p[j * a.r.B.ld + c];
+      sb[q][1] = a.n.B.p[j * a.n.B.ld + c];
+      sb[q][2] = kDen ? a.d.B.p[j * a.d.B.ld + c] : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQA; ++q) {
+      const int e = tid + q * kThreads;
+      const int i = i0 + (e >> 5), c = e & 31;
+      sa[q][0] = kCache ? 0.0f : load_clamped(a.r.A, i, c, I);
+      sa[q][1] = load_clamped(a.n.A, i, c, I);
+      sa[q][2] = kDen ? load_clamped(a.d.A, i, c, I) : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kQB; ++q) {
+      const int e = tid + q * kThreads;
+      const int j = j0 + (e >> 5), c = e & 31;
+      sb[q][0] = kCache ? 0.0f : load_clamped(a.r.B, j, c, J);
+      sb[q][1] = load_clamped(a.n.B, j, c, J);
+      sb[q][2] = kDen ? load_clamped(a.d.B, j, c, J) : 0.0f;
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
+  if (!full) {
+    // the masks after the batch of loads (scale by 0 outside rows x cols)
+#pragma unroll
+    for (int q = 0; q < kQA; ++q) {
+      const int e = tid + q * kThreads;
+      const int i = i0 + (e >> 5), c = e & 31;
+      sa[q][0] *= mask_of(a.r.A, i, c, I);
+      sa[q][1] *= mask_of(a.n.A, i, c, I);
+      sa[q][2] *= mask_of(a.d.A, i, c, I);
+    }
+#pragma unroll
+    for (int q = 0; q < kQB; ++q) {
+      const int e = tid + q * kThreads;
+      const int j = j0 + (e >> 5), c = e & 31;
+      sb[q][0] *= mask_of(a.r.B, j, c, J);
+      sb[q][1] *= mask_of(a.n.B, j, c, J);
+      sb[q][2] *= mask_of(a.d.B, j, c, J);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < kQA; ++q) {
     const int e = tid + q * kThreads;
-    const int i = i0 + (e >> 5), c = e & 31;
-    if (!kCache) sh.ra[(e >> 5) * kSA + c] = sa[q][0] * mask_of(a.r.A, i, c, I);
-    sh.na[e] = sa[q][1] * mask_of(a.n.A, i, c, I);
-    if (kDen) sh.da[e] = sa[q][2] * mask_of(a.d.A, i, c, I);
+    if (!kCache) sh.ra[(e >> 5) * kSA + (e & 31)] = sa[q][0];
+    sh.na[e] = sa[q][1];
+    if (kDen) sh.da[e] = sa[q][2];
   }
 #pragma unroll
   for (int q = 0; q < kQB; ++q) {
     const int e = tid + q * kThreads;
-    const int j = j0 + (e >> 5), c = e & 31;
-    if (!kCache) sh.rb[(e >> 5) * kSA + c] = sb[q][0] * mask_of(a.r.B, j, c, J);
-    sh.nb[e] = sb[q][1] * mask_of(a.n.B, j, c, J);
-    if (kDen) sh.db[e] = sb[q][2] * mask_of(a.d.B, j, c, J);
+    if (!kCache) sh.rb[(e >> 5) * kSA + (e & 31)] = sb[q][0];
+    sh.nb[e] = sb[q][1];
+    if (kDen) sh.db[e] = sb[q][2];
   }
   __syncthreads();
   // bf16 forms of the per-wave operands (split for the rebuild)
