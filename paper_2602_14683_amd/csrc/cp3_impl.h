@@ -1012,11 +1012,22 @@ __device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh,
     // per-slice C operands: rebuild rows (k = kcol, r = 16h + s) and the
     // contraction columns (r = col, k = kslice + 16h + s)
     float crow[16], ctn[16], ctd[16];
+    // a whole slice with 32-wide views: plain loads, without FView::at's guards
+    const bool fullc = kslice + 32 <= K && (kCache || a.r.C.cols == kRP) && a.n.C.cols == kRP && a.d.C.cols == kRP;
+    if (fullc) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      if (!kCache) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
-      ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
-      ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
+      for (int s = 0; s < 16; ++s) {
+        if (!kCache) crow[s] = a.r.C.p[(size_t)kcol * a.r.C.ld + 16 * h + s];
+        ctn[s] = a.n.C.p[(size_t)(kslice + 16 * h + s) * a.n.C.ld + col];
+        ctd[s] = a.d.C.p[(size_t)(kslice + 16 * h + s) * a.d.C.ld + col];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        if (!kCache) crow[s] = a.r.C.at(kcol, 16 * h + s, K);
+        ctn[s] = a.n.C.at(kslice + 16 * h + s, col, K);
+        ctd[s] = a.d.C.at(kslice + 16 * h + s, col, K);
+      }
     }
     float pv[16], qv[16];
     if (kCache) {
