@@ -433,6 +433,11 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
     J.out_pad = w.cur.pad[n];
     J.out_user = m->factors[n];
     J.ld_user = m->rank;
+    // the new block's transforms for the blocks after it (chi_kernel's values)
+    J.chi_ref = w.ref.pad[n];
+    J.chi_x1 = w.num.pad[n];
+    J.chi_x2 = w.den.pad[n];
+    J.chi_beta = (float)o->beta;
     HIP_TRY(launch_slot_update(u, st));
     return COMM_OK;
   };
@@ -470,15 +475,15 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
     return apply(n, np, ns, dp, ds, rt, nb);
   };
   const bool wshare = vkeep;
+  // every block update writes the block's transforms with it, so after the
+  // first sweep's start they are always current
+  if ((rc = chi_of({1, 2}))) return rc;
   for (int l = 0; l < o->inner_sweeps; ++l) {
     if (!wshare) {
-      if ((rc = chi_of({1, 2}))) return rc;
       if ((rc = own_pass(0))) return rc;
-      if ((rc = chi_of({0}))) return rc;
       if ((rc = own_pass(1))) return rc;
     }
     // mode 1: the V pass against the sets of modes 2 and 3
-    if (wshare && (rc = chi_of({1, 2}))) return rc;
     if (wshare) {
       CpPassArgs a = base_pass(x, w, o);
       a.r = ref;
@@ -506,7 +511,6 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
       if ((rc = apply(0, w.m1n, slots, w.m1d, slots, w.g.Ip, nb))) return rc;
     }
     // mode 2: fold the kept V with the new mode-1 transforms
-    if (wshare && (rc = chi_of({0}))) return rc;
     if (wshare) {
       VFoldArgs f = {};
       f.I = w.dims[0];
@@ -524,7 +528,6 @@ int cp3_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts
       if ((rc = apply(1, w.f2n, kVFoldChunks, w.f2d, kVFoldChunks, w.g.Jp, nb))) return rc;
     }
     // mode 3: its own pass against the sets of modes 1 and 2
-    if ((rc = chi_of({1}))) return rc;
     {
       CpPassArgs a = base_pass(x, w, o);
       a.r = ref;

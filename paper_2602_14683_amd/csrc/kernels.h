@@ -195,6 +195,15 @@ struct SlotJob {
   float* out_user;         // optional caller buffer (valid rows x cols), row stride ld_user
   int ld_user;
   float* stats;            // scale mode: [ceil(rows_p / kSlotRows)][3][32]
+  // optional: the J-CoMM transforms of the new block (as chi_kernel computes
+  // them from out_pad), written for rows < rows_p: chi_1 to chi_x1, chi_2 to
+  // chi_x2 (and transposed copies when set), against chi_ref [rows_p][32]
+  const float* chi_ref;
+  float* chi_x1;
+  float* chi_x2;
+  float* chi_x1T;
+  float* chi_x2T;
+  float chi_beta;
 };
 struct SlotUpdateArgs {
   int njobs;

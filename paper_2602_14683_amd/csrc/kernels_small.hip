@@ -87,6 +87,19 @@ hipError_t launch_colsum_prod(const FView* F, const int* rows, int nf, float* pr
 // ----------------------------------------------------------------------------------------
 // chi transforms of up to 4 factors in one launch
 
+// chi_1 = Z~ (Z/Z~)^(beta-1);  chi_2 = Z (beta <= 1) or Z~ (Z/Z~)^beta; zero
+// where Z~ is (the padding).
+__device__ __forceinline__ void chi_pair(float z, float zr, float beta, float& c1, float& c2) {
+  c1 = 0.0f;
+  c2 = 0.0f;
+  if (zr > 0.0f) {
+    const float u = z / zr;
+    const float lu = __builtin_amdgcn_logf(u);
+    c1 = (beta == 1.0f) ? zr : zr * __builtin_amdgcn_exp2f((beta - 1.0f) * lu);
+    c2 = (beta <= 1.0f) ? z : zr * __builtin_amdgcn_exp2f(beta * lu);
+  }
+}
+
 __device__ __forceinline__ void chi_body(const ChiArgs& a, uint3 bid, uint3) {
   int64_t e = (int64_t)bid.x * blockDim.x + threadIdx.x;
   int f = 0;
@@ -95,16 +108,8 @@ __device__ __forceinline__ void chi_body(const ChiArgs& a, uint3 bid, uint3) {
     ++f;
   }
   if (f >= a.nf) return;
-  const float beta = a.beta;
-  const float z = a.cur[f][e], zr = a.ref[f][e];
-  float c1 = 0.0f, c2 = 0.0f;
-  if (zr > 0.0f) {
-    // chi_1 = Z~ (Z/Z~)^(beta-1);  chi_2 = Z (beta < 1) or Z~ (Z/Z~)^beta
-    const float u = z / zr;
-    const float lu = __builtin_amdgcn_logf(u);
-    c1 = (beta == 1.0f) ? zr : zr * __builtin_amdgcn_exp2f((beta - 1.0f) * lu);
-    c2 = (beta <= 1.0f) ? z : zr * __builtin_amdgcn_exp2f(beta * lu);
-  }
+  float c1, c2;
+  chi_pair(a.cur[f][e], a.ref[f][e], a.beta, c1, c2);
   a.x1[f][e] = c1;
   a.x2[f][e] = c2;
   const int row = (int)(e / kRP), c = (int)(e % kRP);
@@ -408,6 +413,14 @@ __device__ __forceinline__ void slot_update_body(const SlotUpdateArgs& a, uint3 
     if (row < J.rows_p) {
       if (J.out_pad) J.out_pad[e] = v;
       if (J.out_padT) J.out_padT[(int64_t)c * J.rows_p + row] = v;
+      if (J.chi_x1) {
+        float c1, c2;
+        chi_pair(v, J.chi_ref[e], J.chi_beta, c1, c2);
+        J.chi_x1[e] = c1;
+        J.chi_x2[e] = c2;
+        if (J.chi_x1T) J.chi_x1T[(int64_t)c * J.rows_p + row] = c1;
+        if (J.chi_x2T) J.chi_x2T[(int64_t)c * J.rows_p + row] = c2;
+      }
     }
     lc[o] = v;
     la[o] = anc;

@@ -509,9 +509,13 @@ int tk_gemms(const TkWs& w, int blk, const TkModel* cs, int sets, Slots* out, hi
 
 // One block update: max(anchor * (Num/Den)^gamma, eps) into the caller's
 // block (and a padded copy).  blk -1 = core.
+float* copy_block(const TkCopy& c, int blk);
+
+// (chi_beta >= 0: also the block's J-CoMM transforms into the num / den sets,
+// as chi_kernel would compute them from the padded copy)
 int tk_apply(const comm_model* m, const TkWs& w, int blk, const Slots& num, const Slots* den,
              const float* den_closed_vec, FView anchor, float* out_pad, float* out_padT, float gamma, float eps,
-             hipStream_t st) {
+             hipStream_t st, float chi_beta = -1.0f) {
   SlotUpdateArgs u = {};
   u.njobs = 1;
   SlotJob& Jb = u.job[0];
@@ -542,6 +546,14 @@ int tk_apply(const comm_model* m, const TkWs& w, int blk, const Slots& num, cons
   Jb.eps = eps;
   Jb.out_pad = out_pad;
   Jb.out_padT = blk == 2 ? out_padT : nullptr;
+  if (chi_beta >= 0.0f) {
+    Jb.chi_ref = copy_block(w.ref, blk);
+    Jb.chi_x1 = copy_block(w.num, blk);
+    Jb.chi_x2 = copy_block(w.den, blk);
+    Jb.chi_x1T = blk == 2 ? w.num.facT2 : nullptr;
+    Jb.chi_x2T = blk == 2 ? w.den.facT2 : nullptr;
+    Jb.chi_beta = chi_beta;
+  }
   HIP_TRY(launch_slot_update(u, st));
   return COMM_OK;
 }
@@ -570,7 +582,7 @@ int tk_closed_den(const TkWs& w, int blk, const TkModel& ds, Slots* core_den, co
 // sets ns / ds from the V of the last V pass (blk -1, 0, 1; reuse_u: the core
 // block's U of this sweep serves mode 1), then the block update.
 int tk_from_v(comm_model* m, const comm_opts* o, const TkWs& w, int blk, const TkModel& ns, const TkModel& ds,
-              bool reuse_u, FView anchor, float* out_pad, hipStream_t st) {
+              bool reuse_u, FView anchor, float* out_pad, hipStream_t st, bool with_chi = false) {
   const bool kl = o->beta == 1.0;
   const int sets = kl ? 1 : 2;
   const TkModel cs[2] = {ns, ds};
@@ -584,7 +596,8 @@ int tk_from_v(comm_model* m, const comm_opts* o, const TkWs& w, int blk, const T
     if ((rc = tk_closed_den(w, blk, ds, &den, &vec, st))) return rc;
     if (blk != -1) denp = nullptr;
   }
-  return tk_apply(m, w, blk, nd[0], denp, vec, anchor, out_pad, w.cur.facT2, gamma_of(o->beta), (float)o->eps, st);
+  return tk_apply(m, w, blk, nd[0], denp, vec, anchor, out_pad, w.cur.facT2, gamma_of(o->beta), (float)o->eps, st,
+                  with_chi ? (float)o->beta : -1.0f);
 }
 
 // The V pass (blocks -1, 0, 1) or the mode-3 pass (block 2) over X rebuilt
@@ -618,10 +631,11 @@ int tk_pass(comm_ctx* ctx, const comm_dense* x, const comm_opts* o, const TkWs& 
 // Update of block blk: its pass, then its numerator / denominator and the update.
 int tk_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts* o, const TkWs& w, int blk,
              const TkModel& rb, const TkModel& ns, const TkModel& ds, const float* cnT, const float* cdT,
-             bool cached, bool want_obj, FView anchor, float* out_pad, double* obj, hipStream_t st) {
+             bool cached, bool want_obj, FView anchor, float* out_pad, double* obj, hipStream_t st,
+             bool with_chi = false) {
   int rc = tk_pass(ctx, x, o, w, blk, rb, cnT, cdT, cached, want_obj, obj, st);
   if (rc) return rc;
-  if (blk != 2) return tk_from_v(m, o, w, blk, ns, ds, false, anchor, out_pad, st);
+  if (blk != 2) return tk_from_v(m, o, w, blk, ns, ds, false, anchor, out_pad, st, with_chi);
   const bool kl = o->beta == 1.0;
   const Slots num{w.m3[0], w.npg, w.Kp};
   Slots den{w.m3[1], w.npg, w.Kp};
@@ -631,7 +645,8 @@ int tk_block(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_opts*
     if ((rc = tk_closed_den(w, blk, ds, &den, &vec, st))) return rc;
     denp = nullptr;
   }
-  return tk_apply(m, w, blk, num, denp, vec, anchor, out_pad, w.cur.facT2, gamma_of(o->beta), (float)o->eps, st);
+  return tk_apply(m, w, blk, num, denp, vec, anchor, out_pad, w.cur.facT2, gamma_of(o->beta), (float)o->eps, st,
+                  with_chi ? (float)o->beta : -1.0f);
 }
 
 // T2 of one model into T2 (and its transposed copy into T2T unless NULL).
@@ -791,39 +806,40 @@ int tucker_jcomm(comm_ctx* ctx, const comm_dense* x, comm_model* m, const comm_o
 
   // beta != 1, per sweep: one V pass serves the core and modes 1 and 2 (the
   // mode-3 sets do not change until the mode-3 block), then the mode-3 pass.
+  // every block update writes the block's transforms with it (tk_apply), so
+  // after the first sweep's start the sets are always current
+  if ((rc = chi({0, 1, 2}))) return rc;
   for (int l = 0; l < o->inner_sweeps; ++l) {
     // core block: sets of the three factors, the V pass, U and the core numerators
-    if ((rc = chi({0, 1, 2}))) return rc;
     TkModel ns = model_of(w, w.num), ds = model_of(w, w.den);
     ns.G = ref.G;  // the active block does not enter its own contraction
     ds.G = ref.G;
     const bool want_obj = obj_pending && !cache;
     if ((rc = tk_pass(ctx, x, o, w, -1, ref, w.num.facT2, w.den.facT2, cache, want_obj, obj, st))) return rc;
     obj_pending = false;
-    if ((rc = tk_from_v(m, o, w, -1, ns, ds, false, block_view(ref, -1), copy_block(w.cur, -1), st))) return rc;
+    if ((rc = tk_from_v(m, o, w, -1, ns, ds, false, block_view(ref, -1), copy_block(w.cur, -1), st, true)))
+      return rc;
     // mode 1 from the same V and U: only the core's sets changed
-    if ((rc = chi({-1}))) return rc;
     ns = model_of(w, w.num);
     ds = model_of(w, w.den);
     ns.A = ref.A;
     ds.A = ref.A;
-    if ((rc = tk_from_v(m, o, w, 0, ns, ds, true, block_view(ref, 0), copy_block(w.cur, 0), st))) return rc;
+    if ((rc = tk_from_v(m, o, w, 0, ns, ds, true, block_view(ref, 0), copy_block(w.cur, 0), st, true))) return rc;
     // mode 2 from the same V: only mode 1's sets changed
-    if ((rc = chi({0}))) return rc;
     ns = model_of(w, w.num);
     ds = model_of(w, w.den);
     ns.B = ref.B;
     ds.B = ref.B;
-    if ((rc = tk_from_v(m, o, w, 1, ns, ds, false, block_view(ref, 1), copy_block(w.cur, 1), st))) return rc;
+    if ((rc = tk_from_v(m, o, w, 1, ns, ds, false, block_view(ref, 1), copy_block(w.cur, 1), st, true)))
+      return rc;
     // mode 3: mode 2's sets, both sets' T2, the mode-3 pass
-    if ((rc = chi({1}))) return rc;
     ns = model_of(w, w.num);
     ds = model_of(w, w.den);
     ns.C = ref.C;
     ds.C = ref.C;
     if ((rc = tk_t2_pair(w, ns, ds, st))) return rc;
     rc = tk_block(ctx, x, m, o, w, 2, ref, ns, ds, nullptr, nullptr, cache, false, block_view(ref, 2),
-                  copy_block(w.cur, 2), nullptr, st);
+                  copy_block(w.cur, 2), nullptr, st, true);
     if (rc) return rc;
   }
   return COMM_OK;
