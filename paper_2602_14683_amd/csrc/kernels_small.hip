@@ -175,9 +175,9 @@ hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, d
 
 // Recurrence of the beta = 1 inner loop: reduces the column statistics of
 // every block (all loads in one round), sums the objective partials, runs the L
-// sweeps on 32-wide vectors in wavefront 0, and leaves the last denominators in
-// den_last.  Every workgroup of kl_apply runs it on the same data in the same
-// order, so all of them agree bitwise without synchronising.
+// sweeps on 32-wide vectors, and leaves the last denominators in den_last.
+// Every workgroup of kl_apply runs it on the same data in the same order, so
+// all of them agree bitwise without synchronising.
 __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsigned bx) {
   __shared__ float red[3 * kMaxModes][32][33];
   __shared__ float S[kMaxModes][32], T[kMaxModes][32], Cmin[kMaxModes][32];
@@ -256,8 +256,13 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
     a.obj_out[0] = s;
   }
 
-  if (t < 64) {
-    const int col = t & 31;
+  // Every thread runs the recurrence of column c = t & 31 (the 32 threads of a
+  // column compute the same values in the same order).  A column whose
+  // clipped entries make T / Den inexact is summed exactly by all 1024
+  // threads: thread (g, c) takes rows g, g + 32, ..., sixteen in flight, and
+  // the 32 partial sums are added in the order of g.
+  {
+    const int col = c;
     const bool real = col < a.R;
     float Sr[kMaxModes], Tr[kMaxModes], Cr[kMaxModes], Dl[kMaxModes];
 #pragma unroll
@@ -267,6 +272,7 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
       Cr[n] = n < a.N ? Cmin[n][col] : 0.0f;
       Dl[n] = 1.0f;
     }
+    float (*part)[33] = red[0];   // the statistics' buffer, free again
     for (int l = 0; l < a.L; ++l) {
 #pragma unroll
       for (int n = 0; n < kMaxModes; ++n) {
@@ -277,27 +283,30 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
           if (m != n && m < a.N) d *= Sr[m];
         const bool clip = real && (Cr[n] < a.eps * d);
         float snew = real ? Tr[n] / d : 0.0f;
+        // every wavefront holds all 32 columns, so its vote is the block's
         if (__any(clip)) {
-          // exact column sum of max(c / Den, eps) for clipped columns; the two
-          // lane halves take alternate rows, combined in order
           float s = 0.0f;
           if (clip) {
-            // rows in the same order as one at a time, sixteen loads in flight
             const float* cp = a.c[n] + col;
             const int rows = a.rows[n];
-            int r = t >> 5;
-            for (; r + 30 < rows; r += 32) {
+            int r = g;
+            for (; r + 15 * 32 < rows; r += 16 * 32) {
               float v[16];
 #pragma unroll
-              for (int u = 0; u < 16; ++u) v[u] = cp[(int64_t)(r + 2 * u) * kRP];
+              for (int u = 0; u < 16; ++u) v[u] = cp[(int64_t)(r + 32 * u) * kRP];
 #pragma unroll
               for (int u = 0; u < 16; ++u) s += fmaxf(v[u] / d, a.eps);
             }
-            for (; r < rows; r += 2) s += fmaxf(cp[(int64_t)r * kRP] / d, a.eps);
+            for (; r < rows; r += 32) s += fmaxf(cp[(int64_t)r * kRP] / d, a.eps);
           }
-          const float other = __shfl_xor(s, 32);
-          const float exact = (t < 32) ? s + other : other + s;
-          if (clip) snew = exact;
+          part[g][col] = s;
+          __syncthreads();
+          if (clip) {
+            float exact = part[0][col];
+            for (int gg = 1; gg < 32; ++gg) exact += part[gg][col];
+            snew = exact;
+          }
+          __syncthreads();
         }
         Sr[n] = snew;
         Dl[n] = d;
@@ -476,7 +485,7 @@ hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s) {
   for (int q = 0; q < a.N; ++q) n += (int64_t)a.rows[q] * kRP;
   int blocks = (int)((n + 1023) / 1024);
   if (blocks > 64) blocks = 64;
-return launch_or_record(kl_apply_kernel, kl_apply_grouped, dim3(blocks), dim3(1024), 0, s, a);
+  return launch_or_record(kl_apply_kernel, kl_apply_grouped, dim3(blocks), dim3(1024), 0, s, a);
 }
 
 // ----------------------------------------------------------------------------------------

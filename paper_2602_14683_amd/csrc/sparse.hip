@@ -211,6 +211,252 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ plan pass
+//
+// The pass over one sorted copy of a plan: the copy's leading slots
+// accumulate by runs; its other slots are not accumulated (the other copy
+// covers them).  Same mapping and arithmetic as coo_pass_kernel (one nonzero
+// per half wave, lane = rank component, each half one contiguous half of the
+// wave's chunk), with the per-nonzero bookkeeping moved out of the step:
+//
+// * Staging.  Each half's nonzeros are taken 32 at a time (a window): lane r
+//   of half h loads nonzero 32 W + r of its half (coalesced), checks its
+//   coordinates, and writes the byte offsets i_q R 4 of its factor rows and
+//   its value to the wave's LDS buffer.  A nonzero with a coordinate outside
+//   [0, dims) gets the value 0 and that coordinate 0; steps past the end of a
+//   half read its last nonzero with the value 0.  Both contribute exactly
+//   nothing (w = 0, objective term 0) and need no test in the step.  Window
+//   W + 1 is loaded while window W is consumed; two buffers alternate.
+// * Step.  A lane reads its half's offsets and value for the step with one
+//   16-byte and one 4-byte LDS read at fixed offsets, adds its column, and
+//   gathers; the gathers of the next four steps are issued before the
+//   current four are evaluated.  A run ends where the row offset changes.
+// * X~ is the half-wave sum by DPP within rows of 16 and one
+//   v_permlane16_swap across the two rows (both rows add in the same order,
+//   so every lane of a half holds the same value).
+struct CooPlanPassArgs {
+  int R;
+  int64_t nnz;
+  int dims[4];              // slot order
+  const int32_t* idx[4];
+  const float* val;
+  const float* A[4];        // factors, slot order, row stride R
+  float* M[4];              // [dims][32] accumulators, slot order
+  float eps;
+  float inv_r4;             // 1 / (4 R): row of a byte offset (R < 32)
+  int64_t chunk;            // nonzeros per wavefront
+  double* obj_part;         // per workgroup, as in coo_pass_kernel (NULL: no objective)
+};
+
+constexpr int kPlanStep = 4;   // steps per batch of gathers
+
+// Half-wave sum for the plan pass: DPP within each row of 16, then the two
+// rows of the half exchanged by v_permlane16_swap.
+__device__ __forceinline__ float half_sum_swap(float v) {
+  // (every source lane of these patterns exists: bound_ctrl changes nothing)
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));  // row_half_mirror
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));  // row_mirror
+  // rows (0, 1, 2, 3) of v: x' = (v0, v0, v2, v2), y' = (v1, v1, v3, v3)
+  const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+
+template <int N, int kRuns, bool kObj, bool kFullR>
+__global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassArgs a) {
+  constexpr int kW = kCooThreads / 64;
+  __shared__ uint4 s_off[kW][2][64];
+  __shared__ float s_x[kW][2][64];
+  __shared__ double lobj[kW];
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t wave = (int64_t)blockIdx.x * kW + wv;
+  const int R = a.R;
+  const bool rlive = kFullR || r < R;
+  const uint32_t rcol4 = 4u * (uint32_t)(kFullR ? r : min(r, R - 1));
+  const uint32_t R4 = 4u * (uint32_t)R;
+  const int64_t w0 = min(a.nnz, wave * a.chunk);
+  const int64_t w1 = min(a.nnz, w0 + a.chunk);
+  const int len = (int)(w1 - w0);
+  const int len0 = (len + 1) >> 1;             // half 0 is the longer half
+  const int lenh = h ? len - len0 : len0;
+  const int64_t bh = w0 + (h ? len0 : 0);
+  double obj = 0.0;
+
+  if (len > 0) {
+    // ---- staging of window W into the lane's registers (lane = nonzero)
+    int li[N];
+    float lx;
+    auto load_window = [&](int W) {
+      const int t = W * 32 + r;
+      const int64_t e = bh + min(t, lenh - 1);   // lenh = 0: half 0's last nonzero
+#pragma unroll
+      for (int q = 0; q < N; ++q) li[q] = a.idx[q][e];
+      lx = t < lenh ? a.val[e] : 0.0f;
+    };
+    auto store_window = [&](int buf) {
+      bool ok = true;
+      uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        const bool in = li[q] >= 0 && li[q] < a.dims[q];
+        ok = ok && in;
+        o[q] = in ? (uint32_t)li[q] * R4 : 0u;
+      }
+      s_off[wv][buf][lane] = make_uint4(o[0], o[1], o[2], o[3]);
+      s_x[wv][buf][lane] = ok ? lx : 0.0f;
+    };
+    auto lds_sync = [&] {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    const int windows = (len0 + 31) >> 5;
+    // window 0 into both buffers (every buffer then holds valid offsets, so
+    // the gathers issued one batch past the last window stay in bounds)
+    load_window(0);
+    store_window(0);
+    store_window(1);
+    if (windows > 1) load_window(1);
+    lds_sync();
+
+    // a run starts at the half's first nonzero; every flush is then real
+    uint32_t cur[kRuns];
+    float acc[kRuns];
+    {
+      const uint4 o4 = s_off[wv][0][32 * h];
+      const uint32_t o[4] = {o4.x, o4.y, o4.z, o4.w};
+#pragma unroll
+      for (int q = 0; q < kRuns; ++q) {
+        cur[q] = o[q];
+        acc[q] = 0.0f;
+      }
+    }
+    float myy = 1.0f;   // X~ of the lane's own nonzero of the current window
+
+    // one batch: four steps' gathers, their run offsets and values
+    struct Batch {
+      float g[kPlanStep][N];
+      uint32_t ro[kPlanStep][kRuns];
+      float x[kPlanStep];
+    };
+    // steps j0 .. j0 + 3 of the window in buffer buf (jj = j0 mod 32)
+    auto issue = [&](int buf, int jj, Batch& B) {
+#pragma unroll
+      for (int u = 0; u < kPlanStep; ++u) {
+        const uint4 o4 = s_off[wv][buf][32 * h + jj + u];
+        B.x[u] = s_x[wv][buf][32 * h + jj + u];
+        const uint32_t o[4] = {o4.x, o4.y, o4.z, o4.w};
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+          B.g[u][q] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(a.A[q]) + (o[q] + rcol4));
+#pragma unroll
+        for (int q = 0; q < kRuns; ++q) B.ro[u][q] = o[q];
+      }
+    };
+    auto moff = [&](uint32_t o) -> int64_t {
+      const uint32_t row = kFullR ? o >> 7 : (uint32_t)fmaf((float)o, a.inv_r4, 0.5f);
+      return (int64_t)row * kRP + r;
+    };
+    auto consume = [&](int jj, const Batch& B) {
+#pragma unroll
+      for (int u = 0; u < kPlanStep; ++u) {
+        float z = B.g[u][0];
+#pragma unroll
+        for (int q = 1; q < N; ++q) z *= B.g[u][q];
+        if (!kFullR) z = rlive ? z : 0.0f;
+        const float y = fmaxf(half_sum_swap(z), a.eps);
+        const float w = z * (B.x[u] * fast_rcp(y));
+#pragma unroll
+        for (int q = 0; q < kRuns; ++q) {
+          if (B.ro[u][q] != cur[q]) {
+            if (rlive) unsafeAtomicAdd(&a.M[q][moff(cur[q])], acc[q]);
+            cur[q] = B.ro[u][q];
+            acc[q] = 0.0f;
+          }
+          acc[q] += w;
+        }
+        if (kObj && r == jj + u) myy = y;
+      }
+    };
+
+    // One iteration per window of 32 steps, eight batches; the gathers of
+    // the next batch are always issued before the current one is evaluated
+    // (past the last step they read valid offsets and go unused).  Steps past
+    // the end of a half carry the value 0.
+    Batch bA, bB;
+    issue(0, 0, bA);
+    for (int W = 0; W < windows; ++W) {
+      const int buf = W & 1;
+#pragma unroll
+      for (int k = 0; k < 8; k += 2) {
+        issue(buf, 4 * (k + 1), bB);
+        consume(4 * k, bA);
+        if (k + 2 < 8) {
+          issue(buf, 4 * (k + 2), bA);
+        } else {
+          // window W + 1 into the other buffer (loaded a window ago), the
+          // loads of window W + 2, then the first batch of window W + 1
+          if (W + 1 < windows) {
+            store_window(buf ^ 1);
+            if (W + 2 < windows) load_window(W + 2);
+          }
+          lds_sync();
+          issue(buf ^ 1, 0, bA);
+        }
+        consume(4 * (k + 1), bB);
+      }
+      if (kObj) {
+        // the lane's own nonzero of window W (value 0 past its half: term 0)
+        const float x = s_x[wv][buf][lane];
+        bool far;
+        float d = kl_series(x, myy, fast_rcp(x + myy), far);
+        if (far) d = kl_direct(x, myy);
+        obj += (double)d - (double)myy;
+      }
+    }
+    if (rlive) {
+#pragma unroll
+      for (int q = 0; q < kRuns; ++q) unsafeAtomicAdd(&a.M[q][moff(cur[q])], acc[q]);
+    }
+  }
+  if (a.obj_part) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
+    if (lane == 0) lobj[wv] = obj;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int q = 0; q < kW; ++q) s += lobj[q];
+      a.obj_part[blockIdx.x] = s;
+    }
+  }
+}
+
+template <int N, int kRuns>
+hipError_t launch_plan_pass_n(const CooPlanPassArgs& a, int blocks, hipStream_t st) {
+  const dim3 grid((unsigned)blocks), block(kCooThreads);
+  const bool full = a.R == 32;
+  if (a.obj_part) {
+    if (full) hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, true, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, true, false>), grid, block, 0, st, a);
+  } else {
+    if (full) hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, false, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, false, false>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_pass(const CooPlanPassArgs& a, int N, int runs, int blocks, hipStream_t st) {
+  if (N == 2 && runs == 2) return launch_plan_pass_n<2, 2>(a, blocks, st);
+  if (N == 3 && runs == 2) return launch_plan_pass_n<3, 2>(a, blocks, st);
+  if (N == 3 && runs == 1) return launch_plan_pass_n<3, 1>(a, blocks, st);
+  if (N == 4 && runs == 2) return launch_plan_pass_n<4, 2>(a, blocks, st);
+  return hipErrorInvalidValue;
+}
+
 template <int N>
 hipError_t launch_coo_n(const CooPassArgs& a, int blocks, hipStream_t st) {
   const dim3 grid((unsigned)blocks), block(kCooThreads);
@@ -388,6 +634,30 @@ int coo_pass(comm_ctx* ctx, int N, const int* order, const int32_t* const* idx, 
   return profiled(ctx, st, [&] { return launch_coo(a, coo_blocks(nnz), st); });
 }
 
+// One pass over plan copy c (plan_pass kernel): its leading `runs` slots
+// accumulate by runs.
+int plan_pass(comm_ctx* ctx, const comm_coo_plan* p, int c, const int* dims, const comm_model* m, const CooWs& w,
+              bool obj, float eps, hipStream_t st) {
+  if (p->nnz <= 0) return COMM_OK;
+  CooPlanPassArgs a = {};
+  a.R = m->rank;
+  a.nnz = p->nnz;
+  for (int q = 0; q < p->ndim; ++q) {
+    const int n = p->order[c][q];
+    a.dims[q] = dims[n];
+    a.idx[q] = p->idx[c][q];
+    a.A[q] = m->factors[n];
+    a.M[q] = w.M[n];
+  }
+  a.val = p->val[c];
+  a.eps = eps;
+  a.inv_r4 = 1.0f / (4.0f * (float)m->rank);
+  a.chunk = coo_chunk(p->nnz);
+  a.obj_part = obj ? w.obj_part : nullptr;
+  const int blocks = coo_blocks(p->nnz);
+  return profiled(ctx, st, [&] { return launch_plan_pass(a, p->ndim, p->runs[c], blocks, st); });
+}
+
 // Zero the accumulators, run `passes`, then the beta = 1 inner loop.
 template <class Passes>
 int coo_outer(comm_ctx* ctx, int N, const int* dims, int64_t nnz, comm_model* m, const comm_opts* o, double* obj,
@@ -464,8 +734,7 @@ int coo_jcomm_kl_plan(comm_ctx* ctx, const comm_coo_plan* p, comm_model* m, cons
   return coo_outer(ctx, N, dims, p->nnz, m, o, obj, st, [&](const CooWs& w) {
     int rc = COMM_OK;
     for (int c = 0; c < p->copies && !rc; ++c)
-      rc = coo_pass(ctx, N, p->order[c], p->idx[c], p->val[c], p->nnz, dims, m, w, p->runs[c], 0,
-                    c == 0 && obj != nullptr, (float)o->eps, st);
+      rc = plan_pass(ctx, p, c, dims, m, w, c == 0 && obj != nullptr, (float)o->eps, st);
     return rc;
   });
 }
