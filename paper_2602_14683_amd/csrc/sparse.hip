@@ -241,7 +241,9 @@ struct CooPlanPassArgs {
   const int32_t* idx[4];
   const float* val;
   const float* A[4];        // factors, slot order, row stride R
-  float* M[4];              // [dims][32] accumulators, slot order
+  float* M[4];              // accumulators, slot order: replicas of [dims][32]
+  int64_t mrep[4];          // floats between replicas
+  int rep_mask;             // workgroup b adds into replica b & rep_mask
   float eps;
   float inv_r4;             // 1 / (4 R): row of a byte offset (R < 32)
   int64_t chunk;            // nonzeros per wavefront
@@ -268,6 +270,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
   constexpr int kW = kCooThreads / 64;
   __shared__ uint4 s_off[kW][2][64];
   __shared__ float s_x[kW][2][64];
+  __shared__ float s_y[kW][64];      // X~ of each step of the current window
   __shared__ double lobj[kW];
   const int lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
@@ -334,7 +337,6 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
         acc[q] = 0.0f;
       }
     }
-    float myy = 1.0f;   // X~ of the lane's own nonzero of the current window
 
     // one batch: four steps' gathers, their run offsets and values
     struct Batch {
@@ -356,6 +358,10 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
         for (int q = 0; q < kRuns; ++q) B.ro[u][q] = o[q];
       }
     };
+    const int64_t rep = (int64_t)(blockIdx.x & (unsigned)a.rep_mask);
+    float* Mq[kRuns];
+#pragma unroll
+    for (int q = 0; q < kRuns; ++q) Mq[q] = a.M[q] + rep * a.mrep[q];
     auto moff = [&](uint32_t o) -> int64_t {
       const uint32_t row = kFullR ? o >> 7 : (uint32_t)fmaf((float)o, a.inv_r4, 0.5f);
       return (int64_t)row * kRP + r;
@@ -372,13 +378,15 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
 #pragma unroll
         for (int q = 0; q < kRuns; ++q) {
           if (B.ro[u][q] != cur[q]) {
-            if (rlive) unsafeAtomicAdd(&a.M[q][moff(cur[q])], acc[q]);
+            if (rlive) unsafeAtomicAdd(&Mq[q][moff(cur[q])], acc[q]);
             cur[q] = B.ro[u][q];
             acc[q] = 0.0f;
           }
           acc[q] += w;
         }
-        if (kObj && r == jj + u) myy = y;
+        // X~ of the step for the objective (one lane per half: a lane
+        // compare per step would pin 32 hoisted masks in scalar registers)
+        if (kObj && r == 0) s_y[wv][32 * h + jj + u] = y;
       }
     };
 
@@ -410,7 +418,9 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
       }
       if (kObj) {
         // the lane's own nonzero of window W (value 0 past its half: term 0)
+        lds_sync();
         const float x = s_x[wv][buf][lane];
+        const float myy = s_y[wv][lane];
         bool far;
         float d = kl_series(x, myy, fast_rcp(x + myy), far);
         if (far) d = kl_direct(x, myy);
@@ -419,7 +429,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
     }
     if (rlive) {
 #pragma unroll
-      for (int q = 0; q < kRuns; ++q) unsafeAtomicAdd(&a.M[q][moff(cur[q])], acc[q]);
+      for (int q = 0; q < kRuns; ++q) unsafeAtomicAdd(&Mq[q][moff(cur[q])], acc[q]);
     }
   }
   if (a.obj_part) {
@@ -572,18 +582,33 @@ int bits_for(uint64_t n) {
 }
 
 struct CooWs {
-  float* M[kMaxModes];
+  float* M[kMaxModes];   // reps replicas of [dims][32] each
   float* stats[kMaxModes];
   double* obj_part;
+  int reps;
   size_t bytes;
 };
 
-CooWs coo_layout(int N, const int* dims, int blocks, char* base) {
+// Accumulator replicas: the plan passes add workgroup b's run sums into
+// replica b mod reps (b mod 8 is the workgroup's XCD), so the flushes of a
+// Zipf-hot row are spread over eight addresses instead of queueing on one;
+// slot_update adds the replicas as partial slots, in order.  One replica
+// when eight would pass 32 MB.
+constexpr int kCooReps = 8;
+
+int coo_reps(int N, const int* dims) {
+  int64_t rows = 0;
+  for (int n = 0; n < N; ++n) rows += dims[n];
+  return rows * kRP * 4 * kCooReps <= ((int64_t)32 << 20) ? kCooReps : 1;
+}
+
+CooWs coo_layout(int N, const int* dims, int blocks, char* base, int reps = 1) {
   CooWs w = {};
   Carve cv;
   cv.base = base;
+  w.reps = reps;
   for (int n = 0; n < N; ++n) {
-    w.M[n] = cv.take<float>((size_t)dims[n] * kRP);
+    w.M[n] = cv.take<float>((size_t)reps * dims[n] * kRP);
     w.stats[n] = cv.take<float>((size_t)((dims[n] + kSlotRows - 1) / kSlotRows) * 96);
   }
   w.obj_part = cv.take<double>((size_t)blocks);
@@ -648,7 +673,9 @@ int plan_pass(comm_ctx* ctx, const comm_coo_plan* p, int c, const int* dims, con
     a.idx[q] = p->idx[c][q];
     a.A[q] = m->factors[n];
     a.M[q] = w.M[n];
+    a.mrep[q] = (int64_t)dims[n] * kRP;
   }
+  a.rep_mask = w.reps - 1;
   a.val = p->val[c];
   a.eps = eps;
   a.inv_r4 = 1.0f / (4.0f * (float)m->rank);
@@ -663,10 +690,11 @@ template <class Passes>
 int coo_outer(comm_ctx* ctx, int N, const int* dims, int64_t nnz, comm_model* m, const comm_opts* o, double* obj,
               hipStream_t st, Passes&& passes) {
   const int blocks = coo_blocks(nnz);
-  CooWs w = coo_layout(N, dims, blocks, nullptr);
+  const int reps = coo_reps(N, dims);
+  CooWs w = coo_layout(N, dims, blocks, nullptr, reps);
   int rc = ensure_ws(ctx, w.bytes, st);
   if (rc) return rc;
-  w = coo_layout(N, dims, blocks, ctx->ws);
+  w = coo_layout(N, dims, blocks, ctx->ws, reps);
   {
     const int64_t n = (int64_t)(reinterpret_cast<char*>(w.stats[N - 1]) - reinterpret_cast<char*>(w.M[0])) / 4;
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.M[0], n);
@@ -686,13 +714,15 @@ int coo_outer(comm_ctx* ctx, int N, const int* dims, int64_t nnz, comm_model* m,
     SlotJob& J = su.job[n];
     J.mode = kSlotCopy;
     J.num_part = w.M[n];
-    J.num_slots = 1;
+    J.num_slots = w.reps;
     J.rows_total = dims[n];
     J.rows = dims[n];
     J.cols = m->rank;
     J.rows_p = dims[n];
     J.anchor = FView{m->factors[n], m->rank, m->rank};
-    J.out_pad = nullptr;
+    // the replicas' sum into replica 0 (each entry is read and written by
+    // the same workgroup), which kl_apply reads as c^(n)
+    J.out_pad = w.reps > 1 ? w.M[n] : nullptr;
     J.stats = w.stats[n];
     k.c[n] = w.M[n];
     k.stats[n] = w.stats[n];
