@@ -584,6 +584,7 @@ int bits_for(uint64_t n) {
 struct CooWs {
   float* M[kMaxModes];   // reps replicas of [dims][32] each
   float* stats[kMaxModes];
+  float* kl_part;        // partial column statistics (kl_apply's pre-pass)
   double* obj_part;
   int reps;
   size_t bytes;
@@ -611,6 +612,7 @@ CooWs coo_layout(int N, const int* dims, int blocks, char* base, int reps = 1) {
     w.M[n] = cv.take<float>((size_t)reps * dims[n] * kRP);
     w.stats[n] = cv.take<float>((size_t)((dims[n] + kSlotRows - 1) / kSlotRows) * 96);
   }
+  w.kl_part = cv.take<float>((size_t)kKlPartFloats);
   w.obj_part = cv.take<double>((size_t)blocks);
   w.bytes = cv.off + 256;
   return w;
@@ -731,6 +733,11 @@ int coo_outer(comm_ctx* ctx, int N, const int* dims, int64_t nnz, comm_model* m,
     k.cur_pad[n] = nullptr;
     k.user[n] = m->factors[n];
   }
+  // many statistics blocks (long modes): reduce them once, in a pre-pass,
+  // instead of in every kl_apply workgroup
+  int64_t nblk = 0;
+  for (int n = 0; n < N; ++n) nblk += k.nblk[n];
+  if (nblk > 4 * 128) k.part = w.kl_part;
   HIP_TRY(launch_slot_update(su, st));
   if (obj) {
     k.obj_part = nnz > 0 ? w.obj_part : nullptr;
