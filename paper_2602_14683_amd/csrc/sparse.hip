@@ -252,17 +252,18 @@ struct CooPlanPassArgs {
 
 constexpr int kPlanStep = 4;   // steps per batch of gathers
 
-// Half-wave sum for the plan pass: DPP within each row of 16, then the two
-// rows of the half exchanged by v_permlane16_swap.
+// Half-wave sum for the plan pass: DPP within each row of 16, then the other
+// row of the half by ds_swizzle (xor 16 within 32 lanes), which costs no
+// vector instruction; a + b and b + a are the same float, so both rows hold
+// the same sum.
 __device__ __forceinline__ float half_sum_swap(float v) {
   // (every source lane of these patterns exists: bound_ctrl changes nothing)
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));  // row_half_mirror
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));  // row_mirror
-  // rows (0, 1, 2, 3) of v: x' = (v0, v0, v2, v2), y' = (v1, v1, v3, v3)
-  const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+  // bit mode: and 0x1f, or 0, xor 0x10
+  return v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
 }
 
 template <int N, int kRuns, bool kObj, bool kFullR>
@@ -373,16 +374,35 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
 #pragma unroll
         for (int q = 1; q < N; ++q) z *= B.g[u][q];
         if (!kFullR) z = rlive ? z : 0.0f;
+        // (z is pinned: left free, the compiler folds its last product into
+        // the first DPP add and computes it twice)
+        asm volatile("" : "+v"(z));
         const float y = fmaxf(half_sum_swap(z), a.eps);
         const float w = z * (B.x[u] * fast_rcp(y));
-#pragma unroll
-        for (int q = 0; q < kRuns; ++q) {
-          if (B.ro[u][q] != cur[q]) {
-            if (rlive) unsafeAtomicAdd(&Mq[q][moff(cur[q])], acc[q]);
-            cur[q] = B.ro[u][q];
-            acc[q] = 0.0f;
+        if constexpr (kRuns == 1) {
+          if (B.ro[u][0] != cur[0]) {
+            if (rlive) unsafeAtomicAdd(&Mq[0][moff(cur[0])], acc[0]);
+            cur[0] = B.ro[u][0];
+            acc[0] = 0.0f;
           }
-          acc[q] += w;
+          acc[0] += w;
+        } else {
+          // slot 1's runs nest in slot 0's (the copy is sorted by both), so
+          // slot 0 accumulates slot 1's finished runs instead of every w;
+          // slot 1's run also ends where slot 0 changes
+          const bool c0 = B.ro[u][0] != cur[0];
+          if (c0 || B.ro[u][1] != cur[1]) {
+            if (rlive) unsafeAtomicAdd(&Mq[1][moff(cur[1])], acc[1]);
+            acc[0] += acc[1];
+            acc[1] = 0.0f;
+            cur[1] = B.ro[u][1];
+            if (c0) {
+              if (rlive) unsafeAtomicAdd(&Mq[0][moff(cur[0])], acc[0]);
+              acc[0] = 0.0f;
+              cur[0] = B.ro[u][0];
+            }
+          }
+          acc[1] += w;
         }
         // X~ of the step for the objective (one lane per half: a lane
         // compare per step would pin 32 hoisted masks in scalar registers)
@@ -428,8 +448,11 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
       }
     }
     if (rlive) {
-#pragma unroll
-      for (int q = 0; q < kRuns; ++q) unsafeAtomicAdd(&Mq[q][moff(cur[q])], acc[q]);
+      if constexpr (kRuns == 2) {
+        unsafeAtomicAdd(&Mq[1][moff(cur[1])], acc[1]);
+        acc[0] += acc[1];
+      }
+      unsafeAtomicAdd(&Mq[0][moff(cur[0])], acc[0]);
     }
   }
   if (a.obj_part) {
