@@ -195,9 +195,9 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
     acc[n][1] = 3.402823e38f;
     acc[n][2] = 0.0f;
   }
+  // the first objective partial goes out with the statistics' first round
   double objs = 0.0;
-  if (a.obj_part)
-    for (int64_t e = t; e < a.obj_n; e += 1024) objs += a.obj_part[e];
+  const double ob0 = (a.obj_part && t < a.obj_n) ? a.obj_part[t] : 0.0;
   if (a.part) {
     // partial statistics of the pre-pass: thread (g, c) reads part g
 #pragma unroll
@@ -227,6 +227,9 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
         acc[n][2] += v[u][n][2];
       }
   }
+  objs += ob0;
+  if (a.obj_part)
+    for (int64_t e = t + 1024; e < a.obj_n; e += 1024) objs += a.obj_part[e];
   lds64[t] = objs;
 #pragma unroll
   for (int n = 0; n < kMaxModes; ++n)
@@ -295,17 +298,19 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
         if (__any(clip)) {
           float s = 0.0f;
           if (clip) {
+            // batches of sixteen rows, the last one's loads clamped to a
+            // valid row and its rows past the end left out of the sum (the
+            // rows are added in the same order as one at a time)
             const float* cp = a.c[n] + col;
             const int rows = a.rows[n];
-            int r = g;
-            for (; r + 15 * 32 < rows; r += 16 * 32) {
+            for (int r = g; r < rows; r += 16 * 32) {
               float v[16];
 #pragma unroll
-              for (int u = 0; u < 16; ++u) v[u] = cp[(int64_t)(r + 32 * u) * kRP];
+              for (int u = 0; u < 16; ++u) v[u] = cp[(int64_t)min(r + 32 * u, rows - 1) * kRP];
 #pragma unroll
-              for (int u = 0; u < 16; ++u) s += fmaxf(v[u] / d, a.eps);
+              for (int u = 0; u < 16; ++u)
+                if (r + 32 * u < rows) s += fmaxf(v[u] / d, a.eps);
             }
-            for (; r < rows; r += 32) s += fmaxf(cp[(int64_t)r * kRP] / d, a.eps);
           }
           part[g][col] = s;
           __syncthreads();
@@ -389,12 +394,64 @@ COMM_GROUPED_KERNELS(kl_stats, KlLoopArgs, 1024)
 // runs the recurrence itself.
 __device__ __forceinline__ void kl_apply_body(const KlLoopArgs& a, uint3 bid, uint3 gdim) {
   __shared__ float den_last[kMaxModes][32];
+  int64_t first[kMaxModes + 1];
+  first[0] = 0;
+#pragma unroll
+  for (int n = 0; n < kMaxModes; ++n) first[n + 1] = first[n] + (n < a.N ? (int64_t)a.rows[n] * kRP : 0);
+  const int64_t total = first[kMaxModes];
+  const int64_t stride = (int64_t)gdim.x * blockDim.x;
+  const int64_t e00 = (int64_t)bid.x * blockDim.x + threadIdx.x;
+  // The thread's first kApplyPre entries: their c values are loaded before
+  // the recurrence, so that the round trip overlaps its loads.  An entry's
+  // mode comes from selects over the (uniform) arguments: indexing the
+  // argument arrays with a per-lane mode would load them per lane.
+  constexpr int kApplyPre = 2;
+  float cv[kApplyPre];
+  int nn[kApplyPre];
+  int64_t ee[kApplyPre];
+#pragma unroll
+  for (int k = 0; k < kApplyPre; ++k) {
+    const int64_t e0 = e00 + k * stride;
+    nn[k] = -1;
+    ee[k] = 0;
+    cv[k] = 0.0f;
+    if (e0 < total) {
+      int n = 0;
+#pragma unroll
+      for (int m = 1; m < kMaxModes; ++m) n += e0 >= first[m] ? 1 : 0;
+      int64_t base = first[0];
+      const float* cp = a.c[0];
+#pragma unroll
+      for (int m = 1; m < kMaxModes; ++m) {
+        base = n == m ? first[m] : base;
+        cp = n == m ? a.c[m] : cp;
+      }
+      nn[k] = n;
+      ee[k] = e0 - base;
+      cv[k] = cp[ee[k]];
+    }
+  }
   kl_recurrence(a, den_last, bid.x);
   __syncthreads();
-  int64_t total = 0;
-  for (int n = 0; n < a.N; ++n) total += (int64_t)a.rows[n] * kRP;
-  for (int64_t e0 = (int64_t)bid.x * blockDim.x + threadIdx.x; e0 < total;
-       e0 += (int64_t)gdim.x * blockDim.x) {
+#pragma unroll
+  for (int k = 0; k < kApplyPre; ++k) {
+    const int n = nn[k];
+    if (n < 0) continue;
+    const int64_t e = ee[k];
+    const int row = (int)(e / kRP), cc = (int)(e % kRP);
+    if (cc >= a.R) continue;
+    float* up = a.user[0];
+    float* pp = a.cur_pad[0];
+#pragma unroll
+    for (int m = 1; m < kMaxModes; ++m) {
+      up = n == m ? a.user[m] : up;
+      pp = n == m ? a.cur_pad[m] : pp;
+    }
+    const float v = fmaxf(cv[k] / den_last[n][cc], a.eps);
+    up[(int64_t)row * a.R + cc] = v;
+    if (pp) pp[e] = v;
+  }
+  for (int64_t e0 = e00 + kApplyPre * stride; e0 < total; e0 += stride) {
     int64_t e = e0;
     int n = 0;
     while (n < a.N && e >= (int64_t)a.rows[n] * kRP) {

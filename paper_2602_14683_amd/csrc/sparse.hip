@@ -556,9 +556,64 @@ __global__ void __launch_bounds__(1024) model_mass_kernel(MassArgs a) {
   }
 }
 
+// The accumulators' replicas added (fixed order) into replica 0, which
+// becomes c^(n), with the column statistics of kl_apply per block of 32 rows:
+// sum of c, min of c over the block's rows, sum of the anchor A~^(n).  One
+// workgroup per (mode, 32-row block), thread (row, column).
+constexpr int kSumRows = 32;
+struct CooSumArgs {
+  int N, R, reps;
+  int rows[kMaxModes];
+  int first_block[kMaxModes + 1];   // workgroups of modes before n
+  float* M[kMaxModes];              // reps replicas of [rows][32]
+  const float* anchor[kMaxModes];   // row stride R
+  float* stats[kMaxModes];          // [blocks][3][32]
+};
+
+__global__ void __launch_bounds__(1024) coo_sum_kernel(CooSumArgs a) {
+  __shared__ float red[3][kSumRows][33];
+  const int t = threadIdx.x;
+  const int c = t & 31, rl = t >> 5;
+  int n = 0;
+  while (n + 1 < a.N && (int)blockIdx.x >= a.first_block[n + 1]) ++n;
+  const int b = (int)blockIdx.x - a.first_block[n];
+  const int row = b * kSumRows + rl;
+  const bool in = row < a.rows[n];
+  const int64_t e = (int64_t)row * kRP + c;
+  const int64_t stride = (int64_t)a.rows[n] * kRP;
+  float v = 0.0f, anc = 0.0f;
+  if (in) {
+    float part[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) part[s] = s < a.reps ? a.M[n][s * stride + e] : 0.0f;
+    v = part[0];
+#pragma unroll
+    for (int s = 1; s < 8; ++s) v += part[s];
+    for (int s = 8; s < a.reps; ++s) v += a.M[n][s * stride + e];
+    if (c < a.R) anc = a.anchor[n][(int64_t)row * a.R + c];
+  }
+  __syncthreads();   // every replica read before replica 0 is overwritten
+  if (in) a.M[n][e] = v;
+  red[0][rl][c] = v;
+  red[1][rl][c] = in ? v : 3.402823e38f;
+  red[2][rl][c] = anc;
+  __syncthreads();
+  if (t < 96) {
+    const int k = t >> 5;
+    float r = red[k][0][c];
+    for (int q = 1; q < kSumRows; ++q) r = k == 1 ? fminf(r, red[k][q][c]) : r + red[k][q][c];
+    a.stats[n][(int64_t)b * 96 + 32 * k + c] = r;
+  }
+}
+
+// p[0 .. n) = 0; p 16-byte aligned: four floats per thread, the tail alone
 __global__ void fill_zero_kernel(float* p, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) p[e] = 0.0f;
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (e + 4 <= n) {
+    *reinterpret_cast<float4*>(p + e) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  } else {
+    for (int64_t f = e; f < n; ++f) p[f] = 0.0f;
+  }
 }
 
 // Sort keys of a plan copy: the coordinates of its leading modes, mixed radix.
@@ -633,7 +688,7 @@ CooWs coo_layout(int N, const int* dims, int blocks, char* base, int reps = 1) {
   w.reps = reps;
   for (int n = 0; n < N; ++n) {
     w.M[n] = cv.take<float>((size_t)reps * dims[n] * kRP);
-    w.stats[n] = cv.take<float>((size_t)((dims[n] + kSlotRows - 1) / kSlotRows) * 96);
+    w.stats[n] = cv.take<float>((size_t)((dims[n] + kSumRows - 1) / kSumRows) * 96);
   }
   w.kl_part = cv.take<float>((size_t)kKlPartFloats);
   w.obj_part = cv.take<double>((size_t)blocks);
@@ -722,46 +777,41 @@ int coo_outer(comm_ctx* ctx, int N, const int* dims, int64_t nnz, comm_model* m,
   w = coo_layout(N, dims, blocks, ctx->ws, reps);
   {
     const int64_t n = (int64_t)(reinterpret_cast<char*>(w.stats[N - 1]) - reinterpret_cast<char*>(w.M[0])) / 4;
-    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.M[0], n);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 1023) / 1024)), dim3(256), 0, st, w.M[0], n);
     HIP_TRY(hipGetLastError());
   }
   if ((rc = passes(w))) return rc;
 
-  // c^(n) = M^(n) with column statistics, then the beta = 1 inner loop
-  SlotUpdateArgs su = {};
-  su.njobs = N;
+  // c^(n) = M^(n) (the replicas added) with column statistics, then the
+  // beta = 1 inner loop
+  CooSumArgs sa = {};
+  sa.N = N;
+  sa.R = m->rank;
+  sa.reps = w.reps;
   KlLoopArgs k = {};
   k.N = N;
   k.R = m->rank;
   k.L = o->inner_sweeps;
   k.eps = (float)o->eps;
   for (int n = 0; n < N; ++n) {
-    SlotJob& J = su.job[n];
-    J.mode = kSlotCopy;
-    J.num_part = w.M[n];
-    J.num_slots = w.reps;
-    J.rows_total = dims[n];
-    J.rows = dims[n];
-    J.cols = m->rank;
-    J.rows_p = dims[n];
-    J.anchor = FView{m->factors[n], m->rank, m->rank};
-    // the replicas' sum into replica 0 (each entry is read and written by
-    // the same workgroup), which kl_apply reads as c^(n)
-    J.out_pad = w.reps > 1 ? w.M[n] : nullptr;
-    J.stats = w.stats[n];
+    const int nb = (dims[n] + kSumRows - 1) / kSumRows;
+    sa.rows[n] = dims[n];
+    sa.first_block[n + 1] = sa.first_block[n] + nb;
+    sa.M[n] = w.M[n];
+    sa.anchor[n] = m->factors[n];
+    sa.stats[n] = w.stats[n];
     k.c[n] = w.M[n];
     k.stats[n] = w.stats[n];
-    k.nblk[n] = (dims[n] + kSlotRows - 1) / kSlotRows;
+    k.nblk[n] = nb;
     k.rows[n] = dims[n];
     k.cur_pad[n] = nullptr;
     k.user[n] = m->factors[n];
   }
   // many statistics blocks (long modes): reduce them once, in a pre-pass,
   // instead of in every kl_apply workgroup
-  int64_t nblk = 0;
-  for (int n = 0; n < N; ++n) nblk += k.nblk[n];
-  if (nblk > 4 * 128) k.part = w.kl_part;
-  HIP_TRY(launch_slot_update(su, st));
+  if (sa.first_block[N] > 4 * 128) k.part = w.kl_part;
+  hipLaunchKernelGGL(coo_sum_kernel, dim3((unsigned)sa.first_block[N]), dim3(1024), 0, st, sa);
+  HIP_TRY(hipGetLastError());
   if (obj) {
     k.obj_part = nnz > 0 ? w.obj_part : nullptr;
     k.obj_n = nnz > 0 ? blocks : 0;
