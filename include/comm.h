@@ -382,8 +382,10 @@ int comm_jcomm_outer_extrap(comm_ctx* ctx, const comm_dense* x, comm_model* mode
                             float* alpha_dev, void* stream);
 
 /* D_beta(X, Xhat(model)) summed over all entries (Sec. 3.2, Definition of the
- * beta-divergence), accumulated in float64, written to the device address
- * out_dev.  Safeguards as in comm_opts. */
+ * beta-divergence), written to the device address out_dev: float32 terms
+ * (cancellation-free), reduced in float64 with compensated (TwoSum) sums over
+ * lanes, wavefronts and workgroups in a fixed order.  Safeguards as in
+ * comm_opts. */
 int comm_beta_objective(comm_ctx* ctx, const comm_dense* x, const comm_model* model,
                         const comm_opts* opts, double* out_dev, void* stream);
 

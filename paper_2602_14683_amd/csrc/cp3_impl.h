@@ -368,7 +368,7 @@ struct PassShared {
   float rb[kCpTJ * kSA];             // rebuild rows of B (j0 .. j0+31)
   float na[kCpTI * 32], nb[kCpTJ * 32];  // contraction rows for P
   float da[kCpTI * 32], db[kCpTJ * 32];  // contraction rows for Q
-  double obj[kWaves];
+  double obj[kWaves][2];
 };
 
 // X (or cached P/Q) values of pair block (ib, jb) in the Xhat layout.
@@ -647,9 +647,13 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       }
     } else {
       const f32x16& xh = xh_cur;
-      // the tile's 16 nonnegative terms per lane are summed in float32 (relative
-      // error <= 15 * 2^-24) before entering the float64 accumulator
-      float objt = 0.0f;
+      // the tile's 16 nonnegative terms per lane enter a float64 sum in pairs
+      // (each pair added once in float32: one rounding, like the terms'
+      // own); a lane adds its wave's eight tiles in float64 (error <= 7 *
+      // 2^-53 of its sum); the lanes, waves and workgroups are then added
+      // compensated
+      double objt = 0.0;
+      float objp = 0.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         float x = xv[v];
@@ -659,7 +663,11 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
         entry<BC, kObj>(x, y, a.bc, p, q, d);
         pv[v] = valid[v] ? p : 0.f;
         qv[v] = valid[v] ? q : 0.f;
-        if (kObj) objt += valid[v] ? d : 0.0f;
+        if (kObj) {
+          const float dv = valid[v] ? d : 0.0f;
+          if (v & 1) objt += (double)(objp + dv);
+          else objp = dv;
+        }
         // the general objective terms are long: keep the scheduler from
         // interleaving all sixteen entries (register pressure).  The KL term
         // is short enough to leave free (two waves per SIMD, no spills).
@@ -670,7 +678,7 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
       // pin the tile's objective here: left free, the compiler sinks the
       // sixteen terms past the contraction and keeps x, y and 1 / (x + y) alive
       if constexpr (kObj && BC == kKL) asm volatile("" : "+v"(objt));
-      if constexpr (kObj) obj += (double)objt;
+      if constexpr (kObj) obj += objt;
       if (kWrite) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -753,15 +761,21 @@ __device__ __forceinline__ void pass_body(const CpPassArgs& a, PassShared& sh, i
 
   // ---------------------------------------------------------------- objective partial
   if (kObj) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) sh.obj[w] = obj;
+    double oc = 0.0;
+    sum2_wave(obj, oc);
+    if (lane == 0) {
+      sh.obj[w][0] = obj;
+      sh.obj[w][1] = oc;
+    }
   }
   __syncthreads();
   if (kObj && tid == 0) {
-    double s = sh.obj[0];
-    for (int q = 1; q < kWaves; ++q) s += sh.obj[q];
-    a.obj_part[wg] = s;
+    double s = sh.obj[0][0], c = sh.obj[0][1];
+    for (int q = 1; q < kWaves; ++q) {
+      sum2_add(s, c, sh.obj[q][0]);
+      c += sh.obj[q][1];
+    }
+    a.obj_part[wg] = s + c;
   }
 
   // ---------------------------------------------------------------- cross-wave reductions
@@ -883,13 +897,14 @@ __device__ __forceinline__ void cp3_pass_entry(const CpPassArgs& a, int wg, int 
     pass_body<BC, kVar, kObj, false, kBf, kR16>(a, sh, wg, bi, bj, bk, gj, gk);
 }
 
-// Waves per SIMD the pass is compiled for: three for KL (its PassShared,
-// with the transpose and reduction buffers aliased, leaves room for three
-// workgroups per CU), two for the other classes without the objective, one
-// with it (their objective terms are long).
+// Waves per SIMD the pass is compiled for: three for KL without the
+// objective (its PassShared, with the transpose and reduction buffers
+// aliased, leaves room for three workgroups per CU), two for KL with it (the
+// float64 objective sums would spill at three), two for the other classes
+// without the objective, one with it (their objective terms are long).
 template <int BC, bool kObj>
 constexpr int pass_waves() {
-  return BC == kKL ? 3 : (!kObj ? 2 : 1);
+  return BC == kKL ? (kObj ? 2 : 3) : (!kObj ? 2 : 1);
 }
 
 template <int BC, int kVar, bool kObj, bool kBf, bool kR16>
@@ -934,7 +949,7 @@ struct VPassShared {
   float ra[kVTI * kSA];                 // rebuild rows of A
   float rb[kVTJ * kSA];                 // rebuild rows of B
   float nb[kVTJ * 32], db[kVTJ * 32];   // B' rows of the numerator / denominator sets
-  double obj[kWaves];
+  double obj[kWaves][2];
 };
 
 template <int BC, bool kCache, bool kObj, bool kBf, bool kInterior>
@@ -987,7 +1002,7 @@ __device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh,
   }
 
   f32x16 vn = {}, vd = {};
-  double obj = 0.0;
+  double obj = 0.0, objc = 0.0;
   const float* src0 = kCache ? a.Pc : a.X;
   const bool xz = !kCache && a.x_zero;
   const int nk = (K + 31) / 32;
@@ -1052,7 +1067,8 @@ __device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh,
 #pragma unroll
         for (int s = 0; s < 16; ++s) xh = mfma32(wr[s], crow[s], xh);
       }
-      float objt = 0.0f;
+      // the tile's terms in float64, the tiles of the lane compensated
+      double objt = 0.0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         float x = xv[v];
@@ -1063,12 +1079,12 @@ __device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh,
         const bool ok = kvalid && pvalid[v];
         pv[v] = ok ? p : 0.0f;
         qv[v] = ok ? q : 0.0f;
-        if (kObj) objt += ok ? d : 0.0f;
+        if (kObj) objt += (double)(ok ? d : 0.0f);
         if constexpr (kObj) {
           if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }
-      if constexpr (kObj) obj += (double)objt;
+      if constexpr (kObj) sum2_add(obj, objc, objt);
     }
     // V += P C' and Vd += Q C'd through the per-wave LDS transpose
 #pragma unroll
@@ -1116,15 +1132,20 @@ __device__ __forceinline__ void vpass_body(const CpPassArgs& a, VPassShared& sh,
     }
   }
   if (kObj) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) sh.obj[w] = obj;
+    sum2_wave(obj, objc);
+    if (lane == 0) {
+      sh.obj[w][0] = obj;
+      sh.obj[w][1] = objc;
+    }
   }
   __syncthreads();
   if (kObj && tid == 0) {
-    double sum = sh.obj[0];
-    for (int q = 1; q < kWaves; ++q) sum += sh.obj[q];
-    a.obj_part[wg] = sum;
+    double s = sh.obj[0][0], c = sh.obj[0][1];
+    for (int q = 1; q < kWaves; ++q) {
+      sum2_add(s, c, sh.obj[q][0]);
+      c += sh.obj[q][1];
+    }
+    a.obj_part[wg] = s + c;
   }
   // M1 rows i0 .. i0 + 3 of slot bj: the four waves' j blocks in order
   for (int e = tid; e < 2 * kVTI * 32; e += kThreads) {

@@ -22,6 +22,29 @@ struct BetaConst {
   float series[kSeriesTerms];    // c_k, k = 2..17, see dbeta_term
 };
 
+// Compensated float64 summation of the objective (Knuth's TwoSum): s holds
+// the running sum, c the rounding errors of the additions into s, and s + c
+// the compensated result.  Every reduction of objective partials over lanes,
+// wavefronts and workgroups goes through these, so the sum carries about one
+// rounding of the float64 result however many partials it adds.
+__device__ __forceinline__ void sum2_add(double& s, double& c, double x) {
+  const double t = s + x;
+  const double bp = t - s;
+  c += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
+// (s, c) of every lane of the wavefront into lane 0, in a fixed order.
+__device__ __forceinline__ void sum2_wave(double& s, double& c) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double s2 = __shfl_down(s, off);
+    const double c2 = __shfl_down(c, off);
+    sum2_add(s, c, s2);
+    c += c2;
+  }
+}
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }

@@ -125,19 +125,26 @@ hipError_t launch_chi(const ChiArgs& a, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------------------
-// float64 sum of partials, fixed order
+// float64 sum of objective partials, compensated, fixed order (valid in
+// thread 0): each thread's partials, then the lanes of each wavefront, then
+// the 16 wavefronts
 
-__device__ double block_sum_f64(const double* __restrict__ part, int64_t n, double* lds) {
+__device__ double block_sum_f64(const double* __restrict__ part, int64_t n, double (*lds)[2]) {
   const int t = threadIdx.x;
-  double s = 0.0;
-  for (int64_t e = t; e < n; e += 1024) s += part[e];
-  lds[t] = s;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) lds[t] += lds[t + w];
-    __syncthreads();
+  double s = 0.0, c = 0.0;
+  for (int64_t e = t; e < n; e += 1024) sum2_add(s, c, part[e]);
+  sum2_wave(s, c);
+  if ((t & 63) == 0) {
+    lds[t >> 6][0] = s;
+    lds[t >> 6][1] = c;
   }
-  return lds[0];
+  __syncthreads();
+  double S = lds[0][0], C = lds[0][1];
+  for (int q = 1; q < 16; ++q) {
+    sum2_add(S, C, lds[q][0]);
+    C += lds[q][1];
+  }
+  return S + C;
 }
 
 struct SumF64Args {
@@ -148,7 +155,7 @@ struct SumF64Args {
 };
 
 __device__ __forceinline__ void sum_f64_body(const SumF64Args& a, uint3, uint3) {
-  __shared__ double lds[1024];
+  __shared__ double lds[16][2];
   const double s = block_sum_f64(a.part, a.n, lds);
   if (threadIdx.x == 0) a.out[0] = s + (a.add_to ? a.add_to[0] : 0.0);
 }
@@ -181,7 +188,7 @@ hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, d
 __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsigned bx) {
   __shared__ float red[3 * kMaxModes][32][33];
   __shared__ float S[kMaxModes][32], T[kMaxModes][32], Cmin[kMaxModes][32];
-  __shared__ double lds64[1024];
+  __shared__ double lds64[16][2];
   const int t = threadIdx.x;
   const int c = t & 31, g = t >> 5;
   int nblk_max = 0;
@@ -195,8 +202,10 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
     acc[n][1] = 3.402823e38f;
     acc[n][2] = 0.0f;
   }
-  // the first objective partial goes out with the statistics' first round
-  double objs = 0.0;
+  // the first objective partial goes out with the statistics' first round;
+  // the partials are added compensated (each thread's, then the lanes, then
+  // the 16 wavefronts)
+  double objs = 0.0, objc = 0.0;
   const double ob0 = (a.obj_part && t < a.obj_n) ? a.obj_part[t] : 0.0;
   if (a.part) {
     // partial statistics of the pre-pass: thread (g, c) reads part g
@@ -227,10 +236,14 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
         acc[n][2] += v[u][n][2];
       }
   }
-  objs += ob0;
+  objs = ob0;
   if (a.obj_part)
-    for (int64_t e = t + 1024; e < a.obj_n; e += 1024) objs += a.obj_part[e];
-  lds64[t] = objs;
+    for (int64_t e = t + 1024; e < a.obj_n; e += 1024) sum2_add(objs, objc, a.obj_part[e]);
+  sum2_wave(objs, objc);
+  if ((t & 63) == 0) {
+    lds64[t >> 6][0] = objs;
+    lds64[t >> 6][1] = objc;
+  }
 #pragma unroll
   for (int n = 0; n < kMaxModes; ++n)
 #pragma unroll
@@ -247,13 +260,14 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
       else S[n][c] = s;
     }
   }
-  for (int w = 512; w > 0; w >>= 1) {
-    __syncthreads();
-    if (t < w) lds64[t] += lds64[t + w];
-  }
   __syncthreads();
   if (a.obj_out && t == 0 && bx == 0) {
-    double s = lds64[0];
+    double s = lds64[0][0], sc = lds64[0][1];
+    for (int q = 1; q < 16; ++q) {
+      sum2_add(s, sc, lds64[q][0]);
+      sc += lds64[q][1];
+    }
+    s += sc;
     if (a.obj_add_model_mass) {
       // sum over all cells of the reference model: sum_r prod_n colsum(A~^(n))_r
       double mass = 0.0;

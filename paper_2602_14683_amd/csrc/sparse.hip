@@ -86,7 +86,7 @@ __device__ __forceinline__ float half_sum(float v) {
 
 template <int N, int kRuns, int kAtoms>
 __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
-  __shared__ double lobj[kCooThreads / 64];
+  __shared__ double lobj[kCooThreads / 64][2];
   const int lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
   const int64_t wave = ((int64_t)blockIdx.x * kCooThreads + threadIdx.x) >> 6;
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
 
   int cur[2] = {-1, -1};
   float acc[2] = {0.0f, 0.0f};
-  double obj = 0.0;
+  double obj = 0.0, objc = 0.0;   // compensated sum of the objective terms
   for (int64_t sb = 0; sb < steps; ++sb) {
     // 32 nonzeros per half, one per lane, coalesced; validity once per
     // nonzero; a nonzero that is not valid reads row 0
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
       bool far;
       float d = kl_series(myx, myy, fast_rcp(myx + myy), far);
       if (far) d = kl_direct(myx, myy);
-      obj += (double)d - (double)myy;
+      sum2_add(obj, objc, (double)d - (double)myy);
     }
   }
   if (rlive) {
@@ -199,14 +199,19 @@ __global__ void __launch_bounds__(kCooThreads) coo_pass_kernel(CooPassArgs a) {
       if (cur[q] >= 0) unsafeAtomicAdd(&a.M[q][(int64_t)cur[q] * kRP + r], acc[q]);
   }
   if (a.obj_part) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) lobj[threadIdx.x >> 6] = obj;
+    sum2_wave(obj, objc);
+    if (lane == 0) {
+      lobj[threadIdx.x >> 6][0] = obj;
+      lobj[threadIdx.x >> 6][1] = objc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int q = 0; q < kCooThreads / 64; ++q) s += lobj[q];
-      a.obj_part[blockIdx.x] = s;
+      double s = lobj[0][0], c = lobj[0][1];
+      for (int q = 1; q < kCooThreads / 64; ++q) {
+        sum2_add(s, c, lobj[q][0]);
+        c += lobj[q][1];
+      }
+      a.obj_part[blockIdx.x] = s + c;
     }
   }
 }
@@ -272,7 +277,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
   __shared__ uint4 s_off[kW][2][64];
   __shared__ float s_x[kW][2][64];
   __shared__ float s_y[kW][64];      // X~ of each step of the current window
-  __shared__ double lobj[kW];
+  __shared__ double lobj[kW][2];
   const int lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -287,7 +292,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
   const int len0 = (len + 1) >> 1;             // half 0 is the longer half
   const int lenh = h ? len - len0 : len0;
   const int64_t bh = w0 + (h ? len0 : 0);
-  double obj = 0.0;
+  double obj = 0.0, objc = 0.0;   // compensated sum of the objective terms
 
   if (len > 0) {
     // ---- staging of window W into the lane's registers (lane = nonzero)
@@ -444,7 +449,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
         bool far;
         float d = kl_series(x, myy, fast_rcp(x + myy), far);
         if (far) d = kl_direct(x, myy);
-        obj += (double)d - (double)myy;
+        sum2_add(obj, objc, (double)d - (double)myy);
       }
     }
     if (rlive) {
@@ -456,14 +461,19 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
     }
   }
   if (a.obj_part) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) lobj[wv] = obj;
+    sum2_wave(obj, objc);
+    if (lane == 0) {
+      lobj[wv][0] = obj;
+      lobj[wv][1] = objc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int q = 0; q < kW; ++q) s += lobj[q];
-      a.obj_part[blockIdx.x] = s;
+      double s = lobj[0][0], c = lobj[0][1];
+      for (int q = 1; q < kW; ++q) {
+        sum2_add(s, c, lobj[q][0]);
+        c += lobj[q][1];
+      }
+      a.obj_part[blockIdx.x] = s + c;
     }
   }
 }

@@ -11,13 +11,13 @@ constexpr int kCooBetaThreads = 256;
 
 template <int BC>
 __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a) {
-  __shared__ double lobj[kCooBetaThreads / 64];
+  __shared__ double lobj[kCooBetaThreads / 64][2];
   const int lane = threadIdx.x & 63;
   const int r = lane & 31;
   const int64_t half = ((int64_t)blockIdx.x * kCooBetaThreads + threadIdx.x) >> 5;
   const int64_t nhalf = ((int64_t)gridDim.x * kCooBetaThreads) >> 5;
   const bool rlive = r < a.R;
-  double obj = 0.0;
+  double obj = 0.0, objc = 0.0;   // compensated sum of the objective terms
   // each half owns a contiguous chunk of the stream, so that equal target
   // rows of consecutive nonzeros are summed in a register (one atomic per run)
   const int64_t chunk = (a.nnz + nhalf - 1) / nhalf;
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
       w = p;
       if (r == 0) {
         if (a.w_out) a.w_out[t] = p;
-        if (a.obj_part) obj += (double)dbeta_term<BC>(x, y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc);
+        if (a.obj_part) sum2_add(obj, objc, (double)dbeta_term<BC>(x, y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc));
       }
     }
     if (a.mode >= 0 && rlive) {
@@ -76,27 +76,32 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_beta_kernel(CooBetaArgs a
   }
   if (run_row >= 0 && rlive) unsafeAtomicAdd(&a.num[(int64_t)run_row * kRP + r], run_acc);
   if (a.obj_part) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) lobj[threadIdx.x >> 6] = obj;
+    sum2_wave(obj, objc);
+    if (lane == 0) {
+      lobj[threadIdx.x >> 6][0] = obj;
+      lobj[threadIdx.x >> 6][1] = objc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int q = 0; q < kCooBetaThreads / 64; ++q) s += lobj[q];
-      a.obj_part[blockIdx.x] = s;
+      double s = lobj[0][0], c = lobj[0][1];
+      for (int q = 1; q < kCooBetaThreads / 64; ++q) {
+        sum2_add(s, c, lobj[q][0]);
+        c += lobj[q][1];
+      }
+      a.obj_part[blockIdx.x] = s + c;
     }
   }
 }
 
 template <int BC>
 __global__ void __launch_bounds__(kCooBetaThreads) coo_tucker_kernel(CooTkArgs a) {
-  __shared__ double lobj[kCooBetaThreads / 64];
+  __shared__ double lobj[kCooBetaThreads / 64][2];
   const int lane = threadIdx.x & 63;
   const int d = lane & 31;
   const int64_t half = ((int64_t)blockIdx.x * kCooBetaThreads + threadIdx.x) >> 5;
   const int64_t nhalf = ((int64_t)gridDim.x * kCooBetaThreads) >> 5;
   const int L = a.N - 1;  // the fibre mode
-  double obj = 0.0;
+  double obj = 0.0, objc = 0.0;   // compensated sum of the objective terms
   // contiguous chunk per half; equal target rows of consecutive nonzeros are
   // summed in a register (one atomic per run)
   const int64_t chunk = (a.nnz + nhalf - 1) / nhalf;
@@ -167,7 +172,7 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_tucker_kernel(CooTkArgs a
         if (d == 0 && live[u]) {
           if (a.w_out) a.w_out[tb + u] = p;
           if (a.obj_part)
-            obj += (double)dbeta_term<BC>(xv[u], y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc);
+            sum2_add(obj, objc, (double)dbeta_term<BC>(xv[u], y, a.bc) - (double)dbeta_term<BC>(0.0f, y, a.bc));
         }
       }
     }
@@ -192,14 +197,19 @@ __global__ void __launch_bounds__(kCooBetaThreads) coo_tucker_kernel(CooTkArgs a
   }
   if (run_row >= 0) unsafeAtomicAdd(&a.out[run_row * kRP + d], run_acc);
   if (a.obj_part) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) lobj[threadIdx.x >> 6] = obj;
+    sum2_wave(obj, objc);
+    if (lane == 0) {
+      lobj[threadIdx.x >> 6][0] = obj;
+      lobj[threadIdx.x >> 6][1] = objc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int q = 0; q < kCooBetaThreads / 64; ++q) s += lobj[q];
-      a.obj_part[blockIdx.x] = s;
+      double s = lobj[0][0], c = lobj[0][1];
+      for (int q = 1; q < kCooBetaThreads / 64; ++q) {
+        sum2_add(s, c, lobj[q][0]);
+        c += lobj[q][1];
+      }
+      a.obj_part[blockIdx.x] = s + c;
     }
   }
 }

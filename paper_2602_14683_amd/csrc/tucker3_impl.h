@@ -68,7 +68,7 @@ __device__ __forceinline__ void load_fibre(const float* __restrict__ row, int64_
 template <int BC, int kMode, bool kObj, int kSets, bool kBf>
 __device__ __forceinline__ void tk_v_body(const TkPassArgs& a, unsigned bx) {
   __shared__ float red[kWaves][kSets > 0 ? kSets : 1][32 * 33];
-  __shared__ double sobj[kWaves];
+  __shared__ double sobj[kWaves][2];
   const int lane = threadIdx.x & 63;
   const int col = lane & 31, h = lane >> 5;
   const int w = threadIdx.x >> 6;
@@ -89,7 +89,7 @@ __device__ __forceinline__ void tk_v_body(const TkPassArgs& a, unsigned bx) {
     split_bf16(t2 + 8, t2h[1], t2l[1]);
   }
   f32x16 vn = {}, vd = {};
-  double obj = 0.0;
+  double obj = 0.0, objc = 0.0;   // compensated sum of the objective tiles
   const float* xrow = a.X + pm * (int64_t)K;
   const float* prow = kMode == kTkCacheRead ? a.Pc + pm * (int64_t)K : nullptr;
   const float* qrow = kMode == kTkCacheRead && kSets == 2 ? a.Qc + pm * (int64_t)K : nullptr;
@@ -127,8 +127,9 @@ __device__ __forceinline__ void tk_v_body(const TkPassArgs& a, unsigned bx) {
 #pragma unroll
         for (int s = 0; s < 16; ++s) xh = mfma32(crow[s], t2[s], xh);
       }
-      // the tile's 16 nonnegative terms per lane in float32, then float64
-      float objt = 0.0f;
+      // the tile's 16 nonnegative terms per lane in float64, the lane's tiles
+      // compensated
+      double objt = 0.0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int k = k0 + out_row(v, h);
@@ -138,11 +139,11 @@ __device__ __forceinline__ void tk_v_body(const TkPassArgs& a, unsigned bx) {
         const float y = fmaxf(xh[v], a.eps);
         float p, q, d = 0.0f;
         entry<BC, kObj>(x, y, a.bc, p, q, d);
-        if constexpr (kObj) objt += ok ? d : 0.0f;
+        if constexpr (kObj) objt += (double)(ok ? d : 0.0f);
         pv[v] = ok ? p : 0.0f;
         qv[v] = ok ? q : 0.0f;
       }
-      if constexpr (kObj) obj += (double)objt;
+      if constexpr (kObj) sum2_add(obj, objc, objt);
       if constexpr (kMode == kTkCacheWrite) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -186,9 +187,11 @@ __device__ __forceinline__ void tk_v_body(const TkPassArgs& a, unsigned bx) {
     }
   }
   if constexpr (kObj) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off);
-    if (lane == 0) sobj[w] = obj;
+    sum2_wave(obj, objc);
+    if (lane == 0) {
+      sobj[w][0] = obj;
+      sobj[w][1] = objc;
+    }
   }
   __syncthreads();
   if constexpr (kSets >= 1) {
@@ -208,9 +211,12 @@ __device__ __forceinline__ void tk_v_body(const TkPassArgs& a, unsigned bx) {
   }
   if constexpr (kObj) {
     if (threadIdx.x == 0) {
-      double s = sobj[0];
-      for (int q = 1; q < kWaves; ++q) s += sobj[q];
-      a.obj_part[bx] = s;
+      double s = sobj[0][0], c = sobj[0][1];
+      for (int q = 1; q < kWaves; ++q) {
+        sum2_add(s, c, sobj[q][0]);
+        c += sobj[q][1];
+      }
+      a.obj_part[bx] = s + c;
     }
   }
 }
