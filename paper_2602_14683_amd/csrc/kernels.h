@@ -166,14 +166,7 @@ struct KlLoopArgs {
   int64_t obj_n;
   double* obj_out;         // written if not NULL
   int obj_add_model_mass;  // also add sum_r prod_n colsum(A~^(n))_r (sparse objective)
-  // optional (many statistics blocks): [kKlParts][kMaxModes][3][32] partial
-  // statistics, reduced by a pre-pass so that every kl_apply workgroup reads
-  // kKlParts entries instead of all blocks
-  float* part;
 };
-constexpr int kKlParts = 32;
-// Workspace floats of KlLoopArgs::part.
-constexpr int64_t kKlPartFloats = (int64_t)kKlParts * kMaxModes * 96;
 hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s);
 // Sets `bit` in *flag if one of the n floats at p is below lo or not finite.
 hipError_t launch_check_range(const float* p, int64_t n, float lo, int bit, int* flag, hipStream_t s);

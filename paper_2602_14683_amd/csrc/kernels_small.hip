@@ -207,15 +207,7 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
   // the 16 wavefronts)
   double objs = 0.0, objc = 0.0;
   const double ob0 = (a.obj_part && t < a.obj_n) ? a.obj_part[t] : 0.0;
-  if (a.part) {
-    // partial statistics of the pre-pass: thread (g, c) reads part g
-#pragma unroll
-    for (int n = 0; n < kMaxModes; ++n)
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        acc[n][k] = a.part[((int64_t)(g * kMaxModes + n) * 3 + k) * 32 + c];
-  }
-  for (int b0 = a.part ? nblk_max : g; b0 < nblk_max; b0 += 4 * 32) {
+  for (int b0 = g; b0 < nblk_max; b0 += 4 * 32) {
     float v[4][kMaxModes][3];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -312,17 +304,19 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
         if (__any(clip)) {
           float s = 0.0f;
           if (clip) {
-            // batches of sixteen rows, the last one's loads clamped to a
-            // valid row and its rows past the end left out of the sum (the
-            // rows are added in the same order as one at a time)
+            // batches of 32 rows per thread (1024 rows per round: a round
+            // reads c written by the previous launch, often on another XCD),
+            // the last one's loads clamped to a valid row and its rows past
+            // the end left out of the sum (the rows are added in the same
+            // order as one at a time)
             const float* cp = a.c[n] + col;
             const int rows = a.rows[n];
-            for (int r = g; r < rows; r += 16 * 32) {
-              float v[16];
+            for (int r = g; r < rows; r += 32 * 32) {
+              float v[32];
 #pragma unroll
-              for (int u = 0; u < 16; ++u) v[u] = cp[(int64_t)min(r + 32 * u, rows - 1) * kRP];
+              for (int u = 0; u < 32; ++u) v[u] = cp[(int64_t)min(r + 32 * u, rows - 1) * kRP];
 #pragma unroll
-              for (int u = 0; u < 16; ++u)
+              for (int u = 0; u < 32; ++u)
                 if (r + 32 * u < rows) s += fmaxf(v[u] / d, a.eps);
             }
           }
@@ -346,63 +340,6 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
     }
   }
 }
-
-// Pre-pass of the column statistics when there are many blocks: workgroup p
-// reduces blocks p, p + kKlParts, ... of every mode (thread (g, c) takes
-// every 32nd of those, four per mode in flight), the 32 row groups added in
-// order, into part p.  Identity entries (0, FLT_MAX, 0) where a part has no
-// block.
-__device__ __forceinline__ void kl_stats_body(const KlLoopArgs& a, uint3 bid, uint3) {
-  __shared__ float red[3 * kMaxModes][32][33];
-  const int t = threadIdx.x;
-  const int c = t & 31, g = t >> 5;
-  const int p = (int)bid.x;
-  int jmax = 0;   // blocks of the longest mode that fall to this part
-#pragma unroll
-  for (int n = 0; n < kMaxModes; ++n)
-    if (n < a.N) jmax = max(jmax, (a.nblk[n] - p + kKlParts - 1) / kKlParts);
-  float acc[kMaxModes][3];
-#pragma unroll
-  for (int n = 0; n < kMaxModes; ++n) {
-    acc[n][0] = 0.0f;
-    acc[n][1] = 3.402823e38f;
-    acc[n][2] = 0.0f;
-  }
-  for (int j0 = g; j0 < jmax; j0 += 4 * 32) {
-    float v[4][kMaxModes][3];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int n = 0; n < kMaxModes; ++n)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int b = p + kKlParts * (j0 + 32 * u);
-          v[u][n][k] = (n < a.N && b < a.nblk[n]) ? a.stats[n][(int64_t)b * 96 + 32 * k + c]
-                                                 : (k == 1 ? 3.402823e38f : 0.0f);
-        }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int n = 0; n < kMaxModes; ++n) {
-        acc[n][0] += v[u][n][0];
-        acc[n][1] = fminf(acc[n][1], v[u][n][1]);
-        acc[n][2] += v[u][n][2];
-      }
-  }
-#pragma unroll
-  for (int n = 0; n < kMaxModes; ++n)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) red[3 * n + k][g][c] = acc[n][k];
-  __syncthreads();
-  if (t < 3 * kMaxModes * 32) {
-    const int q = t >> 5;
-    const int k = q % 3;
-    float s = red[q][0][c];
-    for (int gg = 1; gg < 32; ++gg) s = (k == 1) ? fminf(s, red[q][gg][c]) : s + red[q][gg][c];
-    a.part[((int64_t)p * 3 * kMaxModes + q) * 32 + c] = s;
-  }
-}
-COMM_GROUPED_KERNELS(kl_stats, KlLoopArgs, 1024)
 
 // A^(n) = max(c^(n) / Den_last^(n), eps) for all modes; each workgroup first
 // runs the recurrence itself.
@@ -621,10 +558,6 @@ hipError_t launch_kl_apply(const KlLoopArgs& a, hipStream_t s) {
   for (int q = 0; q < a.N; ++q) n += (int64_t)a.rows[q] * kRP;
   int blocks = (int)((n + 1023) / 1024);
   if (blocks > 64) blocks = 64;
-  if (a.part) {
-    const hipError_t e = launch_or_record(kl_stats_kernel, kl_stats_grouped, dim3(kKlParts), dim3(1024), 0, s, a);
-    if (e != hipSuccess) return e;
-  }
   return launch_or_record(kl_apply_kernel, kl_apply_grouped, dim3(blocks), dim3(1024), 0, s, a);
 }
 

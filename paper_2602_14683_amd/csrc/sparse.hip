@@ -331,7 +331,12 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
     if (windows > 1) load_window(1);
     lds_sync();
 
-    // a run starts at the half's first nonzero; every flush is then real
+    // A run starts at the half's first nonzero; every flush is then real.
+    // Runs are tracked by the row's byte offset; at rank 32 with the lane's
+    // column added, which is also the lane's byte offset in the [dims][32]
+    // accumulator (both rows are 128 bytes), so a flush needs no address
+    // arithmetic.
+    const uint32_t rkey = kFullR ? rcol4 : 0u;
     uint32_t cur[kRuns];
     float acc[kRuns];
     {
@@ -339,7 +344,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
       const uint32_t o[4] = {o4.x, o4.y, o4.z, o4.w};
 #pragma unroll
       for (int q = 0; q < kRuns; ++q) {
-        cur[q] = o[q];
+        cur[q] = o[q] + rkey;
         acc[q] = 0.0f;
       }
     }
@@ -361,16 +366,18 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
         for (int q = 0; q < N; ++q)
           B.g[u][q] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(a.A[q]) + (o[q] + rcol4));
 #pragma unroll
-        for (int q = 0; q < kRuns; ++q) B.ro[u][q] = o[q];
+        for (int q = 0; q < kRuns; ++q) B.ro[u][q] = o[q] + rkey;
       }
     };
     const int64_t rep = (int64_t)(blockIdx.x & (unsigned)a.rep_mask);
     float* Mq[kRuns];
 #pragma unroll
     for (int q = 0; q < kRuns; ++q) Mq[q] = a.M[q] + rep * a.mrep[q];
-    auto moff = [&](uint32_t o) -> int64_t {
-      const uint32_t row = kFullR ? o >> 7 : (uint32_t)fmaf((float)o, a.inv_r4, 0.5f);
-      return (int64_t)row * kRP + r;
+    // the accumulator entry of run key o (R < 32: the row from the offset)
+    auto acc_at = [&](int q, uint32_t o) -> float* {
+      if constexpr (kFullR) return reinterpret_cast<float*>(reinterpret_cast<char*>(Mq[q]) + o);
+      const uint32_t row = (uint32_t)fmaf((float)o, a.inv_r4, 0.5f);
+      return Mq[q] + (int64_t)row * kRP + r;
     };
     auto consume = [&](int jj, const Batch& B) {
 #pragma unroll
@@ -386,7 +393,7 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
         const float w = z * (B.x[u] * fast_rcp(y));
         if constexpr (kRuns == 1) {
           if (B.ro[u][0] != cur[0]) {
-            if (rlive) unsafeAtomicAdd(&Mq[0][moff(cur[0])], acc[0]);
+            if (rlive) unsafeAtomicAdd(acc_at(0, cur[0]), acc[0]);
             cur[0] = B.ro[u][0];
             acc[0] = 0.0f;
           }
@@ -397,12 +404,12 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
           // slot 1's run also ends where slot 0 changes
           const bool c0 = B.ro[u][0] != cur[0];
           if (c0 || B.ro[u][1] != cur[1]) {
-            if (rlive) unsafeAtomicAdd(&Mq[1][moff(cur[1])], acc[1]);
+            if (rlive) unsafeAtomicAdd(acc_at(1, cur[1]), acc[1]);
             acc[0] += acc[1];
             acc[1] = 0.0f;
             cur[1] = B.ro[u][1];
             if (c0) {
-              if (rlive) unsafeAtomicAdd(&Mq[0][moff(cur[0])], acc[0]);
+              if (rlive) unsafeAtomicAdd(acc_at(0, cur[0]), acc[0]);
               acc[0] = 0.0f;
               cur[0] = B.ro[u][0];
             }
@@ -454,10 +461,10 @@ __global__ void __launch_bounds__(kCooThreads) coo_plan_pass_kernel(CooPlanPassA
     }
     if (rlive) {
       if constexpr (kRuns == 2) {
-        unsafeAtomicAdd(&Mq[1][moff(cur[1])], acc[1]);
+        unsafeAtomicAdd(acc_at(1, cur[1]), acc[1]);
         acc[0] += acc[1];
       }
-      unsafeAtomicAdd(&Mq[0][moff(cur[0])], acc[0]);
+      unsafeAtomicAdd(acc_at(0, cur[0]), acc[0]);
     }
   }
   if (a.obj_part) {
@@ -672,7 +679,6 @@ int bits_for(uint64_t n) {
 struct CooWs {
   float* M[kMaxModes];   // reps replicas of [dims][32] each
   float* stats[kMaxModes];
-  float* kl_part;        // partial column statistics (kl_apply's pre-pass)
   double* obj_part;
   int reps;
   size_t bytes;
@@ -700,7 +706,6 @@ CooWs coo_layout(int N, const int* dims, int blocks, char* base, int reps = 1) {
     w.M[n] = cv.take<float>((size_t)reps * dims[n] * kRP);
     w.stats[n] = cv.take<float>((size_t)((dims[n] + kSumRows - 1) / kSumRows) * 96);
   }
-  w.kl_part = cv.take<float>((size_t)kKlPartFloats);
   w.obj_part = cv.take<double>((size_t)blocks);
   w.bytes = cv.off + 256;
   return w;
@@ -817,9 +822,6 @@ int coo_outer(comm_ctx* ctx, int N, const int* dims, int64_t nnz, comm_model* m,
     k.cur_pad[n] = nullptr;
     k.user[n] = m->factors[n];
   }
-  // many statistics blocks (long modes): reduce them once, in a pre-pass,
-  // instead of in every kl_apply workgroup
-  if (sa.first_block[N] > 4 * 128) k.part = w.kl_part;
   hipLaunchKernelGGL(coo_sum_kernel, dim3((unsigned)sa.first_block[N]), dim3(1024), 0, st, sa);
   HIP_TRY(hipGetLastError());
   if (obj) {
