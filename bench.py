@@ -624,7 +624,7 @@ def run_coo(args, ctx):
                            "parallelism": "single GPU"},
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                             "kernel": "coo_pass_kernel (two passes over the sorted copies: gather, model value, run sums)",
+                             "kernel": "coo_plan_pass_kernel (two passes over the sorted copies: LDS-staged row offsets, gathers, model value, run sums)",
                              "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
                              "algorithmic_bytes_per_launch": bytes_},
                 "plan_build_s": round(plan_s, 4),
