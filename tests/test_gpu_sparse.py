@@ -205,3 +205,30 @@ def test_coo_unaligned_factors(ctx):
     want = osp.jcomm_outer_kl(s.idx, s.val, init, L=2)
     for a, b in zip(fac, want):
         assert max_rel(host64(a), b) < 3 * TOL
+
+
+# The plan pass's edge cases: a wave with a single nonzero (its second half
+# empty), odd counts (the halves differ by one), the 32-step windows and the
+# 64-nonzero waves' boundaries, several waves (256 nonzeros per wave at these
+# sizes; 257 leaves one nonzero to the last wave), rank 32 (the offsets that
+# double as accumulator offsets) and rank 5 with an order-3 tensor (one run
+# mode in the second copy).
+@pytest.mark.parametrize("nnz", [1, 2, 3, 63, 64, 65, 129, 257, 1000])
+@pytest.mark.parametrize("dims,rank", [((7, 6, 9, 11), 32), ((7, 6, 29), 5)])
+def test_coo_plan_edge_counts(ctx, nnz, dims, rank):
+    total = int(np.prod(dims))
+    s = workloads.sparse_small(11, dims=dims, density=nnz / total, rank=rank)
+    assert len(s.val) == nnz
+    init = [f32(a) for a in s.init]
+    sidx, sval = _shuffled(s, 3)
+    idx = [torch.tensor(sidx[:, n].astype(np.int32), device="cuda") for n in range(len(dims))]
+    plan = ctx.coo_plan(idx, dev(sval), dims)
+    fac = [dev(a) for a in init]
+    obj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.cp_jcomm_outer_coo_plan(plan, fac, L=1, obj_out=obj)
+    torch.cuda.synchronize()
+    want, fref = osp.jcomm_outer_kl(s.idx, s.val, init, L=1, return_ref_obj=True)
+    for a, b in zip(fac, want):
+        assert max_rel(host64(a), b) < TOL
+    assert abs(obj.item() - fref) / fref < 1e-5
+    plan.close()
