@@ -40,6 +40,10 @@ if ROOT not in sys.path:
 METRIC = "J-CoMM outer iters/s (CP 256³ R32 β=1) + %roofline; batched solves/s, p99 ms"
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# the pass-kernel launches that carry timing events: every 7th, from the
+# first (a prime, so that every launch of a step's fixed launch pattern is
+# sampled alike); a timed dispatch costs the stream a few microseconds
+PROFILE_EVERY = 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cp3_pass_kl_256_r32_traffic.json")
 # sources that define the timed pass kernel; the stored counter figures are
 # trusted only while these files are unchanged
@@ -130,7 +134,7 @@ def control_512(ctx, steps):
     for _ in range(2):
         ctx.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=obj)
     torch.cuda.synchronize()
-    ctx.profile_enable(True)
+    ctx.profile_enable(PROFILE_EVERY)
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=obj)
@@ -274,7 +278,7 @@ def rank16(ctx, steps):
             def step(t):
                 c.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=trace[t:t + 1])
 
-            elapsed, kernel_ms, launches = timed_loop(c, step, 3, steps)
+            elapsed, kernel_ms, launches, seen = timed_loop(c, step, 3, steps)
             avg_us = kernel_ms / max(launches, 1) * 1e3
             tfl = flops / (avg_us * 1e-6) / 1e12
             out["tiles_16" if tile == 0 else "tiles_32"] = {
@@ -287,14 +291,16 @@ def rank16(ctx, steps):
 
 def timed_loop(ctx, step, warmup, steps):
     """Warm up, then time `steps` calls of step(t) between synchronisations;
-    the library records HIP events around every pass-kernel launch on the
-    launch stream meanwhile.  Returns (elapsed s, pass-kernel ms, launches)."""
+    meanwhile every PROFILE_EVERY-th pass-kernel launch on the launch stream
+    carries HIP events that its dispatch stamps with the kernel's start and
+    end.  Returns (elapsed s, summed ms of the timed launches, timed launches,
+    all pass launches)."""
     import torch
     stream = torch.cuda.current_stream()
     for t in range(warmup):
         step(t)
     torch.cuda.synchronize()
-    ctx.profile_enable(True)
+    ctx.profile_enable(PROFILE_EVERY)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -305,9 +311,9 @@ def timed_loop(ctx, step, warmup, steps):
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms, launches = ctx.profile_query()
+    kernel_ms, launches, seen = ctx.profile_query_all()
     ctx.profile_enable(False)
-    return max(wall, ev0.elapsed_time(ev1) / 1e3), kernel_ms, launches
+    return max(wall, ev0.elapsed_time(ev1) / 1e3), kernel_ms, launches, seen
 
 
 def monotone(tr):
@@ -338,7 +344,7 @@ def run_cp(args, ctx):
     def step(t):
         ctx.jcomm_outer(X, fac, beta=beta, L=L, obj_out=trace[t:t + 1])
 
-    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    elapsed, kernel_ms, launches, seen = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()
     steps_tr = tr[args.warmup:args.warmup + args.steps]
 
@@ -350,7 +356,7 @@ def run_cp(args, ctx):
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
                 "traffic": measured_traffic(),
                 "kernel": "cp3_pass_kernel<KL> (fused rebuild + P~ + 3 numerators + FP64 objective)",
-                "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": seen, "launches_timed": launches,
                 "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 4 * entries,
                 "hbm_gbs_algorithmic": round(4 * entries / (avg_ms * 1e-3) / 1e9, 1)}
     out = base_line(args, elapsed)
@@ -391,7 +397,7 @@ def run_tucker(args, ctx):
     def step(t):
         ctx.jcomm_outer(X, F, core=G, beta=beta, L=1, obj_out=trace[t:t + 1])
 
-    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    elapsed, kernel_ms, launches, seen = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
     entries = 200 ** 3
     J = 16
@@ -408,8 +414,8 @@ def run_tucker(args, ctx):
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
                              "kernel": "tk_v_kernel / tk_m3_kernel (fused rebuild + P~, Q~ + numerator and denominator contractions)",
-                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
-                             "passes_per_outer_iteration": round(launches / max(args.steps, 1), 3),
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": seen, "launches_timed": launches,
+                             "passes_per_outer_iteration": round(seen / max(args.steps, 1), 3),
                              "algorithmic_bytes_per_launch": bytes_, "algorithmic_flops_per_launch": flops,
                              "tflops_algorithmic": round(flops / (avg_ms * 1e-3) / 1e12, 2)},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
@@ -490,7 +496,7 @@ def run_cp4(args, ctx):
     def step(t):
         ctx.jcomm_outer(X, fac, beta=beta, L=L, obj_out=trace[t:t + 1])
 
-    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    elapsed, kernel_ms, launches, seen = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
     entries = int(np.prod(dims))
     avg_ms = kernel_ms / max(launches, 1)
@@ -508,7 +514,7 @@ def run_cp4(args, ctx):
                 "roofline": {"bound": "mfma", "achieved": round(tfl, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(tfl / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
                              "kernel": "cp3_pass_kernel on the 5600 x 60 x 50 view",
-                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": seen, "launches_timed": launches,
                              "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 4 * entries,
                              "hbm_gbs_algorithmic": round(4 * entries / (avg_ms * 1e-3) / 1e9, 1)},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
@@ -556,7 +562,7 @@ def run_tuckern(args, ctx, dims, J):
     def step(t):
         ctx.jcomm_outer(X, F, core=G, beta=beta, L=L, obj_out=trace[t:t + 1])
 
-    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    elapsed, kernel_ms, launches, seen = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
     entries = int(np.prod(dims))
     avg_ms = kernel_ms / max(launches, 1)
@@ -574,7 +580,7 @@ def run_tuckern(args, ctx, dims, J):
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
                              "kernel": f"tk_v_kernel / tk_m3_kernel on the {rows} x {dims[-1]} view",
-                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": seen, "launches_timed": launches,
                              "algorithmic_bytes_per_launch": bytes_},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
     if not args.no_cpu_baseline:
@@ -611,7 +617,7 @@ def run_coo(args, ctx):
     def step(t):
         ctx.cp_jcomm_outer_coo_plan(plan, fac, L=1, obj_out=trace[t:t + 1])
 
-    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    elapsed, kernel_ms, launches, seen = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
     nnz = int(val.numel())
     avg_ms = kernel_ms / max(launches, 1)
@@ -625,7 +631,7 @@ def run_coo(args, ctx):
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
                              "kernel": "coo_plan_pass_kernel (two passes over the sorted copies: LDS-staged row offsets, gathers, model value, run sums)",
-                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": seen, "launches_timed": launches,
                              "algorithmic_bytes_per_launch": bytes_},
                 "plan_build_s": round(plan_s, 4),
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
@@ -653,7 +659,7 @@ def run_coo_beta(args, ctx):
     def step(t):
         ctx.cp_jcomm_outer_coo(idx, val, s.dims, fac, L=1, obj_out=trace[t:t + 1], beta=beta)
 
-    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    elapsed, kernel_ms, launches, seen = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
     cells = int(np.prod(s.dims))
     R = 32
@@ -671,7 +677,7 @@ def run_coo_beta(args, ctx):
                 "roofline": {"bound": "mfma", "achieved": round(tfl, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(tfl / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
                              "kernel": "cp3_pass_kernel over the 4392 x 1140 x 1717 view of the zero tensor",
-                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": launches,
+                             "kernel_avg_us": round(avg_ms * 1e3, 2), "launches": seen, "launches_timed": launches,
                              "algorithmic_flops_per_launch": flops},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
     if not args.no_cpu_baseline:
@@ -724,7 +730,7 @@ def run_tucker5_coo(args, ctx):
     def step(t):
         ctx.tucker_jcomm_outer_coo(idx, val, dims, G, F, beta=beta, L=1, obj_out=trace[t:t + 1])
 
-    elapsed, kernel_ms, launches = timed_loop(ctx, step, args.warmup, args.steps)
+    elapsed, kernel_ms, launches, seen = timed_loop(ctx, step, args.warmup, args.steps)
     tr = trace.cpu().numpy()[args.warmup:args.warmup + args.steps]
     nnz = int(val.numel())
     out = base_line(args, elapsed)
@@ -736,7 +742,7 @@ def run_tucker5_coo(args, ctx):
                            "parallelism": "single GPU"},
                 "roofline": None if launches == 0 else {
                     "bound": "hbm", "kernel": "tk_v_kernel / tk_m3_kernel on the zero tensor (Q~ denominators)",
-                    "kernel_avg_us": round(kernel_ms / launches * 1e3, 2), "launches": launches},
+                    "kernel_avg_us": round(kernel_ms / launches * 1e3, 2), "launches": seen, "launches_timed": launches},
                 "objective": {"first": float(tr[0]), "last": float(tr[-1]), "monotone": monotone(tr)}})
     if not args.no_cpu_baseline:
         X = workloads.densify(s)

@@ -266,14 +266,22 @@ const char* comm_last_error(void);
  * Tucker J-CoMM with 256 mode-3 pair groups. */
 size_t comm_workspace_bytes(const comm_dense* x, const comm_model* model, const comm_opts* opts, int op);
 
-/* Measurement hooks.  While enabled, the context records a pair of HIP events
- * on the call's stream around every launch of the fused dense pass kernel
- * (the kernel that streams X).  comm_profile_query() waits for the recorded
- * events, returns the summed kernel time in milliseconds and the number of
- * launches since the last enable/query, and resets the record.  Enabling also
- * resets it. */
-int comm_profile_enable(comm_ctx* ctx, int on);
-int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches);
+/* Measurement hooks.  comm_profile_enable(ctx, every) with every >= 1 times
+ * every `every`-th launch of the fused dense pass kernel (the kernel that
+ * streams X) on the call's stream, starting with the first: the dispatch
+ * itself stamps a pair of HIP events with the kernel's start and end (inside a
+ * stream capture the pair is recorded around the launch instead); every = 0
+ * turns the measurement off; every < 0 is COMM_EINVAL.  Timing a launch costs
+ * the stream a few microseconds, so a sampled measurement (every > 1)
+ * disturbs a timed loop less.  comm_profile_query() waits for the recorded
+ * events, returns the summed time of the timed launches in milliseconds, their
+ * count in *launches and, when `seen` is not NULL, the count of all pass
+ * launches in *seen, since the last enable/query, and resets the record.
+ * Enabling also resets it, and creates the first 2048 event pairs up front (on
+ * the context's device) so that measured launches do not pay for creating
+ * them; the events live until comm_destroy(). */
+int comm_profile_enable(comm_ctx* ctx, int every);
+int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches, int64_t* seen);
 
 /* Block-MM (B-CoMM) update of a CP model (Theorem "CP block multiplicative
  * update"; Algorithm B-CoMM).  block in 0..N-1 updates that factor; block = -1

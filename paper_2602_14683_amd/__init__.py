@@ -137,7 +137,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.comm_tune_lookup.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), P(TuneEntry)]
     lib.comm_tune_set.argtypes = [ctypes.c_void_p, P(Dense), P(Model), P(Opts), P(TuneEntry), ctypes.c_void_p]
     lib.comm_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
+    lib.comm_profile_query.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_int64)]
     for name in ["comm_create", "comm_destroy", "comm_profile_enable", "comm_profile_query", "comm_cp_update", "comm_tucker_update", "comm_jcomm_outer",
                  "comm_beta_objective", "comm_cp_jcomm_outer_coo", "comm_jcomm_outer_batched",
                  "comm_coo_plan_create", "comm_coo_plan_destroy", "comm_cp_jcomm_outer_coo_plan",
@@ -351,15 +351,24 @@ class Context:
 
     # ---------------------------------------------------------------- measurement
 
-    def profile_enable(self, on: bool = True) -> None:
-        _check(self._lib.comm_profile_enable(self._h, 1 if on else 0))
+    def profile_enable(self, on: "bool | int" = True) -> None:
+        """Time the fused dense pass launches: True (or 1) every launch, an
+        integer k > 1 every k-th launch starting with the first, False (or 0) none."""
+        every = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        _check(self._lib.comm_profile_enable(self._h, every))
 
     def profile_query(self):
-        """(total kernel milliseconds, launches) of the fused dense pass since enable / last query."""
+        """(total kernel milliseconds, timed launches) of the fused dense pass since enable / last query."""
+        ms, n, _ = self.profile_query_all()
+        return ms, n
+
+    def profile_query_all(self):
+        """(total kernel milliseconds, timed launches, all pass launches) since enable / last query."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        _check(self._lib.comm_profile_query(self._h, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        seen = ctypes.c_int64()
+        _check(self._lib.comm_profile_query(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(seen)))
+        return ms.value, n.value, seen.value
 
     def workspace_bytes(self, dims: Sequence[int], rank: int = 0, core_dims: Optional[Sequence[int]] = None,
                         beta: float = 1.0, L: int = 1, cache_pq: "bool | str" = False, op: int = 1) -> int:

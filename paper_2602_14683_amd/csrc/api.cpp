@@ -2050,16 +2050,34 @@ int comm_check(comm_ctx* ctx) {
   });
 }
 
-int comm_profile_enable(comm_ctx* ctx, int on) {
+int comm_profile_enable(comm_ctx* ctx, int every) {
   return guarded([&]() -> int {
     if (!ctx) return fail(COMM_EINVAL, "ctx is NULL");
-    ctx->profiling = on != 0;
+    if (every < 0) return fail(COMM_EINVAL, "profile sampling interval %d < 0", every);
+    ctx->profiling = every > 0;
+    ctx->profile_every = every > 0 ? every : 1;
+    ctx->profile_seen = 0;
     ctx->events_used = 0;
+    // create the event pool now, so that the launches being measured do not
+    // pay for event creation (the pool grows past this only on demand)
+    if (ctx->profiling && ctx->events.size() < kProfileEvents) {
+      if (int rc = set_device(ctx)) return rc;
+      ctx->events.reserve(kProfileEvents);
+      while (ctx->events.size() < kProfileEvents) {
+        hipEvent_t a0, a1;
+        HIP_TRY(hipEventCreate(&a0));
+        if (hipEventCreate(&a1) != hipSuccess) {
+          hipEventDestroy(a0);
+          return fail(COMM_EHIP, "hipEventCreate failed");
+        }
+        ctx->events.emplace_back(a0, a1);
+      }
+    }
     return COMM_OK;
   });
 }
 
-int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
+int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches, int64_t* seen) {
   return guarded([&]() -> int {
     if (!ctx || !total_ms || !launches) return fail(COMM_EINVAL, "NULL argument");
     double sum = 0.0;
@@ -2071,7 +2089,9 @@ int comm_profile_query(comm_ctx* ctx, double* total_ms, int64_t* launches) {
     }
     *total_ms = sum;
     *launches = (int64_t)ctx->events_used;
+    if (seen) *seen = ctx->profile_seen;
     ctx->events_used = 0;
+    ctx->profile_seen = 0;
     return COMM_OK;
   });
 }

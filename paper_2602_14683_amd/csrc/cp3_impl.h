@@ -1195,10 +1195,10 @@ hipError_t launch_vpass_t(const CpPassArgs& a, hipStream_t s) {
   const CpVPassLaunch l{a, gj};
   if (a.bf16) {
     if (record_grouped(cp3_vpass_grouped<BC, kCache, kObj, true>, grid, dim3(kThreads), 0, l)) return hipSuccess;
-    hipLaunchKernelGGL((cp3_vpass_kernel<BC, kCache, kObj, true>), grid, dim3(kThreads), 0, s, a, gj);
+    launch_timed(cp3_vpass_kernel<BC, kCache, kObj, true>, grid, dim3(kThreads), 0, s, a, gj);
   } else {
     if (record_grouped(cp3_vpass_grouped<BC, kCache, kObj, false>, grid, dim3(kThreads), 0, l)) return hipSuccess;
-    hipLaunchKernelGGL((cp3_vpass_kernel<BC, kCache, kObj, false>), grid, dim3(kThreads), 0, s, a, gj);
+    launch_timed(cp3_vpass_kernel<BC, kCache, kObj, false>, grid, dim3(kThreads), 0, s, a, gj);
   }
   return hipGetLastError();
 }
@@ -1214,13 +1214,13 @@ hipError_t launch_v(const CpPassArgs& a, const CpGrid& g, hipStream_t s) {
   const CpPassLaunch l{a, g.gj, g.gk};
   if (a.bf16) {
     if (record_grouped(cp3_pass_grouped<BC, kVar, kObj, true, false>, grid, block, 0, l)) return hipSuccess;
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, true, false>), grid, block, 0, s, a, g.gj, g.gk);
+    launch_timed(cp3_pass_kernel<BC, kVar, kObj, true, false>, grid, block, 0, s, a, g.gj, g.gk);
   } else if (a.r16) {
     if (record_grouped(cp3_pass_grouped<BC, kVar, kObj, false, true>, grid, block, 0, l)) return hipSuccess;
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, true>), grid, block, 0, s, a, g.gj, g.gk);
+    launch_timed(cp3_pass_kernel<BC, kVar, kObj, false, true>, grid, block, 0, s, a, g.gj, g.gk);
   } else {
     if (record_grouped(cp3_pass_grouped<BC, kVar, kObj, false, false>, grid, block, 0, l)) return hipSuccess;
-    hipLaunchKernelGGL((cp3_pass_kernel<BC, kVar, kObj, false, false>), grid, block, 0, s, a, g.gj, g.gk);
+    launch_timed(cp3_pass_kernel<BC, kVar, kObj, false, false>, grid, block, 0, s, a, g.gj, g.gk);
   }
   return hipGetLastError();
 }

@@ -15,6 +15,7 @@
 // while recording.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -94,6 +95,28 @@ inline thread_local Recorder* g_recorder = nullptr;
 
 inline Recorder* recorder() { return g_recorder; }
 
+// Timing of one launch.  While `g_timed` holds a pair of events, the next
+// kernel launched through launch_timed() takes them and clears them: the
+// dispatch itself stamps the start and end of that kernel into the events, so
+// nothing else is queued on the stream for the measurement.
+struct TimedLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
+inline thread_local TimedLaunch g_timed;
+
+// Launch errors are left for hipGetLastError(), as with hipLaunchKernelGGL.
+template <class... KArgs, class... Args>
+void launch_timed(void (*k)(KArgs...), dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Args&... args) {
+  if (g_timed.start) {
+    const TimedLaunch t = g_timed;
+    g_timed = TimedLaunch{};
+    hipExtLaunchKernelGGL(k, grid, block, (uint32_t)shmem, s, t.start, t.stop, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(k, grid, block, shmem, s, args...);
+  }
+}
+
 // While recording: append the grouped kernel with the item and return true.
 template <class Args>
 bool record_grouped(void (*grouped)(GroupTable), dim3 grid, dim3 block, size_t shmem, const Args& a) {
@@ -117,7 +140,7 @@ template <class Args>
 hipError_t launch_or_record(void (*single)(Args), void (*grouped)(GroupTable), dim3 grid, dim3 block, size_t shmem,
                             hipStream_t s, const Args& a) {
   if (record_grouped(grouped, grid, block, shmem, a)) return hipSuccess;
-  hipLaunchKernelGGL(single, grid, block, shmem, s, a);
+  launch_timed(single, grid, block, shmem, s, a);
   return hipGetLastError();
 }
 

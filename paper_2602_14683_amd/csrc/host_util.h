@@ -15,6 +15,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "../../include/comm.h"
+#include "group.h"
 #include "kernels.h"
 
 // A roctx range around one entry-point call (host side: the call's enqueue
@@ -54,6 +55,8 @@ struct comm_ctx {
   TuneChoice pick;
   // measurement: event pairs around every fused dense pass launch
   bool profiling = false;
+  int profile_every = 1;       // time every profile_every-th pass launch
+  int64_t profile_seen = 0;    // pass launches since enable / query
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
   // batched calls: one workspace holding every problem's own slice, internal
@@ -162,25 +165,45 @@ inline comm::BetaConst make_beta_const(double beta) {
 inline float gamma_of(double beta) { return beta < 1.0 ? (float)(1.0 / (2.0 - beta)) : 1.0f; }
 
 
-// Launch `launch()` bracketed by timing events when profiling is on (used for
-// every kernel that streams the dense tensor).
+// Event pairs created when profiling is enabled.
+constexpr size_t kProfileEvents = 2048;
+
+// Run `launch()` and, when profiling is on, count it and time the pass kernel
+// it launches if it is a sampled one (used for every kernel that streams the
+// dense tensor).  On an ordinary
+// stream the kernel's own dispatch stamps a pair of events (launch_timed);
+// the pair is returned to the pool when nothing consumed it (the launch was
+// recorded for a grouped batch).  While the stream is being captured into a
+// graph the pair is recorded around the launch instead.
 template <class F>
 int profiled(comm_ctx* ctx, hipStream_t st, F&& launch) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->profiling) {
-    if (ctx->events_used == ctx->events.size()) {
-      hipEvent_t a0, a1;
-      HIP_TRY(hipEventCreate(&a0));
-      HIP_TRY(hipEventCreate(&a1));
-      ctx->events.emplace_back(a0, a1);
-    }
-    e0 = ctx->events[ctx->events_used].first;
-    e1 = ctx->events[ctx->events_used].second;
-    ++ctx->events_used;
-    HIP_TRY(hipEventRecord(e0, st));
+  if (!ctx->profiling || comm::recorder() || ctx->profile_seen++ % ctx->profile_every != 0) {
+    HIP_TRY(launch());
+    return COMM_OK;
   }
-  HIP_TRY(launch());
-  if (e1) HIP_TRY(hipEventRecord(e1, st));
+  if (ctx->events_used == ctx->events.size()) {
+    hipEvent_t a0, a1;
+    HIP_TRY(hipEventCreate(&a0));
+    HIP_TRY(hipEventCreate(&a1));
+    ctx->events.emplace_back(a0, a1);
+  }
+  const hipEvent_t e0 = ctx->events[ctx->events_used].first;
+  const hipEvent_t e1 = ctx->events[ctx->events_used].second;
+  ++ctx->events_used;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) {
+    HIP_TRY(hipEventRecord(e0, st));
+    HIP_TRY(launch());
+    HIP_TRY(hipEventRecord(e1, st));
+    return COMM_OK;
+  }
+  comm::g_timed = comm::TimedLaunch{e0, e1};
+  const hipError_t e = launch();
+  const bool unused = comm::g_timed.start != nullptr;
+  comm::g_timed = comm::TimedLaunch{};
+  if (unused) --ctx->events_used;
+  HIP_TRY(e);
   return COMM_OK;
 }
 

@@ -490,11 +490,11 @@ hipError_t launch_plan_pass_n(const CooPlanPassArgs& a, int blocks, hipStream_t 
   const dim3 grid((unsigned)blocks), block(kCooThreads);
   const bool full = a.R == 32;
   if (a.obj_part) {
-    if (full) hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, true, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, true, false>), grid, block, 0, st, a);
+    if (full) launch_timed(coo_plan_pass_kernel<N, kRuns, true, true>, grid, block, 0, st, a);
+    else launch_timed(coo_plan_pass_kernel<N, kRuns, true, false>, grid, block, 0, st, a);
   } else {
-    if (full) hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, false, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((coo_plan_pass_kernel<N, kRuns, false, false>), grid, block, 0, st, a);
+    if (full) launch_timed(coo_plan_pass_kernel<N, kRuns, false, true>, grid, block, 0, st, a);
+    else launch_timed(coo_plan_pass_kernel<N, kRuns, false, false>, grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -510,11 +510,11 @@ hipError_t launch_plan_pass(const CooPlanPassArgs& a, int N, int runs, int block
 template <int N>
 hipError_t launch_coo_n(const CooPassArgs& a, int blocks, hipStream_t st) {
   const dim3 grid((unsigned)blocks), block(kCooThreads);
-  if (a.run_modes == 0 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 0, 0>), grid, block, 0, st, a);
+  if (a.run_modes == 0 && a.atom_modes == 0) launch_timed(coo_pass_kernel<N, 0, 0>, grid, block, 0, st, a);
   else if constexpr (N <= 4) {
-    if (a.run_modes == 2 && a.atom_modes == N - 2) hipLaunchKernelGGL((coo_pass_kernel<N, 2, N - 2>), grid, block, 0, st, a);
-    else if (a.run_modes == 2 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 2, 0>), grid, block, 0, st, a);
-    else if (a.run_modes == 1 && a.atom_modes == 0) hipLaunchKernelGGL((coo_pass_kernel<N, 1, 0>), grid, block, 0, st, a);
+    if (a.run_modes == 2 && a.atom_modes == N - 2) launch_timed(coo_pass_kernel<N, 2, N - 2>, grid, block, 0, st, a);
+    else if (a.run_modes == 2 && a.atom_modes == 0) launch_timed(coo_pass_kernel<N, 2, 0>, grid, block, 0, st, a);
+    else if (a.run_modes == 1 && a.atom_modes == 0) launch_timed(coo_pass_kernel<N, 1, 0>, grid, block, 0, st, a);
     else return hipErrorInvalidValue;
   } else {
     return hipErrorInvalidValue;

@@ -130,6 +130,32 @@ def _launches(ctx, X, init, core, beta, cache_pq, L=2):
 
 
 @pytest.mark.parametrize("make", [_cp, _tucker])
+def test_sampled_profiling_counts(ctx, make):
+    # every k-th pass launch is timed, starting with the first; all are counted
+    X, init, core = make(9)
+    ctx.profile_query()  # reset
+    ctx.profile_enable(1)
+    for _ in range(3):
+        _run(ctx, X, init, core, 1.5, False)
+    ms1, n1, seen1 = ctx.profile_query_all()
+    assert n1 == seen1 > 0 and ms1 > 0.0
+    for every in (2, 3, 7):
+        ctx.profile_enable(every)
+        for _ in range(3):
+            _run(ctx, X, init, core, 1.5, False)
+        ms, n, seen = ctx.profile_query_all()
+        assert seen == seen1
+        assert n == (seen + every - 1) // every
+        assert ms > 0.0
+    ctx.profile_enable(False)
+    for _ in range(2):
+        _run(ctx, X, init, core, 1.5, False)
+    assert ctx.profile_query_all() == (0.0, 0, 0)
+    with pytest.raises(comm.CommError):
+        ctx.profile_enable(-1)
+
+
+@pytest.mark.parametrize("make", [_cp, _tucker])
 def test_auto_runs_the_recorded_variant(ctx, make):
     # the cached variant writes P~ / Q~ in a pass of its own, so the two differ
     # in their count of fused pass launches: auto must match the recorded one
