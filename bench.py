@@ -192,7 +192,7 @@ def comparisons(ctx, X, init32, steps):
                                                                        precision="bf16"))
     # the bf16 pass time (HIP events on the launch stream) against its HBM
     # floor: X read once, 4 |X| = 67.1 MB at 8 TB/s = 8.39 us
-    _, kms, nl = timed_loop(ctx, lambda t: ctx.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=obj, precision="bf16"),
+    _, kms, nl, _ = timed_loop(ctx, lambda t: ctx.jcomm_outer(X, fac, beta=1.0, L=5, obj_out=obj, precision="bf16"),
                             2, steps)
     bf_us = kms / max(nl, 1) * 1e3
     floor_us = 4 * 256 ** 3 / (PEAK_HBM_GBS * 1e9) * 1e6
@@ -427,7 +427,7 @@ def run_tucker(args, ctx):
     def bf16_step(t):
         ctx.jcomm_outer(X, Fb, core=Gb, beta=beta, L=1, obj_out=trace[t:t + 1], precision="bf16")
 
-    el_b, _, _ = timed_loop(ctx, bf16_step, 2, args.steps)
+    el_b, _, _, _ = timed_loop(ctx, bf16_step, 2, args.steps)
     Gb.copy_(G0)
     for a, b in zip(Fb, F0):
         a.copy_(b)
@@ -445,7 +445,7 @@ def run_tucker(args, ctx):
     def tuned_step(t):
         ctx.jcomm_outer(X, Ft, core=Gt, beta=beta, L=1, obj_out=trace[t:t + 1], cache_pq="auto")
 
-    el_t, _, _ = timed_loop(ctx, tuned_step, 2, args.steps)
+    el_t, _, _, _ = timed_loop(ctx, tuned_step, 2, args.steps)
     out["tuned"] = {"entry": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in entry.items()},
                     "outer_it_s": round(args.steps / el_t, 2)}
     return out
