@@ -185,10 +185,12 @@ hipError_t launch_sum_f64(const double* part, int64_t n, const double* add_to, d
 // sweeps on 32-wide vectors, and leaves the last denominators in den_last.
 // Every workgroup of kl_apply runs it on the same data in the same order, so
 // all of them agree bitwise without synchronising.
-__device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsigned bx) {
+__device__ __forceinline__ void kl_objective_out(const KlLoopArgs& a, float (*S)[32], double (*lds64)[2]);
+
+__device__ __forceinline__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], float (*S)[32],
+                                              double (*lds64)[2], unsigned bx) {
   __shared__ float red[3 * kMaxModes][32][33];
-  __shared__ float S[kMaxModes][32], T[kMaxModes][32], Cmin[kMaxModes][32];
-  __shared__ double lds64[16][2];
+  __shared__ float T[kMaxModes][32], Cmin[kMaxModes][32];
   const int t = threadIdx.x;
   const int c = t & 31, g = t >> 5;
   int nblk_max = 0;
@@ -202,11 +204,12 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
     acc[n][1] = 3.402823e38f;
     acc[n][2] = 0.0f;
   }
-  // the first objective partial goes out with the statistics' first round;
+  // the first two objective partials go out with the statistics' first round;
   // the partials are added compensated (each thread's, then the lanes, then
   // the 16 wavefronts)
   double objs = 0.0, objc = 0.0;
   const double ob0 = (a.obj_part && t < a.obj_n) ? a.obj_part[t] : 0.0;
+  const double ob1 = (a.obj_part && t + 1024 < a.obj_n) ? a.obj_part[t + 1024] : 0.0;
   for (int b0 = g; b0 < nblk_max; b0 += 4 * 32) {
     float v[4][kMaxModes][3];
 #pragma unroll
@@ -229,8 +232,9 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
       }
   }
   objs = ob0;
+  sum2_add(objs, objc, ob1);
   if (a.obj_part)
-    for (int64_t e = t + 1024; e < a.obj_n; e += 1024) sum2_add(objs, objc, a.obj_part[e]);
+    for (int64_t e = t + 2048; e < a.obj_n; e += 1024) sum2_add(objs, objc, a.obj_part[e]);
   sum2_wave(objs, objc);
   if ((t & 63) == 0) {
     lds64[t >> 6][0] = objs;
@@ -253,25 +257,7 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
     }
   }
   __syncthreads();
-  if (a.obj_out && t == 0 && bx == 0) {
-    double s = lds64[0][0], sc = lds64[0][1];
-    for (int q = 1; q < 16; ++q) {
-      sum2_add(s, sc, lds64[q][0]);
-      sc += lds64[q][1];
-    }
-    s += sc;
-    if (a.obj_add_model_mass) {
-      // sum over all cells of the reference model: sum_r prod_n colsum(A~^(n))_r
-      double mass = 0.0;
-      for (int r = 0; r < a.R; ++r) {
-        double p = 1.0;
-        for (int n = 0; n < a.N; ++n) p *= (double)S[n][r];
-        mass += p;
-      }
-      s += mass;
-    }
-    a.obj_out[0] = s;
-  }
+  if (a.obj_out && bx == 0 && t < 64) kl_objective_out(a, S, lds64);
 
   // Every thread runs the recurrence of column c = t & 31 (the 32 threads of a
   // column compute the same values in the same order).  A column whose
@@ -341,10 +327,30 @@ __device__ void kl_recurrence(const KlLoopArgs& a, float (*den_last)[32], unsign
   }
 }
 
+// The objective at the reference, written by wavefront 0 of workgroup 0
+// before the recurrence, all lanes at once so that the recurrence's barriers
+// wait little for it: the 16 wavefront partials added compensated across
+// lanes, plus, for sparse data, the model's mass over every cell,
+// sum_r prod_n colsum(A~^(n))_r (one lane per r).
+__device__ __forceinline__ void kl_objective_out(const KlLoopArgs& a, float (*S)[32], double (*lds64)[2]) {
+  const int t = threadIdx.x;
+  double s = t < 16 ? lds64[t][0] : 0.0, sc = t < 16 ? lds64[t][1] : 0.0;
+  sum2_wave(s, sc);
+  double mass = 0.0;
+  if (a.obj_add_model_mass && t < a.R) {
+    mass = 1.0;
+    for (int n = 0; n < a.N; ++n) mass *= (double)S[n][t];
+  }
+  for (int off = 32; off > 0; off >>= 1) mass += __shfl_down(mass, off);
+  if (t == 0) a.obj_out[0] = (s + sc) + mass;
+}
+
 // A^(n) = max(c^(n) / Den_last^(n), eps) for all modes; each workgroup first
 // runs the recurrence itself.
 __device__ __forceinline__ void kl_apply_body(const KlLoopArgs& a, uint3 bid, uint3 gdim) {
   __shared__ float den_last[kMaxModes][32];
+  __shared__ float S[kMaxModes][32];
+  __shared__ double lds64[16][2];
   int64_t first[kMaxModes + 1];
   first[0] = 0;
 #pragma unroll
@@ -382,7 +388,7 @@ __device__ __forceinline__ void kl_apply_body(const KlLoopArgs& a, uint3 bid, ui
       cv[k] = cp[ee[k]];
     }
   }
-  kl_recurrence(a, den_last, bid.x);
+  kl_recurrence(a, den_last, S, lds64, bid.x);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kApplyPre; ++k) {
